@@ -1,0 +1,914 @@
+/*
+ * fsl_oracle.c -- plain FP64 CPU oracle of the free-surface cumulant LBM step.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the benchmark's
+ * CPU baseline.  It shares no code with the GPU path.  It is written for
+ * clarity, not speed: full PDFs in double, one cell at a time, every rule in
+ * the order the method states it.
+ *
+ * Paper passages followed (Schwarzmeier et al., "Particle-resolved simulation
+ * of antidunes in free-surface flows"):
+ *   Section 2.1: lattice units, D3Q27 cumulant collision with all rates 1 but
+ *     omega, nu = (1/omega - 1/2)/3, bounce-back at solid obstacles, the
+ *     volume-of-fluid free-surface model whose boundary condition carries the
+ *     gas pressure and the Laplace pressure 2*sigma*kappa.
+ *   Section 2.2: no-slip at particle surfaces.
+ *   Section 3.1: periodic x and y, no-slip z boundaries, body force in x.
+ * Where the paper delegates to cited methods, the readings used are:
+ *   collision   -- Geier et al. 2015 cumulant transform (chimera passes,
+ *                  cumulants with first-order central moments taken as zero),
+ *                  no Galilean correction terms; force by shifting the
+ *                  velocity by F/(2 rho) and negating the first-order central
+ *                  moments in the collision;
+ *   walls       -- halfway bounce-back, Ladd's moving-wall term with rho_w=1;
+ *   free surface-- Koerner et al. 2005 anti-bounce-back reconstruction of
+ *                  PDFs coming from gas or from the gas side of the normal,
+ *                  gas density rho_gas + 6 sigma kappa; mass flux weighted by
+ *                  the mean fill level between two interface cells;
+ *   conversion  -- thresholds (1+eps) rho and -eps rho, isolated-cell rules,
+ *                  fill -> cancel -> empty order (Thuerey 2007); excess mass
+ *                  shared evenly among interface neighbours, a pool otherwise;
+ *   geometry    -- Parker-Youngs normal, mean curvature from the finite-
+ *                  difference Hessian of the same 3x3x3 fill stencil.
+ */
+#include "fsl_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 27
+#define REST 13
+
+static int CV[Q][3];
+static double WT[Q];
+static int tables_ready = 0;
+
+static double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+static void tables(void)
+{
+    if (tables_ready) return;
+    for (int i = 0; i < Q; ++i) {
+        CV[i][0] = i % 3 - 1;
+        CV[i][1] = (i / 3) % 3 - 1;
+        CV[i][2] = i / 9 - 1;
+        WT[i] = w1(CV[i][0]) * w1(CV[i][1]) * w1(CV[i][2]);
+    }
+    tables_ready = 1;
+}
+
+static int opp(int i) { return Q - 1 - i; }
+static int K(int a, int b, int c) { return a + 3 * b + 9 * c; }
+static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+void ol_velocities(int32_t c[27][3], double w[27])
+{
+    tables();
+    for (int i = 0; i < Q; ++i) {
+        for (int d = 0; d < 3; ++d) c[i][d] = CV[i][d];
+        w[i] = WT[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collision (Geier et al. 2015 as used in Section 2.1)                      */
+/* ------------------------------------------------------------------------ */
+
+/* One forward chimera step on a triplet of values at velocities -1, 0, +1:
+ * returns the central moments of order 0, 1, 2 about u. */
+static void chimera_fwd(double *fm, double *f0, double *fp, double u)
+{
+    double k0 = *fm + *f0 + *fp;
+    double k1 = (*fp - *fm) - u * k0;
+    double k2 = (*fp + *fm) - 2.0 * u * (*fp - *fm) + u * u * k0;
+    *fm = k0;
+    *f0 = k1;
+    *fp = k2;
+}
+
+/* Inverse of chimera_fwd: central moments of order 0,1,2 -> values at -1,0,+1 */
+static void chimera_bwd(double *k0p, double *k1p, double *k2p, double u)
+{
+    double k0 = *k0p, k1 = *k1p, k2 = *k2p;
+    double f0 = k0 * (1.0 - u * u) - 2.0 * u * k1 - k2;
+    double fm = 0.5 * (k0 * (u * u - u) + k1 * (2.0 * u - 1.0) + k2);
+    double fp = 0.5 * (k0 * (u * u + u) + k1 * (2.0 * u + 1.0) + k2);
+    *k0p = fm;
+    *k1p = f0;
+    *k2p = fp;
+}
+
+/* PDFs (index a+3b+9c, a<->x) -> raw central moments kappa_{abc} about u.
+ * Passes in z, then y, then x. */
+static void central_moments(double M[Q], const double u[3])
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            chimera_fwd(&M[K(a, b, 0)], &M[K(a, b, 1)], &M[K(a, b, 2)], u[2]);
+    for (int a = 0; a < 3; ++a)
+        for (int g = 0; g < 3; ++g)
+            chimera_fwd(&M[K(a, 0, g)], &M[K(a, 1, g)], &M[K(a, 2, g)], u[1]);
+    for (int b = 0; b < 3; ++b)
+        for (int g = 0; g < 3; ++g)
+            chimera_fwd(&M[K(0, b, g)], &M[K(1, b, g)], &M[K(2, b, g)], u[0]);
+}
+
+static void central_to_pdf(double M[Q], const double u[3])
+{
+    for (int b = 0; b < 3; ++b)
+        for (int g = 0; g < 3; ++g)
+            chimera_bwd(&M[K(0, b, g)], &M[K(1, b, g)], &M[K(2, b, g)], u[0]);
+    for (int a = 0; a < 3; ++a)
+        for (int g = 0; g < 3; ++g)
+            chimera_bwd(&M[K(a, 0, g)], &M[K(a, 1, g)], &M[K(a, 2, g)], u[1]);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            chimera_bwd(&M[K(a, b, 0)], &M[K(a, b, 1)], &M[K(a, b, 2)], u[2]);
+}
+
+/* shorthand for normalised central moment / cumulant tables */
+#define k_(a, b, c) k[K(a, b, c)]
+#define C_(a, b, c) C[K(a, b, c)]
+
+/* Cumulants of orders 2..6 from normalised central moments, with the
+ * first-order central moments taken as zero (moment-cumulant relations
+ * restricted to blocks of size >= 2). */
+static void cumulants_from_central(const double k[Q], double C[Q])
+{
+    for (int i = 0; i < Q; ++i) C[i] = k[i]; /* orders 0..3 are unchanged */
+
+    /* order 4 */
+    C_(2, 2, 0) = k_(2, 2, 0) - k_(2, 0, 0) * k_(0, 2, 0) - 2.0 * k_(1, 1, 0) * k_(1, 1, 0);
+    C_(2, 0, 2) = k_(2, 0, 2) - k_(2, 0, 0) * k_(0, 0, 2) - 2.0 * k_(1, 0, 1) * k_(1, 0, 1);
+    C_(0, 2, 2) = k_(0, 2, 2) - k_(0, 2, 0) * k_(0, 0, 2) - 2.0 * k_(0, 1, 1) * k_(0, 1, 1);
+    C_(2, 1, 1) = k_(2, 1, 1) - k_(2, 0, 0) * k_(0, 1, 1) - 2.0 * k_(1, 1, 0) * k_(1, 0, 1);
+    C_(1, 2, 1) = k_(1, 2, 1) - k_(0, 2, 0) * k_(1, 0, 1) - 2.0 * k_(1, 1, 0) * k_(0, 1, 1);
+    C_(1, 1, 2) = k_(1, 1, 2) - k_(0, 0, 2) * k_(1, 1, 0) - 2.0 * k_(1, 0, 1) * k_(0, 1, 1);
+
+    /* order 5 */
+    C_(2, 2, 1) = k_(2, 2, 1) - (k_(2, 0, 0) * k_(0, 2, 1) + k_(0, 2, 0) * k_(2, 0, 1)
+                                 + 4.0 * k_(1, 1, 0) * k_(1, 1, 1) + 2.0 * k_(1, 0, 1) * k_(1, 2, 0)
+                                 + 2.0 * k_(0, 1, 1) * k_(2, 1, 0));
+    C_(2, 1, 2) = k_(2, 1, 2) - (k_(2, 0, 0) * k_(0, 1, 2) + k_(0, 0, 2) * k_(2, 1, 0)
+                                 + 4.0 * k_(1, 0, 1) * k_(1, 1, 1) + 2.0 * k_(1, 1, 0) * k_(1, 0, 2)
+                                 + 2.0 * k_(0, 1, 1) * k_(2, 0, 1));
+    C_(1, 2, 2) = k_(1, 2, 2) - (k_(0, 2, 0) * k_(1, 0, 2) + k_(0, 0, 2) * k_(1, 2, 0)
+                                 + 4.0 * k_(0, 1, 1) * k_(1, 1, 1) + 2.0 * k_(1, 1, 0) * k_(0, 1, 2)
+                                 + 2.0 * k_(1, 0, 1) * k_(0, 2, 1));
+
+    /* order 6: m6 - sum(m2 m4) - sum(m3 m3) + 2 sum(m2 m2 m2) */
+    double s24 = k_(2, 0, 0) * k_(0, 2, 2) + k_(0, 2, 0) * k_(2, 0, 2) + k_(0, 0, 2) * k_(2, 2, 0)
+                 + 4.0 * (k_(1, 1, 0) * k_(1, 1, 2) + k_(1, 0, 1) * k_(1, 2, 1)
+                          + k_(0, 1, 1) * k_(2, 1, 1));
+    double s33 = 2.0 * (k_(2, 1, 0) * k_(0, 1, 2) + k_(2, 0, 1) * k_(0, 2, 1)
+                        + k_(1, 2, 0) * k_(1, 0, 2))
+                 + 4.0 * k_(1, 1, 1) * k_(1, 1, 1);
+    double s222 = k_(2, 0, 0) * k_(0, 2, 0) * k_(0, 0, 2)
+                  + 2.0 * (k_(2, 0, 0) * k_(0, 1, 1) * k_(0, 1, 1)
+                           + k_(0, 2, 0) * k_(1, 0, 1) * k_(1, 0, 1)
+                           + k_(0, 0, 2) * k_(1, 1, 0) * k_(1, 1, 0))
+                  + 8.0 * k_(1, 1, 0) * k_(1, 0, 1) * k_(0, 1, 1);
+    C_(2, 2, 2) = k_(2, 2, 2) - s24 - s33 + 2.0 * s222;
+}
+
+/* Inverse of cumulants_from_central for orders 2..6 (rearranged relations,
+ * using the already rebuilt lower-order moments). */
+static void central_from_cumulants(const double C[Q], double k[Q])
+{
+    for (int i = 0; i < Q; ++i) k[i] = C[i];
+
+    k_(2, 2, 0) = C_(2, 2, 0) + k_(2, 0, 0) * k_(0, 2, 0) + 2.0 * k_(1, 1, 0) * k_(1, 1, 0);
+    k_(2, 0, 2) = C_(2, 0, 2) + k_(2, 0, 0) * k_(0, 0, 2) + 2.0 * k_(1, 0, 1) * k_(1, 0, 1);
+    k_(0, 2, 2) = C_(0, 2, 2) + k_(0, 2, 0) * k_(0, 0, 2) + 2.0 * k_(0, 1, 1) * k_(0, 1, 1);
+    k_(2, 1, 1) = C_(2, 1, 1) + k_(2, 0, 0) * k_(0, 1, 1) + 2.0 * k_(1, 1, 0) * k_(1, 0, 1);
+    k_(1, 2, 1) = C_(1, 2, 1) + k_(0, 2, 0) * k_(1, 0, 1) + 2.0 * k_(1, 1, 0) * k_(0, 1, 1);
+    k_(1, 1, 2) = C_(1, 1, 2) + k_(0, 0, 2) * k_(1, 1, 0) + 2.0 * k_(1, 0, 1) * k_(0, 1, 1);
+
+    k_(2, 2, 1) = C_(2, 2, 1) + (k_(2, 0, 0) * k_(0, 2, 1) + k_(0, 2, 0) * k_(2, 0, 1)
+                                 + 4.0 * k_(1, 1, 0) * k_(1, 1, 1) + 2.0 * k_(1, 0, 1) * k_(1, 2, 0)
+                                 + 2.0 * k_(0, 1, 1) * k_(2, 1, 0));
+    k_(2, 1, 2) = C_(2, 1, 2) + (k_(2, 0, 0) * k_(0, 1, 2) + k_(0, 0, 2) * k_(2, 1, 0)
+                                 + 4.0 * k_(1, 0, 1) * k_(1, 1, 1) + 2.0 * k_(1, 1, 0) * k_(1, 0, 2)
+                                 + 2.0 * k_(0, 1, 1) * k_(2, 0, 1));
+    k_(1, 2, 2) = C_(1, 2, 2) + (k_(0, 2, 0) * k_(1, 0, 2) + k_(0, 0, 2) * k_(1, 2, 0)
+                                 + 4.0 * k_(0, 1, 1) * k_(1, 1, 1) + 2.0 * k_(1, 1, 0) * k_(0, 1, 2)
+                                 + 2.0 * k_(1, 0, 1) * k_(0, 2, 1));
+
+    double s24 = k_(2, 0, 0) * k_(0, 2, 2) + k_(0, 2, 0) * k_(2, 0, 2) + k_(0, 0, 2) * k_(2, 2, 0)
+                 + 4.0 * (k_(1, 1, 0) * k_(1, 1, 2) + k_(1, 0, 1) * k_(1, 2, 1)
+                          + k_(0, 1, 1) * k_(2, 1, 1));
+    double s33 = 2.0 * (k_(2, 1, 0) * k_(0, 1, 2) + k_(2, 0, 1) * k_(0, 2, 1)
+                        + k_(1, 2, 0) * k_(1, 0, 2))
+                 + 4.0 * k_(1, 1, 1) * k_(1, 1, 1);
+    double s222 = k_(2, 0, 0) * k_(0, 2, 0) * k_(0, 0, 2)
+                  + 2.0 * (k_(2, 0, 0) * k_(0, 1, 1) * k_(0, 1, 1)
+                           + k_(0, 2, 0) * k_(1, 0, 1) * k_(1, 0, 1)
+                           + k_(0, 0, 2) * k_(1, 1, 0) * k_(1, 1, 0))
+                  + 8.0 * k_(1, 1, 0) * k_(1, 0, 1) * k_(0, 1, 1);
+    k_(2, 2, 2) = C_(2, 2, 2) + s24 + s33 - 2.0 * s222;
+}
+
+static int order_of(int i) { return i % 3 + (i / 3) % 3 + i / 9; }
+
+/* density, momentum, force-shifted velocity */
+static void macro(const double f[Q], const double g[3], double *rho, double u[3])
+{
+    tables();
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        r += f[i];
+        for (int d = 0; d < 3; ++d) j[d] += f[i] * CV[i][d];
+    }
+    for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * r * g[d]) / r;
+    *rho = r;
+}
+
+void ol_cumulants(const double fin[27], const double g[3], double C[27])
+{
+    double rho, u[3], M[Q], k[Q];
+    macro(fin, g, &rho, u);
+    for (int i = 0; i < Q; ++i) M[i] = fin[i];
+    central_moments(M, u);
+    for (int i = 0; i < Q; ++i) k[i] = M[i] / rho;
+    cumulants_from_central(k, C);
+    C[0] = rho;
+}
+
+void ol_collide(const double fin[27], const double g[3], double omega,
+                double omega_bulk, double omega_high, double fout[27])
+{
+    double rho, u[3], M[Q], k[Q], C[Q], Cs[Q], ks[Q];
+    macro(fin, g, &rho, u);
+    for (int i = 0; i < Q; ++i) M[i] = fin[i];
+    central_moments(M, u);
+    for (int i = 0; i < Q; ++i) k[i] = M[i] / rho;
+    cumulants_from_central(k, C);
+
+    /* relaxation */
+    for (int i = 0; i < Q; ++i) Cs[i] = C[i];
+    /* second order: off-diagonal and deviatoric parts with omega, trace with
+     * omega_bulk towards its equilibrium 3 * c_s^2 = 1 */
+    Cs[K(1, 1, 0)] = (1.0 - omega) * C_(1, 1, 0);
+    Cs[K(1, 0, 1)] = (1.0 - omega) * C_(1, 0, 1);
+    Cs[K(0, 1, 1)] = (1.0 - omega) * C_(0, 1, 1);
+    double D1 = (1.0 - omega) * (C_(2, 0, 0) - C_(0, 2, 0));
+    double D2 = (1.0 - omega) * (C_(2, 0, 0) - C_(0, 0, 2));
+    double T = (1.0 - omega_bulk) * (C_(2, 0, 0) + C_(0, 2, 0) + C_(0, 0, 2)) + omega_bulk * 1.0;
+    Cs[K(2, 0, 0)] = (T + D1 + D2) / 3.0;
+    Cs[K(0, 2, 0)] = (T - 2.0 * D1 + D2) / 3.0;
+    Cs[K(0, 0, 2)] = (T + D1 - 2.0 * D2) / 3.0;
+    /* orders 3..6 relax to their equilibrium value 0 */
+    for (int i = 0; i < Q; ++i)
+        if (order_of(i) >= 3) Cs[i] = (1.0 - omega_high) * C[i];
+
+    central_from_cumulants(Cs, ks);
+    /* zeroth and first order: mass kept, first-order central moments negated
+     * (the velocity shift by F/(2 rho) then adds exactly F to the momentum) */
+    ks[K(0, 0, 0)] = 1.0;
+    ks[K(1, 0, 0)] = -k_(1, 0, 0);
+    ks[K(0, 1, 0)] = -k_(0, 1, 0);
+    ks[K(0, 0, 1)] = -k_(0, 0, 1);
+
+    for (int i = 0; i < Q; ++i) M[i] = rho * ks[i];
+    central_to_pdf(M, u);
+    for (int i = 0; i < Q; ++i) fout[i] = M[i];
+}
+
+#undef k_
+#undef C_
+
+void ol_feq(double rho, const double u[3], double feq[27])
+{
+    tables();
+    for (int i = 0; i < Q; ++i) {
+        double p = rho;
+        for (int d = 0; d < 3; ++d) {
+            double ud = u[d];
+            int c = CV[i][d];
+            double psi = (c == 0) ? (2.0 / 3.0 - ud * ud) : 0.5 * (1.0 / 3.0 + ud * ud + c * ud);
+            p *= psi;
+        }
+        feq[i] = p;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: Parker-Youngs normal and finite-difference mean curvature      */
+/* ------------------------------------------------------------------------ */
+
+static double st(const double phi[27], int a, int b, int c)
+{
+    return phi[(a + 1) + 3 * (b + 1) + 9 * (c + 1)];
+}
+
+void ol_normal_curvature(const double phi[27], double n[3], double *kappa)
+{
+    static const double Wpy[3] = {1.0, 2.0, 1.0};
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+            double wgt = Wpy[p] * Wpy[q];
+            g[0] += wgt * (st(phi, 1, p - 1, q - 1) - st(phi, -1, p - 1, q - 1));
+            g[1] += wgt * (st(phi, p - 1, 1, q - 1) - st(phi, p - 1, -1, q - 1));
+            g[2] += wgt * (st(phi, p - 1, q - 1, 1) - st(phi, p - 1, q - 1, -1));
+        }
+    for (int d = 0; d < 3; ++d) g[d] /= 32.0;
+    double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (gn < 1e-12) {
+        n[0] = n[1] = n[2] = 0.0;
+        *kappa = 0.0;
+        return;
+    }
+    double gh[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+    for (int d = 0; d < 3; ++d) n[d] = -gh[d];
+
+    double H[3][3];
+    double c0 = st(phi, 0, 0, 0);
+    H[0][0] = st(phi, 1, 0, 0) - 2.0 * c0 + st(phi, -1, 0, 0);
+    H[1][1] = st(phi, 0, 1, 0) - 2.0 * c0 + st(phi, 0, -1, 0);
+    H[2][2] = st(phi, 0, 0, 1) - 2.0 * c0 + st(phi, 0, 0, -1);
+    H[0][1] = H[1][0] = 0.25 * (st(phi, 1, 1, 0) - st(phi, 1, -1, 0) - st(phi, -1, 1, 0) + st(phi, -1, -1, 0));
+    H[0][2] = H[2][0] = 0.25 * (st(phi, 1, 0, 1) - st(phi, 1, 0, -1) - st(phi, -1, 0, 1) + st(phi, -1, 0, -1));
+    H[1][2] = H[2][1] = 0.25 * (st(phi, 0, 1, 1) - st(phi, 0, 1, -1) - st(phi, 0, -1, 1) + st(phi, 0, -1, -1));
+    double tr = H[0][0] + H[1][1] + H[2][2];
+    double gHg = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gHg += gh[a] * H[a][b] * gh[b];
+    *kappa = -(tr - gHg) / (2.0 * gn);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice                                                                  */
+/* ------------------------------------------------------------------------ */
+
+enum { MK_TO_LIQ = 1, MK_TO_GAS = 2, MK_EMPTY = 4, MK_NEW_FROM_GAS = 8,
+       MK_NEW_FROM_LIQ = 16, MK_RULE_ISO = 32 };
+
+struct OlLattice {
+    OlParams p;
+    int64_t N;
+    double *f;        /* N*27 post-collision PDFs */
+    double *m, *phi, *rho;
+    uint8_t *type, *mark;
+    int32_t *owner;
+    double *n, *kappa;
+    double *share;    /* excess share of a converted cell */
+    int32_t nsph;
+    double *sph;      /* per sphere: X[3], r, U[3], Omega[3] */
+    double pool;
+    int64_t cnt[8];
+    int64_t steps;
+};
+
+static int64_t cell_of(const OlLattice *L, int x, int y, int z)
+{
+    return (int64_t)x + (int64_t)L->p.nx * ((int64_t)y + (int64_t)L->p.ny * z);
+}
+
+/* neighbour cell + sign*c_i; periodic in x, y; returns -1 beyond the z walls */
+static int64_t nbr(const OlLattice *L, int64_t cell, int i, int sign)
+{
+    int nx = L->p.nx, ny = L->p.ny, nz = L->p.nz;
+    int x = (int)(cell % nx);
+    int y = (int)((cell / nx) % ny);
+    int z = (int)(cell / ((int64_t)nx * ny));
+    x += sign * CV[i][0];
+    y += sign * CV[i][1];
+    z += sign * CV[i][2];
+    if (z < 0 || z >= nz) return -1;
+    x = (x + nx) % nx;
+    y = (y + ny) % ny;
+    return cell_of(L, x, y, z);
+}
+
+static void cell_xyz(const OlLattice *L, int64_t cell, int *x, int *y, int *z)
+{
+    *x = (int)(cell % L->p.nx);
+    *y = (int)((cell / L->p.nx) % L->p.ny);
+    *z = (int)(cell / ((int64_t)L->p.nx * L->p.ny));
+}
+
+/* minimum-image offset along a periodic axis of length n */
+static double min_image(double d, int n)
+{
+    if (d > 0.5 * n) d -= n;
+    else if (d < -0.5 * n) d += n;
+    return d;
+}
+
+static void sphere_wall_velocity(const OlLattice *L, int p, int64_t cell, int j, double uw[3])
+{
+    const double *s = &L->sph[10 * p];
+    int x, y, z;
+    cell_xyz(L, cell, &x, &y, &z);
+    /* wall point: halfway along the link from the fluid cell to the solid one */
+    double r[3];
+    r[0] = min_image((x + 0.5 - 0.5 * CV[j][0]) - s[0], L->p.nx);
+    r[1] = min_image((y + 0.5 - 0.5 * CV[j][1]) - s[1], L->p.ny);
+    r[2] = (z + 0.5 - 0.5 * CV[j][2]) - s[2];
+    const double *U = s + 4, *Om = s + 7;
+    uw[0] = U[0] + (Om[1] * r[2] - Om[2] * r[1]);
+    uw[1] = U[1] + (Om[2] * r[0] - Om[0] * r[2]);
+    uw[2] = U[2] + (Om[0] * r[1] - Om[1] * r[0]);
+}
+
+/* fill value a stencil sees at a neighbour; centre value for walls/solids */
+static double stencil_phi(const OlLattice *L, int64_t y, double centre)
+{
+    if (y < 0) return centre;
+    switch (L->type[y]) {
+    case OL_LIQUID: return 1.0;
+    case OL_GAS: return 0.0;
+    case OL_INTERFACE: return clamp01(L->phi[y]);
+    default: return centre;
+    }
+}
+
+static void geometry_cell(OlLattice *L, int64_t c)
+{
+    double st27[Q];
+    double centre = clamp01(L->phi[c]);
+    for (int i = 0; i < Q; ++i)
+        st27[i] = (i == REST) ? centre : stencil_phi(L, nbr(L, c, i, +1), centre);
+    ol_normal_curvature(st27, &L->n[3 * c], &L->kappa[c]);
+}
+
+static void phase_geometry(OlLattice *L)
+{
+    for (int64_t c = 0; c < L->N; ++c) {
+        if (L->type[c] == OL_INTERFACE) {
+            geometry_cell(L, c);
+        } else {
+            L->n[3 * c] = L->n[3 * c + 1] = L->n[3 * c + 2] = 0.0;
+            L->kappa[c] = 0.0;
+        }
+    }
+}
+
+static double sum27(const double *f)
+{
+    double s = 0.0;
+    for (int i = 0; i < Q; ++i) s += f[i];
+    return s;
+}
+
+static void refresh_fill(OlLattice *L)
+{
+    for (int64_t c = 0; c < L->N; ++c) {
+        switch (L->type[c]) {
+        case OL_INTERFACE: L->phi[c] = L->m[c] / L->rho[c]; break;
+        case OL_LIQUID: L->phi[c] = 1.0; break;
+        default: L->phi[c] = 0.0; break;
+        }
+    }
+}
+
+OlLattice *ol_create(const OlParams *p, const double *fill, const double *rho,
+                     const double *vel)
+{
+    tables();
+    if (!p || !fill || !rho) return NULL;
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return NULL;
+    if (!(p->omega > 0.0 && p->omega < 2.0)) return NULL;
+    OlLattice *L = (OlLattice *)calloc(1, sizeof(OlLattice));
+    L->p = *p;
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    L->N = N;
+    L->f = (double *)calloc((size_t)N * Q, sizeof(double));
+    L->m = (double *)calloc((size_t)N, sizeof(double));
+    L->phi = (double *)calloc((size_t)N, sizeof(double));
+    L->rho = (double *)calloc((size_t)N, sizeof(double));
+    L->type = (uint8_t *)calloc((size_t)N, 1);
+    L->mark = (uint8_t *)calloc((size_t)N, 1);
+    L->owner = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    L->n = (double *)calloc((size_t)N * 3, sizeof(double));
+    L->kappa = (double *)calloc((size_t)N, sizeof(double));
+    L->share = (double *)calloc((size_t)N, sizeof(double));
+    for (int64_t c = 0; c < N; ++c) L->owner[c] = -1;
+
+    /* cell types from the fill level */
+    for (int64_t c = 0; c < N; ++c) {
+        double fl = fill[c];
+        L->type[c] = fl >= 1.0 ? OL_LIQUID : (fl <= 0.0 ? OL_GAS : OL_INTERFACE);
+    }
+    /* closure: a liquid cell next to a gas cell becomes interface */
+    uint8_t *t0 = (uint8_t *)malloc((size_t)N);
+    memcpy(t0, L->type, (size_t)N);
+    for (int64_t c = 0; c < N; ++c) {
+        if (t0[c] != OL_LIQUID) continue;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y >= 0 && t0[y] == OL_GAS) {
+                L->type[c] = OL_INTERFACE;
+                break;
+            }
+        }
+    }
+    free(t0);
+    /* mass, equilibrium PDFs */
+    for (int64_t c = 0; c < N; ++c) {
+        double u[3] = {0.0, 0.0, 0.0};
+        if (vel)
+            for (int d = 0; d < 3; ++d) u[d] = vel[(int64_t)d * N + c];
+        ol_feq(rho[c], u, &L->f[c * Q]);
+        L->rho[c] = sum27(&L->f[c * Q]);
+        L->m[c] = (L->type[c] == OL_GAS) ? 0.0 : clamp01(fill[c]) * rho[c];
+    }
+    refresh_fill(L);
+    phase_geometry(L);
+    return L;
+}
+
+void ol_destroy(OlLattice *L)
+{
+    if (!L) return;
+    free(L->f); free(L->m); free(L->phi); free(L->rho); free(L->type);
+    free(L->mark); free(L->owner); free(L->n); free(L->kappa); free(L->share);
+    free(L->sph);
+    free(L);
+}
+
+int ol_set_particles(OlLattice *L, int32_t n, const double *centre,
+                     const double *radius, const double *vel, const double *angvel)
+{
+    int nx = L->p.nx, ny = L->p.ny, nz = L->p.nz;
+    for (int32_t q = 0; q < n; ++q)
+        if (!(radius[q] > 0.0) || 2.0 * radius[q] >= (nx < ny ? nx : ny)) return -1;
+    free(L->sph);
+    L->nsph = n;
+    L->sph = (double *)calloc((size_t)(n > 0 ? n : 1) * 10, sizeof(double));
+    for (int32_t q = 0; q < n; ++q) {
+        double *s = &L->sph[10 * q];
+        s[0] = centre[3 * q] - nx * floor(centre[3 * q] / nx);
+        s[1] = centre[3 * q + 1] - ny * floor(centre[3 * q + 1] / ny);
+        s[2] = centre[3 * q + 2];
+        s[3] = radius[q];
+        for (int d = 0; d < 3; ++d) {
+            s[4 + d] = vel ? vel[3 * q + d] : 0.0;
+            s[7 + d] = angvel ? angvel[3 * q + d] : 0.0;
+        }
+    }
+    for (int64_t c = 0; c < L->N; ++c) L->owner[c] = -1;
+    for (int32_t q = 0; q < n; ++q) {
+        const double *s = &L->sph[10 * q];
+        double r = s[3];
+        int x0 = (int)floor(s[0] - r) - 1, x1 = (int)floor(s[0] + r) + 1;
+        int y0 = (int)floor(s[1] - r) - 1, y1 = (int)floor(s[1] + r) + 1;
+        int z0 = (int)floor(s[2] - r) - 1, z1 = (int)floor(s[2] + r) + 1;
+        if (z0 < 0) z0 = 0;
+        if (z1 > nz - 1) z1 = nz - 1;
+        for (int z = z0; z <= z1; ++z)
+            for (int yy = y0; yy <= y1; ++yy)
+                for (int xx = x0; xx <= x1; ++xx) {
+                    int x = ((xx % nx) + nx) % nx, y = ((yy % ny) + ny) % ny;
+                    int64_t c = cell_of(L, x, y, z);
+                    if (L->owner[c] >= 0) continue;
+                    double dx = min_image((x + 0.5) - s[0], nx);
+                    double dy = min_image((y + 0.5) - s[1], ny);
+                    double dz = (z + 0.5) - s[2];
+                    if (dx * dx + dy * dy + dz * dz <= r * r) L->owner[c] = q;
+                }
+    }
+    for (int64_t c = 0; c < L->N; ++c) {
+        if (L->owner[c] >= 0) {
+            L->type[c] = OL_SOLID;
+            L->m[c] = 0.0;
+            L->phi[c] = 0.0;
+        }
+    }
+    phase_geometry(L);
+    return 0;
+}
+
+void ol_set_state(OlLattice *L, const uint8_t *type, const double *m, const double *f)
+{
+    memcpy(L->type, type, (size_t)L->N);
+    memcpy(L->m, m, (size_t)L->N * sizeof(double));
+    memcpy(L->f, f, (size_t)L->N * Q * sizeof(double));
+    for (int64_t c = 0; c < L->N; ++c) L->rho[c] = sum27(&L->f[c * Q]);
+    refresh_fill(L);
+    phase_geometry(L);
+}
+
+/* ---- phase 1: streaming, boundaries, mass flux, collision ---------------- */
+static void phase_stream_collide(OlLattice *L)
+{
+    const int64_t N = L->N;
+    const OlParams *p = &L->p;
+    double *fnew = (double *)malloc((size_t)N * Q * sizeof(double));
+    double *mnew = (double *)malloc((size_t)N * sizeof(double));
+    memcpy(fnew, L->f, (size_t)N * Q * sizeof(double));
+    memcpy(mnew, L->m, (size_t)N * sizeof(double));
+
+    for (int64_t c = 0; c < N; ++c) {
+        uint8_t t = L->type[c];
+        if (t != OL_LIQUID && t != OL_INTERFACE) continue;
+        const double *fo = &L->f[c * Q];
+        double fin[Q], feqG[Q];
+
+        if (t == OL_INTERFACE) {
+            /* gas-side equilibrium: gas pressure plus Laplace pressure 2 sigma kappa,
+             * i.e. rho_G = rho_gas + 6 sigma kappa, at the cell's own velocity */
+            double rg = p->rho_gas + 6.0 * p->sigma * L->kappa[c];
+            double r0 = 0.0, j[3] = {0.0, 0.0, 0.0}, uI[3];
+            for (int i = 0; i < Q; ++i) {
+                r0 += fo[i];
+                for (int d = 0; d < 3; ++d) j[d] += fo[i] * CV[i][d];
+            }
+            for (int d = 0; d < 3; ++d) uI[d] = j[d] / r0;
+            ol_feq(rg, uI, feqG);
+        }
+
+        fin[REST] = fo[REST];
+        for (int j = 0; j < Q; ++j) {
+            if (j == REST) continue;
+            int64_t src = nbr(L, c, j, -1);
+            if (src < 0 || L->type[src] == OL_SOLID) {
+                double uw[3] = {0.0, 0.0, 0.0};
+                if (src >= 0) sphere_wall_velocity(L, L->owner[src], c, j, uw);
+                double cu = CV[j][0] * uw[0] + CV[j][1] * uw[1] + CV[j][2] * uw[2];
+                fin[j] = fo[opp(j)] + 6.0 * WT[j] * 1.0 * cu;
+                continue;
+            }
+            int recon = 0;
+            if (t == OL_INTERFACE) {
+                if (L->type[src] == OL_GAS) {
+                    recon = 1;
+                } else {
+                    const double *nn = &L->n[3 * c];
+                    double nc = nn[0] * CV[j][0] + nn[1] * CV[j][1] + nn[2] * CV[j][2];
+                    if (nc < -p->normal_tie) recon = 1;
+                }
+            } else if (L->type[src] == OL_GAS) {
+                L->cnt[7]++;
+            }
+            if (recon)
+                fin[j] = feqG[j] + feqG[opp(j)] - fo[opp(j)];
+            else
+                fin[j] = L->f[src * Q + j];
+        }
+
+        /* mass exchange with every fluid neighbour, from stored post-collision PDFs */
+        double dm = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y < 0) continue;
+            uint8_t ty = L->type[y];
+            if (ty == OL_SOLID || ty == OL_GAS) continue;
+            double s = (t == OL_INTERFACE && ty == OL_INTERFACE)
+                           ? 0.5 * (clamp01(L->phi[c]) + clamp01(L->phi[y]))
+                           : 1.0;
+            dm += s * (L->f[y * Q + opp(i)] - fo[i]);
+        }
+        mnew[c] = L->m[c] + dm;
+
+        ol_collide(fin, p->accel, p->omega, p->omega_bulk, p->omega_high, &fnew[c * Q]);
+        L->rho[c] = sum27(&fnew[c * Q]);
+    }
+    free(L->f);
+    free(L->m);
+    L->f = fnew;
+    L->m = mnew;
+}
+
+/* ---- phase 2: conversion marks ------------------------------------------ */
+static void phase_marks(OlLattice *L)
+{
+    const double eps = L->p.conv_eps;
+    memset(L->mark, 0, (size_t)L->N);
+    for (int64_t c = 0; c < L->N; ++c) {
+        if (L->type[c] != OL_INTERFACE) continue;
+        double m = L->m[c], r = L->rho[c];
+        if (m > (1.0 + eps) * r) {
+            L->mark[c] = MK_TO_LIQ;
+        } else if (m < -eps * r) {
+            L->mark[c] = MK_TO_GAS;
+        } else if (L->p.rule_isolated) {
+            int has_gas = 0, has_liq = 0;
+            for (int i = 0; i < Q; ++i) {
+                if (i == REST) continue;
+                int64_t y = nbr(L, c, i, +1);
+                if (y < 0) continue;
+                if (L->type[y] == OL_GAS) has_gas = 1;
+                if (L->type[y] == OL_LIQUID) has_liq = 1;
+            }
+            if (!has_gas && has_liq) L->mark[c] = MK_TO_LIQ | MK_RULE_ISO;
+            else if (!has_liq && has_gas) L->mark[c] = MK_TO_GAS | MK_RULE_ISO;
+        }
+    }
+}
+
+/* ---- phase 3: conversion processing ------------------------------------- */
+static void phase_convert(OlLattice *L)
+{
+    const int64_t N = L->N;
+    uint8_t *mk = L->mark;
+
+    /* counters of the marks as set from the thresholds and neighbour rules */
+    for (int64_t c = 0; c < N; ++c) {
+        if (mk[c] & MK_TO_LIQ) L->cnt[(mk[c] & MK_RULE_ISO) ? 2 : 0]++;
+    }
+
+    /* 1. filling: gas neighbours of filled cells become interface cells */
+    for (int64_t c = 0; c < N; ++c) {
+        if (!(mk[c] & MK_TO_LIQ)) continue;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y >= 0 && L->type[y] == OL_GAS) mk[y] |= MK_NEW_FROM_GAS;
+        }
+    }
+    /* their PDFs: equilibrium at the mean density and velocity of the liquid
+     * and (old) interface neighbours that are not marked for emptying */
+    for (int64_t c = 0; c < N; ++c) {
+        if (!(mk[c] & MK_NEW_FROM_GAS)) continue;
+        double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
+        int cnt = 0;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y < 0) continue;
+            uint8_t ty = L->type[y];
+            if (ty != OL_LIQUID && ty != OL_INTERFACE) continue;
+            if (mk[y] & MK_TO_GAS) continue;
+            const double *fy = &L->f[y * Q];
+            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < Q; ++k) {
+                r += fy[k];
+                for (int d = 0; d < 3; ++d) j[d] += fy[k] * CV[k][d];
+            }
+            rs += r;
+            for (int d = 0; d < 3; ++d) us[d] += j[d] / r;
+            cnt++;
+        }
+        /* a filled neighbour always qualifies, so cnt >= 1 */
+        double rbar = rs / cnt, ubar[3];
+        for (int d = 0; d < 3; ++d) ubar[d] = us[d] / cnt;
+        ol_feq(rbar, ubar, &L->f[c * Q]);
+        L->rho[c] = sum27(&L->f[c * Q]);
+        L->m[c] = 0.0;
+        L->cnt[5]++;
+    }
+    /* 2. an emptying next to a filling cell is cancelled */
+    for (int64_t c = 0; c < N; ++c) {
+        if (!(mk[c] & MK_TO_GAS)) continue;
+        int near_fill = 0;
+        for (int i = 0; i < Q && !near_fill; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y >= 0 && (mk[y] & MK_TO_LIQ)) near_fill = 1;
+        }
+        if (near_fill) {
+            L->cnt[4]++;
+        } else {
+            mk[c] |= MK_EMPTY;
+            L->cnt[(mk[c] & MK_RULE_ISO) ? 3 : 1]++;
+        }
+    }
+    /* 3. emptying: liquid neighbours of emptied cells become interface cells,
+     * keeping their PDFs and mass */
+    for (int64_t c = 0; c < N; ++c) {
+        if (!(mk[c] & MK_EMPTY)) continue;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y >= 0 && L->type[y] == OL_LIQUID && !(mk[y] & MK_NEW_FROM_LIQ)) {
+                mk[y] |= MK_NEW_FROM_LIQ;
+                L->cnt[6]++;
+            }
+        }
+    }
+    /* commit the new cell types */
+    for (int64_t c = 0; c < N; ++c) {
+        if (mk[c] & MK_TO_LIQ) L->type[c] = OL_LIQUID;
+        else if (mk[c] & MK_EMPTY) L->type[c] = OL_GAS;
+        else if (mk[c] & (MK_NEW_FROM_GAS | MK_NEW_FROM_LIQ)) L->type[c] = OL_INTERFACE;
+    }
+}
+
+/* ---- phase 4: excess mass ------------------------------------------------ */
+static void phase_excess(OlLattice *L)
+{
+    const int64_t N = L->N;
+    uint8_t *mk = L->mark;
+    for (int64_t c = 0; c < N; ++c) {
+        L->share[c] = 0.0;
+        int filled = (mk[c] & MK_TO_LIQ) != 0, emptied = (mk[c] & MK_EMPTY) != 0;
+        if (!filled && !emptied) continue;
+        double e;
+        if (filled) {
+            e = L->m[c] - L->rho[c];
+            L->m[c] = L->rho[c];
+        } else {
+            e = L->m[c];
+            L->m[c] = 0.0;
+        }
+        int recv = 0;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y >= 0 && L->type[y] == OL_INTERFACE) recv++;
+        }
+        if (recv > 0) L->share[c] = e / recv;
+        else L->pool += e;
+    }
+    /* every interface cell gathers the shares of its converted neighbours in
+     * direction order */
+    for (int64_t c = 0; c < N; ++c) {
+        if (L->type[c] != OL_INTERFACE) continue;
+        double add = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y >= 0 && (mk[y] & (MK_TO_LIQ | MK_EMPTY))) add += L->share[y];
+        }
+        L->m[c] += add;
+    }
+    refresh_fill(L);
+}
+
+void ol_phase(OlLattice *L, int32_t phase)
+{
+    tables();
+    switch (phase) {
+    case 1: phase_stream_collide(L); break;
+    case 2: phase_marks(L); break;
+    case 3: phase_convert(L); break;
+    case 4: phase_excess(L); break;
+    case 5: phase_geometry(L); break;
+    default: break;
+    }
+}
+
+void ol_step(OlLattice *L, int32_t nsteps)
+{
+    tables();
+    for (int32_t s = 0; s < nsteps; ++s) {
+        phase_stream_collide(L);
+        phase_marks(L);
+        phase_convert(L);
+        phase_excess(L);
+        phase_geometry(L);
+        L->steps++;
+    }
+}
+
+void ol_read(const OlLattice *L, int32_t field, void *dst)
+{
+    const int64_t N = L->N;
+    switch (field) {
+    case OL_F_TYPE: memcpy(dst, L->type, (size_t)N); break;
+    case OL_F_MASS: memcpy(dst, L->m, (size_t)N * sizeof(double)); break;
+    case OL_F_FILL: memcpy(dst, L->phi, (size_t)N * sizeof(double)); break;
+    case OL_F_RHO: memcpy(dst, L->rho, (size_t)N * sizeof(double)); break;
+    case OL_F_VEL: {
+        double *o = (double *)dst;
+        for (int64_t c = 0; c < N; ++c) {
+            const double *f = &L->f[c * Q];
+            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < Q; ++i) {
+                r += f[i];
+                for (int d = 0; d < 3; ++d) j[d] += f[i] * CV[i][d];
+            }
+            for (int d = 0; d < 3; ++d) o[d * N + c] = (j[d] - 0.5 * r * L->p.accel[d]) / r;
+        }
+        break;
+    }
+    case OL_F_PDF: {
+        double *o = (double *)dst;
+        for (int64_t c = 0; c < N; ++c)
+            for (int i = 0; i < Q; ++i) o[(int64_t)i * N + c] = L->f[c * Q + i];
+        break;
+    }
+    case OL_F_NORMAL: {
+        double *o = (double *)dst;
+        for (int64_t c = 0; c < N; ++c)
+            for (int d = 0; d < 3; ++d) o[d * N + c] = L->n[3 * c + d];
+        break;
+    }
+    case OL_F_CURV: memcpy(dst, L->kappa, (size_t)N * sizeof(double)); break;
+    case OL_F_OWNER: memcpy(dst, L->owner, (size_t)N * sizeof(int32_t)); break;
+    case OL_F_MARKS: memcpy(dst, L->mark, (size_t)N); break;
+    default: break;
+    }
+}
+
+double ol_total_mass(const OlLattice *L)
+{
+    double s = 0.0;
+    for (int64_t c = 0; c < L->N; ++c)
+        if (L->type[c] == OL_LIQUID || L->type[c] == OL_INTERFACE) s += L->m[c];
+    return s + L->pool;
+}
+
+double ol_pool(const OlLattice *L) { return L->pool; }
+
+void ol_counters(const OlLattice *L, int64_t out[8])
+{
+    for (int i = 0; i < 8; ++i) out[i] = L->cnt[i];
+}
+
+int64_t ol_steps_done(const OlLattice *L) { return L->steps; }

@@ -1,0 +1,114 @@
+/*
+ * fsl_oracle.h -- plain FP64 CPU oracle of one free-surface cumulant LBM step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Tests, the smoke check and the benchmark's CPU
+ * baseline call this library; the GPU product path never includes, links or
+ * calls it, and it shares no code with the GPU path.
+ *
+ * What it computes (paper: "Particle-resolved simulation of antidunes in
+ * free-surface flows", Section 2.1, and the methods cited there):
+ *   - D3Q27 lattice in lattice units, dx = dt = 1, reference density 1;
+ *   - cumulant collision of Geier et al. (2015), shear rate omega, every other
+ *     rate 1 (parameters omega_bulk / omega_high exist only so that tests can
+ *     exercise the moment/cumulant transforms; the paper's choice is 1);
+ *   - pull streaming, bounce-back at walls and (moving) sphere surfaces;
+ *   - the free-surface model: fill level, mass flux, gas-side reconstruction
+ *     with gas pressure plus Laplace pressure 2*sigma*kappa, conversion of
+ *     interface cells and redistribution of excess mass;
+ *   - Parker-Youngs normal and finite-difference mean curvature.
+ *
+ * Storage is deliberately naive: cell-major full PDFs f[cell*27 + i], all in
+ * double, cell = x + nx*(y + ny*z).  Direction i = (cx+1) + 3(cy+1) + 9(cz+1).
+ */
+#ifndef FSL_ORACLE_H
+#define FSL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OL_GAS = 0, OL_LIQUID = 1, OL_INTERFACE = 2, OL_SOLID = 3 };
+
+typedef struct {
+    int32_t nx, ny, nz;         /* x and y periodic; halfway bounce-back walls below z=0 and above z=nz-1 */
+    double omega;               /* shear relaxation rate, nu = (1/omega - 1/2)/3 */
+    double omega_bulk;          /* rate of the trace of the second-order cumulants (paper: 1) */
+    double omega_high;          /* rate of every cumulant of order 3..6 (paper: 1) */
+    double accel[3];            /* body acceleration g; force density F = rho*g */
+    double sigma;               /* surface tension */
+    double rho_gas;             /* gas density, p_g = rho_gas/3 */
+    double conv_eps;            /* conversion threshold epsilon */
+    double normal_tie;          /* n.c_j must be below -normal_tie to trigger reconstruction */
+    int32_t rule_isolated;      /* 1: apply the no-gas-neighbour / no-liquid-neighbour conversion rules */
+} OlParams;
+
+typedef struct OlLattice OlLattice;
+
+/* lattice tables (so that tests can check them) */
+void ol_velocities(int32_t c[27][3], double w[27]);
+
+/* --- single-cell operators ------------------------------------------------ */
+/* collision of one cell; g = body acceleration; returns post-collision f */
+void ol_collide(const double fin[27], const double g[3], double omega,
+                double omega_bulk, double omega_high, double fout[27]);
+/* the normalised pre-collision cumulants of one cell (index a+3b+9c for
+ * C_{abc}); entry 0 holds rho, entries 1,3,9 hold the first-order central
+ * moments (which the higher cumulants treat as zero) */
+void ol_cumulants(const double fin[27], const double g[3], double C[27]);
+/* product-form equilibrium */
+void ol_feq(double rho, const double u[3], double feq[27]);
+/* Parker-Youngs normal and mean curvature from a 3x3x3 fill-level stencil in
+ * direction order (entry i is the cell at offset c_i) */
+void ol_normal_curvature(const double phi[27], double n[3], double *kappa);
+
+/* --- lattice -------------------------------------------------------------- */
+/* fill, rho: nx*ny*nz values; vel: 3*nx*ny*nz values (component-major:
+ * vel[d*N + cell]) or NULL for rest.  Returns NULL on bad arguments. */
+OlLattice *ol_create(const OlParams *p, const double *fill, const double *rho,
+                     const double *vel);
+void ol_destroy(OlLattice *L);
+/* spheres: centre[n*3], radius[n], vel[n*3], angvel[n*3] (may be NULL).
+ * Cells with |x_c - X| <= r (minimum image in x and y) become solid; the
+ * lowest sphere index owns a cell covered by several spheres. */
+int ol_set_particles(OlLattice *L, int32_t n, const double *centre,
+                     const double *radius, const double *vel,
+                     const double *angvel);
+/* replace the whole state (used by tests that build states by hand):
+ * type[N], m[N], f[N*27] (cell-major), normal[N*3] may be NULL -> recomputed */
+void ol_set_state(OlLattice *L, const uint8_t *type, const double *m,
+                  const double *f);
+/* full time steps */
+void ol_step(OlLattice *L, int32_t nsteps);
+/* one phase of the step, for unit tests:
+ *   1 stream/boundaries/mass flux/collide, 2 conversion flags,
+ *   3 conversion processing, 4 excess mass + fill refresh, 5 geometry */
+void ol_phase(OlLattice *L, int32_t phase);
+
+/* --- read back ------------------------------------------------------------ */
+enum {
+    OL_F_TYPE = 0,   /* uint8 [N] */
+    OL_F_MASS = 1,   /* double [N] */
+    OL_F_FILL = 2,   /* double [N] */
+    OL_F_RHO = 3,    /* double [N], post-collision density sum_i f_i */
+    OL_F_VEL = 4,    /* double [3*N] component-major, (sum f c - F/2)/rho */
+    OL_F_PDF = 5,    /* double [27*N] direction-major f[i*N + cell] */
+    OL_F_NORMAL = 6, /* double [3*N] component-major */
+    OL_F_CURV = 7,   /* double [N] */
+    OL_F_OWNER = 8,  /* int32 [N], -1 if not inside a sphere */
+    OL_F_MARKS = 9   /* uint8 [N], conversion marks of the last phase 2/3 */
+};
+void ol_read(const OlLattice *L, int32_t field, void *dst);
+double ol_total_mass(const OlLattice *L);   /* sum of m over liquid+interface cells + pool */
+double ol_pool(const OlLattice *L);
+/* counters: [0] filled by rule a, [1] emptied by rule b, [2] filled by rule c,
+ * [3] emptied by rule d, [4] cancelled emptyings, [5] gas->interface,
+ * [6] liquid->interface, [7] liquid cells found next to gas (must stay 0) */
+void ol_counters(const OlLattice *L, int64_t out[8]);
+int64_t ol_steps_done(const OlLattice *L);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,226 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``fsl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark.  The GPU product path never imports it.
+
+The C source is compiled with gcc on first use (or by :func:`build`), with
+``-O2 -ffp-contract=off`` and no fast-math, so every operation rounds as
+written.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "fsl_oracle.c")
+HDR = os.path.join(HERE, "fsl_oracle.h")
+LIB = os.path.join(HERE, "liboracle.so")
+
+GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
+F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS = range(10)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` next to its source."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
+        os.path.getmtime(SRC), os.path.getmtime(HDR)
+    ):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("omega", ctypes.c_double), ("omega_bulk", ctypes.c_double),
+        ("omega_high", ctypes.c_double), ("accel", ctypes.c_double * 3),
+        ("sigma", ctypes.c_double), ("rho_gas", ctypes.c_double),
+        ("conv_eps", ctypes.c_double), ("normal_tie", ctypes.c_double),
+        ("rule_isolated", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        # FSL_ORACLE_LIB points the pins at another build of the oracle (the
+        # mutation test uses it to check that planted mistakes are caught)
+        path = os.environ.get("FSL_ORACLE_LIB") or build(force=False)
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ol_create.restype = ctypes.c_void_p
+        L.ol_create.argtypes = [ctypes.POINTER(_Params), dp, dp, dp]
+        L.ol_destroy.argtypes = [ctypes.c_void_p]
+        L.ol_set_particles.restype = ctypes.c_int
+        L.ol_set_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp, dp, dp, dp]
+        L.ol_set_state.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, dp]
+        L.ol_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.ol_phase.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.ol_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+        L.ol_total_mass.restype = ctypes.c_double
+        L.ol_total_mass.argtypes = [ctypes.c_void_p]
+        L.ol_pool.restype = ctypes.c_double
+        L.ol_pool.argtypes = [ctypes.c_void_p]
+        L.ol_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+        L.ol_steps_done.restype = ctypes.c_int64
+        L.ol_steps_done.argtypes = [ctypes.c_void_p]
+        L.ol_collide.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.ol_cumulants.argtypes = [dp, dp, dp]
+        L.ol_feq.argtypes = [ctypes.c_double, dp, dp]
+        L.ol_normal_curvature.argtypes = [dp, dp, dp]
+        L.ol_velocities.argtypes = [ctypes.c_void_p, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- operators
+def velocities():
+    c = np.zeros((27, 3), dtype=np.int32)
+    w = np.zeros(27)
+    lib().ol_velocities(c.ctypes.data, _dp(w))
+    return c, w
+
+
+def collide(f, g=(0.0, 0.0, 0.0), omega=1.0, omega_bulk=1.0, omega_high=1.0):
+    f = _f64(f)
+    g = _f64(g)
+    out = np.zeros(27)
+    lib().ol_collide(_dp(f), _dp(g), omega, omega_bulk, omega_high, _dp(out))
+    return out
+
+
+def cumulants(f, g=(0.0, 0.0, 0.0)):
+    f = _f64(f)
+    g = _f64(g)
+    out = np.zeros(27)
+    lib().ol_cumulants(_dp(f), _dp(g), _dp(out))
+    return out
+
+
+def feq(rho, u):
+    u = _f64(u)
+    out = np.zeros(27)
+    lib().ol_feq(float(rho), _dp(u), _dp(out))
+    return out
+
+
+def normal_curvature(phi27):
+    phi = _f64(phi27)
+    n = np.zeros(3)
+    k = np.zeros(1)
+    lib().ol_normal_curvature(_dp(phi), _dp(n), _dp(k))
+    return n, float(k[0])
+
+
+# ------------------------------------------------------------------ lattice
+class OracleLattice:
+    """FP64 reference lattice.  Fields are (nz, ny, nx) arrays, x fastest."""
+
+    def __init__(self, shape, omega, accel=(0.0, 0.0, 0.0), sigma=0.0, rho_gas=1.0,
+                 conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
+                 omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None):
+        nx, ny, nz = shape
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        p = _Params()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.omega, p.omega_bulk, p.omega_high = omega, omega_bulk, omega_high
+        for d in range(3):
+            p.accel[d] = accel[d]
+        p.sigma, p.rho_gas, p.conv_eps, p.normal_tie = sigma, rho_gas, conv_eps, normal_tie
+        p.rule_isolated = 1 if rule_isolated else 0
+        self._p = p
+        fill = _f64(np.ones((nz, ny, nx)) if fill is None else fill).reshape(-1)
+        rho = _f64(np.ones((nz, ny, nx)) if rho is None else rho).reshape(-1)
+        vp = None
+        if vel is not None:
+            self._vel = _f64(vel).reshape(-1)
+            vp = _dp(self._vel)
+        h = lib().ol_create(ctypes.byref(p), _dp(fill), _dp(rho), vp)
+        if not h:
+            raise ValueError("oracle rejected the lattice parameters")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().ol_destroy(h)
+            self.h = None
+
+    def set_particles(self, centre, radius, vel=None, angvel=None):
+        centre = _f64(centre).reshape(-1)
+        radius = _f64(radius).reshape(-1)
+        n = radius.size
+        v = _f64(np.zeros((n, 3)) if vel is None else vel).reshape(-1)
+        w = _f64(np.zeros((n, 3)) if angvel is None else angvel).reshape(-1)
+        rc = lib().ol_set_particles(self.h, n, _dp(centre), _dp(radius), _dp(v), _dp(w))
+        if rc != 0:
+            raise ValueError("oracle rejected the particles")
+
+    def set_state(self, type_, m, f_cellmajor):
+        t = np.ascontiguousarray(type_, dtype=np.uint8).reshape(-1)
+        m = _f64(m).reshape(-1)
+        f = _f64(f_cellmajor).reshape(-1)
+        assert t.size == self.N and m.size == self.N and f.size == 27 * self.N
+        lib().ol_set_state(self.h, t.ctypes.data, _dp(m), _dp(f))
+
+    def step(self, n=1):
+        lib().ol_step(self.h, int(n))
+
+    def phase(self, k):
+        lib().ol_phase(self.h, int(k))
+
+    def read(self, field):
+        nx, ny, nz = self.shape
+        N = self.N
+        if field in (F_TYPE, F_MARKS):
+            out = np.zeros(N, dtype=np.uint8)
+        elif field == F_OWNER:
+            out = np.zeros(N, dtype=np.int32)
+        elif field in (F_VEL, F_NORMAL):
+            out = np.zeros(3 * N)
+        elif field == F_PDF:
+            out = np.zeros(27 * N)
+        else:
+            out = np.zeros(N)
+        lib().ol_read(self.h, field, out.ctypes.data)
+        if field in (F_VEL, F_NORMAL):
+            return out.reshape(3, nz, ny, nx)
+        if field == F_PDF:
+            return out.reshape(27, nz, ny, nx)
+        return out.reshape(nz, ny, nx)
+
+    def total_mass(self):
+        return lib().ol_total_mass(self.h)
+
+    def pool(self):
+        return lib().ol_pool(self.h)
+
+    def counters(self):
+        out = np.zeros(8, dtype=np.int64)
+        lib().ol_counters(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        return out
+
+    @property
+    def steps_done(self):
+        return lib().ol_steps_done(self.h)

@@ -1,0 +1,193 @@
+"""Seeded synthetic inputs for the free-surface lattice.
+
+This module only builds initial conditions (fill level, density, velocity,
+spheres and physical parameters).  It holds none of the method's arithmetic,
+so both the GPU path and the CPU oracle can consume its output.
+
+Workloads (all lattice units):
+
+* ``channel_film``: the parity configuration -- 64 x 8 x 32, periodic x/y,
+  walls at both z ends, liquid up to z = 20 + 2 sin(2 pi x / 64), 16 fixed
+  spheres of radius 3 in z < 8, body force g_x = 1e-5, omega = 1.9.
+* ``flume``: a sediment flume shaped like the paper's setup (Section 3.1):
+  a bed of three layers of diameter-10 spheres (a jittered hexagonal base
+  layer plus two jittered close-packed layers), a flat free surface 60 cells
+  above the bed, hydrostatic density, a parabolic velocity profile above the
+  bed with 1 % noise, gravity from Fr = 1.3, slope tan(psi) = 0.044 (Table 2,
+  run E1), omega = 1.997 and sigma from We = 15.62 (Table 1, run E1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: tuple                   # (nx, ny, nz)
+    omega: float
+    accel: tuple                   # body acceleration (gx, gy, gz)
+    sigma: float
+    fill: np.ndarray               # (nz, ny, nx)
+    rho: np.ndarray                # (nz, ny, nx)
+    vel: np.ndarray                # (3, nz, ny, nx)
+    centre: np.ndarray             # (n, 3)
+    radius: np.ndarray             # (n,)
+    sphere_vel: np.ndarray         # (n, 3)
+    sphere_angvel: np.ndarray      # (n, 3)
+    rho_gas: float = 1.0
+    conv_eps: float = 1e-2
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncells(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+
+def height_fill(shape, h):
+    """Fill level of cells below a height field h[y, x]: cell k holds the
+    fraction of [k, k+1] that lies under the surface."""
+    nx, ny, nz = shape
+    k = np.arange(nz, dtype=np.float64)[:, None, None]
+    return np.clip(np.asarray(h, dtype=np.float64)[None, :, :] - k, 0.0, 1.0)
+
+
+def channel_film(seed: int = 1) -> Workload:
+    nx, ny, nz = 64, 8, 32
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xc = np.arange(nx) + 0.5
+    h = 20.0 + 2.0 * np.sin(2.0 * np.pi * xc / nx)
+    fill = height_fill((nx, ny, nz), np.broadcast_to(h[None, :], (ny, nx)))
+    n = 16
+    centre = np.stack([rng.uniform(0.0, nx, n), rng.uniform(0.0, ny, n),
+                       rng.uniform(3.0, 8.0, n)], axis=1)
+    radius = np.full(n, 3.0)
+    return Workload(
+        name="channel_film_64x8x32", shape=(nx, ny, nz), omega=1.9,
+        accel=(1e-5, 0.0, 0.0), sigma=0.0, fill=fill,
+        rho=np.ones((nz, ny, nx)), vel=np.zeros((3, nz, ny, nx)),
+        centre=centre, radius=radius, sphere_vel=np.zeros((n, 3)),
+        sphere_angvel=np.zeros((n, 3)),
+        meta={"seed": seed, "steps": 200})
+
+
+def _bed_spheres(nx, ny, rng, d=10.0, layers=3, z0=5.0, jitter=0.75):
+    """Jittered hexagonal packing of ``layers`` layers of diameter-d spheres
+    that tiles the periodic nx x ny box."""
+    ncol = max(1, int(round(nx / d)))
+    nrow = max(2, 2 * int(round(ny / (d * math.sqrt(3.0)))))
+    sx, sy = nx / ncol, ny / nrow
+    dz = d * math.sqrt(2.0 / 3.0)
+    out = []
+    for layer in range(layers):
+        zl = z0 + layer * dz
+        ox = (layer % 3) * sx / 3.0
+        oy = (layer % 3) * sy / 3.0
+        for r in range(nrow):
+            for c in range(ncol):
+                x = (c + 0.5 * (r % 2)) * sx + ox
+                y = (r + 0.5) * sy + oy
+                out.append((x, y, zl))
+    p = np.array(out, dtype=np.float64)
+    p[:, 0] += rng.uniform(-jitter, jitter, len(p))
+    p[:, 1] += rng.uniform(-jitter, jitter, len(p))
+    p[:, 2] += rng.uniform(-0.5 * jitter, 0.5 * jitter, len(p))
+    p[:, 0] %= nx
+    p[:, 1] %= ny
+    return p
+
+
+def _solid_fraction_profile(shape, centre, radius):
+    """y-averaged solid fraction per (z, x) of the sphere bed (cell centres)."""
+    nx, ny, nz = shape
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    zc = np.arange(nz) + 0.5
+    yc = np.arange(ny) + 0.5
+    xc = np.arange(nx) + 0.5
+    for (X, Y, Z), r in zip(centre, radius):
+        z0, z1 = max(0, int(Z - r) - 1), min(nz, int(Z + r) + 2)
+        dz = zc[z0:z1, None, None] - Z
+        dy = yc[None, :, None] - Y
+        dy = dy - ny * np.round(dy / ny)
+        x0, x1 = int(math.floor(X - r)) - 1, int(math.floor(X + r)) + 2
+        xi = np.arange(x0, x1) % nx
+        dx = xc[xi][None, None, :] - X
+        dx = dx - nx * np.round(dx / nx)
+        inside = dx * dx + dy * dy + dz * dz <= r * r
+        solid[z0:z1, :, xi] |= inside
+    return solid.mean(axis=1)  # (nz, nx)
+
+
+def bed_height(shape, centre, radius, level=0.3):
+    """Bed height where the y-averaged solid fraction drops to ``level``
+    (Section 3.2: linear interpolation of phi_b(x, z) = 0.3), averaged in x."""
+    phib = _solid_fraction_profile(shape, centre, radius)
+    nz = phib.shape[0]
+    hs = []
+    for col in phib.T:
+        k = nz - 1
+        while k > 0 and col[k] < level:
+            k -= 1
+        if k >= nz - 1 or col[k] < level:
+            hs.append(0.0)
+            continue
+        # col[k] >= level > col[k+1]: interpolate between cell centres
+        t = (col[k] - level) / (col[k] - col[k + 1])
+        hs.append(k + 0.5 + t)
+    return float(np.mean(hs))
+
+
+def flume(nx: int = 1536, ny: int = 40, nz: int = 192, seed: int = 2,
+          depth: float = 60.0, U: float = 0.02, Fr: float = 1.3,
+          We: float = 15.62, slope: float = 0.044, omega: float = 1.997,
+          noise: float = 0.01, d: float = 10.0, layers: int = 3,
+          sphere_speed: float = 1e-4) -> Workload:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centre = _bed_spheres(nx, ny, rng, d=d, layers=layers)
+    n = len(centre)
+    radius = np.full(n, 0.5 * d)
+    hb = bed_height((nx, ny, nz), centre, radius)
+    zs = hb + depth
+    if zs >= nz - 2:
+        raise ValueError("free surface does not fit below the top wall")
+    g = (U / Fr) ** 2 / depth            # Fr = U / sqrt(g h0)
+    gx = slope * g                       # depth-slope driving, tan(psi)
+    sigma = U * U * depth / We           # We = rho U^2 h0 / sigma
+    fill = height_fill((nx, ny, nz), np.full((ny, nx), zs))
+    zc = (np.arange(nz) + 0.5)[:, None, None]
+    rho = np.exp(3.0 * g * np.clip(zs - zc, 0.0, None)) * np.ones((1, ny, nx))
+    zeta = np.clip((zc - hb) / depth, 0.0, 1.0)
+    ux = 1.5 * U * (2.0 * zeta - zeta * zeta) * np.ones((1, ny, nx))
+    vel = np.zeros((3, nz, ny, nx))
+    vel[0] = ux
+    liquid = fill > 0.0
+    vel += noise * U * rng.standard_normal((3, nz, ny, nx)) * liquid[None]
+    svel = rng.uniform(-sphere_speed, sphere_speed, (n, 3))
+    return Workload(
+        name=f"flume_{nx}x{ny}x{nz}", shape=(nx, ny, nz), omega=omega,
+        accel=(gx, 0.0, -g), sigma=sigma, fill=fill, rho=rho, vel=vel,
+        centre=centre, radius=radius, sphere_vel=svel,
+        sphere_angvel=np.zeros((n, 3)),
+        meta={"seed": seed, "bed_height": hb, "surface": zs, "spheres": n,
+              "depth": depth, "U": U, "Fr": Fr, "We": We, "slope": slope})
+
+
+def flume_crop(nx: int = 128, seed: int = 3, **kw) -> Workload:
+    """The flume recipe on its own short periodic box (accuracy crop)."""
+    return flume(nx=nx, seed=seed, **kw)
+
+
+def flat_film(shape=(4, 4, 24), h=16.5, omega=1.0, gx=1e-6, gz=0.0, sigma=0.0):
+    """Flat liquid film of height h on the bottom wall, at rest."""
+    nx, ny, nz = shape
+    fill = height_fill(shape, np.full((ny, nx), h))
+    return Workload(
+        name="flat_film", shape=shape, omega=omega, accel=(gx, 0.0, gz),
+        sigma=sigma, fill=fill, rho=np.ones((nz, ny, nx)),
+        vel=np.zeros((3, nz, ny, nx)), centre=np.zeros((0, 3)),
+        radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+        sphere_angvel=np.zeros((0, 3)), meta={"h": h})

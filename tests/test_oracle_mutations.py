@@ -1,0 +1,72 @@
+"""The oracle's pins are sensitive: plausible mistakes planted in a copy of
+the oracle (a dropped term, a wrong sign, a wrong index, a swapped rule)
+make the pin tests fail.  Each mutant is compiled into a temporary
+directory and the pins that should catch it are run against it."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "fsl_oracle.c")
+
+MUTANTS = {
+    "sixth_order_term": ("+ 4.0 * k_(1, 1, 1) * k_(1, 1, 1);\n    double s222",
+                         "+ 2.0 * k_(1, 1, 1) * k_(1, 1, 1);\n    double s222",
+                         "test_oracle_collision.py", "brute_force"),
+    "inverse_chimera": ("double f0 = k0 * (1.0 - u * u) - 2.0 * u * k1 - k2;",
+                        "double f0 = k0 * (1.0 - u * u) - 1.0 * u * k1 - k2;",
+                        "test_oracle_collision.py", "identity"),
+    "force_shift": ("(j[d] + 0.5 * r * g[d]) / r", "(j[d] + 1.0 * r * g[d]) / r",
+                    "test_oracle_collision.py", "momentum"),
+    "shear_rate": ("Cs[K(1, 0, 1)] = (1.0 - omega) * C_(1, 0, 1);",
+                   "Cs[K(1, 0, 1)] = (1.0 - omega_bulk) * C_(1, 0, 1);",
+                   "test_oracle_collision.py", "brute_force or cube"),
+    "moving_wall_sign": ("fin[j] = fo[opp(j)] + 6.0 * WT[j]", "fin[j] = fo[opp(j)] - 6.0 * WT[j]",
+                         "test_oracle_flow.py", "couette"),
+    "laplace_factor": ("p->rho_gas + 6.0 * p->sigma", "p->rho_gas + 3.0 * p->sigma",
+                       "test_oracle_flow.py", "cylinder"),
+    "flux_weight": ("? 0.5 * (clamp01(L->phi[c]) + clamp01(L->phi[y]))", "? clamp01(L->phi[c])",
+                    "test_oracle_flow.py", "channel_film_mass"),
+    "flux_index": ("dm += s * (L->f[y * Q + opp(i)] - fo[i]);", "dm += s * (L->f[y * Q + i] - fo[i]);",
+                   "test_oracle_flow.py", "tracks_density"),
+    "reconstruction": ("fin[j] = feqG[j] + feqG[opp(j)] - fo[opp(j)];",
+                       "fin[j] = 2.0 * feqG[j] - fo[opp(j)];",
+                       "test_oracle_flow.py", "film or hydrostatic"),
+    "normal_side": ("if (nc < -p->normal_tie) recon = 1;", "if (nc > p->normal_tie) recon = 1;",
+                    "test_oracle_flow.py", "gravity_driven_film"),
+    "no_cancel": ("if (near_fill) {\n            L->cnt[4]++;", "if (0) {\n            L->cnt[4]++;",
+                  "test_oracle_conversion.py", "rule_text"),
+    "excess_to_liquid": ("if (y >= 0 && L->type[y] == OL_INTERFACE) recv++;",
+                         "if (y >= 0 && L->type[y] != OL_GAS && L->type[y] != OL_SOLID) recv++;",
+                         "test_oracle_conversion.py", "rule_text"),
+    "mean_includes_emptying": ("if (mk[y] & MK_TO_GAS) continue;", "if (0) continue;",
+                               "test_oracle_conversion.py", "rule_text"),
+    "parker_youngs_weight": ("static const double Wpy[3] = {1.0, 2.0, 1.0};",
+                             "static const double Wpy[3] = {1.0, 1.0, 1.0};",
+                             "test_oracle_geometry.py", "quadratic"),
+    "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
+                       "test_oracle_geometry.py", "quadratic or sphere"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new, target, sel = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation site not found: " + name
+    mdir = tmp_path / "oracle"
+    mdir.mkdir()
+    (mdir / "fsl_oracle.c").write_text(src.replace(old, new, 1))
+    (mdir / "fsl_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "fsl_oracle.h")).read())
+    so = str(mdir / "liboracle.so")
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-o", so, str(mdir / "fsl_oracle.c"), "-lm"], check=True)
+    env = dict(os.environ, FSL_ORACLE_LIB=so)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, target), "-k", sel],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert "failed" in r.stdout or "passed" in r.stdout, r.stdout[-2000:]  # some pin ran
+    assert r.returncode == 1, "mutant %s survived:\n%s" % (name, r.stdout[-2000:])
