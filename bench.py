@@ -1,0 +1,166 @@
+"""Benchmark of the free-surface cumulant LBM step on one MI355X.
+
+One step = one pass of the whole hot path (dense stream-collide, interface
+stream-collide with reconstruction and mass flux, conversion, excess mass,
+normals/curvature) over the synthetic sediment flume 1536 x 40 x 192
+(three layers of diameter-10 spheres with small prescribed velocities, 60
+cells of liquid above the bed, FP32 PDF storage).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fluid_counts(lat, fsl):
+    t = lat.read(fsl.FIELD_TYPE)
+    liq = int((t == fsl.LIQUID).sum())
+    itf = int((t == fsl.INTERFACE).sum())
+    return liq, itf
+
+
+def run_form(w, precision, steps, warmup):
+    import torch
+
+    from paper_2301_10674_amd import fsl
+
+    lat = fsl.lattice_from_workload(w, precision)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    liq0, itf0 = fluid_counts(lat, fsl)
+    M0 = lat.total_mass()
+    lat.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.timing(False)
+    bulk_ms, launches = lat.timing_read()
+    liq1, itf1 = fluid_counts(lat, fsl)
+    M1 = lat.total_mass()
+    secs = t1 - t0
+    liq = 0.5 * (liq0 + liq1)
+    fluid = 0.5 * (liq0 + itf0 + liq1 + itf1)
+    s = STORE_BYTES[precision]
+    bulk_avg_s = bulk_ms / 1e3 / max(launches, 1)
+    bytes_per_launch = liq * (54 * s + 16) + w.ncells * 1
+    res = dict(
+        precision=precision, secs=secs, ms_per_step=1e3 * secs / steps,
+        mlups_fluid=fluid * steps / secs / 1e6, mlups_all=w.ncells * steps / secs / 1e6,
+        bulk_us=1e6 * bulk_avg_s, bulk_launches=launches,
+        bulk_gbs=bytes_per_launch / bulk_avg_s / 1e9, bytes_per_launch=bytes_per_launch,
+        liquid_cells=liq, fluid_cells=fluid, interface_cells=0.5 * (itf0 + itf1),
+        mass_drift=abs(M1 - M0) / M0)
+    lat.destroy()
+    del lat
+    torch.cuda.synchronize()
+    return res
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle, single-threaded, on the same flume recipe cropped to
+    128 x 40 x 192, for as many steps as fit in about seconds_target."""
+    from oracle import oracle as O
+    from paper_2301_10674_amd import inputs
+
+    w = inputs.flume_crop(nx=128, seed=3)
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, rho_gas=w.rho_gas,
+                        conv_eps=w.conv_eps, fill=w.fill, rho=w.rho, vel=w.vel)
+    o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    t = o.read(O.F_TYPE)
+    fluid = int(((t == O.LIQUID) | (t == O.INTERFACE)).sum())
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, int(seconds_target / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    o.step(n)
+    secs = time.perf_counter() - t0
+    return {"value": fluid * n / secs / 1e6, "unit": "MLUPS (fluid cells)", "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 oracle, 1 thread, flume recipe cropped to 128x40x192 "
+                      "(%d fluid cells), %d steps after 1 warm-up step, %.1f s" % (fluid, n, secs)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "fp64"])
+    ap.add_argument("--nx", type=int, default=1536)
+    ap.add_argument("--ny", type=int, default=40)
+    ap.add_argument("--nz", type=int, default=192)
+    ap.add_argument("--forms", default="fp16,fp64",
+                    help="other storage forms timed on the same workload ('' for none)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2301_10674_amd import fsl, inputs
+
+    fsl.lib()  # fails loudly if the HIP library is missing
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    log("building flume %dx%dx%d" % (args.nx, args.ny, args.nz))
+    w = inputs.flume(nx=args.nx, ny=args.ny, nz=args.nz, seed=2)
+    log("spheres %d, bed height %.2f, surface %.2f" % (w.meta["spheres"], w.meta["bed_height"],
+                                                      w.meta["surface"]))
+    main_res = run_form(w, args.precision, args.steps, args.warmup)
+    log("main form:", json.dumps(main_res))
+    forms = {args.precision: main_res}
+    for p in [f for f in args.forms.split(",") if f and f != args.precision]:
+        r = run_form(w, p, max(args.steps // 2, 10), min(args.warmup, 20))
+        log("form:", json.dumps(r))
+        forms[p] = r
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    r = main_res
+    out = {
+        "metric": "MLUPS free-surface D3Q27 cumulant (FP64/FP32/FP16-store), % HBM roofline",
+        "value": r["mlups_fluid"], "unit": "MLUPS (fluid cells)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16-store/f32", "fp64": "f64"}[args.precision],
+        "data": "synthetic seeded flume (no dataset)",
+        "config": {"workload": w.name, "precision": args.precision, "spheres": w.meta["spheres"],
+                   "depth": w.meta["depth"], "cells": w.ncells},
+        "roofline": {"bound": "hbm", "achieved": r["bulk_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["bulk_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_bulk", "bytes_per_launch": r["bytes_per_launch"],
+                     "avg_launch_us": r["bulk_us"]},
+        "cpu_baseline": cpu,
+        "mlups_all_cells": r["mlups_all"],
+        "mass_drift": r["mass_drift"],
+        "forms": {k: {"mlups_fluid": v["mlups_fluid"], "ms_per_step": v["ms_per_step"],
+                      "bulk_gbs": v["bulk_gbs"], "mass_drift": v["mass_drift"]}
+                  for k, v in forms.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

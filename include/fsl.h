@@ -1,0 +1,180 @@
+/*
+ * fsl.h -- C-ABI of the MI355X free-surface cumulant lattice Boltzmann step.
+ *
+ * The library advances a D3Q27 free-surface lattice (Schwarzmeier et al.,
+ * "Particle-resolved simulation of antidunes in free-surface flows",
+ * Section 2.1 for the fluid model, Section 2.2 for no-slip particle surfaces,
+ * Section 3.1 for the boundary conditions and the driving body force) on one
+ * gfx950 GPU.  One time step is: pull streaming with bounce-back at walls and
+ * (moving) sphere surfaces, reconstruction of PDFs arriving from the gas side
+ * with the gas pressure plus the Laplace pressure 2*sigma*kappa, the
+ * volume-of-fluid mass flux, the cumulant collision (Geier et al. 2015: shear
+ * rate omega, every other rate 1), conversion of interface cells with excess
+ * mass redistribution, and the interface normal / curvature update.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, reference density 1 (Section 2.1).
+ *   - Cells are indexed cell = x + nx*(y + ny*z); every per-cell host array
+ *     passed in or out uses that order (x fastest).  Vector fields are
+ *     component-major: v[d*ncells + cell].
+ *   - x and y are periodic; halfway bounce-back walls lie below z = 0 and
+ *     above z = nz-1 (Section 3.1).
+ *   - Device memory: the caller allocates one workspace of
+ *     fsl_workspace_bytes() bytes (for example a torch uint8 tensor) and
+ *     keeps it alive until fsl_destroy().  The library never frees caller
+ *     memory; it owns only small internal buffers (the sphere table).
+ *   - Streams: all device work of a lattice is enqueued on the HIP stream
+ *     given to fsl_create_lattice().  fsl_read_fields() and fsl_total_mass()
+ *     synchronise that stream; fsl_step() does not.
+ *   - Errors: every call returns an FslStatus; no exception crosses the ABI.
+ *     fsl_last_error() returns a thread-local text for the last failure.
+ *   - Host input arrays are copied during the call and may be freed after.
+ */
+#ifndef FSL_H
+#define FSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct FslLattice FslLattice;
+
+typedef enum {
+    FSL_OK = 0,
+    FSL_ERR_ARG = 1,       /* invalid argument (sizes, rates, non-finite input) */
+    FSL_ERR_STATE = 2,     /* call not allowed in the lattice's current state */
+    FSL_ERR_DEVICE = 3,    /* a HIP runtime call failed */
+    FSL_ERR_NOMEM = 4,     /* workspace too small, or an internal allocation failed */
+    FSL_ERR_UNSTABLE = 5   /* watchdog: total mass became non-finite */
+} FslStatus;
+
+/* Storage precision of the PDFs.  Mass, fill level, excess mass and the
+ * total mass are kept in FP64 in every form. */
+typedef enum {
+    FSL_FP64 = 0,          /* PDFs stored as f - w in FP64, FP64 collision */
+    FSL_FP32 = 1,          /* PDFs stored as f - w in FP32, FP32 collision */
+    FSL_FP16_STORE = 2     /* PDFs stored as f - w in FP16 (round to nearest
+                              even, subnormals kept), FP32 collision */
+} FslPrecision;
+
+typedef struct {
+    int32_t nx, ny, nz;     /* lattice size, each >= 3 */
+    int32_t precision;      /* FslPrecision */
+    double omega;           /* shear relaxation rate, 0 < omega < 2;
+                               nu = (1/omega - 1/2)/3 (Section 2.1) */
+    double accel[3];        /* body acceleration g; force density rho*g
+                               (driving force in x and gravity, Section 3.1) */
+    double sigma;           /* surface tension (Laplace pressure 2 sigma kappa) */
+    double rho_gas;         /* gas density; gas pressure p_g = rho_gas/3 */
+    double conv_eps;        /* conversion threshold: fill above (1+eps), empty below -eps */
+    double normal_tie;      /* a direction c_j is reconstructed from the gas side
+                               when n.c_j < -normal_tie */
+    int32_t rule_isolated;  /* 1: convert interface cells without gas (liquid)
+                               neighbours to liquid (gas) */
+    int32_t normals;        /* 0: finite-difference normal and curvature,
+                               1: learned estimator with finite-difference fallback */
+    int32_t check_every;    /* watchdog interval in steps (0: never) */
+    int32_t reserved;       /* must be 0 */
+} FslParams;
+
+/* field ids for fsl_read_fields(); bit k of the mask selects field k */
+enum {
+    FSL_FIELD_TYPE = 0,     /* uint8 [n]: 0 gas, 1 liquid, 2 interface, 3 solid */
+    FSL_FIELD_MASS = 1,     /* double [n]: liquid mass m (0 for gas and solid) */
+    FSL_FIELD_FILL = 2,     /* double [n]: fill level m/rho (1 liquid, 0 gas/solid) */
+    FSL_FIELD_RHO = 3,      /* double [n]: density sum_i f_i of the stored PDFs
+                               (liquid and interface cells; 0 elsewhere) */
+    FSL_FIELD_VEL = 4,      /* double [3n]: (sum_i f_i c_i - F/2)/rho (fluid cells) */
+    FSL_FIELD_PDF = 5,      /* double [27n]: f_i, direction-major f[i*n + cell],
+                               i = (cx+1) + 3(cy+1) + 9(cz+1) (fluid cells) */
+    FSL_FIELD_NORMAL = 6,   /* double [3n]: interface normal, liquid -> gas */
+    FSL_FIELD_CURV = 7,     /* double [n]: mean curvature (interface cells) */
+    FSL_FIELD_OWNER = 8,    /* int32 [n]: owning sphere of a solid cell, -1 otherwise */
+    FSL_NFIELDS = 9
+};
+
+/* Bytes of device workspace the lattice needs (0 for invalid params). */
+size_t fsl_workspace_bytes(const FslParams *params);
+
+/* Create a lattice in the caller's workspace and initialise it (Section 3.1:
+ * fill level, density and velocity per cell).
+ *   params      lattice and model parameters (copied)
+ *   dev_workspace, bytes   device memory of at least fsl_workspace_bytes()
+ *   hip_stream  hipStream_t on which all work is enqueued (NULL: default)
+ *   fill        host double [n]: fill level; >= 1 liquid, <= 0 gas,
+ *               in between interface.  A liquid cell next to a gas cell
+ *               becomes an interface cell.
+ *   rho         host double [n]: density (> 0)
+ *   vel         host double [3n] component-major, or NULL for rest
+ *   out         receives the lattice handle
+ * Mass is m = clamp(fill, 0, 1) * rho and the PDFs start at equilibrium. */
+FslStatus fsl_create_lattice(const FslParams *params, void *dev_workspace,
+                             size_t bytes, void *hip_stream,
+                             const double *fill, const double *rho,
+                             const double *vel, FslLattice **out);
+
+/* Map resolved spheres onto the lattice (Section 2.2: no-slip on particle
+ * surfaces via bounce-back).  A cell is solid when its centre lies within
+ * radius of a sphere centre (minimum image in x and y); the lowest sphere
+ * index owns a cell covered twice.  Wall velocity at a link is
+ * vel + angvel x (link midpoint - centre).
+ *   n           number of spheres (>= 0)
+ *   centre      host double [3n]; x and y are wrapped into the box
+ *   radius      host double [n], 0 < r < min(nx, ny)/2
+ *   vel         host double [3n] or NULL (at rest)
+ *   angvel      host double [3n] or NULL (not rotating)
+ * The geometry is mapped by the first call, which must come before the
+ * first fsl_step(); later calls may only change velocities (same n, centres
+ * after wrapping, radii), else FSL_ERR_STATE.  Mass inside newly solid
+ * cells leaves the system. */
+FslStatus fsl_set_particles(FslLattice *lat, int32_t n, const double *centre,
+                            const double *radius, const double *vel,
+                            const double *angvel);
+
+/* Advance nsteps time steps (asynchronous on the lattice's stream).
+ * Returns FSL_ERR_UNSTABLE if the watchdog (every check_every steps) finds a
+ * non-finite total mass; the state then stays readable. */
+FslStatus fsl_step(FslLattice *lat, int32_t nsteps);
+
+/* Copy fields out.  dst[k] is the destination of field k when bit k of
+ * field_mask is set (entries of unselected fields are ignored).  dst points
+ * to host memory, or to device memory when dst_on_device != 0.  Synchronises
+ * the lattice's stream. */
+FslStatus fsl_read_fields(FslLattice *lat, uint32_t field_mask, void *const *dst,
+                          int32_t dst_on_device);
+
+/* Total liquid mass: sum of m over liquid and interface cells plus the pool
+ * of excess mass that found no interface neighbour (FP64, fixed summation
+ * order).  Synchronises the lattice's stream. */
+FslStatus fsl_total_mass(FslLattice *lat, double *mass);
+
+/* Cumulative conversion counters since creation: [0] filled by the mass
+ * threshold, [1] emptied by the mass threshold, [2] filled by the no-gas-
+ * neighbour rule, [3] emptied by the no-liquid-neighbour rule, [4] cancelled
+ * emptyings, [5] gas -> interface, [6] liquid -> interface, [7] reserved (0).
+ * Synchronises the lattice's stream. */
+FslStatus fsl_counters(FslLattice *lat, int64_t out[8]);
+
+/* Steps done and current number of interface cells (synchronises). */
+FslStatus fsl_info(FslLattice *lat, int64_t *steps, int64_t *interface_cells);
+
+/* Per-launch timing of the dense stream-collide kernel with HIP events on
+ * the lattice's stream.  enable=1 starts recording (and clears the sums),
+ * enable=0 stops.  fsl_timing_read() synchronises and returns the summed
+ * kernel time in milliseconds and the number of timed launches. */
+FslStatus fsl_timing(FslLattice *lat, int32_t enable);
+FslStatus fsl_timing_read(FslLattice *lat, double *ms_total, int64_t *launches);
+
+/* Thread-local text of the last error (never NULL). */
+const char *fsl_last_error(void);
+
+/* Release the lattice's host state and internal buffers (not the workspace). */
+void fsl_destroy(FslLattice *lat);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,769 @@
+// fsl_api.hip -- host runtime of the free-surface LBM library: workspace
+// layout, lattice set-up (initial state, sphere mapping), step sequencing,
+// reductions, read-back and the C-ABI declared in include/fsl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fsl.h"
+#include "fsl_device.h"
+#include "fsl_kernels.h"
+
+namespace fsl {
+template <class S>
+void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream_t st,
+                 hipEvent_t ev0, hipEvent_t ev1);
+template <class R>
+void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
+}  // namespace fsl
+
+using namespace fsl;
+
+static thread_local std::string g_err = "no error";
+
+static FslStatus fail(FslStatus s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(FSL_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct FslLattice {
+    FslParams P;
+    Dev d;
+    hipStream_t st;
+    int parity = 0;           // PDFs of the current state are in pdf[parity]
+    int64_t steps = 0;
+    uint32_t epoch = 0;       // epoch of the last step's marks
+    int list_blocks = 64;
+    int nsph = 0;
+    bool geometry_set = false;
+    std::vector<double> sph_host;
+    double *sph_dev = nullptr;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t ev_used = 0;
+};
+
+// ---------------------------------------------------------------- workspace
+static size_t store_bytes(int prec) { return prec == FSL_FP64 ? 8 : (prec == FSL_FP32 ? 4 : 2); }
+
+static bool params_ok(const FslParams *p, std::string &why)
+{
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) { why = "each lattice extent must be >= 3"; return false; }
+    if ((double)p->nx * p->ny * p->nz > 1.5e9) { why = "lattice too large"; return false; }
+    if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return false; }
+    if (!(p->omega > 0.0 && p->omega < 2.0)) { why = "omega must lie in (0, 2)"; return false; }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->accel[a])) { why = "non-finite acceleration"; return false; }
+    if (!std::isfinite(p->sigma) || p->sigma < 0.0) { why = "sigma must be finite and >= 0"; return false; }
+    if (!(p->rho_gas > 0.0) || !std::isfinite(p->rho_gas)) { why = "rho_gas must be > 0"; return false; }
+    if (!(p->conv_eps >= 0.0 && p->conv_eps < 1.0)) { why = "conv_eps must lie in [0, 1)"; return false; }
+    if (!(p->normal_tie >= 0.0)) { why = "normal_tie must be >= 0"; return false; }
+    if (p->normals != 0) { why = "learned normals are not available in this build"; return false; }
+    if (p->check_every < 0 || p->reserved != 0) { why = "check_every < 0 or reserved != 0"; return false; }
+    return true;
+}
+
+struct Layout {
+    size_t pdf[2], mq, phi, rho, share, poolc, geom, mark, owner, flags, list0, list1, lnew, cnt,
+        stats, partial, total;
+};
+
+static Layout layout(const FslParams *p)
+{
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const size_t s = store_bytes(p->precision);
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    L.pdf[0] = take(27 * N * s);
+    L.pdf[1] = take(27 * N * s);
+    L.mq = take(8 * N);
+    L.phi = take(8 * N);
+    L.rho = take(8 * N);
+    L.share = take(8 * N);
+    L.poolc = take(8 * N);
+    L.geom = take((p->precision == FSL_FP64 ? 32 : 16) * N);
+    L.mark = take(4 * N);
+    L.owner = take(4 * N);
+    L.flags = take(N + 4);
+    L.list0 = take(4 * N);
+    L.list1 = take(4 * N);
+    L.lnew = take(4 * N);
+    L.cnt = take(64);
+    L.stats = take(8 * 8);
+    L.partial = take(8 * (RED_BLOCKS + 8));
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------- set-up kernels
+template <class S>
+__global__ void k_init(Dev d, const double *fill, const double *rho, const double *vel)
+{
+    using R = typename Real<S>::type;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    const double fl = fill[c];
+    const uint8_t ty = fl >= 1.0 ? T_LIQ : (fl <= 0.0 ? T_GAS : T_IF);
+    d.flags[c] = ty;
+    d.owner[c] = -1;
+    d.mark[c] = 0;
+    d.share[c] = 0.0;
+    d.poolc[c] = 0.0;
+    const double cl = fl < 0.0 ? 0.0 : (fl > 1.0 ? 1.0 : fl);
+    d.mq[c] = ty == T_GAS ? 0.0 : cl * rho[c];
+    R u[3] = {R(0), R(0), R(0)};
+    if (vel)
+        for (int a = 0; a < 3; ++a) u[a] = R(vel[(size_t)a * d.N + c]);
+    R e[27];
+    feq_dev<R>(R(rho[c] - 1.0), u[0], u[1], u[2], e);
+    S *pdf = (S *)d.pdf[0];
+    for (int i = 0; i < 27; ++i) pdf[(size_t)i * d.N + c] = to_store<S, R>(e[i]);
+}
+
+__device__ static int nbr(const Dev &d, int c, int i)
+{
+    const int x = c % d.nx, y = (c / d.nx) % d.ny, z = c / (d.nx * d.ny);
+    const int zz = z + cz(i);
+    if (zz < 0 || zz >= d.nz) return -1;
+    const int xx = (x + cx(i) + d.nx) % d.nx, yy = (y + cy(i) + d.ny) % d.ny;
+    return xx + d.nx * (yy + d.ny * zz);
+}
+
+// a liquid cell next to a gas cell becomes an interface cell
+__global__ void k_closure(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N || (d.flags[c] & T_MASK) != T_LIQ) return;
+    for (int i = 0; i < 27; ++i) {
+        if (i == REST) continue;
+        const int y = nbr(d, c, i);
+        if (y >= 0 && (d.flags[y] & T_MASK) == T_GAS) {
+            d.flags[c] = (uint8_t)((d.flags[c] & ~T_MASK) | T_IF);
+            return;
+        }
+    }
+}
+
+// liquid cells: switch between the mass m and the stored form m - own outgoing
+template <class S>
+__global__ void k_liquid_form(Dev d, int p, int to_q)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N || (d.flags[c] & T_MASK) != T_LIQ) return;
+    const S *pdf = (const S *)d.pdf[p];
+    double fluid = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        if (i == REST) continue;
+        const int y = nbr(d, c, i);
+        if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + (size_t)i * d.N + c);
+    }
+    d.mq[c] = to_q ? d.mq[c] - fluid : d.mq[c] + fluid;
+}
+
+// sphere -> solid cells; owner = lowest covering sphere index
+__global__ void k_map(Dev d, int nsph)
+{
+    const int q = blockIdx.x;
+    if (q >= nsph) return;
+    const double *s = d.sph + 10 * q;
+    const double r = s[3];
+    const int x0 = (int)floor(s[0] - r) - 1, x1 = (int)floor(s[0] + r) + 1;
+    const int y0 = (int)floor(s[1] - r) - 1, y1 = (int)floor(s[1] + r) + 1;
+    const int z0 = max((int)floor(s[2] - r) - 1, 0), z1 = min((int)floor(s[2] + r) + 1, d.nz - 1);
+    const int wx = x1 - x0 + 1, wy = y1 - y0 + 1, wz = z1 - z0 + 1;
+    if (wz <= 0) return;
+    const int total = wx * wy * wz;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int xx = x0 + t % wx, yy = y0 + (t / wx) % wy, z = z0 + t / (wx * wy);
+        const int x = ((xx % d.nx) + d.nx) % d.nx, y = ((yy % d.ny) + d.ny) % d.ny;
+        // same rounding as written: no contraction into fused multiply-adds
+        double dx = (x + 0.5) - s[0];
+        if (dx > 0.5 * d.nx) dx -= d.nx; else if (dx < -0.5 * d.nx) dx += d.nx;
+        double dy = (y + 0.5) - s[1];
+        if (dy > 0.5 * d.ny) dy -= d.ny; else if (dy < -0.5 * d.ny) dy += d.ny;
+        const double dz = (z + 0.5) - s[2];
+        const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+        if (r2 <= __dmul_rn(r, r)) atomicMin(&d.owner[x + d.nx * (y + d.ny * z)], q);
+    }
+}
+
+__global__ void k_owner_reset(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < d.N) d.owner[c] = INT_MAX;
+}
+
+// cells inside spheres become solid (their mass leaves the system)
+__global__ void k_apply_solid(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    if (d.owner[c] == INT_MAX) {
+        d.owner[c] = -1;
+    } else {
+        d.flags[c] = T_SOLID;
+        d.mq[c] = 0.0;
+    }
+}
+
+__global__ void k_near_solid(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    bool ns = false;
+    for (int i = 0; i < 27 && !ns; ++i) {
+        if (i == REST) continue;
+        const int y = nbr(d, c, i);
+        ns = y < 0 || (d.flags[y] & T_MASK) == T_SOLID;
+    }
+    d.flags[c] = (uint8_t)((d.flags[c] & T_MASK) | (ns ? F_NEAR_SOLID : 0));
+}
+
+// interface cells: density of the stored PDFs and fill level
+template <class S>
+__global__ void k_refresh_if(Dev d, int p)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N || (d.flags[c] & T_MASK) != T_IF) return;
+    const S *pdf = (const S *)d.pdf[p];
+    double s = 0.0;
+    for (int i = 0; i < 27; ++i) s += (double)ld(pdf + (size_t)i * d.N + c);
+    d.rho[c] = 1.0 + s;
+    d.phi[c] = d.mq[c] / d.rho[c];
+}
+
+__global__ void k_build_list(Dev d, int which)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool pred = c < d.N && (d.flags[c] & T_MASK) == T_IF;
+    list_append(d.list[which], &d.cnt[which], pred, c);
+}
+
+__global__ void k_zero_counts(Dev d)
+{
+    if (threadIdx.x < 3) d.cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 8) d.stats[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------- reductions
+// total mass, fixed order: block partials, then one block over the partials
+template <class S>
+__global__ __launch_bounds__(256) void k_mass_partial(Dev d, int p)
+{
+    __shared__ double sh[256];
+    const S *pdf = (const S *)d.pdf[p];
+    double acc = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) {
+        const uint8_t ty = d.flags[c] & T_MASK;
+        double m = 0.0;
+        if (ty == T_IF) {
+            m = d.mq[c];
+        } else if (ty == T_LIQ) {
+            double fluid = 0.0;
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) continue;
+                const int y = nbr(d, c, i);
+                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + (size_t)i * d.N + c);
+            }
+            m = d.mq[c] + fluid;
+        }
+        acc += m + d.poolc[c];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(Dev d, int n, int out_slot)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += d.partial[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.partial[out_slot] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_pool_partial(Dev d)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) acc += d.poolc[c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = sh[0];
+}
+
+// ---------------------------------------------------------------- read-back
+template <class S, class R4>
+__global__ void k_read(Dev d, int p, int field, void *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    const size_t N = (size_t)d.N;
+    const uint8_t ty = d.flags[c] & T_MASK;
+    const bool fluid = ty == T_LIQ || ty == T_IF;
+    const S *pdf = (const S *)d.pdf[p];
+    switch (field) {
+    case FSL_FIELD_TYPE: ((uint8_t *)out)[c] = ty; break;
+    case FSL_FIELD_MASS: {
+        double m = 0.0;
+        if (ty == T_IF) m = d.mq[c];
+        if (ty == T_LIQ) {
+            double fl = 0.0;
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) continue;
+                const int y = nbr(d, c, i);
+                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fl += (double)ld(pdf + (size_t)i * N + c);
+            }
+            m = d.mq[c] + fl;
+        }
+        ((double *)out)[c] = m;
+        break;
+    }
+    case FSL_FIELD_FILL: ((double *)out)[c] = ty == T_IF ? d.phi[c] : (ty == T_LIQ ? 1.0 : 0.0); break;
+    case FSL_FIELD_RHO:
+    case FSL_FIELD_VEL: {
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        if (fluid)
+            for (int i = 0; i < 27; ++i) {
+                const double v = (double)ld(pdf + (size_t)i * N + c);
+                r += v;
+                j[0] += cx(i) * v;
+                j[1] += cy(i) * v;
+                j[2] += cz(i) * v;
+            }
+        r += 1.0;
+        if (field == FSL_FIELD_RHO) {
+            ((double *)out)[c] = fluid ? r : 0.0;
+        } else {
+            const double g[3] = {d.gx, d.gy, d.gz};
+            for (int a = 0; a < 3; ++a)
+                ((double *)out)[(size_t)a * N + c] = fluid ? (j[a] - 0.5 * r * g[a]) / r : 0.0;
+        }
+        break;
+    }
+    case FSL_FIELD_PDF:
+        for (int i = 0; i < 27; ++i)
+            ((double *)out)[(size_t)i * N + c] = fluid ? wgt(i) + (double)ld(pdf + (size_t)i * N + c) : 0.0;
+        break;
+    case FSL_FIELD_NORMAL: {
+        const R4 g = ((const R4 *)d.geom)[c];
+        const bool itf = ty == T_IF;
+        ((double *)out)[c] = itf ? (double)g.x : 0.0;
+        ((double *)out)[N + c] = itf ? (double)g.y : 0.0;
+        ((double *)out)[2 * N + c] = itf ? (double)g.z : 0.0;
+        break;
+    }
+    case FSL_FIELD_CURV: {
+        const R4 g = ((const R4 *)d.geom)[c];
+        ((double *)out)[c] = ty == T_IF ? (double)g.w : 0.0;
+        break;
+    }
+    case FSL_FIELD_OWNER: ((int32_t *)out)[c] = d.owner[c]; break;
+    default: break;
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+static int blocks_for(int n) { return (n + 255) / 256; }
+
+template <class S>
+static void run_setup(FslLattice *L, const double *fill, const double *rho, const double *vel)
+{
+    const Dev &d = L->d;
+    k_init<S><<<blocks_for(d.N), 256, 0, L->st>>>(d, fill, rho, vel);
+    k_closure<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+}
+
+template <class S> static void run_liquid_form(FslLattice *L, int to_q)
+{
+    k_liquid_form<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, to_q);
+}
+
+template <class S> static void run_refresh(FslLattice *L)
+{
+    k_refresh_if<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity);
+}
+
+template <class S> static void run_mass(FslLattice *L)
+{
+    k_mass_partial<S><<<RED_BLOCKS, 256, 0, L->st>>>(L->d, L->parity);
+    k_sum_partials<<<1, 256, 0, L->st>>>(L->d, RED_BLOCKS, RED_BLOCKS);
+}
+
+template <class S> static void run_read(FslLattice *L, int field, void *out)
+{
+    using R = typename Real<S>::type;
+    using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+    k_read<S, R4><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, field, out);
+}
+
+#define DISPATCH(L, fn, ...)                                         \
+    do {                                                             \
+        switch ((L)->P.precision) {                                  \
+        case FSL_FP64: fn<double>(__VA_ARGS__); break;               \
+        case FSL_FP32: fn<float>(__VA_ARGS__); break;                \
+        default: fn<_Float16>(__VA_ARGS__); break;                   \
+        }                                                            \
+    } while (0)
+
+// rebuild everything derived from the cell types: near-solid bits, the
+// interface list and the interface geometry
+static void finalize(FslLattice *L)
+{
+    Dev &d = L->d;
+    k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+    DISPATCH(L, run_refresh, L);
+    k_zero_counts<<<1, 64, 0, L->st>>>(d);
+    k_build_list<<<blocks_for(d.N), 256, 0, L->st>>>(d, L->parity);
+    if (L->P.precision == FSL_FP64)
+        launch_geom<double>(d, L->parity, L->list_blocks, L->st);
+    else
+        launch_geom<float>(d, L->parity, L->list_blocks, L->st);
+}
+
+// ---------------------------------------------------------------- C-ABI
+extern "C" {
+
+size_t fsl_workspace_bytes(const FslParams *params)
+{
+    std::string why;
+    if (!params_ok(params, why)) {
+        g_err = why;
+        return 0;
+    }
+    return layout(params).total;
+}
+
+FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, void *hip_stream,
+                             const double *fill, const double *rho, const double *vel,
+                             FslLattice **out)
+{
+    std::string why;
+    if (!out) return fail(FSL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!params_ok(params, why)) return fail(FSL_ERR_ARG, why);
+    if (!ws || !fill || !rho) return fail(FSL_ERR_ARG, "workspace, fill and rho are required");
+    const Layout lay = layout(params);
+    if (bytes < lay.total) return fail(FSL_ERR_NOMEM, "workspace smaller than fsl_workspace_bytes()");
+    if (((uintptr_t)ws & 255) != 0) return fail(FSL_ERR_ARG, "workspace must be 256-byte aligned");
+    const size_t N = (size_t)params->nx * params->ny * params->nz;
+    for (size_t c = 0; c < N; ++c) {
+        if (!std::isfinite(fill[c]) || !std::isfinite(rho[c]) || !(rho[c] > 0.0))
+            return fail(FSL_ERR_ARG, "fill and rho must be finite, rho > 0");
+        if (vel)
+            for (int a = 0; a < 3; ++a)
+                if (!std::isfinite(vel[a * N + c])) return fail(FSL_ERR_ARG, "non-finite velocity");
+    }
+
+    FslLattice *L = new FslLattice();
+    L->P = *params;
+    L->st = (hipStream_t)hip_stream;
+    char *base = (char *)ws;
+    Dev &d = L->d;
+    d.nx = params->nx;
+    d.ny = params->ny;
+    d.nz = params->nz;
+    d.N = (int)N;
+    d.nbx = (d.nx + BULK_THREADS - 1) / BULK_THREADS;
+    d.rows = d.ny * d.nz;
+    d.xcd_map = (d.rows % 8) == 0;
+    d.pdf[0] = base + lay.pdf[0];
+    d.pdf[1] = base + lay.pdf[1];
+    d.mq = (double *)(base + lay.mq);
+    d.phi = (double *)(base + lay.phi);
+    d.rho = (double *)(base + lay.rho);
+    d.share = (double *)(base + lay.share);
+    d.poolc = (double *)(base + lay.poolc);
+    d.geom = base + lay.geom;
+    d.mark = (uint32_t *)(base + lay.mark);
+    d.owner = (int32_t *)(base + lay.owner);
+    d.flags = (uint8_t *)(base + lay.flags);
+    d.list[0] = (int32_t *)(base + lay.list0);
+    d.list[1] = (int32_t *)(base + lay.list1);
+    d.lnew = (int32_t *)(base + lay.lnew);
+    d.cnt = (int32_t *)(base + lay.cnt);
+    d.stats = (unsigned long long *)(base + lay.stats);
+    d.partial = (double *)(base + lay.partial);
+    d.sph = nullptr;
+    d.omega = params->omega;
+    d.gx = params->accel[0];
+    d.gy = params->accel[1];
+    d.gz = params->accel[2];
+    d.sigma = params->sigma;
+    d.rho_gas = params->rho_gas;
+    d.eps = params->conv_eps;
+    d.tie = params->normal_tie;
+    d.rule_iso = params->rule_isolated;
+    L->list_blocks = (int)std::min<size_t>(2048, std::max<size_t>(64, N / 4096));
+
+    // stage the host inputs
+    double *tmp = nullptr;
+    const size_t nin = N * (vel ? 5 : 2);
+    hipError_t e = hipMalloc(&tmp, nin * sizeof(double));
+    if (e != hipSuccess) {
+        delete L;
+        return fail(FSL_ERR_NOMEM, "staging buffer for the initial state");
+    }
+    e = hipMemcpyAsync(tmp, fill, N * 8, hipMemcpyHostToDevice, L->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp + N, rho, N * 8, hipMemcpyHostToDevice, L->st);
+    if (e == hipSuccess && vel) e = hipMemcpyAsync(tmp + 2 * N, vel, 3 * N * 8, hipMemcpyHostToDevice, L->st);
+    if (e == hipSuccess) {
+        DISPATCH(L, run_setup, L, tmp, tmp + N, vel ? tmp + 2 * N : nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        d.sph = nullptr;
+        // m -> stored liquid form, then everything derived from the types
+        k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+        DISPATCH(L, run_liquid_form, L, 1);
+        finalize(L);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(L->st);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        delete L;
+        return fail(FSL_ERR_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    }
+    *out = L;
+    return FSL_OK;
+}
+
+FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, const double *radius,
+                            const double *vel, const double *angvel)
+{
+    if (!L) return fail(FSL_ERR_ARG, "lattice is NULL");
+    if (n < 0 || (n > 0 && (!centre || !radius))) return fail(FSL_ERR_ARG, "bad sphere arrays");
+    const int nx = L->P.nx, ny = L->P.ny;
+    std::vector<double> t((size_t)std::max(n, 1) * 10, 0.0);
+    for (int q = 0; q < n; ++q) {
+        double *s = &t[10 * (size_t)q];
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(centre[3 * q + a])) return fail(FSL_ERR_ARG, "non-finite centre");
+        if (!(radius[q] > 0.0) || !(2.0 * radius[q] < std::min(nx, ny)))
+            return fail(FSL_ERR_ARG, "radius must satisfy 0 < r < min(nx, ny)/2");
+        s[0] = centre[3 * q] - nx * std::floor(centre[3 * q] / nx);
+        s[1] = centre[3 * q + 1] - ny * std::floor(centre[3 * q + 1] / ny);
+        s[2] = centre[3 * q + 2];
+        s[3] = radius[q];
+        for (int a = 0; a < 3; ++a) {
+            s[4 + a] = vel ? vel[3 * q + a] : 0.0;
+            s[7 + a] = angvel ? angvel[3 * q + a] : 0.0;
+            if (!std::isfinite(s[4 + a]) || !std::isfinite(s[7 + a]))
+                return fail(FSL_ERR_ARG, "non-finite sphere velocity");
+        }
+    }
+    if (L->geometry_set) {
+        // the geometry is mapped once; later calls may only change velocities
+        bool same = n == L->nsph;
+        for (int q = 0; same && q < n; ++q)
+            for (int a = 0; a < 4; ++a) same = same && t[10 * q + a] == L->sph_host[10 * q + a];
+        if (!same) return fail(FSL_ERR_STATE, "sphere geometry is already mapped; only velocities may change");
+        L->sph_host = t;
+        HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), t.size() * 8, hipMemcpyHostToDevice, L->st));
+        HIP_TRY(hipStreamSynchronize(L->st));
+        return FSL_OK;
+    }
+    if (L->steps > 0) return fail(FSL_ERR_STATE, "spheres must be mapped before the first step");
+    HIP_TRY(hipMalloc(&L->sph_dev, t.size() * 8));
+    HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), t.size() * 8, hipMemcpyHostToDevice, L->st));
+    L->sph_host = t;
+    L->nsph = n;
+    L->geometry_set = true;
+    Dev &d = L->d;
+    d.sph = L->sph_dev;
+    // liquid cells back to m, re-map, then the stored form with the new solids
+    DISPATCH(L, run_liquid_form, L, 0);
+    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+    if (n > 0) k_map<<<n, 256, 0, L->st>>>(d, n);
+    k_apply_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+    k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+    DISPATCH(L, run_liquid_form, L, 1);
+    finalize(L);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+static FslStatus check_mass(FslLattice *L)
+{
+    DISPATCH(L, run_mass, L);
+    double m = 0.0;
+    HIP_TRY(hipMemcpyAsync(&m, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    if (!std::isfinite(m)) return fail(FSL_ERR_UNSTABLE, "total mass is not finite");
+    return FSL_OK;
+}
+
+FslStatus fsl_step(FslLattice *L, int32_t nsteps)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (nsteps < 0) return fail(FSL_ERR_ARG, "nsteps < 0");
+    for (int s = 0; s < nsteps; ++s) {
+        uint32_t ep = L->epoch + 1;
+        if (ep >= (1u << 24)) {
+            // epoch stamps wrap: clear every mark before reusing small epochs
+            HIP_TRY(hipMemsetAsync(L->d.mark, 0, (size_t)L->d.N * 4, L->st));
+            ep = 1;
+        }
+        L->epoch = ep;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (L->timing) {
+            if (L->ev_used == L->events.size()) {
+                hipEvent_t a, b;
+                HIP_TRY(hipEventCreate(&a));
+                HIP_TRY(hipEventCreate(&b));
+                L->events.push_back({a, b});
+            }
+            e0 = L->events[L->ev_used].first;
+            e1 = L->events[L->ev_used].second;
+            ++L->ev_used;
+        }
+        switch (L->P.precision) {
+        case FSL_FP64: launch_step<double>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1); break;
+        case FSL_FP32: launch_step<float>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1); break;
+        default: launch_step<_Float16>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1); break;
+        }
+        L->parity ^= 1;
+        ++L->steps;
+        if (L->P.check_every > 0 && L->steps % L->P.check_every == 0) {
+            FslStatus r = check_mass(L);
+            if (r != FSL_OK) return r;
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return FSL_OK;
+}
+
+FslStatus fsl_read_fields(FslLattice *L, uint32_t mask, void *const *dst, int32_t on_device)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!dst) return fail(FSL_ERR_ARG, "dst is NULL");
+    const size_t N = (size_t)L->d.N;
+    for (int f = 0; f < FSL_NFIELDS; ++f) {
+        if (!(mask & (1u << f))) continue;
+        if (!dst[f]) return fail(FSL_ERR_ARG, "destination of a selected field is NULL");
+        size_t bytes = N * 8;
+        if (f == FSL_FIELD_TYPE) bytes = N;
+        if (f == FSL_FIELD_OWNER) bytes = N * 4;
+        if (f == FSL_FIELD_VEL || f == FSL_FIELD_NORMAL) bytes = 3 * N * 8;
+        if (f == FSL_FIELD_PDF) bytes = 27 * N * 8;
+        void *buf = dst[f];
+        if (!on_device) HIP_TRY(hipMalloc(&buf, bytes));
+        DISPATCH(L, run_read, L, f, buf);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && !on_device) {
+            e = hipMemcpyAsync(dst[f], buf, bytes, hipMemcpyDeviceToHost, L->st);
+            if (e == hipSuccess) e = hipStreamSynchronize(L->st);
+            (void)hipFree(buf);
+        }
+        if (e != hipSuccess) return fail(FSL_ERR_DEVICE, std::string("read_fields: ") + hipGetErrorString(e));
+    }
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_total_mass(FslLattice *L, double *mass)
+{
+    if (!L || !mass) return fail(FSL_ERR_ARG, "NULL argument");
+    DISPATCH(L, run_mass, L);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(mass, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_counters(FslLattice *L, int64_t out[8])
+{
+    if (!L || !out) return fail(FSL_ERR_ARG, "NULL argument");
+    unsigned long long h[8];
+    HIP_TRY(hipMemcpyAsync(h, L->d.stats, sizeof(h), hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    for (int i = 0; i < 8; ++i) out[i] = (int64_t)h[i];
+    out[7] = 0;
+    return FSL_OK;
+}
+
+FslStatus fsl_info(FslLattice *L, int64_t *steps, int64_t *interface_cells)
+{
+    if (!L) return fail(FSL_ERR_ARG, "NULL argument");
+    int32_t c[3];
+    HIP_TRY(hipMemcpyAsync(c, L->d.cnt, sizeof(c), hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    if (steps) *steps = L->steps;
+    if (interface_cells) *interface_cells = c[L->parity];
+    return FSL_OK;
+}
+
+FslStatus fsl_timing(FslLattice *L, int32_t enable)
+{
+    if (!L) return fail(FSL_ERR_ARG, "NULL argument");
+    L->timing = enable != 0;
+    if (enable) L->ev_used = 0;
+    return FSL_OK;
+}
+
+FslStatus fsl_timing_read(FslLattice *L, double *ms_total, int64_t *launches)
+{
+    if (!L) return fail(FSL_ERR_ARG, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(L->st));
+    double tot = 0.0;
+    for (size_t i = 0; i < L->ev_used; ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, L->events[i].first, L->events[i].second));
+        tot += ms;
+    }
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = (int64_t)L->ev_used;
+    return FSL_OK;
+}
+
+const char *fsl_last_error(void) { return g_err.c_str(); }
+
+void fsl_destroy(FslLattice *L)
+{
+    if (!L) return;
+    (void)hipStreamSynchronize(L->st);
+    for (auto &p : L->events) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (L->sph_dev) (void)hipFree(L->sph_dev);
+    delete L;
+}
+
+}  // extern "C"

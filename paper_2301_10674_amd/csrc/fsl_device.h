@@ -1,0 +1,234 @@
+// fsl_device.h -- device-side building blocks of the free-surface LBM step
+// on gfx950: D3Q27 constants, PDF storage formats, the cumulant collision
+// written on deviations from the rest weights, the product equilibrium, and
+// small wavefront helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace fsl {
+
+// ---------------------------------------------------------------- lattice
+// Direction i = (cx+1) + 3(cy+1) + 9(cz+1); rest = 13; opposite = 26 - i.
+__host__ __device__ constexpr int cx(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int opp(int i) { return 26 - i; }
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double wgt(int i) { return w1(cx(i)) * w1(cy(i)) * w1(cz(i)); }
+__host__ __device__ constexpr int MI(int a, int b, int c) { return a + 3 * b + 9 * c; }
+constexpr int REST = 13;
+
+// cell types (low two bits of the flag byte) and static flag bits
+enum : uint8_t { T_GAS = 0, T_LIQ = 1, T_IF = 2, T_SOLID = 3, T_MASK = 3, F_NEAR_SOLID = 4 };
+// conversion marks (low byte of the epoch-stamped mark word)
+enum : uint32_t { MK_TO_LIQ = 1, MK_TO_GAS = 2, MK_EMPTY = 4, MK_NEW = 8, MK_ISO = 16 };
+
+__device__ __forceinline__ uint32_t mark_bits(uint32_t mk, uint32_t epoch)
+{
+    return (mk >> 8) == epoch ? (mk & 0xffu) : 0u;
+}
+
+// ---------------------------------------------------------------- storage
+// PDFs are stored as deviations d_i = f_i - w_i in S; the collision runs in
+// Real<S>::type.
+template <class S> struct Real { using type = float; };
+template <> struct Real<double> { using type = double; };
+
+template <class S> __device__ __forceinline__ typename Real<S>::type ld(const S *p)
+{
+    return (typename Real<S>::type)(*p);
+}
+__device__ __forceinline__ float ld(const _Float16 *p) { return (float)(*p); }
+
+template <class S, class R> __device__ __forceinline__ S to_store(R v) { return (S)v; }
+
+// ---------------------------------------------------------------- equilibrium
+// Deviation of the product-form equilibrium from the rest weights,
+// D_i(u) = prod_d psi(c_d, u_d) - w_i with psi(0,u) = 2/3 - u^2 and
+// psi(+-1,u) = (1/3 + u^2 +- u)/2, written as nested differences so that no
+// O(1) quantity is subtracted.
+template <class R>
+__device__ __forceinline__ void product_dev(R ux, R uy, R uz, R D[27])
+{
+    const R u[3] = {ux, uy, uz};
+    R e[3][3], w[3];
+    w[0] = R(1.0 / 6.0);
+    w[1] = R(2.0 / 3.0);
+    w[2] = R(1.0 / 6.0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        R uu = u[d] * u[d];
+        e[d][0] = R(0.5) * (uu - u[d]);
+        e[d][1] = -uu;
+        e[d][2] = R(0.5) * (uu + u[d]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R d2 = e[0][a] * (w[b] + e[1][b]) + w[a] * e[1][b];
+                D[MI(a, b, c)] = d2 * (w[c] + e[2][c]) + (w[a] * w[b]) * e[2][c];
+            }
+}
+
+// f^eq(rho, u) - w  with rho = 1 + drho
+template <class R>
+__device__ __forceinline__ void feq_dev(R drho, R ux, R uy, R uz, R out[27])
+{
+    R D[27];
+    product_dev(ux, uy, uz, D);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[i] = drho * (R(wgt(i)) + D[i]) + D[i];
+}
+
+// ---------------------------------------------------------------- collision
+// One 1D inverse chimera step: central moments (k0,k1,k2) about u ->
+// values at velocities -1, 0, +1.
+template <class R>
+__device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
+{
+    R k0 = a, k1 = b, k2 = c, uu = u * u;
+    R f0 = k0 * (R(1) - uu) - R(2) * u * k1 - k2;
+    R fm = R(0.5) * (k0 * (uu - u) + k1 * (R(2) * u - R(1)) + k2);
+    R fp = R(0.5) * (k0 * (uu + u) + k1 * (R(2) * u + R(1)) + k2);
+    a = fm;
+    b = f0;
+    c = fp;
+}
+
+// Cumulant collision (Geier et al. 2015, as chosen in Section 2.1: shear
+// rate omega, bulk and all higher-order rates 1, no Galilean correction) on
+// PDF deviations d_i = f_i - w_i, in place.  g is the body acceleration:
+// the velocity is shifted by F/(2 rho) and the first-order central moments
+// leave the collision as +F/(2 rho) = g/2.
+//
+// With every higher-order rate equal to 1 the post-collision cumulants of
+// order >= 3 vanish, so the post-collision central moments are the Gaussian
+// (Isserlis) moments of the relaxed second-order cumulant tensor K*; only
+// rho, the momentum and the second moments of the input matter.  Everything
+// is carried as a deviation from the rest state (rho = 1, u = 0, K = I/3) so
+// FP32 keeps the small quantities exact enough.
+template <class R>
+__device__ __forceinline__ void collide(R d[27], R omega, R gx, R gy, R gz)
+{
+    // raw moments of the deviations, passes x, y, z of (sum, odd, even)
+    R m[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) m[i] = d[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            R vm = m[MI(0, b, c)], v0 = m[MI(1, b, c)], vp = m[MI(2, b, c)];
+            m[MI(0, b, c)] = vm + v0 + vp;
+            m[MI(1, b, c)] = vp - vm;
+            m[MI(2, b, c)] = vp + vm;
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R vm = m[MI(a, 0, c)], v0 = m[MI(a, 1, c)], vp = m[MI(a, 2, c)];
+            m[MI(a, 0, c)] = vm + v0 + vp;
+            m[MI(a, 1, c)] = vp - vm;
+            m[MI(a, 2, c)] = vp + vm;
+        }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R vm = m[MI(a, b, 0)], v0 = m[MI(a, b, 1)], vp = m[MI(a, b, 2)];
+            m[MI(a, b, 0)] = vm + v0 + vp;
+            m[MI(a, b, 1)] = vp - vm;
+            m[MI(a, b, 2)] = vp + vm;
+        }
+    const R drho = m[MI(0, 0, 0)];
+    const R rho = R(1) + drho;
+    const R irho = R(1) / rho;
+    const R jx = m[MI(1, 0, 0)], jy = m[MI(0, 1, 0)], jz = m[MI(0, 0, 1)];
+    const R ux = (jx + R(0.5) * rho * gx) * irho;
+    const R uy = (jy + R(0.5) * rho * gy) * irho;
+    const R uz = (jz + R(0.5) * rho * gz) * irho;
+    const R third = R(1.0 / 3.0);
+    const R dtr = drho * irho * third;
+    // second-order central moments minus I/3
+    R Kxx = (m[MI(2, 0, 0)] - R(2) * ux * jx) * irho + ux * ux - dtr;
+    R Kyy = (m[MI(0, 2, 0)] - R(2) * uy * jy) * irho + uy * uy - dtr;
+    R Kzz = (m[MI(0, 0, 2)] - R(2) * uz * jz) * irho + uz * uz - dtr;
+    R Kxy = (m[MI(1, 1, 0)] - ux * jy - uy * jx) * irho + ux * uy;
+    R Kxz = (m[MI(1, 0, 1)] - ux * jz - uz * jx) * irho + ux * uz;
+    R Kyz = (m[MI(0, 1, 1)] - uy * jz - uz * jy) * irho + uy * uz;
+    // relaxation: deviator with omega, trace to equilibrium
+    const R om1 = R(1) - omega;
+    const R tr3 = (Kxx + Kyy + Kzz) * third;
+    const R ax = om1 * (Kxx - tr3), ay = om1 * (Kyy - tr3), az = om1 * (Kzz - tr3);
+    const R bxy = om1 * Kxy, bxz = om1 * Kxz, byz = om1 * Kyz;
+    // post-collision central moments minus their rest values
+    R k[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) k[i] = R(0);
+    k[MI(1, 0, 0)] = R(0.5) * gx;
+    k[MI(0, 1, 0)] = R(0.5) * gy;
+    k[MI(0, 0, 1)] = R(0.5) * gz;
+    k[MI(2, 0, 0)] = ax;
+    k[MI(0, 2, 0)] = ay;
+    k[MI(0, 0, 2)] = az;
+    k[MI(1, 1, 0)] = bxy;
+    k[MI(1, 0, 1)] = bxz;
+    k[MI(0, 1, 1)] = byz;
+    const R sx = third + ax, sy = third + ay, sz = third + az;
+    k[MI(2, 2, 0)] = (ax + ay) * third + ax * ay + R(2) * bxy * bxy;
+    k[MI(2, 0, 2)] = (ax + az) * third + ax * az + R(2) * bxz * bxz;
+    k[MI(0, 2, 2)] = (ay + az) * third + ay * az + R(2) * byz * byz;
+    k[MI(2, 1, 1)] = sx * byz + R(2) * bxy * bxz;
+    k[MI(1, 2, 1)] = sy * bxz + R(2) * bxy * byz;
+    k[MI(1, 1, 2)] = sz * bxy + R(2) * bxz * byz;
+    k[MI(2, 2, 2)] = (ax + ay + az) * R(1.0 / 9.0) + (ax * ay + ay * az + ax * az) * third
+                     + ax * ay * az
+                     + R(2) * (sx * byz * byz + sy * bxz * bxz + sz * bxy * bxy)
+                     + R(8) * bxy * bxz * byz;
+    // back to velocity space about u (linear, so applied to the deviations)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) inv_chimera(k[MI(0, b, c)], k[MI(1, b, c)], k[MI(2, b, c)], ux);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) inv_chimera(k[MI(a, 0, c)], k[MI(a, 1, c)], k[MI(a, 2, c)], uy);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) inv_chimera(k[MI(a, b, 0)], k[MI(a, b, 1)], k[MI(a, b, 2)], uz);
+    // rest state about u is the product equilibrium: f* = rho (w + D + G)
+    R D[27];
+    product_dev(ux, uy, uz, D);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) d[i] = drho * (R(wgt(i)) + D[i]) + D[i] + rho * k[i];
+}
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int wrap_m(int v, int n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ int wrap_p(int v, int n) { return v == n - 1 ? 0 : v + 1; }
+
+// Wave-aggregated append of `value` to list[] when pred holds: one atomic
+// per wavefront.  Call with every active lane of the wave.
+__device__ __forceinline__ void list_append(int32_t *list, int32_t *counter, bool pred, int32_t value)
+{
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) list[base + (int)__popcll(mask & ((1ull << lane) - 1ull))] = value;
+}
+
+}  // namespace fsl

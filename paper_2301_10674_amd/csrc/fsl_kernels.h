@@ -1,0 +1,40 @@
+// fsl_kernels.h -- device state shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsl {
+
+// Everything a kernel needs, passed by value.  Per-cell arrays are dense
+// over the whole lattice (cell = x + nx*(y + ny*z)); PDF arrays are
+// direction-major: pdf[i*N + cell].
+struct Dev {
+    int nx, ny, nz, N;
+    int nbx, rows;            // dense grid: x-blocks of 256 cells per (y, z) row
+    int xcd_map;              // 1: rows are interleaved over the 8 XCDs
+    void *pdf[2];             // storage type depends on the precision form
+    double *mq;               // interface: mass m; liquid: m minus own outgoing PDFs
+    double *phi;              // interface fill level m / rho*
+    double *rho;              // interface post-collision density
+    double *share;            // excess-mass share of a cell converted this step
+    double *poolc;            // per-cell excess mass that found no receiver
+    void *geom;               // interface normal (xyz) and curvature (w): double4 or float4
+    uint32_t *mark;           // conversion marks, epoch << 8 | bits
+    int32_t *owner;           // owning sphere of a solid cell, -1 otherwise
+    uint8_t *flags;           // cell type (2 bits) | near-solid bit
+    int32_t *list[2];         // interface cells, current / next step
+    int32_t *lnew;            // cells that become interface cells this step
+    int32_t *cnt;             // [0],[1] list lengths, [2] lnew length
+    unsigned long long *stats;  // conversion counters
+    const double *sph;        // spheres: X[3], r, U[3], Omega[3]
+    double *partial;          // reduction partials
+    double omega, gx, gy, gz, sigma, rho_gas, eps, tie;
+    int rule_iso;
+};
+
+constexpr int BULK_THREADS = 256;
+constexpr int LIST_THREADS = 256;
+constexpr int RED_BLOCKS = 1024;
+
+}  // namespace fsl

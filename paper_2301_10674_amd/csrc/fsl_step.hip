@@ -1,0 +1,581 @@
+// fsl_step.hip -- the kernels of one free-surface LBM time step on gfx950.
+//
+// Per step (Section 2.1 fluid model; readings of the cited free-surface
+// method as listed in the design notes):
+//   k_bulk    dense over the lattice, liquid cells: pull streaming,
+//             bounce-back next to walls and spheres, mass bookkeeping,
+//             cumulant collision, store.  This is the HBM-bound hot kernel.
+//   k_iface   interface list: the same plus reconstruction of PDFs from the
+//             gas side, the fill-weighted mass flux and the conversion marks.
+//   k_conv1   interface list: cancel emptyings next to fillings, mark the
+//             cells that become interface cells (list lnew).
+//   k_conv2   lnew: initialise the new interface cells.
+//   k_conv3   interface list: excess mass of converted cells.
+//   k_conv4   interface list + lnew: commit cell types, gather excess mass,
+//             refresh fill levels, build the next interface list.
+//   k_geom    next interface list: normal and curvature from the 3x3x3
+//             fill stencil.
+#include "fsl_device.h"
+#include "fsl_kernels.h"
+
+namespace fsl {
+
+// ---------------------------------------------------------------- indexing
+struct Cell {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Cell cell_xyz(const Dev &d, int c)
+{
+    Cell r;
+    r.x = c % d.nx;
+    int t = c / d.nx;
+    r.y = t % d.ny;
+    r.z = t / d.ny;
+    return r;
+}
+
+// neighbour x + c_i (periodic x, y); -1 beyond the z walls
+__device__ __forceinline__ int nb_of(const Dev &d, const Cell &p, int i)
+{
+    int z = p.z + cz(i);
+    if (z < 0 || z >= d.nz) return -1;
+    int x = cx(i) == 1 ? wrap_p(p.x, d.nx) : (cx(i) == -1 ? wrap_m(p.x, d.nx) : p.x);
+    int y = cy(i) == 1 ? wrap_p(p.y, d.ny) : (cy(i) == -1 ? wrap_m(p.y, d.ny) : p.y);
+    return x + d.nx * (y + d.ny * z);
+}
+
+__device__ __forceinline__ double min_image(double v, int n)
+{
+    if (v > 0.5 * n) v -= n;
+    else if (v < -0.5 * n) v += n;
+    return v;
+}
+
+// Moving-wall bounce-back term 6 w_j (c_j . u_w) for the link from fluid
+// cell p along -c_j into the solid cell s (Ladd; wall density 1).
+template <class R>
+__device__ __forceinline__ R bb_term(const Dev &d, int s, int j, const Cell &p)
+{
+    const double *sp = d.sph + 10 * d.owner[s];
+    double rx = min_image((p.x + 0.5 - 0.5 * cx(j)) - sp[0], d.nx);
+    double ry = min_image((p.y + 0.5 - 0.5 * cy(j)) - sp[1], d.ny);
+    double rz = (p.z + 0.5 - 0.5 * cz(j)) - sp[2];
+    double ux = sp[4] + (sp[8] * rz - sp[9] * ry);
+    double uy = sp[5] + (sp[9] * rx - sp[7] * rz);
+    double uz = sp[6] + (sp[7] * ry - sp[8] * rx);
+    return R(6.0 * wgt(j) * (cx(j) * ux + cy(j) * uy + cz(j) * uz));
+}
+
+// ---------------------------------------------------------------- dense step
+// Block -> (x-block, row).  With xcd_map, hardware block b runs on XCD
+// b % 8; XCD k then works through whole rows k, k+8, k+16, ... so that the
+// x-blocks of one row (which share cache lines at their edges) meet in the
+// same L2, while the liquid/gas split in z stays balanced over the XCDs.
+__device__ __forceinline__ void bulk_block(const Dev &d, int &bx, int &row)
+{
+    const int b = blockIdx.x;
+    if (d.xcd_map) {
+        const int k = b & 7, s = b >> 3;
+        row = k + 8 * (s / d.nbx);
+        bx = s % d.nbx;
+    } else {
+        row = b / d.nbx;
+        bx = b % d.nbx;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
+{
+    using R = typename Real<S>::type;
+    const S *__restrict__ src = (const S *)d.pdf[p];
+    S *__restrict__ dst = (S *)d.pdf[p ^ 1];
+    int bx, row;
+    bulk_block(d, bx, row);
+    const int x = bx * BULK_THREADS + (int)threadIdx.x;
+    if (x >= d.nx) return;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const size_t N = (size_t)d.N;
+    const int y = row % ny, z = row / ny;
+    const int c = x + nx * (y + ny * z);
+    const uint8_t fl = d.flags[c];
+    if ((fl & T_MASK) != T_LIQ) return;
+
+    // source coordinate x - c_i for c_i = -1, 0, +1 (z clamped; the wall
+    // layers are near-solid cells and are fixed below)
+    const int xs[3] = {wrap_p(x, nx), x, wrap_m(x, nx)};
+    const int ys[3] = {wrap_p(y, ny), y, wrap_m(y, ny)};
+    const int zs[3] = {z < nz - 1 ? z + 1 : z, z, z > 0 ? z - 1 : z};
+    R f[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int s = xs[i % 3] + nx * (ys[(i / 3) % 3] + ny * zs[i / 9]);
+        f[i] = ld(src + (size_t)i * N + s);
+    }
+
+    uint32_t solid = 0;
+    if (fl & F_NEAR_SOLID) {
+        const Cell pc = {x, y, z};
+#pragma unroll
+        for (int j = 0; j < 27; ++j) {
+            if (j == REST) continue;
+            const int sz = z - cz(j);
+            const bool wall = sz < 0 || sz >= nz;
+            const int s = xs[j % 3] + nx * (ys[(j / 3) % 3] + ny * (wall ? z : sz));
+            if (wall || (d.flags[s] & T_MASK) == T_SOLID) {
+                solid |= 1u << j;
+                R v = ld(src + (size_t)opp(j) * N + c);
+                if (!wall) v += bb_term<R>(d, s, j, pc);
+                f[j] = v;
+            }
+        }
+    }
+
+    // mass: m' = (m - own outgoing) + incoming, over non-solid links
+    double m = d.mq[c];
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST) continue;
+        m += ((solid >> j) & 1u) ? 0.0 : (double)f[j];
+    }
+
+    collide<R>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz));
+
+    double out = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const S v = to_store<S, R>(f[i]);
+        dst[(size_t)i * N + c] = v;
+        if (i != REST && !((solid >> opp(i)) & 1u)) out += (double)ld(&v);
+    }
+    d.mq[c] = m - out;
+}
+
+// ---------------------------------------------------------------- interface
+template <class S>
+__global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t epoch)
+{
+    using R = typename Real<S>::type;
+    using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.cnt[p ^ 1] = 0;
+        d.cnt[2] = 0;
+    }
+    const S *__restrict__ src = (const S *)d.pdf[p];
+    S *__restrict__ dst = (S *)d.pdf[p ^ 1];
+    const int32_t *list = d.list[p];
+    const int count = d.cnt[p];
+    const size_t N = (size_t)d.N;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int c = list[t];
+        const Cell pc = cell_xyz(d, c);
+        // neighbour x + c_i and its type (walls count as solid)
+        int nbc[27];
+        uint8_t nty[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            nbc[i] = i == REST ? c : nb_of(d, pc, i);
+            nty[i] = nbc[i] < 0 ? (uint8_t)T_SOLID : (uint8_t)(d.flags[nbc[i]] & T_MASK);
+        }
+        R own[27], pulled[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            own[i] = ld(src + (size_t)i * N + c);
+            // source of incoming i is x - c_i = neighbour opp(i)
+            const int s = nbc[opp(i)];
+            pulled[i] = s < 0 ? own[i] : ld(src + (size_t)i * N + s);
+        }
+        const double phic = d.phi[c];
+        const double phicl = phic < 0.0 ? 0.0 : (phic > 1.0 ? 1.0 : phic);
+
+        // mass flux from the stored PDFs: s_i (f*_{-i}(x+c_i) - f*_i(x))
+        double dm = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (i == REST) continue;
+            const uint8_t ty = nty[i];
+            if (ty == T_SOLID || ty == T_GAS) continue;
+            double s = 1.0;
+            if (ty == T_IF) {
+                double ph = d.phi[nbc[i]];
+                ph = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
+                s = 0.5 * (phicl + ph);
+            }
+            dm += s * ((double)pulled[opp(i)] - (double)own[i]);
+        }
+
+        // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
+        // post-collision velocity
+        const R4 gm = ((const R4 *)d.geom)[c];
+        R drho_o = R(0), jxo = R(0), jyo = R(0), jzo = R(0);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            drho_o += own[i];
+            jxo += R(cx(i)) * own[i];
+            jyo += R(cy(i)) * own[i];
+            jzo += R(cz(i)) * own[i];
+        }
+        const R irho_o = R(1) / (R(1) + drho_o);
+        R E[27];
+        feq_dev<R>(R(d.rho_gas - 1.0 + 6.0 * d.sigma * (double)gm.w), jxo * irho_o,
+                   jyo * irho_o, jzo * irho_o, E);
+
+        R f[27];
+#pragma unroll
+        for (int j = 0; j < 27; ++j) {
+            if (j == REST) {
+                f[j] = own[REST];
+                continue;
+            }
+            const int sj = opp(j);  // source direction index
+            const uint8_t st = nty[sj];
+            if (st == T_SOLID) {
+                R v = own[sj];
+                if (nbc[sj] >= 0) v += bb_term<R>(d, nbc[sj], j, pc);
+                f[j] = v;
+            } else {
+                const R nc = gm.x * R(cx(j)) + gm.y * R(cy(j)) + gm.z * R(cz(j));
+                const bool recon = st == T_GAS || (double)nc < -d.tie;
+                f[j] = recon ? E[j] + E[sj] - own[sj] : pulled[j];
+            }
+        }
+
+        collide<R>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz));
+
+        double rs = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const S v = to_store<S, R>(f[i]);
+            dst[(size_t)i * N + c] = v;
+            rs += (double)ld(&v);
+        }
+        const double rho = 1.0 + rs;
+        const double m = d.mq[c] + dm;
+        d.mq[c] = m;
+        d.rho[c] = rho;
+
+        uint32_t bits = 0;
+        if (m > (1.0 + d.eps) * rho) {
+            bits = MK_TO_LIQ;
+        } else if (m < -d.eps * rho) {
+            bits = MK_TO_GAS;
+        } else if (d.rule_iso) {
+            bool has_gas = false, has_liq = false;
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST || nbc[i] < 0) continue;
+                has_gas |= nty[i] == T_GAS;
+                has_liq |= nty[i] == T_LIQ;
+            }
+            if (!has_gas && has_liq) bits = MK_TO_LIQ | MK_ISO;
+            else if (!has_liq && has_gas) bits = MK_TO_GAS | MK_ISO;
+        }
+        d.mark[c] = (epoch << 8) | bits;
+    }
+}
+
+// ---------------------------------------------------------------- conversion
+__device__ __forceinline__ void push_new(const Dev &d, int c, uint32_t epoch, unsigned long long stat)
+{
+    const uint32_t old = atomicMax(&d.mark[c], (epoch << 8) | MK_NEW);
+    if ((old >> 8) != epoch) {
+        const int k = atomicAdd(&d.cnt[2], 1);
+        d.lnew[k] = c;
+        atomicAdd(&d.stats[stat], 1ull);
+    }
+}
+
+__global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t epoch)
+{
+    const int32_t *list = d.list[p];
+    const int count = d.cnt[p];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int c = list[t];
+        const uint32_t mk = mark_bits(d.mark[c], epoch);
+        if (!(mk & (MK_TO_LIQ | MK_TO_GAS))) continue;
+        const Cell pc = cell_xyz(d, c);
+        if (mk & MK_TO_LIQ) {
+            atomicAdd(&d.stats[(mk & MK_ISO) ? 2 : 0], 1ull);
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) continue;
+                const int y = nb_of(d, pc, i);
+                if (y >= 0 && (d.flags[y] & T_MASK) == T_GAS) push_new(d, y, epoch, 5);
+            }
+        } else {
+            bool near_fill = false;
+            for (int i = 0; i < 27 && !near_fill; ++i) {
+                if (i == REST) continue;
+                const int y = nb_of(d, pc, i);
+                if (y >= 0 && (mark_bits(d.mark[y], epoch) & MK_TO_LIQ)) near_fill = true;
+            }
+            if (near_fill) {
+                atomicAdd(&d.stats[4], 1ull);
+                continue;
+            }
+            atomicOr(&d.mark[c], MK_EMPTY);
+            atomicAdd(&d.stats[(mk & MK_ISO) ? 3 : 1], 1ull);
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) continue;
+                const int y = nb_of(d, pc, i);
+                if (y >= 0 && (d.flags[y] & T_MASK) == T_LIQ) push_new(d, y, epoch, 6);
+            }
+        }
+    }
+}
+
+// sum of a cell's stored deviations over all directions (all) and over the
+// outgoing directions whose target is not solid, rest excluded (fluid)
+template <class S>
+__device__ __forceinline__ void stored_sums(const Dev &d, const S *pdf, int c, const Cell &pc,
+                                            double &all, double &fluid)
+{
+    const size_t N = (size_t)d.N;
+    all = 0.0;
+    fluid = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        const double v = (double)ld(pdf + (size_t)i * N + c);
+        all += v;
+        if (i == REST) continue;
+        const int y = nb_of(d, pc, i);
+        if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += v;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(LIST_THREADS) void k_conv2(Dev d, int p, uint32_t epoch)
+{
+    using R = typename Real<S>::type;
+    S *pdf = (S *)d.pdf[p ^ 1];
+    const int count = d.cnt[2];
+    const size_t N = (size_t)d.N;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int c = d.lnew[t];
+        const Cell pc = cell_xyz(d, c);
+        if ((d.flags[c] & T_MASK) == T_GAS) {
+            // equilibrium at the mean density and velocity of the liquid and
+            // old interface neighbours that are not marked for emptying
+            double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
+            int n = 0;
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) continue;
+                const int y = nb_of(d, pc, i);
+                if (y < 0) continue;
+                const uint8_t ty = d.flags[y] & T_MASK;
+                if (ty != T_LIQ && ty != T_IF) continue;
+                if (mark_bits(d.mark[y], epoch) & MK_TO_GAS) continue;
+                double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < 27; ++k) {
+                    const double v = (double)ld(pdf + (size_t)k * N + y);
+                    r += v;
+                    j[0] += cx(k) * v;
+                    j[1] += cy(k) * v;
+                    j[2] += cz(k) * v;
+                }
+                r += 1.0;
+                rs += r;
+                for (int a = 0; a < 3; ++a) us[a] += j[a] / r;
+                ++n;
+            }
+            const double rb = rs / n;
+            R e[27];
+            feq_dev<R>(R(rb - 1.0), R(us[0] / n), R(us[1] / n), R(us[2] / n), e);
+            double sum = 0.0;
+            for (int i = 0; i < 27; ++i) {
+                const S v = to_store<S, R>(e[i]);
+                pdf[(size_t)i * N + c] = v;
+                sum += (double)ld(&v);
+            }
+            d.mq[c] = 0.0;
+            d.rho[c] = 1.0 + sum;
+        } else {
+            // liquid -> interface keeps its PDFs and mass
+            double all, fluid;
+            stored_sums(d, (const S *)pdf, c, pc, all, fluid);
+            d.mq[c] = d.mq[c] + fluid;
+            d.rho[c] = 1.0 + all;
+        }
+    }
+}
+
+__device__ __forceinline__ bool interface_after(const Dev &d, int y, uint32_t epoch)
+{
+    const uint32_t mk = mark_bits(d.mark[y], epoch);
+    if (mk & MK_NEW) return true;
+    return (d.flags[y] & T_MASK) == T_IF && !(mk & (MK_TO_LIQ | MK_EMPTY));
+}
+
+template <class S>
+__global__ __launch_bounds__(LIST_THREADS) void k_conv3(Dev d, int p, uint32_t epoch)
+{
+    const S *pdf = (const S *)d.pdf[p ^ 1];
+    const int32_t *list = d.list[p];
+    const int count = d.cnt[p];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int c = list[t];
+        const uint32_t mk = mark_bits(d.mark[c], epoch);
+        const bool filled = mk & MK_TO_LIQ, emptied = mk & MK_EMPTY;
+        if (!filled && !emptied) continue;
+        const Cell pc = cell_xyz(d, c);
+        double e;
+        if (filled) {
+            e = d.mq[c] - d.rho[c];
+            double all, fluid;
+            stored_sums(d, pdf, c, pc, all, fluid);
+            d.mq[c] = d.rho[c] - fluid;  // liquid form: m minus own outgoing
+        } else {
+            e = d.mq[c];
+            d.mq[c] = 0.0;
+        }
+        int recv = 0;
+        for (int i = 0; i < 27; ++i) {
+            if (i == REST) continue;
+            const int y = nb_of(d, pc, i);
+            if (y >= 0 && interface_after(d, y, epoch)) ++recv;
+        }
+        if (recv > 0) {
+            d.share[c] = e / recv;
+        } else {
+            d.share[c] = 0.0;
+            d.poolc[c] += e;
+        }
+    }
+}
+
+__global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t epoch)
+{
+    const int32_t *list = d.list[p];
+    const int ncur = d.cnt[p];
+    const int total = ncur + d.cnt[2];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        int c;
+        bool keep = true;
+        if (t < ncur) {
+            c = list[t];
+            const uint32_t mk = mark_bits(d.mark[c], epoch);
+            if (mk & (MK_TO_LIQ | MK_EMPTY)) {
+                d.flags[c] = (uint8_t)((d.flags[c] & ~T_MASK) | ((mk & MK_TO_LIQ) ? T_LIQ : T_GAS));
+                keep = false;
+            }
+        } else {
+            c = d.lnew[t - ncur];
+            d.flags[c] = (uint8_t)((d.flags[c] & ~T_MASK) | T_IF);
+        }
+        if (keep) {
+            const Cell pc = cell_xyz(d, c);
+            double add = 0.0;
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) continue;
+                const int y = nb_of(d, pc, i);
+                if (y >= 0 && (mark_bits(d.mark[y], epoch) & (MK_TO_LIQ | MK_EMPTY))) add += d.share[y];
+            }
+            const double m = d.mq[c] + add;
+            d.mq[c] = m;
+            d.phi[c] = m / d.rho[c];
+        }
+        list_append(d.list[p ^ 1], &d.cnt[p ^ 1], keep, c);
+    }
+}
+
+// ---------------------------------------------------------------- geometry
+template <class R>
+__device__ __forceinline__ R stencil_value(const Dev &d, int y, R centre)
+{
+    if (y < 0) return centre;
+    switch (d.flags[y] & T_MASK) {
+    case T_LIQ: return R(1);
+    case T_GAS: return R(0);
+    case T_IF: {
+        double v = d.phi[y];
+        return R(v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v));
+    }
+    default: return centre;
+    }
+}
+
+// Parker-Youngs normal and finite-difference mean curvature of the 3x3x3
+// fill stencil of each interface cell (index MI(a,b,c) = offset (a-1,b-1,c-1)).
+template <class R>
+__global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
+{
+    using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+    const int32_t *list = d.list[which];
+    const int count = d.cnt[which];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int c = list[t];
+        const Cell pc = cell_xyz(d, c);
+        double pv = d.phi[c];
+        const R centre = R(pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv));
+        R s[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) s[i] = i == REST ? centre : stencil_value<R>(d, nb_of(d, pc, i), centre);
+        const R W[3] = {R(1), R(2), R(1)};
+        R gx = R(0), gy = R(0), gz = R(0);
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const R w = W[p] * W[q];
+                gx += w * (s[MI(2, p, q)] - s[MI(0, p, q)]);
+                gy += w * (s[MI(p, 2, q)] - s[MI(p, 0, q)]);
+                gz += w * (s[MI(p, q, 2)] - s[MI(p, q, 0)]);
+            }
+        gx /= R(32);
+        gy /= R(32);
+        gz /= R(32);
+        const R gn = sqrt(gx * gx + gy * gy + gz * gz);
+        R4 out;
+        if (gn < R(1e-12)) {
+            out.x = out.y = out.z = out.w = R(0);
+        } else {
+            const R hx = gx / gn, hy = gy / gn, hz = gz / gn;
+            const R c0 = s[MI(1, 1, 1)];
+            const R Hxx = s[MI(2, 1, 1)] - R(2) * c0 + s[MI(0, 1, 1)];
+            const R Hyy = s[MI(1, 2, 1)] - R(2) * c0 + s[MI(1, 0, 1)];
+            const R Hzz = s[MI(1, 1, 2)] - R(2) * c0 + s[MI(1, 1, 0)];
+            const R Hxy = R(0.25) * (s[MI(2, 2, 1)] - s[MI(2, 0, 1)] - s[MI(0, 2, 1)] + s[MI(0, 0, 1)]);
+            const R Hxz = R(0.25) * (s[MI(2, 1, 2)] - s[MI(2, 1, 0)] - s[MI(0, 1, 2)] + s[MI(0, 1, 0)]);
+            const R Hyz = R(0.25) * (s[MI(1, 2, 2)] - s[MI(1, 2, 0)] - s[MI(1, 0, 2)] + s[MI(1, 0, 0)]);
+            const R tr = Hxx + Hyy + Hzz;
+            const R gHg = hx * hx * Hxx + hy * hy * Hyy + hz * hz * Hzz
+                          + R(2) * (hx * hy * Hxy + hx * hz * Hxz + hy * hz * Hyz);
+            out.x = -hx;
+            out.y = -hy;
+            out.z = -hz;
+            out.w = -(tr - gHg) / (R(2) * gn);
+        }
+        ((R4 *)d.geom)[c] = out;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <class S>
+void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream_t st,
+                 hipEvent_t ev0, hipEvent_t ev1)
+{
+    using R = typename Real<S>::type;
+    const int gb = d.nbx * d.rows;
+    if (ev0) (void)hipEventRecord(ev0, st);
+    k_bulk<S><<<gb, BULK_THREADS, 0, st>>>(d, p);
+    if (ev1) (void)hipEventRecord(ev1, st);
+    k_iface<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv2<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv3<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv4<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_geom<R><<<list_blocks, LIST_THREADS, 0, st>>>(d, p ^ 1);
+}
+
+template void launch_step<double>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_step<float>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_step<_Float16>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+
+template <class R>
+void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st)
+{
+    k_geom<R><<<list_blocks, LIST_THREADS, 0, st>>>(d, which);
+}
+template void launch_geom<double>(const Dev &, int, int, hipStream_t);
+template void launch_geom<float>(const Dev &, int, int, hipStream_t);
+
+}  // namespace fsl

@@ -1,0 +1,237 @@
+"""Python binding of the C-ABI in ``include/fsl.h``.
+
+Argument marshalling only: every step of the method runs in the HIP library
+``libfsl.so`` built next to this file.  PyTorch provides the device workspace
+and the stream.  There is no fallback: if the library is missing, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsl.so")
+
+FSL_OK, FSL_ERR_ARG, FSL_ERR_STATE, FSL_ERR_DEVICE, FSL_ERR_NOMEM, FSL_ERR_UNSTABLE = range(6)
+FP64, FP32, FP16_STORE = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORE}
+(FIELD_TYPE, FIELD_MASS, FIELD_FILL, FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_NORMAL,
+ FIELD_CURV, FIELD_OWNER) = range(9)
+NFIELDS = 9
+GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
+
+# every symbol declared in include/fsl.h
+EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fsl_step",
+           "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
+           "fsl_timing_read", "fsl_last_error", "fsl_destroy")
+
+
+class FslError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("fsl status %d: %s" % (status, msg))
+        self.status = status
+
+
+class FslParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("omega", ctypes.c_double),
+        ("accel", ctypes.c_double * 3), ("sigma", ctypes.c_double),
+        ("rho_gas", ctypes.c_double), ("conv_eps", ctypes.c_double),
+        ("normal_tie", ctypes.c_double), ("rule_isolated", ctypes.c_int32),
+        ("normals", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+def make_params(shape, precision="fp64", omega=1.0, accel=(0.0, 0.0, 0.0), sigma=0.0,
+                rho_gas=1.0, conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
+                normals=0, check_every=0):
+    p = FslParams()
+    p.nx, p.ny, p.nz = (int(v) for v in shape)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.omega = float(omega)
+    for d in range(3):
+        p.accel[d] = float(accel[d])
+    p.sigma, p.rho_gas = float(sigma), float(rho_gas)
+    p.conv_eps, p.normal_tie = float(conv_eps), float(normal_tie)
+    p.rule_isolated = 1 if rule_isolated else 0
+    p.normals, p.check_every, p.reserved = int(normals), int(check_every), 0
+    return p
+
+
+_lib = None
+
+
+def lib():
+    """Load libfsl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfsl.so is not built; run `python -m paper_2301_10674_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
+        L.fsl_workspace_bytes.restype = ctypes.c_size_t
+        L.fsl_workspace_bytes.argtypes = [ctypes.POINTER(FslParams)]
+        L.fsl_create_lattice.restype = ctypes.c_int
+        L.fsl_create_lattice.argtypes = [ctypes.POINTER(FslParams), vp, ctypes.c_size_t, vp,
+                                         dp, dp, dp, ctypes.POINTER(vp)]
+        L.fsl_set_particles.restype = ctypes.c_int
+        L.fsl_set_particles.argtypes = [vp, i32, dp, dp, dp, dp]
+        L.fsl_step.restype = ctypes.c_int
+        L.fsl_step.argtypes = [vp, i32]
+        L.fsl_read_fields.restype = ctypes.c_int
+        L.fsl_read_fields.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(vp), i32]
+        L.fsl_total_mass.restype = ctypes.c_int
+        L.fsl_total_mass.argtypes = [vp, dp]
+        L.fsl_counters.restype = ctypes.c_int
+        L.fsl_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.fsl_info.restype = ctypes.c_int
+        L.fsl_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.fsl_timing.restype = ctypes.c_int
+        L.fsl_timing.argtypes = [vp, i32]
+        L.fsl_timing_read.restype = ctypes.c_int
+        L.fsl_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.fsl_last_error.restype = ctypes.c_char_p
+        L.fsl_last_error.argtypes = []
+        L.fsl_destroy.restype = None
+        L.fsl_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FSL_OK:
+        raise FslError(status, lib().fsl_last_error().decode())
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+
+def workspace_bytes(params: FslParams) -> int:
+    return int(lib().fsl_workspace_bytes(ctypes.byref(params)))
+
+
+class Lattice:
+    """A lattice living in a torch device workspace."""
+
+    def __init__(self, params: FslParams, fill, rho, vel=None, device="cuda"):
+        import torch
+
+        self.params = params
+        self.shape = (params.nx, params.ny, params.nz)
+        self.N = params.nx * params.ny * params.nz
+        nbytes = workspace_bytes(params)
+        if nbytes == 0:
+            raise FslError(FSL_ERR_ARG, lib().fsl_last_error().decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        fill, rho, vel = _f64(fill), _f64(rho), _f64(vel)
+        assert fill.size == self.N and rho.size == self.N
+        assert vel is None or vel.size == 3 * self.N
+        h = ctypes.c_void_p()
+        _check(lib().fsl_create_lattice(ctypes.byref(params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                        nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                        _dp(fill), _dp(rho), _dp(vel), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().fsl_destroy(h)
+        self.h = None
+
+    def set_particles(self, centre, radius, vel=None, angvel=None):
+        centre, radius = _f64(centre), _f64(radius)
+        n = radius.size
+        assert centre.size == 3 * n
+        vel, angvel = _f64(vel), _f64(angvel)
+        _check(lib().fsl_set_particles(self.h, n, _dp(centre), _dp(radius), _dp(vel), _dp(angvel)))
+
+    def step(self, n=1):
+        _check(lib().fsl_step(self.h, int(n)))
+
+    def read_fields(self, fields):
+        """Read the given field ids into new host arrays shaped (.., nz, ny, nx)."""
+        nx, ny, nz = self.shape
+        N = self.N
+        outs = {}
+        ptrs = (ctypes.c_void_p * NFIELDS)()
+        mask = 0
+        for f in fields:
+            if f == FIELD_TYPE:
+                a = np.zeros(N, dtype=np.uint8)
+            elif f == FIELD_OWNER:
+                a = np.zeros(N, dtype=np.int32)
+            elif f in (FIELD_VEL, FIELD_NORMAL):
+                a = np.zeros(3 * N)
+            elif f == FIELD_PDF:
+                a = np.zeros(27 * N)
+            else:
+                a = np.zeros(N)
+            outs[f] = a
+            ptrs[f] = a.ctypes.data
+            mask |= 1 << f
+        _check(lib().fsl_read_fields(self.h, mask, ptrs, 0))
+        res = {}
+        for f, a in outs.items():
+            if f in (FIELD_VEL, FIELD_NORMAL):
+                res[f] = a.reshape(3, nz, ny, nx)
+            elif f == FIELD_PDF:
+                res[f] = a.reshape(27, nz, ny, nx)
+            else:
+                res[f] = a.reshape(nz, ny, nx)
+        return res
+
+    def read(self, field):
+        return self.read_fields([field])[field]
+
+    def total_mass(self):
+        m = ctypes.c_double()
+        _check(lib().fsl_total_mass(self.h, ctypes.byref(m)))
+        return m.value
+
+    def counters(self):
+        out = (ctypes.c_int64 * 8)()
+        _check(lib().fsl_counters(self.h, out))
+        return np.array(out[:], dtype=np.int64)
+
+    def info(self):
+        s, n = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fsl_info(self.h, ctypes.byref(s), ctypes.byref(n)))
+        return s.value, n.value
+
+    def timing(self, enable):
+        _check(lib().fsl_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().fsl_timing_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def create_lattice(params, fill, rho, vel=None, device="cuda"):
+    return Lattice(params, fill, rho, vel, device=device)
+
+
+def lattice_from_workload(w, precision="fp64", check_every=0, **overrides):
+    """Create a lattice from a seeded workload (``inputs.Workload``) and map
+    its spheres."""
+    kw = dict(shape=w.shape, precision=precision, omega=w.omega, accel=w.accel,
+              sigma=w.sigma, rho_gas=w.rho_gas, conv_eps=w.conv_eps, check_every=check_every)
+    kw.update(overrides)
+    lat = Lattice(make_params(**kw), w.fill, w.rho, w.vel)
+    if len(w.radius):
+        lat.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    return lat
