@@ -17,6 +17,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fsl_oracle.c")
+MLP_SRC = os.path.join(HERE, "mlp_oracle.c")
 HDR = os.path.join(HERE, "fsl_oracle.h")
 LIB = os.path.join(HERE, "liboracle.so")
 
@@ -27,12 +28,12 @@ F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS 
 def build(force: bool = True) -> str:
     """Compile ``liboracle.so`` next to its source."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
-        os.path.getmtime(SRC), os.path.getmtime(HDR)
+        os.path.getmtime(SRC), os.path.getmtime(HDR), os.path.getmtime(MLP_SRC)
     ):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"]
+           "-fno-fast-math", "-Wall", "-o", tmp, SRC, MLP_SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -81,6 +82,12 @@ def lib():
         L.ol_feq.argtypes = [ctypes.c_double, dp, dp]
         L.ol_normal_curvature.argtypes = [dp, dp, dp]
         L.ol_velocities.argtypes = [ctypes.c_void_p, dp]
+        L.ol_mlp_nparam.restype = ctypes.c_int32
+        L.ol_mlp_forward.argtypes = [dp, ctypes.c_int32, dp, dp]
+        L.ol_mlp_loss_grad.restype = ctypes.c_double
+        L.ol_mlp_loss_grad.argtypes = [dp, ctypes.c_int32, dp, dp, dp]
+        L.ol_mlp_adam.argtypes = [dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -224,3 +231,35 @@ class OracleLattice:
     @property
     def steps_done(self):
         return lib().ol_steps_done(self.h)
+
+
+# ------------------------------------------------------------------ estimator
+MLP_SHAPES = (("W1", (64, 27)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+              ("W3", (4, 64)), ("b3", (4,)))
+
+
+def mlp_nparam():
+    return int(lib().ol_mlp_nparam())
+
+
+def mlp_forward(params, x):
+    params = _f64(params)
+    x = _f64(x).reshape(-1, 27)
+    y = np.zeros((x.shape[0], 4))
+    lib().ol_mlp_forward(_dp(params), x.shape[0], _dp(x), _dp(y))
+    return y
+
+
+def mlp_loss_grad(params, x, target, want_grad=True):
+    params = _f64(params)
+    x = _f64(x).reshape(-1, 27)
+    target = _f64(target).reshape(-1, 4)
+    g = np.zeros(params.size) if want_grad else None
+    loss = lib().ol_mlp_loss_grad(_dp(params), x.shape[0], _dp(x), _dp(target),
+                                  _dp(g) if want_grad else None)
+    return loss, g
+
+
+def mlp_adam(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    lib().ol_mlp_adam(_dp(params), _dp(m), _dp(v), _dp(_f64(grad)), int(t), lr, beta1, beta2, eps)

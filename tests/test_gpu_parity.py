@@ -76,7 +76,8 @@ def test_initial_state_matches():
     g = F().lattice_from_workload(w, "fp64")
     o = oracle_from(w)
     assert_fp64_parity(gpu_fields(g), oracle_fields(o), 1e-14, "init")
-    assert abs(g.total_mass() - o.total_mass()) < 1e-11
+    # both sums are FP64 over ~1e4 cells in different orders
+    assert abs(g.total_mass() - o.total_mass()) < 1e-14 * o.total_mass()
 
 
 @pytest.mark.parametrize("steps", [1, 5])
@@ -94,7 +95,7 @@ def test_channel_film_200_steps_fp64():
     g = F().lattice_from_workload(w, "fp64")
     o = oracle_from(w)
     M0 = o.total_mass()
-    assert abs(g.total_mass() - M0) < 1e-11
+    assert abs(g.total_mass() - M0) < 1e-14 * M0
     for k in range(4):
         g.step(50)
         o.step(50)

@@ -60,10 +60,12 @@ def test_planted_mistake_is_caught(name, tmp_path):
     mdir = tmp_path / "oracle"
     mdir.mkdir()
     (mdir / "fsl_oracle.c").write_text(src.replace(old, new, 1))
-    (mdir / "fsl_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "fsl_oracle.h")).read())
+    for extra in ("fsl_oracle.h", "mlp_oracle.c"):
+        (mdir / extra).write_text(open(os.path.join(ROOT, "oracle", extra)).read())
     so = str(mdir / "liboracle.so")
     subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                    "-o", so, str(mdir / "fsl_oracle.c"), "-lm"], check=True)
+                    "-o", so, str(mdir / "fsl_oracle.c"), str(mdir / "mlp_oracle.c"), "-lm"],
+                   check=True)
     env = dict(os.environ, FSL_ORACLE_LIB=so)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(HERE, target), "-k", sel],
