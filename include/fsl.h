@@ -22,7 +22,9 @@
  *   - Device memory: the caller allocates one workspace of
  *     fsl_workspace_bytes() bytes (for example a torch uint8 tensor) and
  *     keeps it alive until fsl_destroy().  The library never frees caller
- *     memory; it owns only small internal buffers (the sphere table).
+ *     memory; it owns only internal buffers sized by the sphere geometry
+ *     (the sphere table and the moving-wall bounce-back terms of the cells
+ *     next to spheres), allocated in fsl_set_particles().
  *   - Streams: all device work of a lattice is enqueued on the HIP stream
  *     given to fsl_create_lattice().  fsl_read_fields() and fsl_total_mass()
  *     synchronise that stream; fsl_step() does not.
@@ -167,6 +169,52 @@ FslStatus fsl_info(FslLattice *lat, int64_t *steps, int64_t *interface_cells);
  * kernel time in milliseconds and the number of timed launches. */
 FslStatus fsl_timing(FslLattice *lat, int32_t enable);
 FslStatus fsl_timing_read(FslLattice *lat, double *ms_total, int64_t *launches);
+
+/* ---- learned interface estimator -------------------------------------
+ * The paper needs the local curvature kappa only inside the Laplace
+ * pressure 2 sigma kappa (Section 2.1) and leaves its estimate open.  Besides
+ * the finite-difference estimate (Parker-Youngs normal, Hessian curvature of
+ * the 3x3x3 fill stencil) the library offers a small network: 27 fill levels
+ * (input clamp(phi, 0, 1) - 1/2, stencil entry a + 3b + 9c = offset
+ * (a-1, b-1, c-1)) -> 64 -> 64 -> 4 with tanh hidden layers; outputs 0..2
+ * are an unnormalised normal (liquid -> gas), output 3 is 4 kappa.  Weights
+ * are 6212 floats: W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
+ * (row-major, out x in).  Matrix products run in BF16 on the matrix cores
+ * with FP32 accumulation; the master weights are FP32.
+ * Loss per sample: |y[0..2]/|y[0..2]| - n*|^2 + (y[3] - 4 kappa*)^2, mean over
+ * the batch.  Host arrays: x float [n][27] fill levels, y float [n][4] target
+ * unit normal and kappa. */
+typedef struct {
+    int32_t epochs;         /* passes over the data (> 0) */
+    int32_t batch;          /* samples per Adam step (>= 16) */
+    double lr, beta1, beta2, eps;   /* Adam (Kingma & Ba 2015) */
+    uint64_t seed;          /* seeds the per-epoch shuffles */
+} FslTrainParams;
+
+/* Train in place: weights (host, 6212 floats) hold the initial values and
+ * receive the trained ones; epoch_loss (host, epochs floats, may be NULL)
+ * receives the mean batch loss of each epoch.  Synchronous on hip_stream. */
+FslStatus fsl_estimator_train(const float *x, const float *y, int64_t n,
+                              const FslTrainParams *tp, float *weights,
+                              float *epoch_loss, void *hip_stream);
+
+/* Mean loss and its gradient (6212 floats) over n samples, one pass. */
+FslStatus fsl_estimator_grad(const float *weights, const float *x, const float *y,
+                             int64_t n, float *grad, double *loss, void *hip_stream);
+
+/* Network outputs y float [n][4] for n stencils x float [n][27]. */
+FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n,
+                              float *y, void *hip_stream);
+
+/* Attach trained weights to a lattice.  With params.normals == 1 the
+ * geometry of every interface cell then comes from the network, except where
+ * a stencil cell is solid, |n_raw| is outside [0.5, 2], the network normal
+ * differs from the finite-difference one by more than 30 degrees, or
+ * |kappa| > 0.5: there the finite-difference estimate is kept. */
+FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
+
+/* Interface-cell updates since creation that used the network / fell back. */
+FslStatus fsl_estimator_stats(FslLattice *lat, int64_t *learned, int64_t *fallback);
 
 /* Thread-local text of the last error (never NULL). */
 const char *fsl_last_error(void);

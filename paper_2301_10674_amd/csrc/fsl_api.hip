@@ -14,13 +14,17 @@
 #include "../../include/fsl.h"
 #include "fsl_device.h"
 #include "fsl_kernels.h"
+#include "fsl_mlp.h"
 
 namespace fsl {
 template <class S>
 void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream_t st,
-                 hipEvent_t ev0, hipEvent_t ev1);
+                 hipEvent_t ev0, hipEvent_t ev1, const float *mlpP, const uint16_t *mlpPk);
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
+void launch_setup_links(const Dev &d, hipStream_t st);
+template <class R>
+void launch_bb_terms(const Dev &d, hipStream_t st);
 }  // namespace fsl
 
 using namespace fsl;
@@ -52,6 +56,9 @@ struct FslLattice {
     bool geometry_set = false;
     std::vector<double> sph_host;
     double *sph_dev = nullptr;
+    void *bb_dev = nullptr;   // moving-wall bounce-back records
+    float *mlpP = nullptr;    // learned estimator: FP32 weights
+    uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t ev_used = 0;
@@ -64,7 +71,8 @@ static bool params_ok(const FslParams *p, std::string &why)
 {
     if (!p) { why = "params is NULL"; return false; }
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) { why = "each lattice extent must be >= 3"; return false; }
-    if ((double)p->nx * p->ny * p->nz > 1.5e9) { why = "lattice too large"; return false; }
+    // PDF element offsets are 32-bit byte offsets within one direction array
+    if ((double)p->nx * p->ny * p->nz * 8.0 >= 4294967296.0) { why = "lattice too large"; return false; }
     if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return false; }
     if (!(p->omega > 0.0 && p->omega < 2.0)) { why = "omega must lie in (0, 2)"; return false; }
     for (int a = 0; a < 3; ++a)
@@ -73,14 +81,14 @@ static bool params_ok(const FslParams *p, std::string &why)
     if (!(p->rho_gas > 0.0) || !std::isfinite(p->rho_gas)) { why = "rho_gas must be > 0"; return false; }
     if (!(p->conv_eps >= 0.0 && p->conv_eps < 1.0)) { why = "conv_eps must lie in [0, 1)"; return false; }
     if (!(p->normal_tie >= 0.0)) { why = "normal_tie must be >= 0"; return false; }
-    if (p->normals != 0) { why = "learned normals are not available in this build"; return false; }
+    if (p->normals != 0 && p->normals != 1) { why = "normals must be 0 or 1"; return false; }
     if (p->check_every < 0 || p->reserved != 0) { why = "check_every < 0 or reserved != 0"; return false; }
     return true;
 }
 
 struct Layout {
-    size_t pdf[2], mq, phi, rho, share, poolc, geom, mark, owner, flags, list0, list1, lnew, cnt,
-        stats, partial, total;
+    size_t pdf[2], mq, phi, rho, share, poolc, geom, mark, owner, flags, smask, bbslot, list0, list1,
+        lnew, cnt, stats, partial, total;
 };
 
 static Layout layout(const FslParams *p)
@@ -105,11 +113,13 @@ static Layout layout(const FslParams *p)
     L.mark = take(4 * N);
     L.owner = take(4 * N);
     L.flags = take(N + 4);
+    L.smask = take(4 * N);
+    L.bbslot = take(4 * N);
     L.list0 = take(4 * N);
     L.list1 = take(4 * N);
     L.lnew = take(4 * N);
     L.cnt = take(64);
-    L.stats = take(8 * 8);
+    L.stats = take(8 * 16);
     L.partial = take(8 * (RED_BLOCKS + 8));
     L.total = off;
     return L;
@@ -136,8 +146,13 @@ __global__ void k_init(Dev d, const double *fill, const double *rho, const doubl
         for (int a = 0; a < 3; ++a) u[a] = R(vel[(size_t)a * d.N + c]);
     R e[27];
     feq_dev<R>(R(rho[c] - 1.0), u[0], u[1], u[2], e);
-    S *pdf = (S *)d.pdf[0];
-    for (int i = 0; i < 27; ++i) pdf[(size_t)i * d.N + c] = to_store<S, R>(e[i]);
+    // both buffers: cells that never stream (solid, gas) keep finite values
+    S *pdf0 = (S *)d.pdf[0], *pdf1 = (S *)d.pdf[1];
+    for (int i = 0; i < 27; ++i) {
+        const S v = to_store<S, R>(e[i]);
+        pdf0[(size_t)i * d.N + c] = v;
+        pdf1[(size_t)i * d.N + c] = v;
+    }
 }
 
 __device__ static int nbr(const Dev &d, int c, int i)
@@ -226,17 +241,20 @@ __global__ void k_apply_solid(Dev d)
     }
 }
 
+// solid-link mask (bit j: the source x - c_j of direction j is solid or
+// beyond a z wall) and the near-solid flag bit
 __global__ void k_near_solid(Dev d)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.N) return;
-    bool ns = false;
-    for (int i = 0; i < 27 && !ns; ++i) {
-        if (i == REST) continue;
-        const int y = nbr(d, c, i);
-        ns = y < 0 || (d.flags[y] & T_MASK) == T_SOLID;
+    uint32_t m = 0;
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST) continue;
+        const int y = nbr(d, c, opp(j));
+        if (y < 0 || (d.flags[y] & T_MASK) == T_SOLID) m |= 1u << j;
     }
-    d.flags[c] = (uint8_t)((d.flags[c] & T_MASK) | (ns ? F_NEAR_SOLID : 0));
+    d.smask[c] = m;
+    d.flags[c] = (uint8_t)((d.flags[c] & T_MASK) | (m ? F_NEAR_SOLID : 0));
 }
 
 // interface cells: density of the stored PDFs and fill level
@@ -261,8 +279,8 @@ __global__ void k_build_list(Dev d, int which)
 
 __global__ void k_zero_counts(Dev d)
 {
-    if (threadIdx.x < 3) d.cnt[threadIdx.x] = 0;
-    if (threadIdx.x < 8) d.stats[threadIdx.x] = 0ull;
+    if (threadIdx.x < 5) d.cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 16) d.stats[threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------- reductions
@@ -440,20 +458,74 @@ template <class S> static void run_read(FslLattice *L, int field, void *out)
         }                                                            \
     } while (0)
 
-// rebuild everything derived from the cell types: near-solid bits, the
-// interface list and the interface geometry
-static void finalize(FslLattice *L)
+static void run_bb_terms(FslLattice *L)
+{
+    if (!L->d.bbterm) return;
+    if (L->P.precision == FSL_FP64)
+        launch_bb_terms<double>(L->d, L->st);
+    else
+        launch_bb_terms<float>(L->d, L->st);
+}
+
+// rebuild everything derived from the cell types: solid-link masks,
+// bounce-back records, the highest fluid row, the interface list and the
+// interface geometry
+static FslStatus finalize(FslLattice *L)
 {
     Dev &d = L->d;
     k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_refresh, L);
     k_zero_counts<<<1, 64, 0, L->st>>>(d);
     k_build_list<<<blocks_for(d.N), 256, 0, L->st>>>(d, L->parity);
+    launch_setup_links(d, L->st);
     if (L->P.precision == FSL_FP64)
         launch_geom<double>(d, L->parity, L->list_blocks, L->st);
     else
         launch_geom<float>(d, L->parity, L->list_blocks, L->st);
+    HIP_TRY(hipGetLastError());
+    int32_t nrec = 0;
+    HIP_TRY(hipMemcpyAsync(&nrec, d.cnt + 4, 4, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    if (L->bb_dev) {
+        HIP_TRY(hipFree(L->bb_dev));
+        L->bb_dev = nullptr;
+    }
+    d.bbterm = nullptr;
+    if (nrec > 0) {
+        const size_t rs = L->P.precision == FSL_FP64 ? 8 : 4;
+        HIP_TRY(hipMalloc(&L->bb_dev, (size_t)nrec * 32 * rs));
+        d.bbterm = L->bb_dev;
+        run_bb_terms(L);
+        HIP_TRY(hipGetLastError());
+    }
+    return FSL_OK;
 }
+
+static bool finite_all(const float *v, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// device buffers of a standalone estimator call, freed on scope exit
+struct DevBufs {
+    std::vector<void *> p;
+    ~DevBufs()
+    {
+        for (void *q : p) (void)hipFree(q);
+    }
+    template <class T> hipError_t get(T **out, size_t n)
+    {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, n * sizeof(T) + 16);
+        if (e == hipSuccess) p.push_back(q);
+        *out = (T *)q;
+        return e;
+    }
+};
+
+static const int MLP_GPW = 4;  // groups of 16 samples per wavefront
 
 // ---------------------------------------------------------------- C-ABI
 extern "C" {
@@ -512,6 +584,9 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.mark = (uint32_t *)(base + lay.mark);
     d.owner = (int32_t *)(base + lay.owner);
     d.flags = (uint8_t *)(base + lay.flags);
+    d.smask = (uint32_t *)(base + lay.smask);
+    d.bbslot = (int32_t *)(base + lay.bbslot);
+    d.bbterm = nullptr;
     d.list[0] = (int32_t *)(base + lay.list0);
     d.list[1] = (int32_t *)(base + lay.list1);
     d.lnew = (int32_t *)(base + lay.lnew);
@@ -550,8 +625,8 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
         // m -> stored liquid form, then everything derived from the types
         k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
         DISPATCH(L, run_liquid_form, L, 1);
-        finalize(L);
-        e = hipGetLastError();
+        if (finalize(L) != FSL_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(L->st);
     (void)hipFree(tmp);
@@ -594,7 +669,11 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
             for (int a = 0; a < 4; ++a) same = same && t[10 * q + a] == L->sph_host[10 * q + a];
         if (!same) return fail(FSL_ERR_STATE, "sphere geometry is already mapped; only velocities may change");
         L->sph_host = t;
-        HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), t.size() * 8, hipMemcpyHostToDevice, L->st));
+        if (n > 0) {
+            HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), t.size() * 8, hipMemcpyHostToDevice, L->st));
+            run_bb_terms(L);
+            HIP_TRY(hipGetLastError());
+        }
         HIP_TRY(hipStreamSynchronize(L->st));
         return FSL_OK;
     }
@@ -613,8 +692,8 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
     k_apply_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_liquid_form, L, 1);
-    finalize(L);
-    HIP_TRY(hipGetLastError());
+    FslStatus r = finalize(L);
+    if (r != FSL_OK) return r;
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
 }
@@ -653,10 +732,13 @@ FslStatus fsl_step(FslLattice *L, int32_t nsteps)
             e1 = L->events[L->ev_used].second;
             ++L->ev_used;
         }
+        const bool learned = L->P.normals == 1 && L->mlpP;
+        const float *mP = learned ? L->mlpP : nullptr;
+        const uint16_t *mK = learned ? L->mlpPk : nullptr;
         switch (L->P.precision) {
-        case FSL_FP64: launch_step<double>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1); break;
-        case FSL_FP32: launch_step<float>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1); break;
-        default: launch_step<_Float16>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1); break;
+        case FSL_FP64: launch_step<double>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1, mP, mK); break;
+        case FSL_FP32: launch_step<float>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1, mP, mK); break;
+        default: launch_step<_Float16>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1, mP, mK); break;
         }
         L->parity ^= 1;
         ++L->steps;
@@ -752,6 +834,163 @@ FslStatus fsl_timing_read(FslLattice *L, double *ms_total, int64_t *launches)
     return FSL_OK;
 }
 
+FslStatus fsl_estimator_stats(FslLattice *L, int64_t *learned, int64_t *fallback)
+{
+    if (!L) return fail(FSL_ERR_ARG, "NULL argument");
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpyAsync(h, L->d.stats + 8, sizeof(h), hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    if (learned) *learned = (int64_t)h[0];
+    if (fallback) *fallback = (int64_t)h[1];
+    return FSL_OK;
+}
+
+FslStatus fsl_set_estimator(FslLattice *L, const float *weights)
+{
+    if (!L || !weights) return fail(FSL_ERR_ARG, "NULL argument");
+    if (!finite_all(weights, MLP_NPARAM)) return fail(FSL_ERR_ARG, "non-finite estimator weights");
+    if (!L->mlpP) {
+        HIP_TRY(hipMalloc(&L->mlpP, MLP_NPARAM * sizeof(float)));
+        HIP_TRY(hipMalloc(&L->mlpPk, MLP_PACK_SIZE * sizeof(uint16_t)));
+    }
+    HIP_TRY(hipMemcpyAsync(L->mlpP, weights, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, L->st));
+    mlp_pack(L->mlpP, L->mlpPk, L->st);
+    if (L->P.normals == 1) {
+        // geometry of the current interface cells with the estimator
+        if (L->P.precision == FSL_FP64)
+            launch_geom_mlp<double>(L->d, L->parity, L->list_blocks, L->mlpP, L->mlpPk, L->st);
+        else
+            launch_geom_mlp<float>(L->d, L->parity, L->list_blocks, L->mlpP, L->mlpPk, L->st);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_estimator_grad(const float *weights, const float *x, const float *y, int64_t n,
+                             float *grad_out, double *loss_out, void *hip_stream)
+{
+    if (!weights || !x || !y || !grad_out || n <= 0 || n > (1 << 30)) return fail(FSL_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBufs B;
+    float *P, *X, *T, *part, *ploss, *g, *loss;
+    uint16_t *pk;
+    int32_t *idx;
+    const int nw = (int)((n + 16 * MLP_GPW - 1) / (16 * MLP_GPW));
+    HIP_TRY(B.get(&P, MLP_NPARAM));
+    HIP_TRY(B.get(&pk, MLP_PACK_SIZE));
+    HIP_TRY(B.get(&X, (size_t)n * 27));
+    HIP_TRY(B.get(&T, (size_t)n * 4));
+    HIP_TRY(B.get(&idx, (size_t)n));
+    HIP_TRY(B.get(&part, (size_t)nw * MLP_NPARAM));
+    HIP_TRY(B.get(&ploss, (size_t)nw));
+    HIP_TRY(B.get(&g, MLP_NPARAM));
+    HIP_TRY(B.get(&loss, 1));
+    std::vector<int32_t> id((size_t)n);
+    for (int64_t i = 0; i < n; ++i) id[i] = (int32_t)i;
+    HIP_TRY(hipMemcpyAsync(P, weights, MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(X, x, (size_t)n * 27 * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(T, y, (size_t)n * 16, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx, id.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    mlp_pack(P, pk, st);
+    mlp_grad(X, T, idx, (int)n, 1.0f / (float)n, P, pk, MLP_GPW, part, ploss, nw, g, loss, st);
+    HIP_TRY(hipGetLastError());
+    float lh = 0.f;
+    HIP_TRY(hipMemcpyAsync(grad_out, g, MLP_NPARAM * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&lh, loss, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (loss_out) *loss_out = lh;
+    return FSL_OK;
+}
+
+FslStatus fsl_estimator_train(const float *x, const float *y, int64_t n, const FslTrainParams *tp,
+                              float *weights, float *epoch_loss, void *hip_stream)
+{
+    if (!x || !y || !tp || !weights || n <= 0 || n > (1 << 30)) return fail(FSL_ERR_ARG, "bad argument");
+    if (tp->epochs <= 0 || tp->batch < 16 || !(tp->lr > 0.0)) return fail(FSL_ERR_ARG, "bad training parameters");
+    if (!finite_all(weights, MLP_NPARAM)) return fail(FSL_ERR_ARG, "non-finite initial weights");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int batch = (int)std::min<int64_t>(tp->batch, n);
+    const int nbat = (int)((n + batch - 1) / batch);
+    const int nw = (batch + 16 * MLP_GPW - 1) / (16 * MLP_GPW);
+    DevBufs B;
+    float *P, *M, *V, *X, *T, *part, *ploss, *g, *losses;
+    uint16_t *pk;
+    int32_t *idx;
+    HIP_TRY(B.get(&P, MLP_NPARAM));
+    HIP_TRY(B.get(&M, MLP_NPARAM));
+    HIP_TRY(B.get(&V, MLP_NPARAM));
+    HIP_TRY(B.get(&pk, MLP_PACK_SIZE));
+    HIP_TRY(B.get(&X, (size_t)n * 27));
+    HIP_TRY(B.get(&T, (size_t)n * 4));
+    HIP_TRY(B.get(&idx, (size_t)n));
+    HIP_TRY(B.get(&part, (size_t)nw * MLP_NPARAM));
+    HIP_TRY(B.get(&ploss, (size_t)nw));
+    HIP_TRY(B.get(&g, MLP_NPARAM));
+    HIP_TRY(B.get(&losses, (size_t)nbat));
+    HIP_TRY(hipMemsetAsync(M, 0, MLP_NPARAM * 4, st));
+    HIP_TRY(hipMemsetAsync(V, 0, MLP_NPARAM * 4, st));
+    HIP_TRY(hipMemcpyAsync(P, weights, MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(X, x, (size_t)n * 27 * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(T, y, (size_t)n * 16, hipMemcpyHostToDevice, st));
+    mlp_pack(P, pk, st);
+    // per-epoch shuffles from a seeded 64-bit linear congruential generator
+    std::vector<int32_t> perm((size_t)n);
+    std::vector<float> hl((size_t)nbat);
+    uint64_t rs = tp->seed * 6364136223846793005ull + 1442695040888963407ull;
+    int64_t t = 0;
+    for (int ep = 0; ep < tp->epochs; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+        for (int64_t i = n - 1; i > 0; --i) {
+            rs = rs * 6364136223846793005ull + 1442695040888963407ull;
+            const int64_t j = (int64_t)((rs >> 33) % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        HIP_TRY(hipMemcpyAsync(idx, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+        for (int b = 0; b < nbat; ++b) {
+            const int nb = (int)std::min<int64_t>(batch, n - (int64_t)b * batch);
+            mlp_grad(X, T, idx + (size_t)b * batch, nb, 1.0f / (float)nb, P, pk, MLP_GPW, part, ploss,
+                     (nb + 16 * MLP_GPW - 1) / (16 * MLP_GPW), g, losses + b, st);
+            ++t;
+            const float c1 = (float)(1.0 - std::pow(tp->beta1, (double)t));
+            const float c2 = (float)(1.0 - std::pow(tp->beta2, (double)t));
+            mlp_adam(P, M, V, g, (float)tp->lr, (float)tp->beta1, (float)tp->beta2, (float)tp->eps, c1, c2, pk, st);
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hl.data(), losses, (size_t)nbat * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (epoch_loss) {
+            double s = 0.0;
+            for (int b = 0; b < nbat; ++b) s += hl[b];
+            epoch_loss[ep] = (float)(s / nbat);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(weights, P, MLP_NPARAM * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return FSL_OK;
+}
+
+FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n, float *y, void *hip_stream)
+{
+    if (!weights || !x || !y || n <= 0 || n > (1 << 30)) return fail(FSL_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBufs B;
+    float *P, *X, *Y;
+    uint16_t *pk;
+    HIP_TRY(B.get(&P, MLP_NPARAM));
+    HIP_TRY(B.get(&pk, MLP_PACK_SIZE));
+    HIP_TRY(B.get(&X, (size_t)n * 27));
+    HIP_TRY(B.get(&Y, (size_t)n * 4));
+    HIP_TRY(hipMemcpyAsync(P, weights, MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(X, x, (size_t)n * 27 * 4, hipMemcpyHostToDevice, st));
+    mlp_pack(P, pk, st);
+    mlp_infer(X, (int)n, P, pk, Y, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(y, Y, (size_t)n * 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return FSL_OK;
+}
+
 const char *fsl_last_error(void) { return g_err.c_str(); }
 
 void fsl_destroy(FslLattice *L)
@@ -763,6 +1002,9 @@ void fsl_destroy(FslLattice *L)
         (void)hipEventDestroy(p.second);
     }
     if (L->sph_dev) (void)hipFree(L->sph_dev);
+    if (L->bb_dev) (void)hipFree(L->bb_dev);
+    if (L->mlpP) (void)hipFree(L->mlpP);
+    if (L->mlpPk) (void)hipFree(L->mlpPk);
     delete L;
 }
 

@@ -23,9 +23,13 @@ struct Dev {
     uint32_t *mark;           // conversion marks, epoch << 8 | bits
     int32_t *owner;           // owning sphere of a solid cell, -1 otherwise
     uint8_t *flags;           // cell type (2 bits) | near-solid bit
+    uint32_t *smask;          // bit j: the source x - c_j is solid or beyond a wall
+    int32_t *bbslot;          // record of a cell's moving-wall bounce-back terms, -1: none
+    void *bbterm;             // records of 32 terms (Real type), one per cell with sphere links
     int32_t *list[2];         // interface cells, current / next step
     int32_t *lnew;            // cells that become interface cells this step
-    int32_t *cnt;             // [0],[1] list lengths, [2] lnew length
+    int32_t *cnt;             // [0],[1] list lengths, [2] lnew length, [3] highest fluid z,
+                              // [4] bounce-back records
     unsigned long long *stats;  // conversion counters
     const double *sph;        // spheres: X[3], r, U[3], Omega[3]
     double *partial;          // reduction partials
@@ -34,6 +38,7 @@ struct Dev {
 };
 
 constexpr int BULK_THREADS = 256;
+constexpr int BULK_MAX_BLOCKS = 2048;
 constexpr int LIST_THREADS = 256;
 constexpr int RED_BLOCKS = 1024;
 

@@ -1,0 +1,538 @@
+// fsl_mlp.hip -- the learned interface estimator on gfx950: a 27 -> 64 ->
+// 64 -> 4 perceptron (tanh hidden layers) from the 3x3x3 fill stencil of an
+// interface cell to its normal (outputs 0..2, unnormalised) and 4 x mean
+// curvature (output 3).  BF16 weights and activations on the matrix cores
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation), FP32 master weights, Adam.
+//
+// Layout of the flat FP32 parameter vector (6212 floats):
+//   W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
+//
+// Matrix-core conventions (16x16x16 tile, lane l = r + 16 q):
+//   A (M x K): lane holds A[r][4q .. 4q+3]
+//   B (K x N): lane holds B[4q .. 4q+3][r]
+//   C (M x N): lane holds C[4q .. 4q+3][r]
+// Every layer is computed transposed, Z^T = W H^T, with samples along N: the
+// C tile of one layer (lane: sample r, features 4q..4q+3) is then exactly
+// the B operand of the next layer's K block, so activations never leave the
+// registers in the forward and backward passes.  Only the weight gradients
+// (a contraction over samples) need the activations transposed, via LDS.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fsl_device.h"
+#include "fsl_kernels.h"
+#include "fsl_mlp.h"
+
+namespace fsl {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// FP32 -> BF16 bits, round to nearest even
+__host__ __device__ __forceinline__ uint16_t bf16_bits(float x)
+{
+    uint32_t u;
+    __builtin_memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+__device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
+{
+    v4s v;
+    v[0] = (short)bf16_bits(a);
+    v[1] = (short)bf16_bits(b);
+    v[2] = (short)bf16_bits(c);
+    v[3] = (short)bf16_bits(d);
+    return v;
+}
+
+// 4 consecutive bf16 of a row-major bf16 matrix (8-byte aligned)
+__device__ __forceinline__ v4s ld4(const uint16_t *m)
+{
+    return *(const v4s *)m;
+}
+
+// ---------------------------------------------------------------- packing
+// Packed BF16 copies of the weights, each laid out as the A operand it feeds:
+//   W1p [64][32] (inputs padded), W2p [64][64], W3p [16][64] (outputs padded),
+//   W2t [64][64] = W2^T, W3t [64][16] = W3^T (padded)
+__global__ void k_mlp_pack(const float *P, uint16_t *pk)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MLP_PACK_SIZE) return;
+    float v = 0.f;
+    if (i < MLP_W2P) {                         // W1p
+        const int m = i / 32, k = i % 32;
+        v = k < 27 ? P[MLP_OFF_W1 + m * 27 + k] : 0.f;
+    } else if (i < MLP_W3P) {                  // W2p
+        const int t = i - MLP_W2P;
+        v = P[MLP_OFF_W2 + t];
+    } else if (i < MLP_W2T) {                  // W3p
+        const int t = i - MLP_W3P, m = t / 64, k = t % 64;
+        v = m < 4 ? P[MLP_OFF_W3 + m * 64 + k] : 0.f;
+    } else if (i < MLP_W3T) {                  // W2t[m][k] = W2[k][m]
+        const int t = i - MLP_W2T, m = t / 64, k = t % 64;
+        v = P[MLP_OFF_W2 + k * 64 + m];
+    } else {                                   // W3t[m][k] = W3[k][m]
+        const int t = i - MLP_W3T, m = t / 16, k = t % 16;
+        v = k < 4 ? P[MLP_OFF_W3 + k * 64 + m] : 0.f;
+    }
+    pk[i] = bf16_bits(v);
+}
+
+// ---------------------------------------------------------------- forward
+struct Fwd {
+    float h1[4][4], h2[4][4];  // [tile][j]: sample r, feature 16 t + 4 q + j
+    v4s h1b[4], h2b[4];
+    float y[4];                // lane q == 0: outputs 0..3 of sample r
+};
+
+// forward pass of 16 samples; xb[kt]: B operand of the inputs (K block kt)
+__device__ __forceinline__ void mlp_forward16(const uint16_t *sW, const float *P, const v4s xb[2], Fwd &F)
+{
+    const int l = __lane_id(), r = l & 15, q = l >> 4;
+    const uint16_t *W1p = sW, *W2p = sW + MLP_W2P, *W3p = sW + MLP_W3P;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) acc = mfma(ld4(W1p + (16 * mt + r) * 32 + 16 * kt + 4 * q), xb[kt], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) F.h1[mt][j] = tanhf(acc[j] + P[MLP_OFF_B1 + 16 * mt + 4 * q + j]);
+        F.h1b[mt] = pack4(F.h1[mt][0], F.h1[mt][1], F.h1[mt][2], F.h1[mt][3]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) acc = mfma(ld4(W2p + (16 * mt + r) * 64 + 16 * kt + 4 * q), F.h1b[kt], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) F.h2[mt][j] = tanhf(acc[j] + P[MLP_OFF_B2 + 16 * mt + 4 * q + j]);
+        F.h2b[mt] = pack4(F.h2[mt][0], F.h2[mt][1], F.h2[mt][2], F.h2[mt][3]);
+    }
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) acc = mfma(ld4(W3p + r * 64 + 16 * kt + 4 * q), F.h2b[kt], acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) F.y[j] = q == 0 ? acc[j] + P[MLP_OFF_B3 + j] : 0.f;
+}
+
+// stage the packed weights of one workgroup in LDS
+__device__ __forceinline__ void load_weights(uint16_t *sW, const uint16_t *pk, int n)
+{
+    const uint32_t *s = (const uint32_t *)pk;
+    uint32_t *d = (uint32_t *)sW;
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) d[i] = s[i];
+}
+
+// ---------------------------------------------------------------- training
+// Loss gradient of a batch: each single-wave workgroup takes groups of 16
+// samples (sample ids idx[...]), accumulates the weight gradients of its
+// groups in matrix-core accumulators and writes one partial gradient; the
+// partials are summed in a fixed order by k_mlp_reduce.
+__global__ __launch_bounds__(64) void k_mlp_grad(const float *X, const float *T, const int32_t *idx,
+                                                 int nbatch, float inv_n, const float *P,
+                                                 const uint16_t *pk, int groups_per_wave,
+                                                 float *partial, float *partial_loss)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_PACK_SIZE];
+    __shared__ __attribute__((aligned(16))) uint16_t sX[32 * 16], sH1[64 * 16], sH2[64 * 16],
+        sD1[64 * 16], sD2[64 * 16], sDY[16 * 16];
+    load_weights(sW, pk, MLP_PACK_SIZE);
+    __syncthreads();
+    const uint16_t *W2t = sW + MLP_W2T, *W3t = sW + MLP_W3T;
+    const int l = __lane_id(), r = l & 15, q = l >> 4;
+
+    v4f gW1[4][2], gW2[4][4], gW3[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW3[a] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 2; ++b) gW1[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; ++b) gW2[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    float gb1[4][4] = {}, gb2[4][4] = {}, gb3[4] = {}, loss = 0.f;
+
+    for (int g = 0; g < groups_per_wave; ++g) {
+        const int s = (blockIdx.x * groups_per_wave + g) * 16 + r;
+        const bool valid = s < nbatch;
+        const int sid = valid ? idx[s] : 0;
+        // inputs: clamp(phi) - 1/2, features 16 kt + 4 q + j
+        v4s xb[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * kt + 4 * q + j;
+                float x = (valid && k < 27) ? X[(size_t)sid * 27 + k] : 0.5f;
+                x = fminf(fmaxf(x, 0.f), 1.f) - 0.5f;
+                v[j] = (valid && k < 27) ? x : 0.f;
+                sX[k * 16 + r] = bf16_bits(v[j]);
+            }
+            xb[kt] = pack4(v[0], v[1], v[2], v[3]);
+        }
+        Fwd F;
+        mlp_forward16(sW, P, xb, F);
+        // output gradient (lanes q == 0 own sample r's four outputs)
+        float dy[4] = {0.f, 0.f, 0.f, 0.f};
+        if (q == 0 && valid) {
+            const float *t = T + (size_t)sid * 4;
+            const float rn = sqrtf(F.y[0] * F.y[0] + F.y[1] * F.y[1] + F.y[2] * F.y[2]);
+            float nh[3], e[3];
+            for (int a = 0; a < 3; ++a) {
+                nh[a] = F.y[a] / rn;
+                e[a] = nh[a] - t[a];
+            }
+            const float en = e[0] * nh[0] + e[1] * nh[1] + e[2] * nh[2];
+            const float ek = F.y[3] - 4.f * t[3];
+            for (int a = 0; a < 3; ++a) dy[a] = 2.f * (e[a] - nh[a] * en) / rn * inv_n;
+            dy[3] = 2.f * ek * inv_n;
+            loss += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + ek * ek;
+        }
+        const v4s dyb = pack4(dy[0], dy[1], dy[2], dy[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sDY[(4 * q + j) * 16 + r] = bf16_bits(dy[j]);
+            gb3[j] += dy[j];
+        }
+        // dH2^T = W3^T dY^T, dZ2 = dH2 (1 - H2^2)
+        v4s d2b[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma(ld4(W3t + (16 * mt + r) * 16 + 4 * q), dyb, acc);
+            float dz[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dz[j] = valid ? acc[j] * (1.f - F.h2[mt][j] * F.h2[mt][j]) : 0.f;
+                gb2[mt][j] += dz[j];
+                sD2[(16 * mt + 4 * q + j) * 16 + r] = bf16_bits(dz[j]);
+                sH1[(16 * mt + 4 * q + j) * 16 + r] = bf16_bits(valid ? F.h1[mt][j] : 0.f);
+                sH2[(16 * mt + 4 * q + j) * 16 + r] = bf16_bits(valid ? F.h2[mt][j] : 0.f);
+            }
+            d2b[mt] = pack4(dz[0], dz[1], dz[2], dz[3]);
+        }
+        // dH1^T = W2^T dZ2^T, dZ1 = dH1 (1 - H1^2)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) acc = mfma(ld4(W2t + (16 * mt + r) * 64 + 16 * kt + 4 * q), d2b[kt], acc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float dz = valid ? acc[j] * (1.f - F.h1[mt][j] * F.h1[mt][j]) : 0.f;
+                gb1[mt][j] += dz;
+                sD1[(16 * mt + 4 * q + j) * 16 + r] = bf16_bits(dz);
+            }
+        }
+        __syncthreads();
+        // weight gradients, contracted over the 16 samples of the group:
+        // dW = dZ^T H with A rows = output features, B rows = input features
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const v4s a1 = ld4(sD1 + (16 * mt + r) * 16 + 4 * q);
+            const v4s a2 = ld4(sD2 + (16 * mt + r) * 16 + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) gW1[mt][nt] = mfma(a1, ld4(sX + (16 * nt + r) * 16 + 4 * q), gW1[mt][nt]);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) gW2[mt][nt] = mfma(a2, ld4(sH1 + (16 * nt + r) * 16 + 4 * q), gW2[mt][nt]);
+        }
+        const v4s a3 = ld4(sDY + r * 16 + 4 * q);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) gW3[nt] = mfma(a3, ld4(sH2 + (16 * nt + r) * 16 + 4 * q), gW3[nt]);
+        __syncthreads();
+    }
+
+    // bias sums over the 16 samples held by lanes r = 0..15 of each q
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                gb1[a][j] += __shfl_xor(gb1[a][j], off);
+                gb2[a][j] += __shfl_xor(gb2[a][j], off);
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gb3[j] += __shfl_xor(gb3[j], off);
+        loss += __shfl_xor(loss, off);
+    }
+    float *out = partial + (size_t)blockIdx.x * MLP_NPARAM;
+    // C layout: lane holds rows 4q + j (output feature), column r (input feature)
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = 16 * mt + 4 * q + j;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int k = 16 * nt + r;
+                if (k < 27) out[MLP_OFF_W1 + m * 27 + k] = gW1[mt][nt][j];
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) out[MLP_OFF_W2 + m * 64 + 16 * nt + r] = gW2[mt][nt][j];
+            if (r == 0) {
+                out[MLP_OFF_B1 + m] = gb1[mt][j];
+                out[MLP_OFF_B2 + m] = gb2[mt][j];
+            }
+        }
+    }
+    if (q == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) out[MLP_OFF_W3 + j * 64 + 16 * nt + r] = gW3[nt][j];
+        if (r == 0) {
+            for (int j = 0; j < 4; ++j) out[MLP_OFF_B3 + j] = gb3[j];
+            partial_loss[blockIdx.x] = loss * inv_n;
+        }
+    }
+}
+
+// grad[i] = sum over waves of partial[w][i], fixed order
+__global__ void k_mlp_reduce(const float *partial, const float *partial_loss, int nwaves, float *grad,
+                             float *loss)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < MLP_NPARAM) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += partial[(size_t)w * MLP_NPARAM + i];
+        grad[i] = s;
+    }
+    if (i == 0) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += partial_loss[w];
+        *loss = s;
+    }
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master weights
+__global__ void k_mlp_adam(float *P, float *m, float *v, const float *g, float lr, float b1, float b2,
+                           float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MLP_NPARAM) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------- inference
+// batch inference: 16 samples per wave iteration
+__global__ __launch_bounds__(64) void k_mlp_infer(const float *X, int n, const float *P, const uint16_t *pk,
+                                                  float *Y)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_PACK_SIZE];
+    load_weights(sW, pk, MLP_W2T);  // forward weights only
+    __syncthreads();
+    const int l = __lane_id(), r = l & 15, q = l >> 4;
+    for (int g = blockIdx.x; g * 16 < n; g += gridDim.x) {
+        const int s = g * 16 + r;
+        const bool valid = s < n;
+        v4s xb[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * kt + 4 * q + j;
+                const float x = (valid && k < 27) ? X[(size_t)s * 27 + k] : 0.5f;
+                v[j] = (valid && k < 27) ? fminf(fmaxf(x, 0.f), 1.f) - 0.5f : 0.f;
+            }
+            xb[kt] = pack4(v[0], v[1], v[2], v[3]);
+        }
+        Fwd F;
+        mlp_forward16(sW, P, xb, F);
+        if (q == 0 && valid)
+            for (int j = 0; j < 4; ++j) Y[(size_t)s * 4 + j] = F.y[j];
+    }
+}
+
+// ---------------------------------------------------------------- lattice
+__device__ __forceinline__ int nb_cell(const Dev &d, int x, int y, int z, int i)
+{
+    const int zz = z + cz(i);
+    if (zz < 0 || zz >= d.nz) return -1;
+    const int xx = cx(i) == 1 ? wrap_p(x, d.nx) : (cx(i) == -1 ? wrap_m(x, d.nx) : x);
+    const int yy = cy(i) == 1 ? wrap_p(y, d.ny) : (cy(i) == -1 ? wrap_m(y, d.ny) : y);
+    return xx + d.nx * (yy + d.ny * zz);
+}
+
+// Interface normal and curvature with the learned estimator: per group of 16
+// interface cells, lanes q == 0 gather the fill stencil (liquid 1, gas 0,
+// interface clamp(m/rho), wall/solid = centre), compute the finite-
+// difference estimate, and the wavefront runs the network.  The network's
+// result replaces the finite-difference one unless a stencil cell is solid,
+// |n_raw| lies outside [0.5, 2], the two normals differ by more than 30
+// degrees, or |kappa| > 0.5.
+template <class R>
+__global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *P, const uint16_t *pk)
+{
+    using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+    __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_PACK_SIZE];
+    __shared__ float sS[16][28];
+    load_weights(sW, pk, MLP_W2T);
+    __syncthreads();
+    const int32_t *list = d.list[which];
+    const int count = d.cnt[which];
+    const int l = __lane_id(), r = l & 15, q = l >> 4;
+    for (int g = blockIdx.x; g * 16 < count; g += gridDim.x) {
+        const int t = g * 16 + r;
+        const bool valid = t < count;
+        bool any_solid = false;
+        R fd[4] = {R(0), R(0), R(0), R(0)};
+        int c = 0;
+        if (q == 0 && valid) {
+            c = list[t];
+            const int x = c % d.nx, y = (c / d.nx) % d.ny, z = c / (d.nx * d.ny);
+            double pv = d.phi[c];
+            const R centre = R(pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv));
+            R s[27];
+            for (int i = 0; i < 27; ++i) {
+                if (i == REST) {
+                    s[i] = centre;
+                    continue;
+                }
+                const int yc = nb_cell(d, x, y, z, i);
+                uint8_t ty = yc < 0 ? (uint8_t)T_SOLID : (uint8_t)(d.flags[yc] & T_MASK);
+                if (ty == T_SOLID) {
+                    any_solid = true;
+                    s[i] = centre;
+                } else if (ty == T_LIQ) {
+                    s[i] = R(1);
+                } else if (ty == T_GAS) {
+                    s[i] = R(0);
+                } else {
+                    double v = d.phi[yc];
+                    s[i] = R(v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v));
+                }
+            }
+            for (int i = 0; i < 27; ++i) sS[r][i] = (float)s[i];
+            // finite-difference estimate (Parker-Youngs normal, Hessian curvature)
+            const R W[3] = {R(1), R(2), R(1)};
+            R gx = R(0), gy = R(0), gz = R(0);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const R w = W[a] * W[b];
+                    gx += w * (s[MI(2, a, b)] - s[MI(0, a, b)]);
+                    gy += w * (s[MI(a, 2, b)] - s[MI(a, 0, b)]);
+                    gz += w * (s[MI(a, b, 2)] - s[MI(a, b, 0)]);
+                }
+            gx /= R(32);
+            gy /= R(32);
+            gz /= R(32);
+            const R gn = sqrt(gx * gx + gy * gy + gz * gz);
+            if (gn >= R(1e-12)) {
+                const R hx = gx / gn, hy = gy / gn, hz = gz / gn;
+                const R c0 = s[MI(1, 1, 1)];
+                const R Hxx = s[MI(2, 1, 1)] - R(2) * c0 + s[MI(0, 1, 1)];
+                const R Hyy = s[MI(1, 2, 1)] - R(2) * c0 + s[MI(1, 0, 1)];
+                const R Hzz = s[MI(1, 1, 2)] - R(2) * c0 + s[MI(1, 1, 0)];
+                const R Hxy = R(0.25) * (s[MI(2, 2, 1)] - s[MI(2, 0, 1)] - s[MI(0, 2, 1)] + s[MI(0, 0, 1)]);
+                const R Hxz = R(0.25) * (s[MI(2, 1, 2)] - s[MI(2, 1, 0)] - s[MI(0, 1, 2)] + s[MI(0, 1, 0)]);
+                const R Hyz = R(0.25) * (s[MI(1, 2, 2)] - s[MI(1, 2, 0)] - s[MI(1, 0, 2)] + s[MI(1, 0, 0)]);
+                const R tr = Hxx + Hyy + Hzz;
+                const R gHg = hx * hx * Hxx + hy * hy * Hyy + hz * hz * Hzz
+                              + R(2) * (hx * hy * Hxy + hx * hz * Hxz + hy * hz * Hyz);
+                fd[0] = -hx;
+                fd[1] = -hy;
+                fd[2] = -hz;
+                fd[3] = -(tr - gHg) / (R(2) * gn);
+            }
+        } else if (q == 0) {
+            for (int i = 0; i < 27; ++i) sS[r][i] = 0.5f;
+        }
+        __syncthreads();
+        v4s xb[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * kt + 4 * q + j;
+                v[j] = k < 27 ? sS[r][k] - 0.5f : 0.f;
+            }
+            xb[kt] = pack4(v[0], v[1], v[2], v[3]);
+        }
+        Fwd F;
+        mlp_forward16(sW, P, xb, F);
+        __syncthreads();
+        if (q == 0 && valid) {
+            R4 out;
+            out.x = fd[0];
+            out.y = fd[1];
+            out.z = fd[2];
+            out.w = fd[3];
+            const float rn = sqrtf(F.y[0] * F.y[0] + F.y[1] * F.y[1] + F.y[2] * F.y[2]);
+            bool use = !any_solid && rn >= 0.5f && rn <= 2.f;
+            const float kap = 0.25f * F.y[3];
+            if (use) {
+                const float cosang = ((float)fd[0] * F.y[0] + (float)fd[1] * F.y[1] + (float)fd[2] * F.y[2]) / rn;
+                use = cosang >= 0.8660254f && fabsf(kap) <= 0.5f;
+            }
+            if (use) {
+                out.x = R(F.y[0] / rn);
+                out.y = R(F.y[1] / rn);
+                out.z = R(F.y[2] / rn);
+                out.w = R(kap);
+            }
+            ((R4 *)d.geom)[c] = out;
+            atomicAdd(&d.stats[use ? 8 : 9], 1ull);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+void mlp_pack(const float *P, uint16_t *pk, hipStream_t st)
+{
+    k_mlp_pack<<<(MLP_PACK_SIZE + 255) / 256, 256, 0, st>>>(P, pk);
+}
+
+void mlp_grad(const float *X, const float *T, const int32_t *idx, int nbatch, float inv_n, const float *P,
+              const uint16_t *pk, int groups_per_wave, float *partial, float *partial_loss, int nwaves,
+              float *grad, float *loss, hipStream_t st)
+{
+    k_mlp_grad<<<nwaves, 64, 0, st>>>(X, T, idx, nbatch, inv_n, P, pk, groups_per_wave, partial, partial_loss);
+    k_mlp_reduce<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(partial, partial_loss, nwaves, grad, loss);
+}
+
+void mlp_adam(float *P, float *m, float *v, const float *g, float lr, float b1, float b2, float eps, float c1,
+              float c2, uint16_t *pk, hipStream_t st)
+{
+    k_mlp_adam<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(P, m, v, g, lr, b1, b2, eps, c1, c2);
+    mlp_pack(P, pk, st);
+}
+
+void mlp_infer(const float *X, int n, const float *P, const uint16_t *pk, float *Y, hipStream_t st)
+{
+    int blocks = (n + 15) / 16;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_mlp_infer<<<blocks, 64, 0, st>>>(X, n, P, pk, Y);
+}
+
+template <class R>
+void launch_geom_mlp(const Dev &d, int which, int blocks, const float *P, const uint16_t *pk, hipStream_t st)
+{
+    k_geom_mlp<R><<<blocks, 64, 0, st>>>(d, which, P, pk);
+}
+template void launch_geom_mlp<double>(const Dev &, int, int, const float *, const uint16_t *, hipStream_t);
+template void launch_geom_mlp<float>(const Dev &, int, int, const float *, const uint16_t *, hipStream_t);
+
+}  // namespace fsl

@@ -17,6 +17,7 @@
 //             fill stencil.
 #include "fsl_device.h"
 #include "fsl_kernels.h"
+#include "fsl_mlp.h"
 
 namespace fsl {
 
@@ -68,88 +69,155 @@ __device__ __forceinline__ R bb_term(const Dev &d, int s, int j, const Cell &p)
 }
 
 // ---------------------------------------------------------------- dense step
-// Block -> (x-block, row).  With xcd_map, hardware block b runs on XCD
-// b % 8; XCD k then works through whole rows k, k+8, k+16, ... so that the
-// x-blocks of one row (which share cache lines at their edges) meet in the
-// same L2, while the liquid/gas split in z stays balanced over the XCDs.
-__device__ __forceinline__ void bulk_block(const Dev &d, int &bx, int &row)
+// load / store of direction i at 32-bit element offset e from a per-direction
+// base that is uniform over the wavefront (scalar base + one vector offset)
+template <class S>
+__device__ __forceinline__ typename Real<S>::type ld_at(const S *base, uint32_t e)
 {
-    const int b = blockIdx.x;
-    if (d.xcd_map) {
-        const int k = b & 7, s = b >> 3;
-        row = k + 8 * (s / d.nbx);
-        bx = s % d.nbx;
-    } else {
-        row = b / d.nbx;
-        bx = b % d.nbx;
-    }
+    return ld((const S *)((const char *)base + e * (uint32_t)sizeof(S)));
+}
+template <class S>
+__device__ __forceinline__ void st_at(S *base, uint32_t e, S v)
+{
+    *(S *)((char *)base + e * (uint32_t)sizeof(S)) = v;
 }
 
+// one liquid cell of the dense step
 template <class S>
-__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
+__device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
+                                          int x, int row)
 {
     using R = typename Real<S>::type;
-    const S *__restrict__ src = (const S *)d.pdf[p];
-    S *__restrict__ dst = (S *)d.pdf[p ^ 1];
-    int bx, row;
-    bulk_block(d, bx, row);
-    const int x = bx * BULK_THREADS + (int)threadIdx.x;
     if (x >= d.nx) return;
-    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
     const size_t N = (size_t)d.N;
     const int y = row % ny, z = row / ny;
     const int c = x + nx * (y + ny * z);
     const uint8_t fl = d.flags[c];
     if ((fl & T_MASK) != T_LIQ) return;
 
-    // source coordinate x - c_i for c_i = -1, 0, +1 (z clamped; the wall
-    // layers are near-solid cells and are fixed below)
-    const int xs[3] = {wrap_p(x, nx), x, wrap_m(x, nx)};
-    const int ys[3] = {wrap_p(y, ny), y, wrap_m(y, ny)};
-    const int zs[3] = {z < nz - 1 ? z + 1 : z, z, z > 0 ? z - 1 : z};
+    // element offset of the source x - c_i relative to c, per axis and sign
+    // (periodic in x and y; z clamped -- the wall layers are near-solid cells
+    // whose wall links are replaced below)
+    const int DX[3] = {x == nx - 1 ? 1 - nx : 1, 0, x == 0 ? nx - 1 : -1};
+    const int DY[3] = {y == ny - 1 ? (1 - ny) * nx : nx, 0, y == 0 ? (ny - 1) * nx : -nx};
+    const int DZ[3] = {z == nz - 1 ? 0 : nxy, 0, z == 0 ? 0 : -nxy};
     R f[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int s = xs[i % 3] + nx * (ys[(i / 3) % 3] + ny * zs[i / 9]);
-        f[i] = ld(src + (size_t)i * N + s);
-    }
+    for (int i = 0; i < 27; ++i)
+        f[i] = ld_at(src + (size_t)i * N, (uint32_t)(c + DX[i % 3] + DY[(i / 3) % 3] + DZ[i / 9]));
+
+    double in_sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < 27; ++j)
+        if (j != REST) in_sum += (double)f[j];
 
     uint32_t solid = 0;
     if (fl & F_NEAR_SOLID) {
-        const Cell pc = {x, y, z};
+        // links whose source is solid or beyond a wall bounce back; the
+        // moving-wall terms of sphere links are precomputed per cell
+        solid = d.smask[c];
+        const int slot = d.bbslot[c];
+        const R *rec = (const R *)d.bbterm + (size_t)(slot < 0 ? 0 : slot) * 32;
+        double excl = 0.0;
 #pragma unroll
         for (int j = 0; j < 27; ++j) {
-            if (j == REST) continue;
-            const int sz = z - cz(j);
-            const bool wall = sz < 0 || sz >= nz;
-            const int s = xs[j % 3] + nx * (ys[(j / 3) % 3] + ny * (wall ? z : sz));
-            if (wall || (d.flags[s] & T_MASK) == T_SOLID) {
-                solid |= 1u << j;
-                R v = ld(src + (size_t)opp(j) * N + c);
-                if (!wall) v += bb_term<R>(d, s, j, pc);
-                f[j] = v;
-            }
+            if (j == REST || !((solid >> j) & 1u)) continue;
+            excl += (double)f[j];
+            R v = ld_at(src + (size_t)opp(j) * N, (uint32_t)c);
+            if (slot >= 0) v += rec[j];
+            f[j] = v;
         }
-    }
-
-    // mass: m' = (m - own outgoing) + incoming, over non-solid links
-    double m = d.mq[c];
-#pragma unroll
-    for (int j = 0; j < 27; ++j) {
-        if (j == REST) continue;
-        m += ((solid >> j) & 1u) ? 0.0 : (double)f[j];
+        in_sum -= excl;
     }
 
     collide<R>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz));
 
-    double out = 0.0;
+    double out_sum = 0.0, out_excl = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const S v = to_store<S, R>(f[i]);
-        dst[(size_t)i * N + c] = v;
-        if (i != REST && !((solid >> opp(i)) & 1u)) out += (double)ld(&v);
+        st_at(dst + (size_t)i * N, (uint32_t)c, v);
+        if (i != REST) out_sum += (double)ld(&v);
+        if (i != REST && ((solid >> opp(i)) & 1u)) out_excl += (double)ld(&v);
     }
-    d.mq[c] = m - out;
+    // liquid cells keep m - own outgoing: m' = (m - out) + in over non-solid links
+    d.mq[c] = (d.mq[c] + in_sum) - (out_sum - out_excl);
+}
+
+// Dense step over the rows (y, z) up to the highest fluid row; each block
+// walks over 256-cell row segments.  With xcd_map, hardware block b runs on
+// XCD b % 8 and takes whole rows k, k+8, k+16, ... of that XCD, so the
+// segments of one row (which share cache lines at their edges) meet in one
+// L2 while the liquid/gas split in z stays balanced over the XCDs.
+template <class S>
+__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
+{
+    const S *__restrict__ src = (const S *)d.pdf[p];
+    S *__restrict__ dst = (S *)d.pdf[p ^ 1];
+    const int rowmax = (d.cnt[3] + 1) * d.ny;
+    const int tx = (int)threadIdx.x;
+    if (d.xcd_map) {
+        const int k = blockIdx.x & 7, g8 = gridDim.x >> 3;
+        for (int s = blockIdx.x >> 3;; s += g8) {
+            const int row = k + 8 * (s / d.nbx);
+            if (row >= rowmax) break;
+            bulk_cell<S>(d, src, dst, (s % d.nbx) * BULK_THREADS + tx, row);
+        }
+    } else {
+        for (int it = blockIdx.x;; it += gridDim.x) {
+            const int row = it / d.nbx;
+            if (row >= rowmax) break;
+            bulk_cell<S>(d, src, dst, (it % d.nbx) * BULK_THREADS + tx, row);
+        }
+    }
+}
+
+// moving-wall bounce-back terms of every cell that has sphere links
+template <class R>
+__global__ void k_bb_terms(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    const int slot = d.bbslot[c];
+    if (slot < 0) return;
+    const Cell pc = cell_xyz(d, c);
+    const uint32_t sm = d.smask[c];
+    R *rec = (R *)d.bbterm + (size_t)slot * 32;
+    for (int j = 0; j < 32; ++j) {
+        R t = R(0);
+        if (j < 27 && j != REST && ((sm >> j) & 1u)) {
+            const int s = nb_of(d, pc, opp(j));
+            if (s >= 0) t = bb_term<R>(d, s, j, pc);
+        }
+        rec[j] = t;
+    }
+}
+
+// cells with at least one link into a sphere get a record slot
+__global__ void k_bb_slots(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    int slot = -1;
+    const uint32_t sm = d.smask[c];
+    if (sm != 0 && (d.flags[c] & T_MASK) != T_SOLID) {
+        const Cell pc = cell_xyz(d, c);
+        bool sphere = false;
+        for (int j = 0; j < 27 && !sphere; ++j)
+            if (j != REST && ((sm >> j) & 1u)) sphere = nb_of(d, pc, opp(j)) >= 0;
+        if (sphere) slot = atomicAdd(&d.cnt[4], 1);
+    }
+    d.bbslot[c] = slot;
+}
+
+// highest z that holds a liquid or interface cell
+__global__ void k_zmax(Dev d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    const uint8_t ty = d.flags[c] & T_MASK;
+    if (ty == T_LIQ || ty == T_IF) atomicMax(&d.cnt[3], c / (d.nx * d.ny));
 }
 
 // ---------------------------------------------------------------- interface
@@ -460,6 +528,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t e
         } else {
             c = d.lnew[t - ncur];
             d.flags[c] = (uint8_t)((d.flags[c] & ~T_MASK) | T_IF);
+            atomicMax(&d.cnt[3], c / (d.nx * d.ny));
         }
         if (keep) {
             const Cell pc = cell_xyz(d, c);
@@ -551,10 +620,12 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
 // ---------------------------------------------------------------- launchers
 template <class S>
 void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream_t st,
-                 hipEvent_t ev0, hipEvent_t ev1)
+                 hipEvent_t ev0, hipEvent_t ev1, const float *mlpP, const uint16_t *mlpPk)
 {
     using R = typename Real<S>::type;
-    const int gb = d.nbx * d.rows;
+    int gb = d.nbx * d.rows;
+    if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
+    if (d.xcd_map) gb &= ~7;
     if (ev0) (void)hipEventRecord(ev0, st);
     k_bulk<S><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
@@ -563,12 +634,18 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
     k_conv2<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv3<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv4<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_geom<R><<<list_blocks, LIST_THREADS, 0, st>>>(d, p ^ 1);
+    if (mlpP)
+        launch_geom_mlp<R>(d, p ^ 1, list_blocks, mlpP, mlpPk, st);
+    else
+        k_geom<R><<<list_blocks, LIST_THREADS, 0, st>>>(d, p ^ 1);
 }
 
-template void launch_step<double>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_step<float>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_step<_Float16>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+#define FSL_STEP_INST(S)                                                                          \
+    template void launch_step<S>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t, \
+                                 const float *, const uint16_t *);
+FSL_STEP_INST(double)
+FSL_STEP_INST(float)
+FSL_STEP_INST(_Float16)
 
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st)
@@ -577,5 +654,20 @@ void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st)
 }
 template void launch_geom<double>(const Dev &, int, int, hipStream_t);
 template void launch_geom<float>(const Dev &, int, int, hipStream_t);
+
+void launch_setup_links(const Dev &d, hipStream_t st)
+{
+    const int b = (d.N + 255) / 256;
+    k_bb_slots<<<b, 256, 0, st>>>(d);
+    k_zmax<<<b, 256, 0, st>>>(d);
+}
+
+template <class R>
+void launch_bb_terms(const Dev &d, hipStream_t st)
+{
+    k_bb_terms<R><<<(d.N + 255) / 256, 256, 0, st>>>(d);
+}
+template void launch_bb_terms<double>(const Dev &, hipStream_t);
+template void launch_bb_terms<float>(const Dev &, hipStream_t);
 
 }  // namespace fsl

@@ -26,7 +26,9 @@ GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 # every symbol declared in include/fsl.h
 EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fsl_step",
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
-           "fsl_timing_read", "fsl_last_error", "fsl_destroy")
+           "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
+           "fsl_set_estimator", "fsl_estimator_stats", "fsl_last_error", "fsl_destroy")
+MLP_NPARAM = 6212
 
 
 class FslError(RuntimeError):
@@ -45,6 +47,12 @@ class FslParams(ctypes.Structure):
         ("normals", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
+
+
+class FslTrainParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 def make_params(shape, precision="fp64", omega=1.0, accel=(0.0, 0.0, 0.0), sigma=0.0,
@@ -95,6 +103,17 @@ def lib():
         L.fsl_timing.argtypes = [vp, i32]
         L.fsl_timing_read.restype = ctypes.c_int
         L.fsl_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.fsl_estimator_train.restype = ctypes.c_int
+        L.fsl_estimator_train.argtypes = [fp, fp, ctypes.c_int64, ctypes.POINTER(FslTrainParams), fp, fp, vp]
+        L.fsl_estimator_grad.restype = ctypes.c_int
+        L.fsl_estimator_grad.argtypes = [fp, fp, fp, ctypes.c_int64, fp, dp, vp]
+        L.fsl_estimator_infer.restype = ctypes.c_int
+        L.fsl_estimator_infer.argtypes = [fp, fp, ctypes.c_int64, fp, vp]
+        L.fsl_set_estimator.restype = ctypes.c_int
+        L.fsl_set_estimator.argtypes = [vp, fp]
+        L.fsl_estimator_stats.restype = ctypes.c_int
+        L.fsl_estimator_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.fsl_last_error.restype = ctypes.c_char_p
         L.fsl_last_error.argtypes = []
         L.fsl_destroy.restype = None
@@ -114,6 +133,20 @@ def _dp(a):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def workspace_bytes(params: FslParams) -> int:
@@ -215,6 +248,16 @@ class Lattice:
     def timing(self, enable):
         _check(lib().fsl_timing(self.h, 1 if enable else 0))
 
+    def set_estimator(self, weights):
+        w = _f32(weights)
+        assert w.size == MLP_NPARAM
+        _check(lib().fsl_set_estimator(self.h, _fp(w)))
+
+    def estimator_stats(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fsl_estimator_stats(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def timing_read(self):
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().fsl_timing_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
@@ -235,3 +278,33 @@ def lattice_from_workload(w, precision="fp64", check_every=0, **overrides):
     if len(w.radius):
         lat.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
     return lat
+
+
+# ---------------------------------------------------------------- estimator
+def estimator_train(x, y, weights, epochs=10, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999,
+                    eps=1e-8, seed=0):
+    """Train the interface estimator on the GPU; returns (weights, epoch losses)."""
+    x, y, w = _f32(x), _f32(y), _f32(weights).copy()
+    n = x.size // 27
+    assert x.size == 27 * n and y.size == 4 * n and w.size == MLP_NPARAM
+    tp = FslTrainParams(int(epochs), int(batch), lr, beta1, beta2, eps, int(seed))
+    losses = np.zeros(int(epochs), dtype=np.float32)
+    _check(lib().fsl_estimator_train(_fp(x), _fp(y), n, ctypes.byref(tp), _fp(w), _fp(losses), _stream()))
+    return w, losses
+
+
+def estimator_grad(weights, x, y):
+    x, y, w = _f32(x), _f32(y), _f32(weights)
+    n = x.size // 27
+    g = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(lib().fsl_estimator_grad(_fp(w), _fp(x), _fp(y), n, _fp(g), ctypes.byref(loss), _stream()))
+    return g, loss.value
+
+
+def estimator_infer(weights, x):
+    x, w = _f32(x), _f32(weights)
+    n = x.size // 27
+    y = np.zeros(4 * n, dtype=np.float32)
+    _check(lib().fsl_estimator_infer(_fp(w), _fp(x), n, _fp(y), _stream()))
+    return y.reshape(n, 4)

@@ -46,7 +46,7 @@ def test_workspace_bytes(lib):
 
 
 @pytest.mark.parametrize("kw", [dict(omega=0.0), dict(omega=2.0), dict(conv_eps=-1.0),
-                                dict(rho_gas=0.0), dict(normals=1), dict(check_every=-1)])
+                                dict(rho_gas=0.0), dict(normals=2), dict(check_every=-1)])
 def test_bad_params_rejected(lib, kw):
     base = dict(shape=(16, 8, 8), precision="fp32", omega=1.5)
     base.update(kw)

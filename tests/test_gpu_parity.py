@@ -216,5 +216,8 @@ def test_argument_and_state_errors():
     # velocities alone may change
     g.set_particles(w.centre, w.radius, vel=np.full((len(w.radius), 3), 1e-4))
     with pytest.raises(f.FslError) as e:
-        g.set_particles(w.centre, np.full(len(w.radius), 5.0))
+        g.set_particles(w.centre, np.full(len(w.radius), 2.9))
     assert e.value.status == f.FSL_ERR_STATE
+    with pytest.raises(f.FslError) as e:
+        g.set_particles(w.centre, np.full(len(w.radius), 5.0))   # r >= ny/2
+    assert e.value.status == f.FSL_ERR_ARG
