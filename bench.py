@@ -75,6 +75,25 @@ def run_form(w, precision, steps, warmup):
     return res
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read + write counted), best of reps."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del a, b
+    return best
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle, single-threaded, on the same flume recipe cropped to
     128 x 40 x 192, for as many steps as fit in about seconds_target."""
@@ -136,6 +155,8 @@ def main():
         r = run_form(w, p, max(args.steps // 2, 10), min(args.warmup, 20))
         log("form:", json.dumps(r))
         forms[p] = r
+    copy_gbs = copy_bandwidth()
+    log("device copy bandwidth %.0f GB/s" % copy_gbs)
     cpu = None if args.no_cpu else cpu_baseline()
 
     r = main_res
@@ -151,7 +172,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r["bulk_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["bulk_gbs"] / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_bulk", "bytes_per_launch": r["bytes_per_launch"],
-                     "avg_launch_us": r["bulk_us"]},
+                     "avg_launch_us": r["bulk_us"], "copy_gbs": copy_gbs,
+                     "frac_of_copy": r["bulk_gbs"] / copy_gbs},
         "cpu_baseline": cpu,
         "mlups_all_cells": r["mlups_all"],
         "mass_drift": r["mass_drift"],

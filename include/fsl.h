@@ -177,11 +177,12 @@ FslStatus fsl_timing_read(FslLattice *lat, double *ms_total, int64_t *launches);
  * the 3x3x3 fill stencil) the library offers a small network: 27 fill levels
  * (input clamp(phi, 0, 1) - 1/2, stencil entry a + 3b + 9c = offset
  * (a-1, b-1, c-1)) -> 64 -> 64 -> 4 with tanh hidden layers; outputs 0..2
- * are an unnormalised normal (liquid -> gas), output 3 is 4 kappa.  Weights
+ * are the normal (liquid -> gas; trained towards the unit normal and
+ * normalised when used), output 3 is 4 kappa.  Weights
  * are 6212 floats: W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
  * (row-major, out x in).  Matrix products run in BF16 on the matrix cores
  * with FP32 accumulation; the master weights are FP32.
- * Loss per sample: |y[0..2]/|y[0..2]| - n*|^2 + (y[3] - 4 kappa*)^2, mean over
+ * Loss per sample: |y[0..2] - n*|^2 + (y[3] - 4 kappa*)^2, mean over
  * the batch.  Host arrays: x float [n][27] fill levels, y float [n][4] target
  * unit normal and kappa. */
 typedef struct {

@@ -15,9 +15,10 @@
  * Layout of the flat parameter vector (double, 6212 entries):
  *   W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
  * Input x_k = clamp(phi_k, 0, 1) - 1/2 in direction order (k = a+3b+9c for
- * the offset (a-1, b-1, c-1)).  Output y[0..2] is an unnormalised normal,
- * y[3] is 4 * kappa.  Loss per sample: |y[0..2]/|y[0..2]| - n*|^2 +
- * (y[3] - 4 kappa*)^2, averaged over the batch.
+ * the offset (a-1, b-1, c-1)).  Output y[0..2] is the normal (trained
+ * towards the unit normal, normalised when used), y[3] is 4 * kappa.  Loss
+ * per sample: |y[0..2] - n*|^2 + (y[3] - 4 kappa*)^2, averaged over the
+ * batch.
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,19 +76,12 @@ double ol_mlp_loss_grad(const double *P, int32_t n, const double *x, const doubl
     for (int32_t s = 0; s < n; ++s) {
         const double *xs = x + (size_t)s * NIN, *t = target + (size_t)s * NOUT;
         forward_one(P, xs, h1, h2, y);
-        double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-        double nh[3], e[3];
-        for (int a = 0; a < 3; ++a) {
-            nh[a] = y[a] / r;
-            e[a] = nh[a] - t[a];
-        }
-        double ek = y[3] - 4.0 * t[3];
-        loss += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + ek * ek;
+        double e[4];
+        for (int a = 0; a < 3; ++a) e[a] = y[a] - t[a];
+        e[3] = y[3] - 4.0 * t[3];
+        loss += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + e[3] * e[3];
         if (!grad) continue;
-        /* d/dy of |y/|y| - t|^2: (I - nh nh^T) 2e / |y| */
-        double en = e[0] * nh[0] + e[1] * nh[1] + e[2] * nh[2];
-        for (int a = 0; a < 3; ++a) dy[a] = 2.0 * (e[a] - nh[a] * en) / r / n;
-        dy[3] = 2.0 * ek / n;
+        for (int a = 0; a < 4; ++a) dy[a] = 2.0 * e[a] / n;
         for (int j = 0; j < NOUT; ++j) {
             grad[OFF_B3 + j] += dy[j];
             for (int k = 0; k < NH; ++k) grad[OFF_W3 + j * NH + k] += dy[j] * h2[k];

@@ -37,6 +37,12 @@ __device__ __forceinline__ uint32_t mark_bits(uint32_t mk, uint32_t epoch)
 // Real<S>::type.
 template <class S> struct Real { using type = float; };
 template <> struct Real<double> { using type = double; };
+// type of the equilibrium part and of the final sum of the collision: the
+// equilibrium shift D (nested products of O(u) terms, size ~1e-3) decides the
+// FP32 form's accuracy, so it is formed in FP64 there; with FP16 storage the
+// rounding of the stored values dominates and FP32 suffices
+template <class S> struct Eq { using type = double; };
+template <> struct Eq<_Float16> { using type = float; };
 
 template <class S> __device__ __forceinline__ typename Real<S>::type ld(const S *p)
 {
@@ -114,18 +120,21 @@ __device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
 // rho, the momentum and the second moments of the input matter.  Everything
 // is carried as a deviation from the rest state (rho = 1, u = 0, K = I/3) so
 // FP32 keeps the small quantities exact enough.
-template <class R>
-__device__ __forceinline__ void collide(R d[27], R omega, R gx, R gy, R gz)
+template <class R, class E>
+__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27])
 {
-    // raw moments of the deviations, passes x, y, z of (sum, odd, even)
-    R m[27];
+    // Raw moments of the deviations, passes x, y, z of (sum, odd, even), in
+    // FP64 in every form: the non-equilibrium second moments are small
+    // differences of O(1e-3) sums, which FP32 would resolve only to a few
+    // times the storage rounding.  FP64 adds issue at the FP32 rate here.
+    double m[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) m[i] = d[i];
+    for (int i = 0; i < 27; ++i) m[i] = (double)d[i];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            R vm = m[MI(0, b, c)], v0 = m[MI(1, b, c)], vp = m[MI(2, b, c)];
+            double vm = m[MI(0, b, c)], v0 = m[MI(1, b, c)], vp = m[MI(2, b, c)];
             m[MI(0, b, c)] = vm + v0 + vp;
             m[MI(1, b, c)] = vp - vm;
             m[MI(2, b, c)] = vp + vm;
@@ -134,7 +143,7 @@ __device__ __forceinline__ void collide(R d[27], R omega, R gx, R gy, R gz)
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R vm = m[MI(a, 0, c)], v0 = m[MI(a, 1, c)], vp = m[MI(a, 2, c)];
+            double vm = m[MI(a, 0, c)], v0 = m[MI(a, 1, c)], vp = m[MI(a, 2, c)];
             m[MI(a, 0, c)] = vm + v0 + vp;
             m[MI(a, 1, c)] = vp - vm;
             m[MI(a, 2, c)] = vp + vm;
@@ -143,27 +152,28 @@ __device__ __forceinline__ void collide(R d[27], R omega, R gx, R gy, R gz)
     for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R vm = m[MI(a, b, 0)], v0 = m[MI(a, b, 1)], vp = m[MI(a, b, 2)];
+            double vm = m[MI(a, b, 0)], v0 = m[MI(a, b, 1)], vp = m[MI(a, b, 2)];
             m[MI(a, b, 0)] = vm + v0 + vp;
             m[MI(a, b, 1)] = vp - vm;
             m[MI(a, b, 2)] = vp + vm;
         }
-    const R drho = m[MI(0, 0, 0)];
-    const R rho = R(1) + drho;
-    const R irho = R(1) / rho;
-    const R jx = m[MI(1, 0, 0)], jy = m[MI(0, 1, 0)], jz = m[MI(0, 0, 1)];
-    const R ux = (jx + R(0.5) * rho * gx) * irho;
-    const R uy = (jy + R(0.5) * rho * gy) * irho;
-    const R uz = (jz + R(0.5) * rho * gz) * irho;
-    const R third = R(1.0 / 3.0);
-    const R dtr = drho * irho * third;
+    const double drho_d = m[MI(0, 0, 0)];
+    const double rho_d = 1.0 + drho_d;
+    const double irho_d = 1.0 / rho_d;
+    const double jxd = m[MI(1, 0, 0)], jyd = m[MI(0, 1, 0)], jzd = m[MI(0, 0, 1)];
+    const double uxd = (jxd + 0.5 * rho_d * (double)gx) * irho_d;
+    const double uyd = (jyd + 0.5 * rho_d * (double)gy) * irho_d;
+    const double uzd = (jzd + 0.5 * rho_d * (double)gz) * irho_d;
+    const double dtr = drho_d * irho_d * (1.0 / 3.0);
     // second-order central moments minus I/3
-    R Kxx = (m[MI(2, 0, 0)] - R(2) * ux * jx) * irho + ux * ux - dtr;
-    R Kyy = (m[MI(0, 2, 0)] - R(2) * uy * jy) * irho + uy * uy - dtr;
-    R Kzz = (m[MI(0, 0, 2)] - R(2) * uz * jz) * irho + uz * uz - dtr;
-    R Kxy = (m[MI(1, 1, 0)] - ux * jy - uy * jx) * irho + ux * uy;
-    R Kxz = (m[MI(1, 0, 1)] - ux * jz - uz * jx) * irho + ux * uz;
-    R Kyz = (m[MI(0, 1, 1)] - uy * jz - uz * jy) * irho + uy * uz;
+    const R Kxx = R((m[MI(2, 0, 0)] - 2.0 * uxd * jxd) * irho_d + uxd * uxd - dtr);
+    const R Kyy = R((m[MI(0, 2, 0)] - 2.0 * uyd * jyd) * irho_d + uyd * uyd - dtr);
+    const R Kzz = R((m[MI(0, 0, 2)] - 2.0 * uzd * jzd) * irho_d + uzd * uzd - dtr);
+    const R Kxy = R((m[MI(1, 1, 0)] - uxd * jyd - uyd * jxd) * irho_d + uxd * uyd);
+    const R Kxz = R((m[MI(1, 0, 1)] - uxd * jzd - uzd * jxd) * irho_d + uxd * uzd);
+    const R Kyz = R((m[MI(0, 1, 1)] - uyd * jzd - uzd * jyd) * irho_d + uyd * uzd);
+    const R ux = R(uxd), uy = R(uyd), uz = R(uzd);
+    const R third = R(1.0 / 3.0);
     // relaxation: deviator with omega, trace to equilibrium
     const R om1 = R(1) - omega;
     const R tr3 = (Kxx + Kyy + Kzz) * third;
@@ -207,10 +217,11 @@ __device__ __forceinline__ void collide(R d[27], R omega, R gx, R gy, R gz)
 #pragma unroll
         for (int a = 0; a < 3; ++a) inv_chimera(k[MI(a, b, 0)], k[MI(a, b, 1)], k[MI(a, b, 2)], uz);
     // rest state about u is the product equilibrium: f* = rho (w + D + G)
-    R D[27];
-    product_dev(ux, uy, uz, D);
+    E D[27];
+    product_dev(E(uxd), E(uyd), E(uzd), D);
+    const E dre = E(drho_d), re = E(rho_d);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) d[i] = drho * (R(wgt(i)) + D[i]) + D[i] + rho * k[i];
+    for (int i = 0; i < 27; ++i) out[i] = dre * (E(wgt(i)) + D[i]) + D[i] + re * E(k[i]);
 }
 
 // ---------------------------------------------------------------- helpers

@@ -1,8 +1,9 @@
 // fsl_mlp.hip -- the learned interface estimator on gfx950: a 27 -> 64 ->
 // 64 -> 4 perceptron (tanh hidden layers) from the 3x3x3 fill stencil of an
-// interface cell to its normal (outputs 0..2, unnormalised) and 4 x mean
-// curvature (output 3).  BF16 weights and activations on the matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation), FP32 master weights, Adam.
+// interface cell to its normal (outputs 0..2, trained towards the unit
+// normal and normalised when used) and 4 x mean curvature (output 3).  BF16
+// weights and activations on the matrix cores (v_mfma_f32_16x16x16_bf16,
+// FP32 accumulation), FP32 master weights, Adam.
 //
 // Layout of the flat FP32 parameter vector (6212 floats):
 //   W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
@@ -189,18 +190,13 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *X, const float *T,
         // output gradient (lanes q == 0 own sample r's four outputs)
         float dy[4] = {0.f, 0.f, 0.f, 0.f};
         if (q == 0 && valid) {
+            // loss |y[0..2] - n*|^2 + (y[3] - 4 kappa*)^2
             const float *t = T + (size_t)sid * 4;
-            const float rn = sqrtf(F.y[0] * F.y[0] + F.y[1] * F.y[1] + F.y[2] * F.y[2]);
-            float nh[3], e[3];
-            for (int a = 0; a < 3; ++a) {
-                nh[a] = F.y[a] / rn;
-                e[a] = nh[a] - t[a];
-            }
-            const float en = e[0] * nh[0] + e[1] * nh[1] + e[2] * nh[2];
-            const float ek = F.y[3] - 4.f * t[3];
-            for (int a = 0; a < 3; ++a) dy[a] = 2.f * (e[a] - nh[a] * en) / rn * inv_n;
-            dy[3] = 2.f * ek * inv_n;
-            loss += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + ek * ek;
+            float e[4];
+            for (int a = 0; a < 3; ++a) e[a] = F.y[a] - t[a];
+            e[3] = F.y[3] - 4.f * t[3];
+            for (int a = 0; a < 4; ++a) dy[a] = 2.f * e[a] * inv_n;
+            loss += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + e[3] * e[3];
         }
         const v4s dyb = pack4(dy[0], dy[1], dy[2], dy[3]);
 #pragma unroll

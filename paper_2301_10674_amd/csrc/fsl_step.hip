@@ -131,12 +131,14 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
         in_sum -= excl;
     }
 
-    collide<R>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz));
+    using E = typename Eq<S>::type;
+    E fo[27];
+    collide<R, E>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
 
     double out_sum = 0.0, out_excl = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const S v = to_store<S, R>(f[i]);
+        const S v = to_store<S, E>(fo[i]);
         st_at(dst + (size_t)i * N, (uint32_t)c, v);
         if (i != REST) out_sum += (double)ld(&v);
         if (i != REST && ((solid >> opp(i)) & 1u)) out_excl += (double)ld(&v);
@@ -309,12 +311,14 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
             }
         }
 
-        collide<R>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz));
+        using Et = typename Eq<S>::type;
+        Et fo[27];
+        collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
 
         double rs = 0.0;
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
-            const S v = to_store<S, R>(f[i]);
+            const S v = to_store<S, Et>(fo[i]);
             dst[(size_t)i * N + c] = v;
             rs += (double)ld(&v);
         }

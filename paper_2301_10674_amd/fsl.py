@@ -80,6 +80,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libfsl.so is not built; run `python -m paper_2301_10674_amd.build`")
+        # torch provides the device memory and streams: bring its HIP runtime
+        # up first so the library binds to the same, initialised runtime
+        import torch
+
+        if torch.cuda.is_available():
+            torch.cuda.init()
         L = ctypes.CDLL(LIB_PATH)
         vp, dp, i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
         L.fsl_workspace_bytes.restype = ctypes.c_size_t

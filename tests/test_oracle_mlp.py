@@ -79,7 +79,7 @@ def test_loss_is_zero_at_perfect_prediction():
     rng = np.random.default_rng(2)
     p = np.zeros(NP)
     q = split(p)
-    q["b3"][:] = [0.0, 0.0, 3.0, 0.8]   # predicts n = +z (any length), 4 kappa = 0.8
+    q["b3"][:] = [0.0, 0.0, 1.0, 0.8]   # predicts n = +z, 4 kappa = 0.8
     x, _ = random_batch(rng, 5)
     t = np.tile([0.0, 0.0, 1.0, 0.2], (5, 1))
     loss, g = O.mlp_loss_grad(p, x, t)
