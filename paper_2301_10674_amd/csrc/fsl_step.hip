@@ -276,20 +276,23 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
         }
 
         // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
-        // post-collision velocity
+        // post-collision velocity (formed like the collision's equilibrium
+        // part, in FP64 unless the storage is FP16)
+        using Et = typename Eq<S>::type;
         const R4 gm = ((const R4 *)d.geom)[c];
-        R drho_o = R(0), jxo = R(0), jyo = R(0), jzo = R(0);
+        double drho_o = 0.0, jxo = 0.0, jyo = 0.0, jzo = 0.0;
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
-            drho_o += own[i];
-            jxo += R(cx(i)) * own[i];
-            jyo += R(cy(i)) * own[i];
-            jzo += R(cz(i)) * own[i];
+            const double v = (double)own[i];
+            drho_o += v;
+            jxo += cx(i) * v;
+            jyo += cy(i) * v;
+            jzo += cz(i) * v;
         }
-        const R irho_o = R(1) / (R(1) + drho_o);
-        R E[27];
-        feq_dev<R>(R(d.rho_gas - 1.0 + 6.0 * d.sigma * (double)gm.w), jxo * irho_o,
-                   jyo * irho_o, jzo * irho_o, E);
+        const double irho_o = 1.0 / (1.0 + drho_o);
+        Et E[27];
+        feq_dev<Et>(Et(d.rho_gas - 1.0 + 6.0 * d.sigma * (double)gm.w), Et(jxo * irho_o),
+                    Et(jyo * irho_o), Et(jzo * irho_o), E);
 
         R f[27];
 #pragma unroll
@@ -307,11 +310,10 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
             } else {
                 const R nc = gm.x * R(cx(j)) + gm.y * R(cy(j)) + gm.z * R(cz(j));
                 const bool recon = st == T_GAS || (double)nc < -d.tie;
-                f[j] = recon ? E[j] + E[sj] - own[sj] : pulled[j];
+                f[j] = recon ? R(E[j] + E[sj] - Et(own[sj])) : pulled[j];
             }
         }
 
-        using Et = typename Eq<S>::type;
         Et fo[27];
         collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
 
@@ -417,7 +419,6 @@ __device__ __forceinline__ void stored_sums(const Dev &d, const S *pdf, int c, c
 template <class S>
 __global__ __launch_bounds__(LIST_THREADS) void k_conv2(Dev d, int p, uint32_t epoch)
 {
-    using R = typename Real<S>::type;
     S *pdf = (S *)d.pdf[p ^ 1];
     const int count = d.cnt[2];
     const size_t N = (size_t)d.N;
@@ -449,12 +450,13 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv2(Dev d, int p, uint32_t e
                 for (int a = 0; a < 3; ++a) us[a] += j[a] / r;
                 ++n;
             }
+            using Et = typename Eq<S>::type;
             const double rb = rs / n;
-            R e[27];
-            feq_dev<R>(R(rb - 1.0), R(us[0] / n), R(us[1] / n), R(us[2] / n), e);
+            Et e[27];
+            feq_dev<Et>(Et(rb - 1.0), Et(us[0] / n), Et(us[1] / n), Et(us[2] / n), e);
             double sum = 0.0;
             for (int i = 0; i < 27; ++i) {
-                const S v = to_store<S, R>(e[i]);
+                const S v = to_store<S, Et>(e[i]);
                 pdf[(size_t)i * N + c] = v;
                 sum += (double)ld(&v);
             }
