@@ -224,6 +224,51 @@ __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz
     for (int i = 0; i < 27; ++i) out[i] = dre * (E(wgt(i)) + D[i]) + D[i] + re * E(k[i]);
 }
 
+// ---------------------------------------------------------------- geometry
+// Finite-difference interface geometry of a 3x3x3 fill stencil s (index
+// MI(a,b,c) = offset (a-1,b-1,c-1)), Section 2.2: Parker-Youngs normal
+// (gradient of the fill level with weights 1-2-1 across, pointing from
+// liquid to gas) and mean curvature -(tr H - h.H.h) / (2 |g|) from the
+// central-difference Hessian H.  Returns (nx, ny, nz, kappa); all zero where
+// the gradient vanishes.  FP64: the normal decides which links are
+// reconstructed, so the decision is taken at the fill level's precision.
+__device__ __forceinline__ void fd_geometry(const double s[27], double o[4])
+{
+    const double W[3] = {1.0, 2.0, 1.0};
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double w = W[p] * W[q];
+            gx += w * (s[MI(2, p, q)] - s[MI(0, p, q)]);
+            gy += w * (s[MI(p, 2, q)] - s[MI(p, 0, q)]);
+            gz += w * (s[MI(p, q, 2)] - s[MI(p, q, 0)]);
+        }
+    gx /= 32.0;
+    gy /= 32.0;
+    gz /= 32.0;
+    const double gn = sqrt(gx * gx + gy * gy + gz * gz);
+    if (gn < 1e-12) {
+        o[0] = o[1] = o[2] = o[3] = 0.0;
+        return;
+    }
+    const double hx = gx / gn, hy = gy / gn, hz = gz / gn;
+    const double c0 = s[MI(1, 1, 1)];
+    const double Hxx = s[MI(2, 1, 1)] - 2.0 * c0 + s[MI(0, 1, 1)];
+    const double Hyy = s[MI(1, 2, 1)] - 2.0 * c0 + s[MI(1, 0, 1)];
+    const double Hzz = s[MI(1, 1, 2)] - 2.0 * c0 + s[MI(1, 1, 0)];
+    const double Hxy = 0.25 * (s[MI(2, 2, 1)] - s[MI(2, 0, 1)] - s[MI(0, 2, 1)] + s[MI(0, 0, 1)]);
+    const double Hxz = 0.25 * (s[MI(2, 1, 2)] - s[MI(2, 1, 0)] - s[MI(0, 1, 2)] + s[MI(0, 1, 0)]);
+    const double Hyz = 0.25 * (s[MI(1, 2, 2)] - s[MI(1, 2, 0)] - s[MI(1, 0, 2)] + s[MI(1, 0, 0)]);
+    const double tr = Hxx + Hyy + Hzz;
+    const double gHg = hx * hx * Hxx + hy * hy * Hyy + hz * hz * Hzz + 2.0 * (hx * hy * Hxy + hx * hz * Hxz + hy * hz * Hyz);
+    o[0] = -hx;
+    o[1] = -hy;
+    o[2] = -hz;
+    o[3] = -(tr - gHg) / (2.0 * gn);
+}
+
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int wrap_m(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_p(int v, int n) { return v == n - 1 ? 0 : v + 1; }

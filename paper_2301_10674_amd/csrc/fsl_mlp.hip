@@ -392,14 +392,14 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
         const int t = g * 16 + r;
         const bool valid = t < count;
         bool any_solid = false;
-        R fd[4] = {R(0), R(0), R(0), R(0)};
+        double fd[4] = {0.0, 0.0, 0.0, 0.0};
         int c = 0;
         if (q == 0 && valid) {
             c = list[t];
             const int x = c % d.nx, y = (c / d.nx) % d.ny, z = c / (d.nx * d.ny);
             double pv = d.phi[c];
-            const R centre = R(pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv));
-            R s[27];
+            const double centre = pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv);
+            double s[27];
             for (int i = 0; i < 27; ++i) {
                 if (i == REST) {
                     s[i] = centre;
@@ -411,46 +411,16 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
                     any_solid = true;
                     s[i] = centre;
                 } else if (ty == T_LIQ) {
-                    s[i] = R(1);
+                    s[i] = 1.0;
                 } else if (ty == T_GAS) {
-                    s[i] = R(0);
+                    s[i] = 0.0;
                 } else {
-                    double v = d.phi[yc];
-                    s[i] = R(v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v));
+                    const double v = d.phi[yc];
+                    s[i] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
                 }
             }
             for (int i = 0; i < 27; ++i) sS[r][i] = (float)s[i];
-            // finite-difference estimate (Parker-Youngs normal, Hessian curvature)
-            const R W[3] = {R(1), R(2), R(1)};
-            R gx = R(0), gy = R(0), gz = R(0);
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    const R w = W[a] * W[b];
-                    gx += w * (s[MI(2, a, b)] - s[MI(0, a, b)]);
-                    gy += w * (s[MI(a, 2, b)] - s[MI(a, 0, b)]);
-                    gz += w * (s[MI(a, b, 2)] - s[MI(a, b, 0)]);
-                }
-            gx /= R(32);
-            gy /= R(32);
-            gz /= R(32);
-            const R gn = sqrt(gx * gx + gy * gy + gz * gz);
-            if (gn >= R(1e-12)) {
-                const R hx = gx / gn, hy = gy / gn, hz = gz / gn;
-                const R c0 = s[MI(1, 1, 1)];
-                const R Hxx = s[MI(2, 1, 1)] - R(2) * c0 + s[MI(0, 1, 1)];
-                const R Hyy = s[MI(1, 2, 1)] - R(2) * c0 + s[MI(1, 0, 1)];
-                const R Hzz = s[MI(1, 1, 2)] - R(2) * c0 + s[MI(1, 1, 0)];
-                const R Hxy = R(0.25) * (s[MI(2, 2, 1)] - s[MI(2, 0, 1)] - s[MI(0, 2, 1)] + s[MI(0, 0, 1)]);
-                const R Hxz = R(0.25) * (s[MI(2, 1, 2)] - s[MI(2, 1, 0)] - s[MI(0, 1, 2)] + s[MI(0, 1, 0)]);
-                const R Hyz = R(0.25) * (s[MI(1, 2, 2)] - s[MI(1, 2, 0)] - s[MI(1, 0, 2)] + s[MI(1, 0, 0)]);
-                const R tr = Hxx + Hyy + Hzz;
-                const R gHg = hx * hx * Hxx + hy * hy * Hyy + hz * hz * Hzz
-                              + R(2) * (hx * hy * Hxy + hx * hz * Hxz + hy * hz * Hyz);
-                fd[0] = -hx;
-                fd[1] = -hy;
-                fd[2] = -hz;
-                fd[3] = -(tr - gHg) / (R(2) * gn);
-            }
+            fd_geometry(s, fd);
         } else if (q == 0) {
             for (int i = 0; i < 27; ++i) sS[r][i] = 0.5f;
         }
@@ -471,10 +441,10 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
         __syncthreads();
         if (q == 0 && valid) {
             R4 out;
-            out.x = fd[0];
-            out.y = fd[1];
-            out.z = fd[2];
-            out.w = fd[3];
+            out.x = R(fd[0]);
+            out.y = R(fd[1]);
+            out.z = R(fd[2]);
+            out.w = R(fd[3]);
             const float rn = sqrtf(F.y[0] * F.y[0] + F.y[1] * F.y[1] + F.y[2] * F.y[2]);
             bool use = !any_solid && rn >= 0.5f && rn <= 2.f;
             const float kap = 0.25f * F.y[3];

@@ -82,19 +82,28 @@ __device__ __forceinline__ void st_at(S *base, uint32_t e, S v)
     *(S *)((char *)base + e * (uint32_t)sizeof(S)) = v;
 }
 
-// one liquid cell of the dense step
+// one liquid cell of the dense step.  Every load of the cell is issued
+// before any arithmetic so that a wavefront keeps all of its streams in
+// flight; fl is the cell's flag byte (liquid).
 template <class S>
 __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
-                                          int x, int row)
+                                          int x, int row, uint8_t fl)
 {
     using R = typename Real<S>::type;
-    if (x >= d.nx) return;
     const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
     const size_t N = (size_t)d.N;
     const int y = row % ny, z = row / ny;
-    const int c = x + nx * (y + ny * z);
-    const uint8_t fl = d.flags[c];
-    if ((fl & T_MASK) != T_LIQ) return;
+    const int c = x + nx * row;
+    const bool near = (fl & F_NEAR_SOLID) != 0;
+
+    // bookkeeping loads first: the record slot gates a second round of loads
+    const double mq0 = d.mq[c];
+    uint32_t solid = 0;
+    int slot = -1;
+    if (near) {
+        solid = d.smask[c];
+        slot = d.bbslot[c];
+    }
 
     // element offset of the source x - c_i relative to c, per axis and sign
     // (periodic in x and y; z clamped -- the wall layers are near-solid cells
@@ -107,51 +116,60 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     for (int i = 0; i < 27; ++i)
         f[i] = ld_at(src + (size_t)i * N, (uint32_t)(c + DX[i % 3] + DY[(i / 3) % 3] + DZ[i / 9]));
 
+    // links whose source is solid or beyond a wall bounce back: the cell's
+    // own post-collision value of the opposite direction, plus the
+    // precomputed moving-wall term of sphere links (zero for wall links)
+    R fb[27], rec[28];
+#pragma unroll
+    for (int j = 0; j < 27; ++j) fb[j] = R(0);
+#pragma unroll
+    for (int j = 0; j < 28; ++j) rec[j] = R(0);
+    if (near) {
+#pragma unroll
+        for (int j = 0; j < 27; ++j)
+            if (j != REST) fb[j] = ld_at(src + (size_t)opp(j) * N, (uint32_t)c);
+        if (slot >= 0) {
+            constexpr int NV = 28 * (int)sizeof(R) / 16;
+            const uint4 *rp = (const uint4 *)((const R *)d.bbterm + (size_t)slot * 32);
+            uint4 v[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] = rp[k];
+            __builtin_memcpy(rec, v, sizeof(v));
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // incoming mass over the non-solid links
     double in_sum = 0.0;
 #pragma unroll
-    for (int j = 0; j < 27; ++j)
-        if (j != REST) in_sum += (double)f[j];
-
-    uint32_t solid = 0;
-    if (fl & F_NEAR_SOLID) {
-        // links whose source is solid or beyond a wall bounce back; the
-        // moving-wall terms of sphere links are precomputed per cell
-        solid = d.smask[c];
-        const int slot = d.bbslot[c];
-        const R *rec = (const R *)d.bbterm + (size_t)(slot < 0 ? 0 : slot) * 32;
-        double excl = 0.0;
-#pragma unroll
-        for (int j = 0; j < 27; ++j) {
-            if (j == REST || !((solid >> j) & 1u)) continue;
-            excl += (double)f[j];
-            R v = ld_at(src + (size_t)opp(j) * N, (uint32_t)c);
-            if (slot >= 0) v += rec[j];
-            f[j] = v;
-        }
-        in_sum -= excl;
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST) continue;
+        const bool sj = (solid >> j) & 1u;
+        in_sum += sj ? 0.0 : (double)f[j];
+        f[j] = sj ? fb[j] + rec[j] : f[j];
     }
 
     using E = typename Eq<S>::type;
     E fo[27];
     collide<R, E>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
 
-    double out_sum = 0.0, out_excl = 0.0;
+    double out_sum = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const S v = to_store<S, E>(fo[i]);
         st_at(dst + (size_t)i * N, (uint32_t)c, v);
-        if (i != REST) out_sum += (double)ld(&v);
-        if (i != REST && ((solid >> opp(i)) & 1u)) out_excl += (double)ld(&v);
+        if (i != REST) out_sum += ((solid >> opp(i)) & 1u) ? 0.0 : (double)ld(&v);
     }
     // liquid cells keep m - own outgoing: m' = (m - out) + in over non-solid links
-    d.mq[c] = (d.mq[c] + in_sum) - (out_sum - out_excl);
+    d.mq[c] = (mq0 + in_sum) - out_sum;
 }
 
 // Dense step over the rows (y, z) up to the highest fluid row; each block
-// walks over 256-cell row segments.  With xcd_map, hardware block b runs on
-// XCD b % 8 and takes whole rows k, k+8, k+16, ... of that XCD, so the
-// segments of one row (which share cache lines at their edges) meet in one
-// L2 while the liquid/gas split in z stays balanced over the XCDs.
+// walks over 256-cell row segments, loading the flag byte of its next
+// segment before it works on the current one.  With xcd_map, hardware block
+// b runs on XCD b % 8 and takes whole rows k, k+8, k+16, ... of that XCD, so
+// the segments of one row (which share cache lines at their edges) meet in
+// one L2 while the liquid/gas split in z stays balanced over the XCDs.
 template <class S>
 __global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
 {
@@ -159,19 +177,28 @@ __global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
     S *__restrict__ dst = (S *)d.pdf[p ^ 1];
     const int rowmax = (d.cnt[3] + 1) * d.ny;
     const int tx = (int)threadIdx.x;
+    const int nx = d.nx, nbx = d.nbx;
+    int s, step, k;
     if (d.xcd_map) {
-        const int k = blockIdx.x & 7, g8 = gridDim.x >> 3;
-        for (int s = blockIdx.x >> 3;; s += g8) {
-            const int row = k + 8 * (s / d.nbx);
-            if (row >= rowmax) break;
-            bulk_cell<S>(d, src, dst, (s % d.nbx) * BULK_THREADS + tx, row);
-        }
+        k = blockIdx.x & 7;
+        s = blockIdx.x >> 3;
+        step = gridDim.x >> 3;
     } else {
-        for (int it = blockIdx.x;; it += gridDim.x) {
-            const int row = it / d.nbx;
-            if (row >= rowmax) break;
-            bulk_cell<S>(d, src, dst, (it % d.nbx) * BULK_THREADS + tx, row);
-        }
+        k = 0;
+        s = blockIdx.x;
+        step = gridDim.x;
+    }
+    const int rmul = d.xcd_map ? 8 : 1;
+    int row = k + rmul * (s / nbx), x = (s % nbx) * BULK_THREADS + tx;
+    uint8_t fl = (row < rowmax && x < nx) ? d.flags[x + nx * row] : (uint8_t)0;
+    while (row < rowmax) {
+        s += step;
+        const int row2 = k + rmul * (s / nbx), x2 = (s % nbx) * BULK_THREADS + tx;
+        const uint8_t fl2 = (row2 < rowmax && x2 < nx) ? d.flags[x2 + nx * row2] : (uint8_t)0;
+        if ((fl & T_MASK) == T_LIQ) bulk_cell<S>(d, src, dst, x, row, fl);
+        row = row2;
+        x = x2;
+        fl = fl2;
     }
 }
 
@@ -308,8 +335,8 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
                 if (nbc[sj] >= 0) v += bb_term<R>(d, nbc[sj], j, pc);
                 f[j] = v;
             } else {
-                const R nc = gm.x * R(cx(j)) + gm.y * R(cy(j)) + gm.z * R(cz(j));
-                const bool recon = st == T_GAS || (double)nc < -d.tie;
+                const double nc = (double)gm.x * cx(j) + (double)gm.y * cy(j) + (double)gm.z * cz(j);
+                const bool recon = st == T_GAS || nc < -d.tie;
                 f[j] = recon ? R(E[j] + E[sj] - Et(own[sj])) : pulled[j];
             }
         }
@@ -568,8 +595,8 @@ __device__ __forceinline__ R stencil_value(const Dev &d, int y, R centre)
     }
 }
 
-// Parker-Youngs normal and finite-difference mean curvature of the 3x3x3
-// fill stencil of each interface cell (index MI(a,b,c) = offset (a-1,b-1,c-1)).
+// Normal and curvature of each interface cell from its fill stencil
+// (finite differences, evaluated in FP64 for every storage form), stored as R.
 template <class R>
 __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
 {
@@ -579,46 +606,17 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
         const int c = list[t];
         const Cell pc = cell_xyz(d, c);
-        double pv = d.phi[c];
-        const R centre = R(pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv));
-        R s[27];
+        const double pv = d.phi[c];
+        const double centre = pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv);
+        double s[27], o[4];
 #pragma unroll
-        for (int i = 0; i < 27; ++i) s[i] = i == REST ? centre : stencil_value<R>(d, nb_of(d, pc, i), centre);
-        const R W[3] = {R(1), R(2), R(1)};
-        R gx = R(0), gy = R(0), gz = R(0);
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const R w = W[p] * W[q];
-                gx += w * (s[MI(2, p, q)] - s[MI(0, p, q)]);
-                gy += w * (s[MI(p, 2, q)] - s[MI(p, 0, q)]);
-                gz += w * (s[MI(p, q, 2)] - s[MI(p, q, 0)]);
-            }
-        gx /= R(32);
-        gy /= R(32);
-        gz /= R(32);
-        const R gn = sqrt(gx * gx + gy * gy + gz * gz);
+        for (int i = 0; i < 27; ++i) s[i] = i == REST ? centre : stencil_value<double>(d, nb_of(d, pc, i), centre);
+        fd_geometry(s, o);
         R4 out;
-        if (gn < R(1e-12)) {
-            out.x = out.y = out.z = out.w = R(0);
-        } else {
-            const R hx = gx / gn, hy = gy / gn, hz = gz / gn;
-            const R c0 = s[MI(1, 1, 1)];
-            const R Hxx = s[MI(2, 1, 1)] - R(2) * c0 + s[MI(0, 1, 1)];
-            const R Hyy = s[MI(1, 2, 1)] - R(2) * c0 + s[MI(1, 0, 1)];
-            const R Hzz = s[MI(1, 1, 2)] - R(2) * c0 + s[MI(1, 1, 0)];
-            const R Hxy = R(0.25) * (s[MI(2, 2, 1)] - s[MI(2, 0, 1)] - s[MI(0, 2, 1)] + s[MI(0, 0, 1)]);
-            const R Hxz = R(0.25) * (s[MI(2, 1, 2)] - s[MI(2, 1, 0)] - s[MI(0, 1, 2)] + s[MI(0, 1, 0)]);
-            const R Hyz = R(0.25) * (s[MI(1, 2, 2)] - s[MI(1, 2, 0)] - s[MI(1, 0, 2)] + s[MI(1, 0, 0)]);
-            const R tr = Hxx + Hyy + Hzz;
-            const R gHg = hx * hx * Hxx + hy * hy * Hyy + hz * hz * Hzz
-                          + R(2) * (hx * hy * Hxy + hx * hz * Hxz + hy * hz * Hyz);
-            out.x = -hx;
-            out.y = -hy;
-            out.z = -hz;
-            out.w = -(tr - gHg) / (R(2) * gn);
-        }
+        out.x = R(o[0]);
+        out.y = R(o[1]);
+        out.z = R(o[2]);
+        out.w = R(o[3]);
         ((R4 *)d.geom)[c] = out;
     }
 }
