@@ -764,6 +764,14 @@ FslStatus fsl_read_fields(FslLattice *L, uint32_t mask, void *const *dst, int32_
         if (f == FSL_FIELD_OWNER) bytes = N * 4;
         if (f == FSL_FIELD_VEL || f == FSL_FIELD_NORMAL) bytes = 3 * N * 8;
         if (f == FSL_FIELD_PDF) bytes = 27 * N * 8;
+        if ((f == FSL_FIELD_NORMAL || f == FSL_FIELD_CURV) && !(L->P.normals == 1 && L->mlpP)) {
+            // the plain estimator evaluates the geometry inside the step;
+            // evaluate it here for the current interface list
+            if (L->P.precision == FSL_FP64)
+                launch_geom<double>(L->d, L->parity, L->list_blocks, L->st);
+            else
+                launch_geom<float>(L->d, L->parity, L->list_blocks, L->st);
+        }
         void *buf = dst[f];
         if (!on_device) HIP_TRY(hipMalloc(&buf, bytes));
         DISPATCH(L, run_read, L, f, buf);

@@ -83,6 +83,30 @@ __device__ __forceinline__ void product_dev(R ux, R uy, R uz, R D[27])
             }
 }
 
+// One entry of feq_dev below, from the 1D factors of product_dev:
+// e[d][k] = psi(k-1, u_d) - w1(k-1).  Same arithmetic as the full table.
+template <class R>
+__device__ __forceinline__ void psi_dev(R ux, R uy, R uz, R e[3][3])
+{
+    const R u[3] = {ux, uy, uz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        R uu = u[d] * u[d];
+        e[d][0] = R(0.5) * (uu - u[d]);
+        e[d][1] = -uu;
+        e[d][2] = R(0.5) * (uu + u[d]);
+    }
+}
+template <class R>
+__device__ __forceinline__ R feq_dev_one(R drho, const R e[3][3], int i)
+{
+    const R w[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+    const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+    R d2 = e[0][a] * (w[b] + e[1][b]) + w[a] * e[1][b];
+    R D = d2 * (w[c] + e[2][c]) + (w[a] * w[b]) * e[2][c];
+    return drho * (R(wgt(i)) + D) + D;
+}
+
 // f^eq(rho, u) - w  with rho = 1 + drho
 template <class R>
 __device__ __forceinline__ void feq_dev(R drho, R ux, R uy, R uz, R out[27])
@@ -232,7 +256,7 @@ __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz
 // central-difference Hessian H.  Returns (nx, ny, nz, kappa); all zero where
 // the gradient vanishes.  FP64: the normal decides which links are
 // reconstructed, so the decision is taken at the fill level's precision.
-__device__ __forceinline__ void fd_geometry(const double s[27], double o[4])
+__device__ __forceinline__ double4 fd_geometry(const double s[27])
 {
     const double W[3] = {1.0, 2.0, 1.0};
     double gx = 0.0, gy = 0.0, gz = 0.0;
@@ -249,10 +273,8 @@ __device__ __forceinline__ void fd_geometry(const double s[27], double o[4])
     gy /= 32.0;
     gz /= 32.0;
     const double gn = sqrt(gx * gx + gy * gy + gz * gz);
-    if (gn < 1e-12) {
-        o[0] = o[1] = o[2] = o[3] = 0.0;
-        return;
-    }
+    double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (gn < 1e-12) return o;
     const double hx = gx / gn, hy = gy / gn, hz = gz / gn;
     const double c0 = s[MI(1, 1, 1)];
     const double Hxx = s[MI(2, 1, 1)] - 2.0 * c0 + s[MI(0, 1, 1)];
@@ -263,10 +285,11 @@ __device__ __forceinline__ void fd_geometry(const double s[27], double o[4])
     const double Hyz = 0.25 * (s[MI(1, 2, 2)] - s[MI(1, 2, 0)] - s[MI(1, 0, 2)] + s[MI(1, 0, 0)]);
     const double tr = Hxx + Hyy + Hzz;
     const double gHg = hx * hx * Hxx + hy * hy * Hyy + hz * hz * Hzz + 2.0 * (hx * hy * Hxy + hx * hz * Hxz + hy * hz * Hyz);
-    o[0] = -hx;
-    o[1] = -hy;
-    o[2] = -hz;
-    o[3] = -(tr - gHg) / (2.0 * gn);
+    o.x = -hx;
+    o.y = -hy;
+    o.z = -hz;
+    o.w = -(tr - gHg) / (2.0 * gn);
+    return o;
 }
 
 // ---------------------------------------------------------------- helpers

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
         const int t = g * 16 + r;
         const bool valid = t < count;
         bool any_solid = false;
-        double fd[4] = {0.0, 0.0, 0.0, 0.0};
+        double4 fd = make_double4(0.0, 0.0, 0.0, 0.0);
         int c = 0;
         if (q == 0 && valid) {
             c = list[t];
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
                 }
             }
             for (int i = 0; i < 27; ++i) sS[r][i] = (float)s[i];
-            fd_geometry(s, fd);
+            fd = fd_geometry(s);
         } else if (q == 0) {
             for (int i = 0; i < 27; ++i) sS[r][i] = 0.5f;
         }
@@ -441,15 +441,15 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
         __syncthreads();
         if (q == 0 && valid) {
             R4 out;
-            out.x = R(fd[0]);
-            out.y = R(fd[1]);
-            out.z = R(fd[2]);
-            out.w = R(fd[3]);
+            out.x = R(fd.x);
+            out.y = R(fd.y);
+            out.z = R(fd.z);
+            out.w = R(fd.w);
             const float rn = sqrtf(F.y[0] * F.y[0] + F.y[1] * F.y[1] + F.y[2] * F.y[2]);
             bool use = !any_solid && rn >= 0.5f && rn <= 2.f;
             const float kap = 0.25f * F.y[3];
             if (use) {
-                const float cosang = ((float)fd[0] * F.y[0] + (float)fd[1] * F.y[1] + (float)fd[2] * F.y[2]) / rn;
+                const float cosang = ((float)fd.x * F.y[0] + (float)fd.y * F.y[1] + (float)fd.z * F.y[2]) / rn;
                 use = cosang >= 0.8660254f && fabsf(kap) <= 0.5f;
             }
             if (use) {

@@ -2,19 +2,22 @@
 //
 // Per step (Section 2.1 fluid model; readings of the cited free-surface
 // method as listed in the design notes):
-//   k_bulk    dense over the lattice, liquid cells: pull streaming,
-//             bounce-back next to walls and spheres, mass bookkeeping,
-//             cumulant collision, store.  This is the HBM-bound hot kernel.
-//   k_iface   interface list: the same plus reconstruction of PDFs from the
-//             gas side, the fill-weighted mass flux and the conversion marks.
+//   k_bulk    dense over the liquid rows: pull streaming, bounce-back next
+//             to walls and spheres, mass bookkeeping, cumulant collision,
+//             store.  This is the HBM-bound hot kernel.
+//   k_iface   interface list: the same plus the interface normal and
+//             curvature (finite differences on the fill stencil),
+//             reconstruction of PDFs from the gas side, the fill-weighted
+//             mass flux and the conversion marks.
 //   k_conv1   interface list: cancel emptyings next to fillings, mark the
 //             cells that become interface cells (list lnew).
-//   k_conv2   lnew: initialise the new interface cells.
-//   k_conv3   interface list: excess mass of converted cells.
+//   k_conv23  lnew: initialise the new interface cells; interface list:
+//             excess mass of converted cells.
 //   k_conv4   interface list + lnew: commit cell types, gather excess mass,
 //             refresh fill levels, build the next interface list.
-//   k_geom    next interface list: normal and curvature from the 3x3x3
-//             fill stencil.
+//   k_geom_mlp (learned estimator only) next interface list: normal and
+//             curvature from the network, finite differences as fallback.
+//   k_geom    normal and curvature of the list, for set-up and reads.
 #include "fsl_device.h"
 #include "fsl_kernels.h"
 #include "fsl_mlp.h"
@@ -80,6 +83,23 @@ template <class S>
 __device__ __forceinline__ void st_at(S *base, uint32_t e, S v)
 {
     *(S *)((char *)base + e * (uint32_t)sizeof(S)) = v;
+}
+// Ties a loaded value to this point (an empty asm statement that reads and
+// writes the register; no instruction is emitted).  Placed after all loads
+// of a stage, it keeps the compiler from sinking a load into the branch of
+// a select that consumes it, which would serialise the loads.
+template <class T>
+__device__ __forceinline__ void keep(T &v)
+{
+    asm volatile("" : "+v"(v));
+}
+
+// plain load of element e of a per-cell array (element offsets fit in 32
+// bits: the lattice is limited to 2^32 / 8 cells)
+template <class T>
+__device__ __forceinline__ T at(const T *base, uint32_t e)
+{
+    return *(const T *)((const char *)base + e * (uint32_t)sizeof(T));
 }
 
 // one liquid cell of the dense step.  Every load of the cell is issued
@@ -164,29 +184,29 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     d.mq[c] = (mq0 + in_sum) - out_sum;
 }
 
-// Dense step over the rows (y, z) up to the highest fluid row; each block
+// Dense part over the rows (y, z) up to the highest fluid row; each block
 // walks over 256-cell row segments, loading the flag byte of its next
-// segment before it works on the current one.  With xcd_map, hardware block
-// b runs on XCD b % 8 and takes whole rows k, k+8, k+16, ... of that XCD, so
-// the segments of one row (which share cache lines at their edges) meet in
-// one L2 while the liquid/gas split in z stays balanced over the XCDs.
+// segment before it works on the current one.  With xcd_map, hardware
+// block b runs on XCD b % 8 and takes whole rows k, k+8, k+16, ... of that
+// XCD, so the segments of one row (which share cache lines at their edges)
+// meet in one L2 while the liquid/gas split in z stays balanced over the
+// XCDs.
 template <class S>
-__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
+__device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
+                                           int b, int nblocks)
 {
-    const S *__restrict__ src = (const S *)d.pdf[p];
-    S *__restrict__ dst = (S *)d.pdf[p ^ 1];
     const int rowmax = (d.cnt[3] + 1) * d.ny;
     const int tx = (int)threadIdx.x;
     const int nx = d.nx, nbx = d.nbx;
     int s, step, k;
     if (d.xcd_map) {
-        k = blockIdx.x & 7;
-        s = blockIdx.x >> 3;
-        step = gridDim.x >> 3;
+        k = b & 7;
+        s = b >> 3;
+        step = nblocks >> 3;
     } else {
         k = 0;
-        s = blockIdx.x;
-        step = gridDim.x;
+        s = b;
+        step = nblocks;
     }
     const int rmul = d.xcd_map ? 8 : 1;
     int row = k + rmul * (s / nbx), x = (s % nbx) * BULK_THREADS + tx;
@@ -250,11 +270,182 @@ __global__ void k_zmax(Dev d)
 }
 
 // ---------------------------------------------------------------- interface
-template <class S>
-__global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t epoch)
+// One interface cell: pull streaming with bounce-back at solid links and
+// reconstruction of the links from the gas side (and of the links that
+// point against the normal), the fill-weighted mass flux, collision, and
+// the conversion marks.  GI: the normal and curvature are evaluated here
+// from the fill stencil (finite differences); otherwise they are read from
+// the geometry array (learned estimator).
+template <class S, bool GI>
+__device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
+                                           int c, uint32_t epoch)
 {
     using R = typename Real<S>::type;
     using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+    using Et = typename Eq<S>::type;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
+    const size_t N = (size_t)d.N;
+    const int x = c % nx, row = c / nx, y = row % ny, z = row / ny;
+    // neighbour x + c_i = c + OX[cx+1] + OY[cy+1] + OZ[cz+1] (periodic in x
+    // and y); -1 beyond the z walls
+    const int OX[3] = {x == 0 ? nx - 1 : -1, 0, x == nx - 1 ? 1 - nx : 1};
+    const int OY[3] = {y == 0 ? (ny - 1) * nx : -nx, 0, y == ny - 1 ? (1 - ny) * nx : nx};
+    const int OZ[3] = {-nxy, 0, nxy};
+    const bool WZ[3] = {z == 0, false, z == nz - 1};
+    auto nb = [&](int i) { return WZ[i / 9] ? -1 : c + OX[i % 3] + OY[(i / 3) % 3] + OZ[i / 9]; };
+
+    // stage 1: neighbour types (walls count as solid, 2 bits each) and the
+    // fill stencil (liquid 1, gas 0, interface clamped fill, solid the centre)
+    const double phic = d.phi[c];
+    const int slot = d.bbslot[c];
+    const double phicl = phic < 0.0 ? 0.0 : (phic > 1.0 ? 1.0 : phic);
+    uint32_t fl[27];
+    double ph[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int n = nb(i);
+        const uint32_t a = (uint32_t)(n < 0 ? c : n);
+        fl[i] = at(d.flags, a);
+        ph[i] = at(d.phi, a);
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        keep(fl[i]);
+        keep(ph[i]);
+    }
+    uint64_t tyb = 0;
+    double sv[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const uint32_t t = nb(i) < 0 ? (uint32_t)T_SOLID : (fl[i] & T_MASK);
+        const double pv = ph[i] < 0.0 ? 0.0 : (ph[i] > 1.0 ? 1.0 : ph[i]);
+        tyb |= (uint64_t)t << (2 * i);
+        sv[i] = i == REST ? phicl : (t == T_LIQ ? 1.0 : (t == T_GAS ? 0.0 : (t == T_IF ? pv : phicl)));
+    }
+    auto ty = [&](int i) { return (uint32_t)(tyb >> (2 * i)) & 3u; };
+    double4 gn;
+    if constexpr (GI) {
+        gn = fd_geometry(sv);
+    } else {
+        const R4 g = ((const R4 *)d.geom)[c];
+        gn = make_double4((double)g.x, (double)g.y, (double)g.z, (double)g.w);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // stage 2: the cell's own post-collision PDFs and the pulled ones
+    R own[27], pulled[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        own[i] = ld_at(src + (size_t)i * N, (uint32_t)c);
+        // source of incoming i is x - c_i = neighbour opp(i)
+        const int s = nb(opp(i));
+        pulled[i] = ld_at(src + (size_t)i * N, (uint32_t)(s < 0 ? c : s));
+    }
+    double mq0 = d.mq[c];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        keep(own[i]);
+        keep(pulled[i]);
+    }
+    keep(mq0);
+
+    // mass flux from the stored PDFs: s_i (f*_{-i}(x+c_i) - f*_i(x))
+    double dm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const uint32_t t = ty(i);
+        if (i == REST || t == T_SOLID || t == T_GAS) continue;
+        const double sw = t == T_IF ? 0.5 * (phicl + sv[i]) : 1.0;
+        dm += sw * ((double)pulled[opp(i)] - (double)own[i]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // stage 3: moving-wall terms of the links into spheres (zero for walls)
+    R rec[28];
+#pragma unroll
+    for (int j = 0; j < 28; ++j) rec[j] = R(0);
+    if (slot >= 0) {
+        constexpr int NV = 28 * (int)sizeof(R) / 16;
+        const uint4 *rp = (const uint4 *)((const R *)d.bbterm + (size_t)slot * 32);
+        uint4 v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = rp[k];
+        __builtin_memcpy(rec, v, sizeof(v));
+    }
+
+    // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
+    // post-collision velocity (formed like the collision's equilibrium
+    // part, in FP64 unless the storage is FP16)
+    double drho_o = 0.0, jxo = 0.0, jyo = 0.0, jzo = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const double v = (double)own[i];
+        drho_o += v;
+        jxo += cx(i) * v;
+        jyo += cy(i) * v;
+        jzo += cz(i) * v;
+    }
+    const double irho_o = 1.0 / (1.0 + drho_o);
+    Et ef[3][3];
+    psi_dev<Et>(Et(jxo * irho_o), Et(jyo * irho_o), Et(jzo * irho_o), ef);
+    const Et drg = Et(d.rho_gas - 1.0 + 6.0 * d.sigma * gn.w);
+
+    // incoming PDFs, by pairs (j, opp j) that share the sum of the two
+    // gas-side equilibria
+    R f[27];
+    f[REST] = own[REST];
+#pragma unroll
+    for (int j = 0; j < REST; ++j) {
+        const int sj = opp(j);
+        const Et G = feq_dev_one<Et>(drg, ef, j) + feq_dev_one<Et>(drg, ef, sj);
+        const double nc = gn.x * cx(j) + gn.y * cy(j) + gn.z * cz(j);  // n . c_j = -(n . c_sj)
+        const uint32_t tj = ty(j), tsj = ty(sj);
+        // incoming j comes from neighbour sj, incoming sj from neighbour j
+        const bool rj = tsj == T_GAS || nc < -d.tie;
+        const bool rsj = tj == T_GAS || -nc < -d.tie;
+        f[j] = tsj == T_SOLID ? own[sj] + rec[j] : (rj ? R(G - Et(own[sj])) : pulled[j]);
+        f[sj] = tj == T_SOLID ? own[j] + rec[sj] : (rsj ? R(G - Et(own[j])) : pulled[sj]);
+    }
+
+    Et fo[27];
+    collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
+
+    double rs = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const S v = to_store<S, Et>(fo[i]);
+        st_at(dst + (size_t)i * N, (uint32_t)c, v);
+        rs += (double)ld(&v);
+    }
+    const double rho = 1.0 + rs;
+    const double m = mq0 + dm;
+    d.mq[c] = m;
+    d.rho[c] = rho;
+
+    uint32_t bits = 0;
+    if (m > (1.0 + d.eps) * rho) {
+        bits = MK_TO_LIQ;
+    } else if (m < -d.eps * rho) {
+        bits = MK_TO_GAS;
+    } else if (d.rule_iso) {
+        bool has_gas = false, has_liq = false;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (i == REST || nb(i) < 0) continue;
+            has_gas |= ty(i) == T_GAS;
+            has_liq |= ty(i) == T_LIQ;
+        }
+        if (!has_gas && has_liq) bits = MK_TO_LIQ | MK_ISO;
+        else if (!has_liq && has_gas) bits = MK_TO_GAS | MK_ISO;
+    }
+    d.mark[c] = (epoch << 8) | bits;
+}
+
+// Interface list of the step (one cell per thread).  Block 0 starts the
+// next list and the new-cell list empty.
+template <class S, bool GI>
+__global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t epoch)
+{
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         d.cnt[p ^ 1] = 0;
         d.cnt[2] = 0;
@@ -263,117 +454,15 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
     S *__restrict__ dst = (S *)d.pdf[p ^ 1];
     const int32_t *list = d.list[p];
     const int count = d.cnt[p];
-    const size_t N = (size_t)d.N;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const int c = list[t];
-        const Cell pc = cell_xyz(d, c);
-        // neighbour x + c_i and its type (walls count as solid)
-        int nbc[27];
-        uint8_t nty[27];
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            nbc[i] = i == REST ? c : nb_of(d, pc, i);
-            nty[i] = nbc[i] < 0 ? (uint8_t)T_SOLID : (uint8_t)(d.flags[nbc[i]] & T_MASK);
-        }
-        R own[27], pulled[27];
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            own[i] = ld(src + (size_t)i * N + c);
-            // source of incoming i is x - c_i = neighbour opp(i)
-            const int s = nbc[opp(i)];
-            pulled[i] = s < 0 ? own[i] : ld(src + (size_t)i * N + s);
-        }
-        const double phic = d.phi[c];
-        const double phicl = phic < 0.0 ? 0.0 : (phic > 1.0 ? 1.0 : phic);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x)
+        iface_cell<S, GI>(d, src, dst, list[t], epoch);
+}
 
-        // mass flux from the stored PDFs: s_i (f*_{-i}(x+c_i) - f*_i(x))
-        double dm = 0.0;
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            if (i == REST) continue;
-            const uint8_t ty = nty[i];
-            if (ty == T_SOLID || ty == T_GAS) continue;
-            double s = 1.0;
-            if (ty == T_IF) {
-                double ph = d.phi[nbc[i]];
-                ph = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
-                s = 0.5 * (phicl + ph);
-            }
-            dm += s * ((double)pulled[opp(i)] - (double)own[i]);
-        }
-
-        // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
-        // post-collision velocity (formed like the collision's equilibrium
-        // part, in FP64 unless the storage is FP16)
-        using Et = typename Eq<S>::type;
-        const R4 gm = ((const R4 *)d.geom)[c];
-        double drho_o = 0.0, jxo = 0.0, jyo = 0.0, jzo = 0.0;
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const double v = (double)own[i];
-            drho_o += v;
-            jxo += cx(i) * v;
-            jyo += cy(i) * v;
-            jzo += cz(i) * v;
-        }
-        const double irho_o = 1.0 / (1.0 + drho_o);
-        Et E[27];
-        feq_dev<Et>(Et(d.rho_gas - 1.0 + 6.0 * d.sigma * (double)gm.w), Et(jxo * irho_o),
-                    Et(jyo * irho_o), Et(jzo * irho_o), E);
-
-        R f[27];
-#pragma unroll
-        for (int j = 0; j < 27; ++j) {
-            if (j == REST) {
-                f[j] = own[REST];
-                continue;
-            }
-            const int sj = opp(j);  // source direction index
-            const uint8_t st = nty[sj];
-            if (st == T_SOLID) {
-                R v = own[sj];
-                if (nbc[sj] >= 0) v += bb_term<R>(d, nbc[sj], j, pc);
-                f[j] = v;
-            } else {
-                const double nc = (double)gm.x * cx(j) + (double)gm.y * cy(j) + (double)gm.z * cz(j);
-                const bool recon = st == T_GAS || nc < -d.tie;
-                f[j] = recon ? R(E[j] + E[sj] - Et(own[sj])) : pulled[j];
-            }
-        }
-
-        Et fo[27];
-        collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
-
-        double rs = 0.0;
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const S v = to_store<S, Et>(fo[i]);
-            dst[(size_t)i * N + c] = v;
-            rs += (double)ld(&v);
-        }
-        const double rho = 1.0 + rs;
-        const double m = d.mq[c] + dm;
-        d.mq[c] = m;
-        d.rho[c] = rho;
-
-        uint32_t bits = 0;
-        if (m > (1.0 + d.eps) * rho) {
-            bits = MK_TO_LIQ;
-        } else if (m < -d.eps * rho) {
-            bits = MK_TO_GAS;
-        } else if (d.rule_iso) {
-            bool has_gas = false, has_liq = false;
-#pragma unroll
-            for (int i = 0; i < 27; ++i) {
-                if (i == REST || nbc[i] < 0) continue;
-                has_gas |= nty[i] == T_GAS;
-                has_liq |= nty[i] == T_LIQ;
-            }
-            if (!has_gas && has_liq) bits = MK_TO_LIQ | MK_ISO;
-            else if (!has_liq && has_gas) bits = MK_TO_GAS | MK_ISO;
-        }
-        d.mark[c] = (epoch << 8) | bits;
-    }
+// Dense stream-collide over the liquid rows.
+template <class S>
+__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
+{
+    dense_rows<S>(d, (const S *)d.pdf[p], (S *)d.pdf[p ^ 1], (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------- conversion
@@ -443,14 +532,13 @@ __device__ __forceinline__ void stored_sums(const Dev &d, const S *pdf, int c, c
     }
 }
 
+// a cell that becomes an interface cell this step
 template <class S>
-__global__ __launch_bounds__(LIST_THREADS) void k_conv2(Dev d, int p, uint32_t epoch)
+__device__ __forceinline__ void conv2_cell(const Dev &d, int p, uint32_t epoch, int c)
 {
     S *pdf = (S *)d.pdf[p ^ 1];
-    const int count = d.cnt[2];
     const size_t N = (size_t)d.N;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const int c = d.lnew[t];
+    {
         const Cell pc = cell_xyz(d, c);
         if ((d.flags[c] & T_MASK) == T_GAS) {
             // equilibrium at the mean density and velocity of the liquid and
@@ -506,17 +594,15 @@ __device__ __forceinline__ bool interface_after(const Dev &d, int y, uint32_t ep
     return (d.flags[y] & T_MASK) == T_IF && !(mk & (MK_TO_LIQ | MK_EMPTY));
 }
 
+// excess mass of an interface cell that fills or empties this step
 template <class S>
-__global__ __launch_bounds__(LIST_THREADS) void k_conv3(Dev d, int p, uint32_t epoch)
+__device__ __forceinline__ void conv3_cell(const Dev &d, int p, uint32_t epoch, int c)
 {
     const S *pdf = (const S *)d.pdf[p ^ 1];
-    const int32_t *list = d.list[p];
-    const int count = d.cnt[p];
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const int c = list[t];
+    {
         const uint32_t mk = mark_bits(d.mark[c], epoch);
         const bool filled = mk & MK_TO_LIQ, emptied = mk & MK_EMPTY;
-        if (!filled && !emptied) continue;
+        if (!filled && !emptied) return;
         const Cell pc = cell_xyz(d, c);
         double e;
         if (filled) {
@@ -543,6 +629,19 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv3(Dev d, int p, uint32_t e
     }
 }
 
+// The new interface cells (lnew) and the converted cells of the interface
+// list touch disjoint cells, so both run in one launch.
+template <class S>
+__global__ __launch_bounds__(LIST_THREADS) void k_conv23(Dev d, int p, uint32_t epoch)
+{
+    const int nnew = d.cnt[2], ncur = d.cnt[p];
+    const int n = nnew > ncur ? nnew : ncur;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        if (t < nnew) conv2_cell<S>(d, p, epoch, d.lnew[t]);
+        if (t < ncur) conv3_cell<S>(d, p, epoch, d.list[p][t]);
+    }
+}
+
 __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t epoch)
 {
     const int32_t *list = d.list[p];
@@ -565,15 +664,21 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t e
         }
         if (keep) {
             const Cell pc = cell_xyz(d, c);
-            double add = 0.0;
+            const double mq0 = d.mq[c], rho0 = d.rho[c];
+            int nb[27];
+            uint32_t mk[27];
+#pragma unroll
             for (int i = 0; i < 27; ++i) {
-                if (i == REST) continue;
-                const int y = nb_of(d, pc, i);
-                if (y >= 0 && (mark_bits(d.mark[y], epoch) & (MK_TO_LIQ | MK_EMPTY))) add += d.share[y];
+                nb[i] = i == REST ? -1 : nb_of(d, pc, i);
+                mk[i] = nb[i] < 0 ? 0u : d.mark[nb[i]];
             }
-            const double m = d.mq[c] + add;
+            double add = 0.0;
+#pragma unroll
+            for (int i = 0; i < 27; ++i)
+                if (nb[i] >= 0 && (mark_bits(mk[i], epoch) & (MK_TO_LIQ | MK_EMPTY))) add += d.share[nb[i]];
+            const double m = mq0 + add;
             d.mq[c] = m;
-            d.phi[c] = m / d.rho[c];
+            d.phi[c] = m / rho0;
         }
         list_append(d.list[p ^ 1], &d.cnt[p ^ 1], keep, c);
     }
@@ -608,15 +713,15 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
         const Cell pc = cell_xyz(d, c);
         const double pv = d.phi[c];
         const double centre = pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv);
-        double s[27], o[4];
+        double s[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) s[i] = i == REST ? centre : stencil_value<double>(d, nb_of(d, pc, i), centre);
-        fd_geometry(s, o);
+        const double4 o = fd_geometry(s);
         R4 out;
-        out.x = R(o[0]);
-        out.y = R(o[1]);
-        out.z = R(o[2]);
-        out.w = R(o[3]);
+        out.x = R(o.x);
+        out.y = R(o.y);
+        out.z = R(o.z);
+        out.w = R(o.w);
         ((R4 *)d.geom)[c] = out;
     }
 }
@@ -633,15 +738,14 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
     if (ev0) (void)hipEventRecord(ev0, st);
     k_bulk<S><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
-    k_iface<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_conv2<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_conv3<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_conv4<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     if (mlpP)
-        launch_geom_mlp<R>(d, p ^ 1, list_blocks, mlpP, mlpPk, st);
+        k_iface<S, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     else
-        k_geom<R><<<list_blocks, LIST_THREADS, 0, st>>>(d, p ^ 1);
+        k_iface<S, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv23<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv4<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    if (mlpP) launch_geom_mlp<R>(d, p ^ 1, list_blocks, mlpP, mlpPk, st);
 }
 
 #define FSL_STEP_INST(S)                                                                          \
