@@ -1,18 +1,31 @@
 """Benchmark of the free-surface cumulant LBM step on one MI355X.
 
 One step = one pass of the whole hot path (dense stream-collide, interface
-stream-collide with reconstruction and mass flux, conversion, excess mass,
-normals/curvature) over the synthetic sediment flume 1536 x 40 x 192
+stream-collide with normals/curvature, reconstruction and mass flux,
+conversion, excess mass) over the synthetic sediment flume 1536 x 40 x 192
 (three layers of diameter-10 spheres with small prescribed velocities, 60
 cells of liquid above the bed, FP32 PDF storage).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+
+HBM traffic of the dense kernel comes from two rocprofv3 counter runs of
+this same command (FETCH_SIZE, then WRITE_SIZE), summarised by
+
+    python bench.py --pmc-summary FETCH_DIR WRITE_DIR > profiles/<name>.md
+
+The 1 GiB device copy that the bench times (rocclr copyBuffer) calibrates
+the counters; the summary stores a hash of the dense kernel's sources and
+the traffic is reported only while the sources still match.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,6 +36,103 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
+COPY_BYTES = 1 << 30          # the calibration copy: 1 GiB read + 1 GiB written
+BULK_SOURCES = ["paper_2301_10674_amd/csrc/fsl_step.hip", "paper_2301_10674_amd/csrc/fsl_device.h",
+                "paper_2301_10674_amd/csrc/fsl_kernels.h"]
+KERNEL_NAMES = {"fp32": "k_bulk<float>", "fp64": "k_bulk<double>", "fp16": "k_bulkIDF16_"}
+
+
+def bulk_source_hash():
+    h = hashlib.sha256()
+    for f in BULK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    return [r for f in files for r in csv.DictReader(open(f))]
+
+
+def counter_means(rows, copy_grid):
+    """Mean counter value (KiB per dispatch) of the dense kernel per storage
+    form and of the calibration copies (copyBuffer dispatches of grid size
+    copy_grid)."""
+    vals = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        key = None
+        if "copyBuffer" in name and r["Grid_Size"] == copy_grid:
+            key = "copy"
+        for prec, kn in KERNEL_NAMES.items():
+            if kn in name:
+                key = prec
+        if key:
+            vals.setdefault(key, []).append(float(r["Counter_Value"]))
+    return rows[0]["Counter_Name"], {k: sum(v) / len(v) for k, v in vals.items()}, \
+        {k: len(v) for k, v in vals.items()}
+
+
+def pmc_summary(fetch_dir, write_dir):
+    rf, rw = counter_rows(fetch_dir), counter_rows(write_dir)
+    # the calibration copies are the copyBuffer dispatches that write 1 GiB
+    grids = {r["Grid_Size"] for r in rw if "copyBuffer" in r["Kernel_Name"]
+             and abs(float(r["Counter_Value"]) * 1024.0 - COPY_BYTES) < 0.01 * COPY_BYTES}
+    assert len(grids) == 1, grids
+    g = grids.pop()
+    cf, fetch, nf = counter_means(rf, g)
+    cw, write, nw = counter_means(rw, g)
+    assert cf == "FETCH_SIZE" and cw == "WRITE_SIZE", (cf, cw)
+    # the copy moves COPY_BYTES each way: scale = true bytes / counted bytes
+    kf = COPY_BYTES / (fetch["copy"] * 1024.0)
+    kw = COPY_BYTES / (write["copy"] * 1024.0)
+    out = {"source_hash": bulk_source_hash(), "fetch_scale": kf, "write_scale": kw, "forms": {}}
+    lines = ["| form | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | read GB | written GB | traffic GB |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for prec in ("fp32", "fp16", "fp64"):
+        if prec in fetch and prec in write:
+            rd = fetch[prec] * 1024.0 * kf / 1e9
+            wr = write[prec] * 1024.0 * kw / 1e9
+            out["forms"][prec] = {"fetch_kib": fetch[prec], "write_kib": write[prec], "read_gb": rd,
+                                  "write_gb": wr, "traffic_gb": rd + wr, "dispatches": nf[prec]}
+            lines.append("| %s | %.0f | %.0f | %.3f | %.3f | %.3f |" % (prec, fetch[prec], write[prec], rd, wr, rd + wr))
+    print("Calibration: the 1 GiB device copy reads %.0f KiB (FETCH_SIZE) and writes %.0f KiB "
+          "(WRITE_SIZE) per dispatch, so the scales are x%.3f and x%.3f.\n" % (fetch["copy"], write["copy"], kf, kw))
+    print("\n".join(lines))
+    print("\n```json\n%s\n```" % json.dumps(out, indent=1))
+
+
+def trace_summary(d):
+    """Per-kernel table from a rocprofv3 --kernel-trace --stats run (CSV)."""
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no kernel_stats.csv under %s" % d)
+    rows = list(csv.DictReader(open(files[0])))
+    print("| kernel | calls | avg µs | min µs | max µs | total ms | % |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        name = re.sub(r"\(.*", "", r["Name"]).replace("void ", "")
+        print("| %s | %s | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+
+
+def stored_traffic(workload, precision):
+    """Traffic per launch (bytes) of the dense kernel from the committed
+    counter summary, or None when there is none or the sources changed."""
+    f = os.path.join(ROOT, "profiles", "k_bulk_%s_traffic.md" % workload)
+    if not os.path.exists(f):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(f).read(), re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != bulk_source_hash() or precision not in d.get("forms", {}):
+        return None
+    return d["forms"][precision]["traffic_gb"] * 1e9
 
 
 def log(*a):
@@ -131,7 +241,17 @@ def main():
     ap.add_argument("--forms", default="fp16,fp64",
                     help="other storage forms timed on the same workload ('' for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 counter runs of this command and exit")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run of this command and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -160,6 +280,7 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline()
 
     r = main_res
+    traffic = stored_traffic(w.name, args.precision)
     out = {
         "metric": "MLUPS free-surface D3Q27 cumulant (FP64/FP32/FP16-store), % HBM roofline",
         "value": r["mlups_fluid"], "unit": "MLUPS (fluid cells)", "n_gpus": 1,
@@ -170,7 +291,7 @@ def main():
         "config": {"workload": w.name, "precision": args.precision, "spheres": w.meta["spheres"],
                    "depth": w.meta["depth"], "cells": w.ncells},
         "roofline": {"bound": "hbm", "achieved": r["bulk_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["bulk_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r["bulk_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_bulk", "bytes_per_launch": r["bytes_per_launch"],
                      "avg_launch_us": r["bulk_us"], "copy_gbs": copy_gbs,
                      "frac_of_copy": r["bulk_gbs"] / copy_gbs},
