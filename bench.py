@@ -146,16 +146,57 @@ def fluid_counts(lat, fsl):
     return liq, itf
 
 
-def run_form(w, precision, steps, warmup):
+def interface_error(lat, fsl):
+    """RMS angle (degrees) and RMS curvature error of the normals and
+    curvatures the lattice uses, against height-function labels of its own
+    fill field (interface cells whose 3x3 columns of 7 cells are bracketed
+    by liquid and gas)."""
+    from paper_2301_10674_amd import estimator as E
+    from paper_2301_10674_amd import train as T
+
+    X, Y, cells = T.lattice_samples(lat, fsl)
+    f = lat.read_fields([fsl.FIELD_NORMAL, fsl.FIELD_CURV])
+    n = f[fsl.FIELD_NORMAL].reshape(3, -1)[:, cells].T
+    k = f[fsl.FIELD_CURV].reshape(-1)[cells]
+    ang, kap = E.errors(np.concatenate([n, k[:, None]], axis=1), Y)
+    return {"rms_angle_deg": ang, "rms_kappa": kap, "cells": int(len(cells))}
+
+
+def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=10, seed=0):
+    """Train the estimator for a lattice: analytic stencils plus height-
+    function labelled stencils of the lattice's own fill fields (taken while
+    it runs the plain estimator), on the GPU; returns weights and report."""
+    from paper_2301_10674_amd import train as T
+
+    t0 = time.perf_counter()
+    Xa, Ya = T.analytic_dataset(n_analytic, seed=seed)
+    Xf, Yf = T.flume_dataset(lat, fsl, steps, every, n_analytic, seed=seed)
+    X, Y = np.concatenate([Xa, Xf]), np.concatenate([Ya, Yf])
+    Xt, Yt, Xv, Yv = T.split(X, Y, 0.1, seed=seed)
+    rep = T.train(fsl, Xt, Yt, Xv, Yv, epochs=epochs, seed=seed)
+    rep["data_seconds"] = time.perf_counter() - t0 - rep["train_seconds"]
+    w = rep.pop("weights")
+    rep.pop("losses")
+    return w, rep
+
+
+def run_form(w, form, steps, warmup):
     import torch
 
     from paper_2301_10674_amd import fsl
 
-    lat = fsl.lattice_from_workload(w, precision)
+    precision, learned = form.split("-")[0], form.endswith("-learned")
+    lat = fsl.lattice_from_workload(w, precision, normals=1 if learned else 0)
+    est = None
+    if learned:
+        weights, est = learned_weights(lat, fsl)
+        if est["gate"]:
+            lat.set_estimator(weights)
     lat.step(warmup)
     torch.cuda.synchronize()
     liq0, itf0 = fluid_counts(lat, fsl)
     M0 = lat.total_mass()
+    used0 = lat.estimator_stats() if learned else (0, 0)
     lat.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -173,12 +214,15 @@ def run_form(w, precision, steps, warmup):
     bulk_avg_s = bulk_ms / 1e3 / max(launches, 1)
     bytes_per_launch = liq * (54 * s + 16) + w.ncells * 1
     res = dict(
-        precision=precision, secs=secs, ms_per_step=1e3 * secs / steps,
+        form=form, precision=precision, secs=secs, ms_per_step=1e3 * secs / steps,
         mlups_fluid=fluid * steps / secs / 1e6, mlups_all=w.ncells * steps / secs / 1e6,
         bulk_us=1e6 * bulk_avg_s, bulk_launches=launches,
         bulk_gbs=bytes_per_launch / bulk_avg_s / 1e9, bytes_per_launch=bytes_per_launch,
         liquid_cells=liq, fluid_cells=fluid, interface_cells=0.5 * (itf0 + itf1),
-        mass_drift=abs(M1 - M0) / M0)
+        mass_drift=abs(M1 - M0) / M0, interface_error=interface_error(lat, fsl))
+    if learned:
+        used1 = lat.estimator_stats()
+        res["estimator"] = dict(est, network_cells=used1[0] - used0[0], fallback_cells=used1[1] - used0[1])
     lat.destroy()
     del lat
     torch.cuda.synchronize()
@@ -234,12 +278,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "fp64", "fp32-learned", "fp16-learned"])
     ap.add_argument("--nx", type=int, default=1536)
     ap.add_argument("--ny", type=int, default=40)
     ap.add_argument("--nz", type=int, default=192)
-    ap.add_argument("--forms", default="fp16,fp64",
-                    help="other storage forms timed on the same workload ('' for none)")
+    ap.add_argument("--forms", default="fp16,fp64,fp32-learned",
+                    help="other forms timed on the same workload ('' for none): fp16, fp64, fp32, "
+                         "fp32-learned (estimator trained in the run, see train.py)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 counter runs of this command and exit")
@@ -280,13 +325,14 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline()
 
     r = main_res
-    traffic = stored_traffic(w.name, args.precision)
+    base = args.precision.split("-")[0]
+    traffic = stored_traffic(w.name, base)
     out = {
         "metric": "MLUPS free-surface D3Q27 cumulant (FP64/FP32/FP16-store), % HBM roofline",
         "value": r["mlups_fluid"], "unit": "MLUPS (fluid cells)", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16-store/f32", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "fp16": "f16-store/f32", "fp64": "f64"}[base],
         "data": "synthetic seeded flume (no dataset)",
         "config": {"workload": w.name, "precision": args.precision, "spheres": w.meta["spheres"],
                    "depth": w.meta["depth"], "cells": w.ncells},
@@ -298,8 +344,8 @@ def main():
         "cpu_baseline": cpu,
         "mlups_all_cells": r["mlups_all"],
         "mass_drift": r["mass_drift"],
-        "forms": {k: {"mlups_fluid": v["mlups_fluid"], "ms_per_step": v["ms_per_step"],
-                      "bulk_gbs": v["bulk_gbs"], "mass_drift": v["mass_drift"]}
+        "forms": {k: {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_gbs", "mass_drift",
+                                          "interface_error", "estimator") if kk in v}
                   for k, v in forms.items()},
     }
     print(json.dumps(out), flush=True)

@@ -176,15 +176,16 @@ FslStatus fsl_timing_read(FslLattice *lat, double *ms_total, int64_t *launches);
  * the finite-difference estimate (Parker-Youngs normal, Hessian curvature of
  * the 3x3x3 fill stencil) the library offers a small network: 27 fill levels
  * (input clamp(phi, 0, 1) - 1/2, stencil entry a + 3b + 9c = offset
- * (a-1, b-1, c-1)) -> 64 -> 64 -> 4 with tanh hidden layers; outputs 0..2
- * are the normal (liquid -> gas; trained towards the unit normal and
- * normalised when used), output 3 is 4 kappa.  Weights
- * are 6212 floats: W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
- * (row-major, out x in).  Matrix products run in BF16 on the matrix cores
- * with FP32 accumulation; the master weights are FP32.
- * Loss per sample: |y[0..2] - n*|^2 + (y[3] - 4 kappa*)^2, mean over
- * the batch.  Host arrays: x float [n][27] fill levels, y float [n][4] target
- * unit normal and kappa. */
+ * (a-1, b-1, c-1)) -> 64 -> 64 -> 4 with tanh hidden layers.  Inside a
+ * lattice its outputs y correct the finite-difference estimate (n_fd, k_fd)
+ * of the same stencil: n = (n_fd + y[0..2]) / |n_fd + y[0..2]| (liquid ->
+ * gas), kappa = k_fd + y[3] / 4.  Weights are 6212 floats: W1[64][27],
+ * b1[64], W2[64][64], b2[64], W3[4][64], b3[4] (row-major, out x in).
+ * Matrix products run in BF16 on the matrix cores with FP32 accumulation;
+ * the master weights are FP32.  Loss per sample against targets t:
+ * |y[0..2] - t[0..2]|^2 + (y[3] - 4 t[3])^2, mean over the batch (for use
+ * in a lattice, t = (n* - n_fd, kappa* - k_fd)).  Host arrays: x float
+ * [n][27] fill levels, y float [n][4] targets. */
 typedef struct {
     int32_t epochs;         /* passes over the data (> 0) */
     int32_t batch;          /* samples per Adam step (>= 16) */
@@ -207,11 +208,22 @@ FslStatus fsl_estimator_grad(const float *weights, const float *x, const float *
 FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n,
                               float *y, void *hip_stream);
 
+/* Finite-difference geometry (Section 2.1 curvature; Parker-Youngs normal
+ * and Hessian mean curvature, evaluated in FP64) of n stencils x float
+ * [n][27] of fill levels (entry a + 3b + 9c = offset (a-1, b-1, c-1);
+ * values are clamped to [0, 1]).  y float [n][4] receives the unit normal
+ * pointing from liquid to gas and kappa (0 where the gradient vanishes).
+ * Host arrays, owned by the caller; FSL_ERR_ARG for NULL or n outside
+ * [1, 2^30]; synchronises hip_stream.  This is the estimate the learned
+ * network is compared with and falls back to. */
+FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream);
+
 /* Attach trained weights to a lattice.  With params.normals == 1 the
- * geometry of every interface cell then comes from the network, except where
- * a stencil cell is solid, |n_raw| is outside [0.5, 2], the network normal
- * differs from the finite-difference one by more than 30 degrees, or
- * |kappa| > 0.5: there the finite-difference estimate is kept. */
+ * geometry of every interface cell then comes from the corrected estimate,
+ * except where a stencil cell is solid, |n_fd + y[0..2]| is outside
+ * [0.5, 2], the corrected normal differs from the finite-difference one by
+ * more than 30 degrees, or |kappa| > 0.5: there the finite-difference
+ * estimate is kept. */
 FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
 
 /* Interface-cell updates since creation that used the network / fell back. */

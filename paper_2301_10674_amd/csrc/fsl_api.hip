@@ -999,6 +999,22 @@ FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n, f
     return FSL_OK;
 }
 
+FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream)
+{
+    if (!x || !y || n <= 0 || n > (1 << 30)) return fail(FSL_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBufs B;
+    float *X, *Y;
+    HIP_TRY(B.get(&X, (size_t)n * 27));
+    HIP_TRY(B.get(&Y, (size_t)n * 4));
+    HIP_TRY(hipMemcpyAsync(X, x, (size_t)n * 27 * 4, hipMemcpyHostToDevice, st));
+    fd_stencils(X, (int)n, Y, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(y, Y, (size_t)n * 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return FSL_OK;
+}
+
 const char *fsl_last_error(void) { return g_err.c_str(); }
 
 void fsl_destroy(FslLattice *L)

@@ -31,6 +31,7 @@ void mlp_grad(const float *X, const float *T, const int32_t *idx, int nbatch, fl
 void mlp_adam(float *P, float *m, float *v, const float *g, float lr, float b1, float b2, float eps, float c1,
               float c2, uint16_t *pk, hipStream_t st);
 void mlp_infer(const float *X, int n, const float *P, const uint16_t *pk, float *Y, hipStream_t st);
+void fd_stencils(const float *X, int n, float *Y, hipStream_t st);
 template <class R>
 void launch_geom_mlp(const Dev &d, int which, int blocks, const float *P, const uint16_t *pk, hipStream_t st);
 

@@ -1,9 +1,11 @@
 // fsl_mlp.hip -- the learned interface estimator on gfx950: a 27 -> 64 ->
 // 64 -> 4 perceptron (tanh hidden layers) from the 3x3x3 fill stencil of an
-// interface cell to its normal (outputs 0..2, trained towards the unit
-// normal and normalised when used) and 4 x mean curvature (output 3).  BF16
-// weights and activations on the matrix cores (v_mfma_f32_16x16x16_bf16,
-// FP32 accumulation), FP32 master weights, Adam.
+// interface cell to the correction of its finite-difference normal (outputs
+// 0..2) and of 4 x its mean curvature (output 3).  BF16 weights and
+// activations on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation), FP32 master weights, Adam.  The kernels train and evaluate
+// the network on whatever targets they are given; the lattice kernel adds
+// its outputs to the finite-difference estimate.
 //
 // Layout of the flat FP32 parameter vector (6212 floats):
 //   W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
@@ -370,61 +372,81 @@ __device__ __forceinline__ int nb_cell(const Dev &d, int x, int y, int z, int i)
     return xx + d.nx * (yy + d.ny * zz);
 }
 
+// Ties a loaded value to this point so that the loads of a stage are issued
+// together (empty asm statement on the register; no instruction).
+template <class T>
+__device__ __forceinline__ void keep_reg(T &v)
+{
+    asm volatile("" : "+v"(v));
+}
+
 // Interface normal and curvature with the learned estimator: per group of 16
-// interface cells, lanes q == 0 gather the fill stencil (liquid 1, gas 0,
-// interface clamp(m/rho), wall/solid = centre), compute the finite-
-// difference estimate, and the wavefront runs the network.  The network's
-// result replaces the finite-difference one unless a stencil cell is solid,
-// |n_raw| lies outside [0.5, 2], the two normals differ by more than 30
-// degrees, or |kappa| > 0.5.
+// interface cells, the four lanes of a cell (lane = cell + 16 q) gather
+// entries q, q+4, ... of its fill stencil (liquid 1, gas 0, interface
+// clamp(m/rho), wall/solid = centre), lanes q == 0 compute the finite-
+// difference estimate (n_fd, k_fd) and the wavefront runs the network, whose
+// outputs y correct it: n_raw = n_fd + y[0..2], kappa = k_fd + y[3] / 4.
+// The corrected estimate replaces the finite-difference one unless a stencil
+// cell is solid, |n_raw| lies outside [0.5, 2], the two normals differ by
+// more than 30 degrees, or |kappa| > 0.5.  Counters are aggregated per
+// wavefront.
 template <class R>
 __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *P, const uint16_t *pk)
 {
     using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
-    __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_PACK_SIZE];
-    __shared__ float sS[16][28];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_W2T];
+    __shared__ double sS[16][28];
     load_weights(sW, pk, MLP_W2T);
     __syncthreads();
     const int32_t *list = d.list[which];
     const int count = d.cnt[which];
     const int l = __lane_id(), r = l & 15, q = l >> 4;
+    unsigned long long used = 0, fell = 0;
     for (int g = blockIdx.x; g * 16 < count; g += gridDim.x) {
         const int t = g * 16 + r;
         const bool valid = t < count;
-        bool any_solid = false;
-        double4 fd = make_double4(0.0, 0.0, 0.0, 0.0);
-        int c = 0;
-        if (q == 0 && valid) {
-            c = list[t];
-            const int x = c % d.nx, y = (c / d.nx) % d.ny, z = c / (d.nx * d.ny);
-            double pv = d.phi[c];
-            const double centre = pv < 0.0 ? 0.0 : (pv > 1.0 ? 1.0 : pv);
-            double s[27];
-            for (int i = 0; i < 27; ++i) {
-                if (i == REST) {
-                    s[i] = centre;
-                    continue;
-                }
-                const int yc = nb_cell(d, x, y, z, i);
-                uint8_t ty = yc < 0 ? (uint8_t)T_SOLID : (uint8_t)(d.flags[yc] & T_MASK);
-                if (ty == T_SOLID) {
-                    any_solid = true;
-                    s[i] = centre;
-                } else if (ty == T_LIQ) {
-                    s[i] = 1.0;
-                } else if (ty == T_GAS) {
-                    s[i] = 0.0;
-                } else {
-                    const double v = d.phi[yc];
-                    s[i] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
-                }
-            }
-            for (int i = 0; i < 27; ++i) sS[r][i] = (float)s[i];
-            fd = fd_geometry(s);
-        } else if (q == 0) {
-            for (int i = 0; i < 27; ++i) sS[r][i] = 0.5f;
+        const int c = valid ? list[t] : 0;
+        const int x = c % d.nx, y = (c / d.nx) % d.ny, z = c / (d.nx * d.ny);
+        // entries k = q + 4 m of the stencil, all loads issued together
+        uint32_t fl[7];
+        double ph[7];
+        double pc = d.phi[c];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            const int k = q + 4 * m;
+            const int yc = k < 27 ? nb_cell(d, x, y, z, k) : -1;
+            const uint32_t a = (uint32_t)(yc < 0 ? c : yc);
+            fl[m] = yc < 0 ? (uint32_t)T_SOLID : (uint32_t)d.flags[a];
+            ph[m] = d.phi[a];
         }
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            keep_reg(fl[m]);
+            keep_reg(ph[m]);
+        }
+        keep_reg(pc);
+        const double centre = pc < 0.0 ? 0.0 : (pc > 1.0 ? 1.0 : pc);
+        bool solid = false;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            const int k = q + 4 * m;
+            if (k >= 27) continue;
+            const uint32_t ty = fl[m] & T_MASK;
+            const double pv = ph[m] < 0.0 ? 0.0 : (ph[m] > 1.0 ? 1.0 : ph[m]);
+            solid |= k != REST && ty == T_SOLID;
+            sS[r][k] = k == REST ? centre
+                                 : (ty == T_LIQ ? 1.0 : (ty == T_GAS ? 0.0 : (ty == T_IF ? pv : centre)));
+        }
+        const uint64_t sb = __ballot(solid);
+        const bool any_solid = ((sb >> r) | (sb >> (r + 16)) | (sb >> (r + 32)) | (sb >> (r + 48))) & 1ull;
         __syncthreads();
+        double4 fd = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (q == 0) {
+            double st[27];
+#pragma unroll
+            for (int i = 0; i < 27; ++i) st[i] = sS[r][i];
+            fd = fd_geometry(st);
+        }
         v4s xb[2];
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) {
@@ -432,39 +454,75 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = 16 * kt + 4 * q + j;
-                v[j] = k < 27 ? sS[r][k] - 0.5f : 0.f;
+                v[j] = (valid && k < 27) ? (float)sS[r][k] - 0.5f : 0.f;
             }
             xb[kt] = pack4(v[0], v[1], v[2], v[3]);
         }
         Fwd F;
         mlp_forward16(sW, P, xb, F);
         __syncthreads();
+        bool use = false;
         if (q == 0 && valid) {
             R4 out;
             out.x = R(fd.x);
             out.y = R(fd.y);
             out.z = R(fd.z);
             out.w = R(fd.w);
-            const float rn = sqrtf(F.y[0] * F.y[0] + F.y[1] * F.y[1] + F.y[2] * F.y[2]);
-            bool use = !any_solid && rn >= 0.5f && rn <= 2.f;
-            const float kap = 0.25f * F.y[3];
+            // the network corrects the finite-difference estimate
+            const double nx = fd.x + (double)F.y[0], ny = fd.y + (double)F.y[1], nz = fd.z + (double)F.y[2];
+            const double rn = sqrt(nx * nx + ny * ny + nz * nz);
+            const double kap = fd.w + 0.25 * (double)F.y[3];
+            use = !any_solid && rn >= 0.5 && rn <= 2.0;
             if (use) {
-                const float cosang = ((float)fd.x * F.y[0] + (float)fd.y * F.y[1] + (float)fd.z * F.y[2]) / rn;
-                use = cosang >= 0.8660254f && fabsf(kap) <= 0.5f;
+                const double cosang = (fd.x * nx + fd.y * ny + fd.z * nz) / rn;
+                use = cosang >= 0.8660254037844386 && fabs(kap) <= 0.5;
             }
             if (use) {
-                out.x = R(F.y[0] / rn);
-                out.y = R(F.y[1] / rn);
-                out.z = R(F.y[2] / rn);
+                out.x = R(nx / rn);
+                out.y = R(ny / rn);
+                out.z = R(nz / rn);
                 out.w = R(kap);
             }
             ((R4 *)d.geom)[c] = out;
-            atomicAdd(&d.stats[use ? 8 : 9], 1ull);
         }
+        used += __popcll(__ballot(q == 0 && valid && use));
+        fell += __popcll(__ballot(q == 0 && valid && !use));
+    }
+    if (l == 0) {
+        if (used) atomicAdd(&d.stats[8], used);
+        if (fell) atomicAdd(&d.stats[9], fell);
+    }
+}
+
+// finite-difference geometry of stencils given as fill levels [n][27]
+__global__ __launch_bounds__(256) void k_fd_stencils(const float *X, int n, float *Y)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        double s[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const double v = (double)X[(size_t)t * 27 + i];
+            s[i] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+        }
+        const double4 g = fd_geometry(s);
+        float4 o;
+        o.x = (float)g.x;
+        o.y = (float)g.y;
+        o.z = (float)g.z;
+        o.w = (float)g.w;
+        ((float4 *)Y)[t] = o;
     }
 }
 
 // ---------------------------------------------------------------- launchers
+void fd_stencils(const float *X, int n, float *Y, hipStream_t st)
+{
+    int blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_fd_stencils<<<blocks, 256, 0, st>>>(X, n, Y);
+}
+
 void mlp_pack(const float *P, uint16_t *pk, hipStream_t st)
 {
     k_mlp_pack<<<(MLP_PACK_SIZE + 255) / 256, 256, 0, st>>>(P, pk);

@@ -1,11 +1,21 @@
-"""Training driver of the learned interface estimator.
+"""Learned interface estimator: targets, composition and the gate.
 
 The network, its loss, the training kernels and the inference inside the
-lattice step live in the HIP library (``fsl_estimator_*``); this module only
-prepares data, initial weights and the validation gate:
+lattice step live in the HIP library (``fsl_estimator_*``).  The network
+reads the 3x3x3 fill stencil and predicts the correction to the finite-
+difference estimate of the same stencil (Parker-Youngs normal n_fd and
+Hessian curvature k_fd):
 
-* ``init_weights``: seeded Glorot-uniform weights, zero biases, except that
-  the output bias starts the normal at +z (so |n_raw| > 0 from the start);
+    n_raw = n_fd + y[0:3],  n = n_raw / |n_raw|,  kappa = k_fd + y[3] / 4,
+
+so that planar interfaces, where finite differences are exact, stay exact,
+and the curvature keeps the finite-difference response to the fill field.
+This module prepares the training targets and initial weights, composes
+predictions, and holds the validation gate:
+
+* ``init_weights``: seeded Glorot-uniform weights, zero biases;
+* ``residual_targets`` / ``compose``: labels -> network targets, network
+  outputs -> (normal, curvature);
 * ``errors``: RMS angle (degrees) and RMS curvature error of predictions;
 * ``gate``: the network is used by a lattice only if it beats the finite-
   difference estimate on held-out data in both errors.
@@ -26,9 +36,27 @@ def init_weights(seed: int = 0) -> np.ndarray:
             parts.append(rng.uniform(-lim, lim, shp).ravel())
         else:
             parts.append(np.zeros(shp))
-    w = np.concatenate(parts).astype(np.float32)
-    w[-2] = 1.0   # b3[2]: start the normal at +z
-    return w
+    return np.concatenate(parts).astype(np.float32)
+
+
+def residual_targets(labels, fd):
+    """Network targets: (n* - n_fd, kappa* - k_fd) for labels (n*, kappa*)
+    and the finite-difference estimates fd, both (n, 4)."""
+    labels = np.asarray(labels, dtype=np.float64)
+    fd = np.asarray(fd, dtype=np.float64)
+    return (labels - fd).astype(np.float32)
+
+
+def compose(y, fd):
+    """(normal, kappa) from raw network outputs y and the finite-difference
+    estimates fd, both (n, 4)."""
+    y = np.asarray(y, dtype=np.float64)
+    fd = np.asarray(fd, dtype=np.float64)
+    out = np.empty_like(y)
+    n = fd[:, :3] + y[:, :3]
+    out[:, :3] = n / np.maximum(np.linalg.norm(n, axis=1, keepdims=True), 1e-30)
+    out[:, 3] = fd[:, 3] + 0.25 * y[:, 3]
+    return out
 
 
 def errors(pred, labels):
@@ -37,13 +65,6 @@ def errors(pred, labels):
     cosang = np.clip((n * labels[:, :3]).sum(1), -1.0, 1.0)
     ang = np.degrees(np.arccos(cosang))
     return float(np.sqrt(np.mean(ang ** 2))), float(np.sqrt(np.mean((pred[:, 3] - labels[:, 3]) ** 2)))
-
-
-def network_outputs(y):
-    """Raw network outputs -> (normal, kappa) columns (output 3 is 4 kappa)."""
-    out = np.array(y, dtype=np.float64)
-    out[:, 3] *= 0.25
-    return out
 
 
 def gate(net_err, fd_err):

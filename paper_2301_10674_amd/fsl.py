@@ -27,6 +27,7 @@ GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fsl_step",
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
+           "fsl_fd_geometry",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
 
@@ -116,6 +117,8 @@ def lib():
         L.fsl_estimator_grad.argtypes = [fp, fp, fp, ctypes.c_int64, fp, dp, vp]
         L.fsl_estimator_infer.restype = ctypes.c_int
         L.fsl_estimator_infer.argtypes = [fp, fp, ctypes.c_int64, fp, vp]
+        L.fsl_fd_geometry.restype = ctypes.c_int
+        L.fsl_fd_geometry.argtypes = [fp, ctypes.c_int64, fp, vp]
         L.fsl_set_estimator.restype = ctypes.c_int
         L.fsl_set_estimator.argtypes = [vp, fp]
         L.fsl_estimator_stats.restype = ctypes.c_int
@@ -313,4 +316,13 @@ def estimator_infer(weights, x):
     n = x.size // 27
     y = np.zeros(4 * n, dtype=np.float32)
     _check(lib().fsl_estimator_infer(_fp(w), _fp(x), n, _fp(y), _stream()))
+    return y.reshape(n, 4)
+
+
+def fd_geometry(x):
+    """Finite-difference normal and curvature of stencils x (n, 27) -> (n, 4)."""
+    x = _f32(x)
+    n = x.size // 27
+    y = np.zeros(4 * n, dtype=np.float32)
+    _check(lib().fsl_fd_geometry(_fp(x), n, _fp(y), _stream()))
     return y.reshape(n, 4)

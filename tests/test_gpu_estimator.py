@@ -4,8 +4,9 @@
   BF16-rounded weights and inputs (the GPU also rounds activations to BF16,
   hence the 2e-2 relative tolerance);
 * training lowers the loss;
-* gain test: trained on seeded analytic stencils, the network beats the
-  finite-difference estimate (Parker-Youngs normal, Hessian curvature) on
+* gain test: trained on seeded analytic stencils towards the corrections of
+  the finite-difference estimate (Parker-Youngs normal, Hessian curvature;
+  the oracle's), the corrected estimate beats the finite-difference one on
   held-out stencils in both RMS angle and RMS curvature error;
 * a lattice with the estimator attached runs, uses the network and falls
   back where required, and still conserves mass.
@@ -91,9 +92,10 @@ def fd_predictions(X):
 
 def test_network_beats_finite_differences(data):
     X, Y, Xh, Yh = data
-    w, losses = F().estimator_train(X, Y, E.init_weights(6), epochs=25, batch=512, lr=2e-3, seed=2)
-    net = E.network_outputs(F().estimator_infer(w, Xh))
+    T = E.residual_targets(Y, fd_predictions(X))
+    w, losses = F().estimator_train(X, T, E.init_weights(6), epochs=25, batch=512, lr=2e-3, seed=2)
     fd = fd_predictions(Xh)
+    net = E.compose(F().estimator_infer(w, Xh), fd)
     e_net, e_fd = E.errors(net, Yh), E.errors(fd, Yh)
     print("held-out RMS angle / kappa error: network %.2f deg / %.4f, finite differences %.2f deg / %.4f"
           % (e_net[0], e_net[1], e_fd[0], e_fd[1]))
@@ -102,7 +104,8 @@ def test_network_beats_finite_differences(data):
 
 def test_lattice_with_estimator_conserves_mass(data):
     X, Y = data[0][:20000], data[1][:20000]
-    w, _ = F().estimator_train(X, Y, E.init_weights(7), epochs=10, batch=512, lr=2e-3, seed=3)
+    T = E.residual_targets(Y, fd_predictions(X))
+    w, _ = F().estimator_train(X, T, E.init_weights(7), epochs=10, batch=512, lr=2e-3, seed=3)
     f = F()
     wl = I.channel_film()
     g = f.lattice_from_workload(wl, "fp32", normals=1)
@@ -117,3 +120,10 @@ def test_lattice_with_estimator_conserves_mass(data):
     itf = t == f.INTERFACE
     nn = np.linalg.norm(n[:, itf], axis=0)
     assert np.all((np.abs(nn - 1.0) < 1e-5) | (nn == 0.0))
+
+
+def test_gpu_finite_differences_match_oracle(data):
+    X = data[2][:2000]
+    g = F().fd_geometry(X)
+    o = fd_predictions(X)
+    assert np.abs(g - o).max() < 1e-6
