@@ -191,3 +191,25 @@ def flat_film(shape=(4, 4, 24), h=16.5, omega=1.0, gx=1e-6, gz=0.0, sigma=0.0):
         vel=np.zeros((3, nz, ny, nx)), centre=np.zeros((0, 3)),
         radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
         sphere_angvel=np.zeros((0, 3)), meta={"h": h})
+
+
+def droplet(n: int = 40, radius: float = 10.0, sigma: float = 1e-3, omega: float = 1.0,
+            ss: int = 4) -> Workload:
+    """Static droplet of the given radius centred in an n^3 box at rest, no
+    gravity; fill levels by supersampling each cell on an ss^3 grid."""
+    o = (np.arange(ss) + 0.5) / ss
+    g = np.arange(n) - 0.5 * n
+    fill = np.zeros((n, n, n))
+    for a in o:
+        for b in o:
+            for c in o:
+                z = (g + a)[:, None, None]
+                y = (g + b)[None, :, None]
+                x = (g + c)[None, None, :]
+                fill += x * x + y * y + z * z <= radius * radius
+    fill /= ss ** 3
+    return Workload(
+        name="droplet_%d_r%g" % (n, radius), shape=(n, n, n), omega=omega, accel=(0.0, 0.0, 0.0),
+        sigma=sigma, fill=fill, rho=np.ones((n, n, n)), vel=np.zeros((3, n, n, n)),
+        centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+        sphere_angvel=np.zeros((0, 3)), meta={"radius": radius})
