@@ -30,12 +30,18 @@
  *                  shared evenly among interface neighbours, a pool otherwise;
  *   geometry    -- Parker-Youngs normal, mean curvature from the finite-
  *                  difference Hessian of the same 3x3x3 fill stencil.
+ * The two per-cell phases (stream-collide, geometry) may run their cells on
+ * several threads (OpenMP): every cell reads the previous state and writes
+ * only its own entries, so the result does not depend on the thread count.
  */
 #include "fsl_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 27
 #define REST 13
@@ -436,6 +442,7 @@ static void geometry_cell(OlLattice *L, int64_t c)
 
 static void phase_geometry(OlLattice *L)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < L->N; ++c) {
         if (L->type[c] == OL_INTERFACE) {
             geometry_cell(L, c);
@@ -444,6 +451,28 @@ static void phase_geometry(OlLattice *L)
             L->kappa[c] = 0.0;
         }
     }
+}
+
+/* Nearest IEEE binary16 value: 11 significant bits for |x| >= 2^-14 (the
+ * smallest normal), spacing 2^-24 below; ties to even (nearbyint in the
+ * default rounding mode).  Deviations stay far below the FP16 maximum. */
+double ol_round_half(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e); /* |x| in [2^(e-1), 2^e) */
+    const double q = (e - 1 >= -14) ? ldexp(1.0, e - 11) : ldexp(1.0, -24);
+    return nearbyint(x / q) * q;
+}
+
+/* the storage form: FP64 as is, or deviations from w rounded to FP32 (the
+ * C conversion rounds to nearest even) or to FP16 */
+static void store_form(const OlLattice *L, double *f)
+{
+    if (L->p.store == 1)
+        for (int i = 0; i < Q; ++i) f[i] = WT[i] + (double)(float)(f[i] - WT[i]);
+    else if (L->p.store == 2)
+        for (int i = 0; i < Q; ++i) f[i] = WT[i] + ol_round_half(f[i] - WT[i]);
 }
 
 static double sum27(const double *f)
@@ -513,6 +542,7 @@ OlLattice *ol_create(const OlParams *p, const double *fill, const double *rho,
         if (vel)
             for (int d = 0; d < 3; ++d) u[d] = vel[(int64_t)d * N + c];
         ol_feq(rho[c], u, &L->f[c * Q]);
+        store_form(L, &L->f[c * Q]);
         L->rho[c] = sum27(&L->f[c * Q]);
         L->m[c] = (L->type[c] == OL_GAS) ? 0.0 : clamp01(fill[c]) * rho[c];
     }
@@ -599,9 +629,15 @@ static void phase_stream_collide(OlLattice *L)
     const OlParams *p = &L->p;
     double *fnew = (double *)malloc((size_t)N * Q * sizeof(double));
     double *mnew = (double *)malloc((size_t)N * sizeof(double));
-    memcpy(fnew, L->f, (size_t)N * Q * sizeof(double));
-    memcpy(mnew, L->m, (size_t)N * sizeof(double));
+    /* cells that do not stream keep their state */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        memcpy(&fnew[c * Q], &L->f[c * Q], Q * sizeof(double));
+        mnew[c] = L->m[c];
+    }
+    int64_t liquid_next_to_gas = 0;
 
+#pragma omp parallel for schedule(static) reduction(+ : liquid_next_to_gas)
     for (int64_t c = 0; c < N; ++c) {
         uint8_t t = L->type[c];
         if (t != OL_LIQUID && t != OL_INTERFACE) continue;
@@ -642,7 +678,7 @@ static void phase_stream_collide(OlLattice *L)
                     if (nc < -p->normal_tie) recon = 1;
                 }
             } else if (L->type[src] == OL_GAS) {
-                L->cnt[7]++;
+                liquid_next_to_gas++;
             }
             if (recon)
                 fin[j] = feqG[j] + feqG[opp(j)] - fo[opp(j)];
@@ -666,8 +702,10 @@ static void phase_stream_collide(OlLattice *L)
         mnew[c] = L->m[c] + dm;
 
         ol_collide(fin, p->accel, p->omega, p->omega_bulk, p->omega_high, &fnew[c * Q]);
+        store_form(L, &fnew[c * Q]);
         L->rho[c] = sum27(&fnew[c * Q]);
     }
+    L->cnt[7] += liquid_next_to_gas;
     free(L->f);
     free(L->m);
     L->f = fnew;
@@ -748,6 +786,7 @@ static void phase_convert(OlLattice *L)
         double rbar = rs / cnt, ubar[3];
         for (int d = 0; d < 3; ++d) ubar[d] = us[d] / cnt;
         ol_feq(rbar, ubar, &L->f[c * Q]);
+        store_form(L, &L->f[c * Q]);
         L->rho[c] = sum27(&L->f[c * Q]);
         L->m[c] = 0.0;
         L->cnt[5]++;
@@ -912,3 +951,21 @@ void ol_counters(const OlLattice *L, int64_t out[8])
 }
 
 int64_t ol_steps_done(const OlLattice *L) { return L->steps; }
+
+void ol_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
+int32_t ol_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

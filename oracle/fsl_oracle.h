@@ -42,6 +42,9 @@ typedef struct {
     double conv_eps;            /* conversion threshold epsilon */
     double normal_tie;          /* n.c_j must be below -normal_tie to trigger reconstruction */
     int32_t rule_isolated;      /* 1: apply the no-gas-neighbour / no-liquid-neighbour conversion rules */
+    int32_t store;              /* storage form: 0 FP64; 1 and 2: every stored PDF is
+                                   w_i + (f_i - w_i) rounded to the nearest FP32 (1) or FP16 (2)
+                                   value, as the reduced-precision forms store deviations */
 } OlParams;
 
 typedef struct OlLattice OlLattice;
@@ -107,6 +110,12 @@ double ol_pool(const OlLattice *L);
  * [6] liquid->interface, [7] liquid cells found next to gas (must stay 0) */
 void ol_counters(const OlLattice *L, int64_t out[8]);
 int64_t ol_steps_done(const OlLattice *L);
+/* threads of the per-cell phases (n <= 0: all processors; results do not
+ * depend on it) and the number in use */
+void ol_set_threads(int32_t n);
+/* nearest FP16 value of x (ties to even, subnormals kept), as a double */
+double ol_round_half(double x);
+int32_t ol_threads(void);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", tmp, SRC, MLP_SRC, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, MLP_SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
         ("omega_high", ctypes.c_double), ("accel", ctypes.c_double * 3),
         ("sigma", ctypes.c_double), ("rho_gas", ctypes.c_double),
         ("conv_eps", ctypes.c_double), ("normal_tie", ctypes.c_double),
-        ("rule_isolated", ctypes.c_int32),
+        ("rule_isolated", ctypes.c_int32), ("store", ctypes.c_int32),
     ]
 
 
@@ -77,6 +77,10 @@ def lib():
         L.ol_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         L.ol_steps_done.restype = ctypes.c_int64
         L.ol_steps_done.argtypes = [ctypes.c_void_p]
+        L.ol_set_threads.argtypes = [ctypes.c_int32]
+        L.ol_round_half.restype = ctypes.c_double
+        L.ol_round_half.argtypes = [ctypes.c_double]
+        L.ol_threads.restype = ctypes.c_int32
         L.ol_collide.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.ol_cumulants.argtypes = [dp, dp, dp]
         L.ol_feq.argtypes = [ctypes.c_double, dp, dp]
@@ -98,6 +102,19 @@ def _dp(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def round_half(x: float) -> float:
+    """Nearest FP16 value of x (ties to even), as the oracle's FP16 storage
+    form rounds the stored deviations."""
+    return float(lib().ol_round_half(float(x)))
+
+
+def set_threads(n: int) -> int:
+    """Threads of the per-cell phases (n <= 0: all processors); returns the
+    number in use.  Results do not depend on it."""
+    lib().ol_set_threads(int(n))
+    return int(lib().ol_threads())
 
 
 # ---------------------------------------------------------------- operators
@@ -145,7 +162,7 @@ class OracleLattice:
 
     def __init__(self, shape, omega, accel=(0.0, 0.0, 0.0), sigma=0.0, rho_gas=1.0,
                  conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
-                 omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None):
+                 omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None, store="fp64"):
         nx, ny, nz = shape
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -156,6 +173,7 @@ class OracleLattice:
             p.accel[d] = accel[d]
         p.sigma, p.rho_gas, p.conv_eps, p.normal_tie = sigma, rho_gas, conv_eps, normal_tie
         p.rule_isolated = 1 if rule_isolated else 0
+        p.store = {"fp64": 0, "fp32": 1, "fp16": 2}[store]
         self._p = p
         fill = _f64(np.ones((nz, ny, nx)) if fill is None else fill).reshape(-1)
         rho = _f64(np.ones((nz, ny, nx)) if rho is None else rho).reshape(-1)

@@ -209,3 +209,60 @@ def test_static_cylinder_laplace_jump():
     # spurious currents from the noisy curvature stay small
     assert np.abs(u[:, liq]).max() < 1e-5
     assert abs(L.total_mass() - M0) < 1e-12 * M0
+
+
+def test_threads_do_not_change_the_result():
+    """The per-cell phases run on several threads; the state after a few
+    steps of the channel film (spheres, interface, conversions) must be
+    bit-identical to the single-threaded run."""
+    w = I.channel_film()
+    out = []
+    for threads in (1, 4):
+        O.set_threads(threads)
+        o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, fill=w.fill, rho=w.rho,
+                            vel=w.vel)
+        o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+        o.step(20)
+        out.append([o.read(f) for f in (O.F_TYPE, O.F_MASS, O.F_PDF, O.F_NORMAL, O.F_CURV)]
+                   + [o.counters(), o.total_mass()])
+    O.set_threads(0)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_half_rounding_matches_numpy():
+    """The FP16 storage form's rounding against numpy's binary16 conversion
+    (round to nearest, ties to even, subnormals kept) over all binades a
+    stored deviation can fall in, including exact ties."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    x = np.concatenate([
+        rng.uniform(-1, 1, 20000) * 10.0 ** rng.uniform(-9, 0, 20000),
+        # exact ties between neighbouring FP16 values
+        (np.arange(1, 2000) + 0.5) * 2.0 ** -24,
+        (1024 + np.arange(0, 1000) + 0.5) * 2.0 ** -20,
+        [0.0, 2.0 ** -14, -2.0 ** -14, 2.0 ** -25, 3 * 2.0 ** -26],
+    ])
+    ours = np.array([O.round_half(v) for v in x])
+    ref = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(ours, ref)
+
+
+def test_storage_forms_conserve_mass_and_store_reduced_deviations():
+    w = I.channel_film()
+    res = []
+    for form in ("fp64", "fp16", "fp32"):
+        o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, fill=w.fill, rho=w.rho,
+                            vel=w.vel, store=form)
+        o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+        M0 = o.total_mass()
+        o.step(50)
+        assert abs(o.total_mass() - M0) <= 1e-13 * M0
+        res.append(o.read(O.F_PDF))
+    c, wt = O.velocities()
+    dev16 = res[1] - wt[:, None, None, None]
+    dev32 = res[2] - wt[:, None, None, None]
+    # every stored deviation of a reduced form is a value of that format
+    assert np.array_equal(dev16.astype(np.float16).astype(np.float64), dev16)
+    assert np.array_equal(dev32.astype(np.float32).astype(np.float64), dev32)
+    assert 0 < np.abs(res[1] - res[0]).max() < 1e-3
+    assert 0 < np.abs(res[2] - res[0]).max() < 1e-6
