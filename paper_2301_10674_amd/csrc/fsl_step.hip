@@ -105,7 +105,10 @@ __device__ __forceinline__ T at(const T *base, uint32_t e)
 // one liquid cell of the dense step.  Every load of the cell is issued
 // before any arithmetic so that a wavefront keeps all of its streams in
 // flight; fl is the cell's flag byte (liquid).
-template <class S>
+// NEAR: the wavefront holds a cell next to a solid or a wall (the other
+// lanes run the same code with an empty solid mask); without it the code
+// has no bounce-back part at all.
+template <class S, bool NEAR>
 __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
                                           int x, int row, uint8_t fl)
 {
@@ -114,7 +117,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     const size_t N = (size_t)d.N;
     const int y = row % ny, z = row / ny;
     const int c = x + nx * row;
-    const bool near = (fl & F_NEAR_SOLID) != 0;
+    const bool near = NEAR && (fl & F_NEAR_SOLID) != 0;
 
     // bookkeeping loads first: the record slot gates a second round of loads
     const double mq0 = d.mq[c];
@@ -209,16 +212,37 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
         step = nblocks;
     }
     const int rmul = d.xcd_map ? 8 : 1;
-    int row = k + rmul * (s / nbx), x = (s % nbx) * BULK_THREADS + tx;
-    uint8_t fl = (row < rowmax && x < nx) ? d.flags[x + nx * row] : (uint8_t)0;
-    while (row < rowmax) {
-        s += step;
-        const int row2 = k + rmul * (s / nbx), x2 = (s % nbx) * BULK_THREADS + tx;
-        const uint8_t fl2 = (row2 < rowmax && x2 < nx) ? d.flags[x2 + nx * row2] : (uint8_t)0;
-        if ((fl & T_MASK) == T_LIQ) bulk_cell<S>(d, src, dst, x, row, fl);
-        row = row2;
-        x = x2;
-        fl = fl2;
+    // segment s -> (row, x); out-of-range lanes read as interface cells
+    // (nothing to do).  Each pass takes the segments s and s + step.
+    auto seg = [&](int sg, int &row, int &x, uint8_t &fl) {
+        row = k + rmul * (sg / nbx);
+        x = (sg % nbx) * BULK_THREADS + tx;
+        fl = (row < rowmax && x < nx) ? d.flags[x + nx * row] : (uint8_t)T_IF;
+    };
+    int rowa, xa, rowb, xb;
+    uint8_t fla, flb;
+    seg(s, rowa, xa, fla);
+    seg(s + step, rowb, xb, flb);
+    while (rowa < rowmax) {
+        s += 2 * step;
+        int rowc, xc, rowd, xd;
+        uint8_t flc, fld;
+        seg(s, rowc, xc, flc);
+        seg(s + step, rowd, xd, fld);
+        const bool la = (fla & T_MASK) == T_LIQ, lb = (flb & T_MASK) == T_LIQ;
+        if (__ballot((la && (fla & F_NEAR_SOLID)) || (lb && (flb & F_NEAR_SOLID))) != 0) {
+            if (la) bulk_cell<S, true>(d, src, dst, xa, rowa, fla);
+            if (lb) bulk_cell<S, true>(d, src, dst, xb, rowb, flb);
+        } else if (__ballot(la || lb) != 0) {
+            if (la) bulk_cell<S, false>(d, src, dst, xa, rowa, fla);
+            if (lb) bulk_cell<S, false>(d, src, dst, xb, rowb, flb);
+        }
+        rowa = rowc;
+        xa = xc;
+        fla = flc;
+        rowb = rowd;
+        xb = xd;
+        flb = fld;
     }
 }
 
