@@ -666,36 +666,74 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv23(Dev d, int p, uint32_t 
     }
 }
 
+// Block-aggregated append of `value` to list[] when pred holds: one atomic
+// per workgroup.  Every thread of the block must call it (uniform control).
+__device__ __forceinline__ void block_append(int32_t *list, int32_t *counter, bool pred, int32_t value)
+{
+    __shared__ int s_cnt[LIST_THREADS / 64];
+    __shared__ int s_base;
+    const uint64_t m = __ballot(pred);
+    const int w = (int)threadIdx.x >> 6, lane = __lane_id();
+    if (lane == 0) s_cnt[w] = (int)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < LIST_THREADS / 64; ++k) tot += s_cnt[k];
+        s_base = tot ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    int base = s_base;
+    for (int k = 0; k < w; ++k) base += s_cnt[k];
+    if (pred) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = value;
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t epoch)
 {
     const int32_t *list = d.list[p];
     const int ncur = d.cnt[p];
     const int total = ncur + d.cnt[2];
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-        int c;
-        bool keep = true;
+    const int nxy = d.nx * d.ny;
+    // block-uniform trip count: every thread reaches the block-wide append
+    for (int t0 = blockIdx.x * LIST_THREADS; t0 < total; t0 += gridDim.x * LIST_THREADS) {
+        const int t = t0 + (int)threadIdx.x;
+        int c = 0;
+        bool kept = false;
+        int newz = -1;
         if (t < ncur) {
             c = list[t];
             const uint32_t mk = mark_bits(d.mark[c], epoch);
+            kept = true;
             if (mk & (MK_TO_LIQ | MK_EMPTY)) {
                 d.flags[c] = (uint8_t)((d.flags[c] & ~T_MASK) | ((mk & MK_TO_LIQ) ? T_LIQ : T_GAS));
-                keep = false;
+                kept = false;
             }
-        } else {
+        } else if (t < total) {
             c = d.lnew[t - ncur];
             d.flags[c] = (uint8_t)((d.flags[c] & ~T_MASK) | T_IF);
-            atomicMax(&d.cnt[3], c / (d.nx * d.ny));
+            newz = c / nxy;
+            kept = true;
         }
-        if (keep) {
+        // highest fluid row: one atomic per wavefront
+        int zw = newz;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) zw = max(zw, __shfl_xor(zw, o));
+        if (__lane_id() == 0 && zw >= 0) atomicMax(&d.cnt[3], zw);
+        if (kept) {
             const Cell pc = cell_xyz(d, c);
-            const double mq0 = d.mq[c], rho0 = d.rho[c];
+            double mq0 = d.mq[c], rho0 = d.rho[c];
             int nb[27];
             uint32_t mk[27];
 #pragma unroll
             for (int i = 0; i < 27; ++i) {
                 nb[i] = i == REST ? -1 : nb_of(d, pc, i);
-                mk[i] = nb[i] < 0 ? 0u : d.mark[nb[i]];
+                mk[i] = at(d.mark, (uint32_t)(nb[i] < 0 ? c : nb[i]));
             }
+#pragma unroll
+            for (int i = 0; i < 27; ++i) keep(mk[i]);
+            keep(mq0);
+            keep(rho0);
             double add = 0.0;
 #pragma unroll
             for (int i = 0; i < 27; ++i)
@@ -704,7 +742,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t e
             d.mq[c] = m;
             d.phi[c] = m / rho0;
         }
-        list_append(d.list[p ^ 1], &d.cnt[p ^ 1], keep, c);
+        block_append(d.list[p ^ 1], &d.cnt[p ^ 1], kept, c);
     }
 }
 
