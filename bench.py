@@ -213,11 +213,16 @@ def run_form(w, form, steps, warmup):
     s = STORE_BYTES[precision]
     bulk_avg_s = bulk_ms / 1e3 / max(launches, 1)
     bytes_per_launch = liq * (54 * s + 16) + w.ncells * 1
+    # whole step: the dense pass plus the interface cells (own and pulled
+    # PDFs read, PDFs written, fill level, mass, density, mark)
+    itf = 0.5 * (itf0 + itf1)
+    bytes_per_step = bytes_per_launch + itf * (81 * s + 44)
     res = dict(
         form=form, precision=precision, secs=secs, ms_per_step=1e3 * secs / steps,
         mlups_fluid=fluid * steps / secs / 1e6, mlups_all=w.ncells * steps / secs / 1e6,
         bulk_us=1e6 * bulk_avg_s, bulk_launches=launches,
         bulk_gbs=bytes_per_launch / bulk_avg_s / 1e9, bytes_per_launch=bytes_per_launch,
+        step_gbs=bytes_per_step / (secs / steps) / 1e9, bytes_per_step=bytes_per_step,
         liquid_cells=liq, fluid_cells=fluid, interface_cells=0.5 * (itf0 + itf1),
         mass_drift=abs(M1 - M0) / M0, interface_error=interface_error(lat, fsl))
     if learned:
@@ -352,6 +357,8 @@ def main():
                      "kernel": "k_bulk", "bytes_per_launch": r["bytes_per_launch"],
                      "avg_launch_us": r["bulk_us"], "copy_gbs": copy_gbs,
                      "frac_of_copy": r["bulk_gbs"] / copy_gbs},
+        "step_roofline": {"achieved": r["step_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": r["step_gbs"] / HBM_PEAK_GBS, "bytes_per_step": r["bytes_per_step"]},
         "cpu_baseline": cpu,
         "mlups_all_cells": r["mlups_all"],
         "mass_drift": r["mass_drift"],

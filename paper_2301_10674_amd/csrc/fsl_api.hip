@@ -525,7 +525,7 @@ struct DevBufs {
     }
 };
 
-static const int MLP_GPW = 4;  // groups of 16 samples per wavefront
+static const int MLP_GPW = 1;  // groups of 16 samples per wavefront
 
 // ---------------------------------------------------------------- C-ABI
 extern "C" {
@@ -922,7 +922,7 @@ FslStatus fsl_estimator_train(const float *x, const float *y, int64_t n, const F
     const int nbat = (int)((n + batch - 1) / batch);
     const int nw = (batch + 16 * MLP_GPW - 1) / (16 * MLP_GPW);
     DevBufs B;
-    float *P, *M, *V, *X, *T, *part, *ploss, *g, *losses;
+    float *P, *M, *V, *X, *T, *part, *ploss, *losses;
     uint16_t *pk;
     int32_t *idx;
     HIP_TRY(B.get(&P, MLP_NPARAM));
@@ -934,7 +934,6 @@ FslStatus fsl_estimator_train(const float *x, const float *y, int64_t n, const F
     HIP_TRY(B.get(&idx, (size_t)n));
     HIP_TRY(B.get(&part, (size_t)nw * MLP_NPARAM));
     HIP_TRY(B.get(&ploss, (size_t)nw));
-    HIP_TRY(B.get(&g, MLP_NPARAM));
     HIP_TRY(B.get(&losses, (size_t)nbat));
     HIP_TRY(hipMemsetAsync(M, 0, MLP_NPARAM * 4, st));
     HIP_TRY(hipMemsetAsync(V, 0, MLP_NPARAM * 4, st));
@@ -957,12 +956,12 @@ FslStatus fsl_estimator_train(const float *x, const float *y, int64_t n, const F
         HIP_TRY(hipMemcpyAsync(idx, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
         for (int b = 0; b < nbat; ++b) {
             const int nb = (int)std::min<int64_t>(batch, n - (int64_t)b * batch);
-            mlp_grad(X, T, idx + (size_t)b * batch, nb, 1.0f / (float)nb, P, pk, MLP_GPW, part, ploss,
-                     (nb + 16 * MLP_GPW - 1) / (16 * MLP_GPW), g, losses + b, st);
             ++t;
             const float c1 = (float)(1.0 - std::pow(tp->beta1, (double)t));
             const float c2 = (float)(1.0 - std::pow(tp->beta2, (double)t));
-            mlp_adam(P, M, V, g, (float)tp->lr, (float)tp->beta1, (float)tp->beta2, (float)tp->eps, c1, c2, pk, st);
+            mlp_train_step(X, T, idx + (size_t)b * batch, nb, 1.0f / (float)nb, P, M, V, pk, MLP_GPW, part, ploss,
+                           (nb + 16 * MLP_GPW - 1) / (16 * MLP_GPW), (float)tp->lr, (float)tp->beta1,
+                           (float)tp->beta2, (float)tp->eps, c1, c2, losses + b, st);
         }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(hl.data(), losses, (size_t)nbat * 4, hipMemcpyDeviceToHost, st));

@@ -28,8 +28,12 @@ void mlp_pack(const float *P, uint16_t *pk, hipStream_t st);
 void mlp_grad(const float *X, const float *T, const int32_t *idx, int nbatch, float inv_n, const float *P,
               const uint16_t *pk, int groups_per_wave, float *partial, float *partial_loss, int nwaves,
               float *grad, float *loss, hipStream_t st);
-void mlp_adam(float *P, float *m, float *v, const float *g, float lr, float b1, float b2, float eps, float c1,
-              float c2, uint16_t *pk, hipStream_t st);
+// one Adam step on a batch: gradient partials, then the fused update (sum,
+// Adam, BF16 copies, batch loss)
+void mlp_train_step(const float *X, const float *T, const int32_t *idx, int nbatch, float inv_n, float *P,
+                    float *m, float *v, uint16_t *pk, int groups_per_wave, float *partial, float *partial_loss,
+                    int nwaves, float lr, float b1, float b2, float eps, float c1, float c2, float *loss,
+                    hipStream_t st);
 void mlp_infer(const float *X, int n, const float *P, const uint16_t *pk, float *Y, hipStream_t st);
 void fd_stencils(const float *X, int n, float *Y, hipStream_t st);
 template <class R>

@@ -52,6 +52,15 @@ __device__ __forceinline__ float bf16_float(uint16_t h)
     return f;
 }
 
+// tanh(x) = 1 - 2 / (e^{2x} + 1) with the hardware base-2 exponential and
+// reciprocal: no branches, saturates to +-1 (e^{2x} -> inf or 0), absolute
+// error ~1e-7 -- far below the BF16 rounding of the activations.
+__device__ __forceinline__ float act_tanh(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // e^{2x}
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
 {
     v4s v;
@@ -114,7 +123,7 @@ __device__ __forceinline__ void mlp_forward16(const uint16_t *sW, const float *P
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) acc = mfma(ld4(W1p + (16 * mt + r) * 32 + 16 * kt + 4 * q), xb[kt], acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) F.h1[mt][j] = tanhf(acc[j] + P[MLP_OFF_B1 + 16 * mt + 4 * q + j]);
+        for (int j = 0; j < 4; ++j) F.h1[mt][j] = act_tanh(acc[j] + P[MLP_OFF_B1 + 16 * mt + 4 * q + j]);
         F.h1b[mt] = pack4(F.h1[mt][0], F.h1[mt][1], F.h1[mt][2], F.h1[mt][3]);
     }
 #pragma unroll
@@ -123,7 +132,7 @@ __device__ __forceinline__ void mlp_forward16(const uint16_t *sW, const float *P
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) acc = mfma(ld4(W2p + (16 * mt + r) * 64 + 16 * kt + 4 * q), F.h1b[kt], acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) F.h2[mt][j] = tanhf(acc[j] + P[MLP_OFF_B2 + 16 * mt + 4 * q + j]);
+        for (int j = 0; j < 4; ++j) F.h2[mt][j] = act_tanh(acc[j] + P[MLP_OFF_B2 + 16 * mt + 4 * q + j]);
         F.h2b[mt] = pack4(F.h2[mt][0], F.h2[mt][1], F.h2[mt][2], F.h2[mt][3]);
     }
     v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -133,12 +142,28 @@ __device__ __forceinline__ void mlp_forward16(const uint16_t *sW, const float *P
     for (int j = 0; j < 4; ++j) F.y[j] = q == 0 ? acc[j] + P[MLP_OFF_B3 + j] : 0.f;
 }
 
-// stage the packed weights of one workgroup in LDS
-__device__ __forceinline__ void load_weights(uint16_t *sW, const uint16_t *pk, int n)
+// stage the first n packed weights (n a multiple of 8) of one workgroup in
+// LDS: 16-byte loads, eight per thread in flight before they are stored
+template <int N>
+__device__ __forceinline__ void load_weights(uint16_t *sW, const uint16_t *pk)
 {
-    const uint32_t *s = (const uint32_t *)pk;
-    uint32_t *d = (uint32_t *)sW;
-    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) d[i] = s[i];
+    static_assert(N % 8 == 0, "16-byte chunks");
+    constexpr int NV = N / 8;
+    const uint4 *s = (const uint4 *)pk;
+    uint4 *d = (uint4 *)sW;
+    for (int i0 = 0; i0 < NV; i0 += 8 * (int)blockDim.x) {
+        uint4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
+            if (i < NV) v[k] = s[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
+            if (i < NV) d[i] = v[k];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- training
@@ -154,7 +179,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *X, const float *T,
     __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_PACK_SIZE];
     __shared__ __attribute__((aligned(16))) uint16_t sX[32 * 16], sH1[64 * 16], sH2[64 * 16],
         sD1[64 * 16], sD2[64 * 16], sDY[16 * 16];
-    load_weights(sW, pk, MLP_PACK_SIZE);
+    load_weights<MLP_PACK_SIZE>(sW, pk);
     __syncthreads();
     const uint16_t *W2t = sW + MLP_W2T, *W3t = sW + MLP_W3T;
     const int l = __lane_id(), r = l & 15, q = l >> 4;
@@ -317,18 +342,42 @@ __global__ void k_mlp_reduce(const float *partial, const float *partial_loss, in
     }
 }
 
-// Adam (Kingma & Ba 2015) on the FP32 master weights
-__global__ void k_mlp_adam(float *P, float *m, float *v, const float *g, float lr, float b1, float b2,
-                           float eps, float c1, float c2)
+// One training update per parameter: sum the per-wave partial gradients in a
+// fixed order, apply Adam (Kingma & Ba 2015) to the FP32 master weight and refresh its BF16
+// copies in the packed operands (the padding entries stay as packed at the
+// start); thread 0 also sums the batch loss.
+__global__ void k_mlp_update(const float *partial, const float *partial_loss, int nwaves, float *P, float *m,
+                             float *v, float lr, float b1, float b2, float eps, float c1, float c2,
+                             uint16_t *pk, float *loss)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += partial_loss[w];
+        *loss = s;
+    }
     if (i >= MLP_NPARAM) return;
-    const float gi = g[i];
+    float gi = 0.f;
+    for (int w = 0; w < nwaves; ++w) gi += partial[(size_t)w * MLP_NPARAM + i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float pi = P[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    P[i] = pi;
+    const uint16_t h = bf16_bits(pi);
+    if (i < MLP_OFF_B1) {
+        const int t = i - MLP_OFF_W1;
+        pk[(t / 27) * 32 + t % 27] = h;
+    } else if (i >= MLP_OFF_W2 && i < MLP_OFF_B2) {
+        const int t = i - MLP_OFF_W2;
+        pk[MLP_W2P + t] = h;
+        pk[MLP_W2T + (t % 64) * 64 + t / 64] = h;
+    } else if (i >= MLP_OFF_W3 && i < MLP_OFF_B3) {
+        const int t = i - MLP_OFF_W3;
+        pk[MLP_W3P + (t / 64) * 64 + t % 64] = h;
+        pk[MLP_W3T + (t % 64) * 16 + t / 64] = h;
+    }
 }
 
 // ---------------------------------------------------------------- inference
@@ -337,7 +386,7 @@ __global__ __launch_bounds__(64) void k_mlp_infer(const float *X, int n, const f
                                                   float *Y)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_PACK_SIZE];
-    load_weights(sW, pk, MLP_W2T);  // forward weights only
+    load_weights<MLP_W2T>(sW, pk);  // forward weights only
     __syncthreads();
     const int l = __lane_id(), r = l & 15, q = l >> 4;
     for (int g = blockIdx.x; g * 16 < n; g += gridDim.x) {
@@ -396,7 +445,7 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
     using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
     __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_W2T];
     __shared__ double sS[16][28];
-    load_weights(sW, pk, MLP_W2T);
+    load_weights<MLP_W2T>(sW, pk);
     __syncthreads();
     const int32_t *list = d.list[which];
     const int count = d.cnt[which];
@@ -536,11 +585,14 @@ void mlp_grad(const float *X, const float *T, const int32_t *idx, int nbatch, fl
     k_mlp_reduce<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(partial, partial_loss, nwaves, grad, loss);
 }
 
-void mlp_adam(float *P, float *m, float *v, const float *g, float lr, float b1, float b2, float eps, float c1,
-              float c2, uint16_t *pk, hipStream_t st)
+void mlp_train_step(const float *X, const float *T, const int32_t *idx, int nbatch, float inv_n, float *P,
+                    float *m, float *v, uint16_t *pk, int groups_per_wave, float *partial, float *partial_loss,
+                    int nwaves, float lr, float b1, float b2, float eps, float c1, float c2, float *loss,
+                    hipStream_t st)
 {
-    k_mlp_adam<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(P, m, v, g, lr, b1, b2, eps, c1, c2);
-    mlp_pack(P, pk, st);
+    k_mlp_grad<<<nwaves, 64, 0, st>>>(X, T, idx, nbatch, inv_n, P, pk, groups_per_wave, partial, partial_loss);
+    k_mlp_update<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(partial, partial_loss, nwaves, P, m, v, lr, b1, b2,
+                                                          eps, c1, c2, pk, loss);
 }
 
 void mlp_infer(const float *X, int n, const float *P, const uint16_t *pk, float *Y, hipStream_t st)
