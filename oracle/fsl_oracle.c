@@ -21,6 +21,8 @@
  *                  velocity by F/(2 rho) and negating the first-order central
  *                  moments in the collision;
  *   walls       -- halfway bounce-back, Ladd's moving-wall term with rho_w=1;
+ *   particles   -- momentum exchange in the Galilean-invariant form of Wen
+ *                  et al. 2014 at the link midpoints (ol_particle_forces);
  *   free surface-- Koerner et al. 2005 anti-bounce-back reconstruction of
  *                  PDFs coming from gas or from the gas side of the normal,
  *                  gas density rho_gas + 6 sigma kappa; mass flux weighted by
@@ -403,16 +405,25 @@ static double min_image(double d, int n)
     return d;
 }
 
-static void sphere_wall_velocity(const OlLattice *L, int p, int64_t cell, int j, double uw[3])
+/* wall point of the link from fluid cell `cell` to the solid cell cell - c_j:
+ * halfway along the link; returned as its offset from the centre of sphere p
+ * (minimum image in x and y) */
+static void link_offset(const OlLattice *L, int p, int64_t cell, int j, double r[3])
 {
     const double *s = &L->sph[10 * p];
     int x, y, z;
     cell_xyz(L, cell, &x, &y, &z);
-    /* wall point: halfway along the link from the fluid cell to the solid one */
-    double r[3];
     r[0] = min_image((x + 0.5 - 0.5 * CV[j][0]) - s[0], L->p.nx);
     r[1] = min_image((y + 0.5 - 0.5 * CV[j][1]) - s[1], L->p.ny);
     r[2] = (z + 0.5 - 0.5 * CV[j][2]) - s[2];
+}
+
+/* rigid-body velocity of sphere p at the wall point of that link */
+static void sphere_wall_velocity(const OlLattice *L, int p, int64_t cell, int j, double uw[3])
+{
+    const double *s = &L->sph[10 * p];
+    double r[3];
+    link_offset(L, p, cell, j, r);
     const double *U = s + 4, *Om = s + 7;
     uw[0] = U[0] + (Om[1] * r[2] - Om[2] * r[1]);
     uw[1] = U[1] + (Om[2] * r[0] - Om[0] * r[2]);
@@ -951,6 +962,45 @@ void ol_counters(const OlLattice *L, int64_t out[8])
 }
 
 int64_t ol_steps_done(const OlLattice *L) { return L->steps; }
+
+/* Hydrodynamic force and torque on each sphere by momentum exchange
+ * (Section 2.2 couples fluid and particles this way and cites Aidun et al.
+ * 1998 and Wen et al. 2014; the form here is Wen's Galilean-invariant one).
+ * Evaluated on the stored state, i.e. for the streaming of the next step:
+ * every liquid or interface cell x with a link j whose source x - c_j is a
+ * sphere cell sends f*_{opp j}(x) towards the wall and gets back
+ * f_j = f*_{opp j} + 6 w_j c_j.u_w; relative to the wall velocity u_w at the
+ * link midpoint, the sphere gains
+ *   F = (c_{opp j} - u_w) f*_{opp j} - (c_j - u_w) f_j
+ * and the torque r x F, r the midpoint's offset from the sphere centre.
+ * out: 6 values per sphere, force then torque, summed in cell order. */
+void ol_particle_forces(const OlLattice *L, double *out)
+{
+    for (int64_t k = 0; k < 6 * (int64_t)L->nsph; ++k) out[k] = 0.0;
+    for (int64_t c = 0; c < L->N; ++c) {
+        const uint8_t t = L->type[c];
+        if (t != OL_LIQUID && t != OL_INTERFACE) continue;
+        for (int j = 0; j < Q; ++j) {
+            if (j == REST) continue;
+            const int64_t s = nbr(L, c, j, -1);
+            if (s < 0 || L->type[s] != OL_SOLID) continue;
+            const int p = L->owner[s];
+            double r[3], uw[3], F[3];
+            link_offset(L, p, c, j, r);
+            sphere_wall_velocity(L, p, c, j, uw);
+            const double fout = L->f[c * Q + opp(j)];
+            const double cu = CV[j][0] * uw[0] + CV[j][1] * uw[1] + CV[j][2] * uw[2];
+            const double fin = fout + 6.0 * WT[j] * cu;
+            for (int d = 0; d < 3; ++d)
+                F[d] = (-CV[j][d] - uw[d]) * fout - (CV[j][d] - uw[d]) * fin;
+            double *o = out + 6 * (int64_t)p;
+            for (int d = 0; d < 3; ++d) o[d] += F[d];
+            o[3] += r[1] * F[2] - r[2] * F[1];
+            o[4] += r[2] * F[0] - r[0] * F[2];
+            o[5] += r[0] * F[1] - r[1] * F[0];
+        }
+    }
+}
 
 void ol_set_threads(int32_t n)
 {

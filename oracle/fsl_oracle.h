@@ -110,6 +110,11 @@ double ol_pool(const OlLattice *L);
  * [6] liquid->interface, [7] liquid cells found next to gas (must stay 0) */
 void ol_counters(const OlLattice *L, int64_t out[8]);
 int64_t ol_steps_done(const OlLattice *L);
+/* hydrodynamic force and torque on each sphere by momentum exchange
+ * (Galilean-invariant form, link midpoints) for the streaming of the next
+ * step; out[6*n]: per sphere Fx, Fy, Fz, Tx, Ty, Tz (torque about the
+ * sphere centre) */
+void ol_particle_forces(const OlLattice *L, double *out);
 /* threads of the per-cell phases (n <= 0: all processors; results do not
  * depend on it) and the number in use */
 void ol_set_threads(int32_t n);

@@ -77,6 +77,7 @@ def lib():
         L.ol_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         L.ol_steps_done.restype = ctypes.c_int64
         L.ol_steps_done.argtypes = [ctypes.c_void_p]
+        L.ol_particle_forces.argtypes = [ctypes.c_void_p, dp]
         L.ol_set_threads.argtypes = [ctypes.c_int32]
         L.ol_round_half.restype = ctypes.c_double
         L.ol_round_half.argtypes = [ctypes.c_double]
@@ -201,6 +202,7 @@ class OracleLattice:
         rc = lib().ol_set_particles(self.h, n, _dp(centre), _dp(radius), _dp(v), _dp(w))
         if rc != 0:
             raise ValueError("oracle rejected the particles")
+        self.nsph = n
 
     def set_state(self, type_, m, f_cellmajor):
         t = np.ascontiguousarray(type_, dtype=np.uint8).reshape(-1)
@@ -249,6 +251,14 @@ class OracleLattice:
     @property
     def steps_done(self):
         return lib().ol_steps_done(self.h)
+
+    def particle_forces(self):
+        """(n, 6): force and torque on each sphere by momentum exchange for
+        the streaming of the next step."""
+        n = getattr(self, "nsph", 0)
+        out = np.zeros(6 * max(n, 1))
+        lib().ol_particle_forces(self.h, _dp(out))
+        return out[:6 * n].reshape(n, 6)
 
 
 # ------------------------------------------------------------------ estimator
