@@ -228,6 +228,15 @@ def run_form(w, form, steps, warmup):
     if learned:
         used1 = lat.estimator_stats()
         res["estimator"] = dict(est, network_cells=used1[0] - used0[0], fallback_cells=used1[1] - used0[1])
+    # momentum-exchange force and torque on every sphere (outside the timed
+    # steps; the coupling would call it once per step)
+    if len(w.radius):
+        lat.particle_forces()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            lat.particle_forces()
+        res["particle_forces_ms"] = 1e3 * (time.perf_counter() - t0) / 10
     lat.destroy()
     del lat
     torch.cuda.synchronize()
@@ -363,7 +372,7 @@ def main():
         "mlups_all_cells": r["mlups_all"],
         "mass_drift": r["mass_drift"],
         "forms": {k: {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_gbs", "mass_drift",
-                                          "interface_error", "estimator") if kk in v}
+                                          "interface_error", "estimator", "particle_forces_ms") if kk in v}
                   for k, v in forms.items()},
     }
     print(json.dumps(out), flush=True)

@@ -226,6 +226,23 @@ FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream)
  * estimate is kept. */
 FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
 
+/* Hydrodynamic force and torque on every sphere by momentum exchange
+ * (Section 2.2 couples fluid and particles this way, citing Aidun et al.
+ * 1998 and Wen et al. 2014; this is Wen's Galilean-invariant form).  It is
+ * evaluated on the current state, i.e. for the streaming of the next step:
+ * each liquid or interface cell x with a link j whose source x - c_j is a
+ * cell of sphere q sends f*_{-j}(x) towards the wall and receives
+ * f_j = f*_{-j} + 6 w_j c_j.u_w (u_w: the sphere's rigid-body velocity at the
+ * link midpoint); q gains (c_{-j} - u_w) f*_{-j} - (c_j - u_w) f_j and the
+ * torque r x that force, r the midpoint's offset from the sphere centre
+ * (minimum image in x and y).
+ * out: 6 doubles per sphere in the order given to fsl_set_particles():
+ * Fx, Fy, Fz, Tx, Ty, Tz (lattice units); host memory, or device memory when
+ * out_on_device != 0.  Sums run in FP64 in a fixed order (deterministic).
+ * Nothing is written when no spheres are mapped; FSL_ERR_ARG for a NULL out
+ * otherwise.  Allocates nothing; synchronises the lattice's stream. */
+FslStatus fsl_particle_forces(FslLattice *lat, double *out, int32_t out_on_device);
+
 /* Interface-cell updates since creation that used the network / fell back. */
 FslStatus fsl_estimator_stats(FslLattice *lat, int64_t *learned, int64_t *fallback);
 

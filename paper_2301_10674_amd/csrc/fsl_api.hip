@@ -23,6 +23,11 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
 void launch_setup_links(const Dev &d, hipStream_t st);
+void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st);
+void launch_mem_fill(const Dev &d, int nsph, const int32_t *offs, int2 *ent, hipStream_t st);
+template <class S>
+void launch_mem(const Dev &d, int p, int nsph, const int32_t *offs, const int2 *ent, double *out,
+                hipStream_t st);
 template <class R>
 void launch_bb_terms(const Dev &d, hipStream_t st);
 }  // namespace fsl
@@ -57,6 +62,8 @@ struct FslLattice {
     std::vector<double> sph_host;
     double *sph_dev = nullptr;
     void *bb_dev = nullptr;   // moving-wall bounce-back records
+    void *mem_dev = nullptr;  // momentum exchange: per-sphere entry offsets, then the entries
+    size_t mem_ent_off = 0;
     float *mlpP = nullptr;    // learned estimator: FP32 weights
     uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
     bool timing = false;
@@ -279,7 +286,7 @@ __global__ void k_build_list(Dev d, int which)
 
 __global__ void k_zero_counts(Dev d)
 {
-    if (threadIdx.x < 5) d.cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 6) d.cnt[threadIdx.x] = 0;
     if (threadIdx.x < 16) d.stats[threadIdx.x] = 0ull;
 }
 
@@ -467,6 +474,46 @@ static void run_bb_terms(FslLattice *L)
         launch_bb_terms<float>(L->d, L->st);
 }
 
+template <class S>
+static void run_mem(FslLattice *L, double *out)
+{
+    const int32_t *offs = (const int32_t *)L->mem_dev;
+    const int2 *ent = (const int2 *)((const char *)L->mem_dev + L->mem_ent_off);
+    launch_mem<S>(L->d, L->parity, L->nsph, offs, ent, out, L->st);
+}
+
+// Per-sphere lists of the cells that can link into each sphere (for the
+// momentum exchange): count on the device, offsets on the host, fill.
+static FslStatus build_mem_lists(FslLattice *L)
+{
+    Dev &d = L->d;
+    if (L->mem_dev) {
+        HIP_TRY(hipFree(L->mem_dev));
+        L->mem_dev = nullptr;
+    }
+    const int n = L->nsph;
+    if (n == 0 || !d.sph) return FSL_OK;
+    // the per-sphere counts use the new-cell list as scratch (free between steps; n <= N)
+    launch_mem_count(d, n, d.lnew, L->st);
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> offs((size_t)n + 1, 0);
+    HIP_TRY(hipMemcpyAsync(offs.data() + 1, d.lnew, (size_t)n * 4, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    int64_t total = 0;
+    for (int q = 0; q < n; ++q) {
+        total += offs[q + 1];
+        if (total > INT32_MAX) return fail(FSL_ERR_NOMEM, "too many momentum-exchange entries");
+        offs[q + 1] = (int32_t)total;
+    }
+    L->mem_ent_off = (((size_t)n + 1) * 4 + 255) & ~(size_t)255;
+    HIP_TRY(hipMalloc(&L->mem_dev, L->mem_ent_off + (size_t)std::max<int64_t>(total, 1) * 8));
+    HIP_TRY(hipMemcpyAsync(L->mem_dev, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, L->st));
+    launch_mem_fill(d, n, (const int32_t *)L->mem_dev, (int2 *)((char *)L->mem_dev + L->mem_ent_off), L->st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
 // rebuild everything derived from the cell types: solid-link masks,
 // bounce-back records, the highest fluid row, the interface list and the
 // interface geometry
@@ -483,22 +530,26 @@ static FslStatus finalize(FslLattice *L)
     else
         launch_geom<float>(d, L->parity, L->list_blocks, L->st);
     HIP_TRY(hipGetLastError());
-    int32_t nrec = 0;
-    HIP_TRY(hipMemcpyAsync(&nrec, d.cnt + 4, 4, hipMemcpyDeviceToHost, L->st));
+    int32_t nrec[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(nrec, d.cnt + 4, 8, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
     if (L->bb_dev) {
         HIP_TRY(hipFree(L->bb_dev));
         L->bb_dev = nullptr;
     }
     d.bbterm = nullptr;
-    if (nrec > 0) {
+    d.bbfull = nullptr;
+    if (nrec[0] > 0 || nrec[1] > 0) {
+        // compact records, then the full ones, in one allocation
         const size_t rs = L->P.precision == FSL_FP64 ? 8 : 4;
-        HIP_TRY(hipMalloc(&L->bb_dev, (size_t)nrec * 32 * rs));
+        const size_t hb = ((size_t)nrec[0] * 8 * rs + 255) & ~(size_t)255;
+        HIP_TRY(hipMalloc(&L->bb_dev, hb + (size_t)nrec[1] * 32 * rs));
         d.bbterm = L->bb_dev;
+        d.bbfull = (char *)L->bb_dev + hb;
         run_bb_terms(L);
         HIP_TRY(hipGetLastError());
     }
-    return FSL_OK;
+    return build_mem_lists(L);
 }
 
 static bool finite_all(const float *v, size_t n)
@@ -587,6 +638,8 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.smask = (uint32_t *)(base + lay.smask);
     d.bbslot = (int32_t *)(base + lay.bbslot);
     d.bbterm = nullptr;
+    d.bbfull = nullptr;
+    d.rec_compact = params->precision != FSL_FP16_STORE;
     d.list[0] = (int32_t *)(base + lay.list0);
     d.list[1] = (int32_t *)(base + lay.list1);
     d.lnew = (int32_t *)(base + lay.lnew);
@@ -678,7 +731,8 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
         return FSL_OK;
     }
     if (L->steps > 0) return fail(FSL_ERR_STATE, "spheres must be mapped before the first step");
-    HIP_TRY(hipMalloc(&L->sph_dev, t.size() * 8));
+    // the sphere table, then room for one force/torque evaluation (6 per sphere)
+    HIP_TRY(hipMalloc(&L->sph_dev, t.size() * 8 + (size_t)std::max(n, 1) * 6 * 8));
     HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), t.size() * 8, hipMemcpyHostToDevice, L->st));
     L->sph_host = t;
     L->nsph = n;
@@ -694,6 +748,21 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
     DISPATCH(L, run_liquid_form, L, 1);
     FslStatus r = finalize(L);
     if (r != FSL_OK) return r;
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (L->nsph == 0) return FSL_OK;
+    if (!out) return fail(FSL_ERR_ARG, "out is NULL");
+    if (!L->mem_dev) return fail(FSL_ERR_STATE, "sphere link lists missing");
+    double *buf = out_on_device ? out : L->sph_dev + (size_t)L->nsph * 10;
+    DISPATCH(L, run_mem, L, buf);
+    HIP_TRY(hipGetLastError());
+    if (!out_on_device)
+        HIP_TRY(hipMemcpyAsync(out, buf, (size_t)L->nsph * 6 * 8, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
 }
@@ -1026,6 +1095,7 @@ void fsl_destroy(FslLattice *L)
     }
     if (L->sph_dev) (void)hipFree(L->sph_dev);
     if (L->bb_dev) (void)hipFree(L->bb_dev);
+    if (L->mem_dev) (void)hipFree(L->mem_dev);
     if (L->mlpP) (void)hipFree(L->mlpP);
     if (L->mlpPk) (void)hipFree(L->mlpPk);
     delete L;

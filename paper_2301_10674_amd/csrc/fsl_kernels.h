@@ -24,12 +24,19 @@ struct Dev {
     int32_t *owner;           // owning sphere of a solid cell, -1 otherwise
     uint8_t *flags;           // cell type (2 bits) | near-solid bit
     uint32_t *smask;          // bit j: the source x - c_j is solid or beyond a wall
-    int32_t *bbslot;          // record of a cell's moving-wall bounce-back terms, -1: none
-    void *bbterm;             // records of 32 terms (Real type), one per cell with sphere links
+    int32_t *bbslot;          // moving-wall record of a cell with sphere links: k >= 0 compact
+                              // record k, k <= -2 full record -k-2, -1 none
+    void *bbterm;             // compact records, 8 Real values each: the rigid velocities of
+                              // the first two spheres at the cell centre (3 + 3), the mask of the
+                              // links into the second sphere (uint32 bits), unused
+    void *bbfull;             // full records of cells next to three or more spheres (every
+                              // cell in the FP16-storage form): the moving-wall term of each
+                              // direction, 32 Real values each
+    int rec_compact;          // 1: compact records where they suffice (FP64, FP32 storage)
     int32_t *list[2];         // interface cells, current / next step
     int32_t *lnew;            // cells that become interface cells this step
     int32_t *cnt;             // [0],[1] list lengths, [2] lnew length, [3] highest fluid z,
-                              // [4] bounce-back records
+                              // [4] compact and [5] full bounce-back records
     unsigned long long *stats;  // conversion counters
     const double *sph;        // spheres: X[3], r, U[3], Omega[3]
     double *partial;          // reduction partials

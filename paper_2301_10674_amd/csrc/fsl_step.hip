@@ -71,6 +71,71 @@ __device__ __forceinline__ R bb_term(const Dev &d, int s, int j, const Cell &p)
     return R(6.0 * wgt(j) * (cx(j) * ux + cy(j) * uy + cz(j) * uz));
 }
 
+// Rigid-body velocity of sphere q at the centre of cell p.  The wall term of
+// a link from p into q, taken at the link midpoint p - c_j/2, equals
+// 6 w_j (c_j . V) with this V, since c_j . (Omega x c_j) = 0.
+__device__ __forceinline__ void rigid_velocity(const Dev &d, int q, const Cell &p, double V[3])
+{
+    const double *sp = d.sph + 10 * q;
+    const double rx = min_image((p.x + 0.5) - sp[0], d.nx);
+    const double ry = min_image((p.y + 0.5) - sp[1], d.ny);
+    const double rz = (p.z + 0.5) - sp[2];
+    V[0] = sp[4] + (sp[8] * rz - sp[9] * ry);
+    V[1] = sp[5] + (sp[9] * rx - sp[7] * rz);
+    V[2] = sp[6] + (sp[7] * ry - sp[8] * rx);
+}
+
+// Does the periodic image of sphere q nearest to the link midpoint of
+// direction j equal the one nearest to the cell centre?  (Only on lattices
+// barely wider than a sphere can they differ; such cells keep per-link terms.)
+__device__ __forceinline__ bool same_image(const Dev &d, int q, const Cell &p, int j)
+{
+    const double *sp = d.sph + 10 * q;
+    const double mx = min_image((p.x + 0.5 - 0.5 * cx(j)) - sp[0], d.nx);
+    const double my = min_image((p.y + 0.5 - 0.5 * cy(j)) - sp[1], d.ny);
+    const double cxm = min_image((p.x + 0.5) - sp[0], d.nx) - 0.5 * cx(j);
+    const double cym = min_image((p.y + 0.5) - sp[1], d.ny) - 0.5 * cy(j);
+    // images differ by a whole period (>= 3 cells); rounding differs by far less
+    return fabs(mx - cxm) < 0.25 && fabs(my - cym) < 0.25;
+}
+
+// A cell's moving-wall record (bbslot k; one uint4 array per Real type):
+// NU = 28 Real values in u.  k >= 0: compact record (first 8 values);
+// k <= -2: full record.  Nothing is loaded for k == -1.
+template <class R>
+__device__ __forceinline__ void load_record(const Dev &d, int k, uint4 (&u)[28 * sizeof(R) / 16])
+{
+    constexpr int NF = 28 * (int)sizeof(R) / 16, NH = 8 * (int)sizeof(R) / 16;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) u[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (k >= 0) {
+        const uint4 *hp = (const uint4 *)((const R *)d.bbterm + (size_t)k * 8);
+#pragma unroll
+        for (int i = 0; i < NH; ++i) u[i] = hp[i];
+    } else if (k <= -2) {
+        const uint4 *fp = (const uint4 *)((const R *)d.bbfull + (size_t)(-k - 2) * 32);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) u[i] = fp[i];
+    }
+}
+
+// Moving-wall term of link j from a loaded record; zero for k == -1 and for
+// links the caller does not treat as sphere links.
+template <class R>
+__device__ __forceinline__ R record_term(const R (&r)[28], int k, int j)
+{
+    if (k <= -2) return r[j];
+    uint32_t m2;
+    __builtin_memcpy(&m2, &r[6], 4);
+    const bool two = (m2 >> j) & 1u;
+    const R vx = two ? r[3] : r[0], vy = two ? r[4] : r[1], vz = two ? r[5] : r[2];
+    R cu = R(0);
+    if (cx(j)) cu += cx(j) > 0 ? vx : -vx;
+    if (cy(j)) cu += cy(j) > 0 ? vy : -vy;
+    if (cz(j)) cu += cz(j) > 0 ? vz : -vz;
+    return R(6.0 * wgt(j)) * cu;
+}
+
 // ---------------------------------------------------------------- dense step
 // load / store of direction i at 32-bit element offset e from a per-direction
 // base that is uniform over the wavefront (scalar base + one vector offset)
@@ -142,34 +207,33 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     // links whose source is solid or beyond a wall bounce back: the cell's
     // own post-collision value of the opposite direction, plus the
     // precomputed moving-wall term of sphere links (zero for wall links)
-    R fb[27], rec[28];
+    R fb[27];
 #pragma unroll
     for (int j = 0; j < 27; ++j) fb[j] = R(0);
-#pragma unroll
-    for (int j = 0; j < 28; ++j) rec[j] = R(0);
+    uint4 rv[28 * sizeof(R) / 16];
     if (near) {
 #pragma unroll
         for (int j = 0; j < 27; ++j)
             if (j != REST) fb[j] = ld_at(src + (size_t)opp(j) * N, (uint32_t)c);
-        if (slot >= 0) {
-            constexpr int NV = 28 * (int)sizeof(R) / 16;
-            const uint4 *rp = (const uint4 *)((const R *)d.bbterm + (size_t)slot * 32);
-            uint4 v[NV];
-#pragma unroll
-            for (int k = 0; k < NV; ++k) v[k] = rp[k];
-            __builtin_memcpy(rec, v, sizeof(v));
-        }
     }
+    load_record<R>(d, slot, rv);
     __builtin_amdgcn_sched_barrier(0);
+    R rec[28];
+    __builtin_memcpy(rec, rv, sizeof(rv));
 
-    // incoming mass over the non-solid links
+    // incoming mass over the non-solid links; links beyond a z wall (the
+    // bottom and top rows, uniform over the wavefront) carry no wall term
     double in_sum = 0.0;
 #pragma unroll
     for (int j = 0; j < 27; ++j) {
         if (j == REST) continue;
         const bool sj = (solid >> j) & 1u;
         in_sum += sj ? 0.0 : (double)f[j];
-        f[j] = sj ? fb[j] + rec[j] : f[j];
+        const bool wall = (z == 0 && j / 9 == 2) || (z == nz - 1 && j / 9 == 0);
+        // FP16 storage keeps full records: its dense pass is bound by ALU work
+        // rather than by the record bytes
+        const R tm = sizeof(S) > 2 ? (wall ? R(0) : record_term<R>(rec, slot, j)) : rec[j];
+        f[j] = sj ? fb[j] + tm : f[j];
     }
 
     using E = typename Eq<S>::type;
@@ -246,28 +310,223 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
     }
 }
 
-// moving-wall bounce-back terms of every cell that has sphere links
+// moving-wall records of every cell that has sphere links
 template <class R>
 __global__ void k_bb_terms(Dev d)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.N) return;
     const int slot = d.bbslot[c];
-    if (slot < 0) return;
+    if (slot == -1) return;
     const Cell pc = cell_xyz(d, c);
     const uint32_t sm = d.smask[c];
-    R *rec = (R *)d.bbterm + (size_t)slot * 32;
-    for (int j = 0; j < 32; ++j) {
-        R t = R(0);
-        if (j < 27 && j != REST && ((sm >> j) & 1u)) {
-            const int s = nb_of(d, pc, opp(j));
-            if (s >= 0) t = bb_term<R>(d, s, j, pc);
+    if (slot <= -2) {
+        R *rec = (R *)d.bbfull + (size_t)(-slot - 2) * 32;
+        for (int j = 0; j < 32; ++j) {
+            R t = R(0);
+            if (j < 27 && j != REST && ((sm >> j) & 1u)) {
+                const int s = nb_of(d, pc, opp(j));
+                if (s >= 0) t = bb_term<R>(d, s, j, pc);
+            }
+            rec[j] = t;
         }
-        rec[j] = t;
+        return;
+    }
+    // compact: the (at most two) spheres in link order
+    int q1 = -1, q2 = -1;
+    uint32_t m2 = 0;
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST || !((sm >> j) & 1u)) continue;
+        const int s = nb_of(d, pc, opp(j));
+        if (s < 0) continue;
+        const int q = d.owner[s];
+        if (q1 < 0 || q == q1) {
+            q1 = q;
+        } else {
+            q2 = q;
+            m2 |= 1u << j;
+        }
+    }
+    double V1[3] = {0.0, 0.0, 0.0}, V2[3] = {0.0, 0.0, 0.0};
+    if (q1 >= 0) rigid_velocity(d, q1, pc, V1);
+    if (q2 >= 0) rigid_velocity(d, q2, pc, V2);
+    R *h = (R *)d.bbterm + (size_t)slot * 8;
+    for (int a = 0; a < 3; ++a) {
+        h[a] = R(V1[a]);
+        h[3 + a] = R(V2[a]);
+    }
+    R mbits = R(0);
+    __builtin_memcpy(&mbits, &m2, 4);
+    h[6] = mbits;
+    h[7] = R(0);
+}
+
+// ---------------------------------------------------------------- momentum exchange
+// Force and torque on the spheres, Galilean-invariant momentum exchange for
+// the streaming of the next step: each liquid or interface cell x with a
+// link j whose source x - c_j belongs to sphere q sends f*_{opp j}(x)
+// towards the wall and receives f_j = f*_{opp j} + 6 w_j c_j.u_w; q gains
+// (c_{opp j} - u_w) f*_{opp j} - (c_j - u_w) f_j and the torque r x F, r the
+// link midpoint's offset from the centre (u_w the rigid velocity there).
+//
+// Per sphere, the cells that can link into it are listed once per geometry
+// (entries: cell index and the mask of its links into that sphere), in the
+// fixed order of a walk over the sphere's bounding box widened by two cells
+// (at most one period per axis).  The evaluation sums each sphere's entries
+// in FP64 in a fixed order and reduces over a fixed tree: the result does
+// not depend on scheduling.
+struct SphereBox {
+    int x0, y0, z0, ex, ey, ez;
+};
+
+__device__ __forceinline__ SphereBox sphere_box(const Dev &d, int q)
+{
+    const double *sp = d.sph + 10 * q;
+    const double X = sp[0], Y = sp[1], Z = sp[2], rad = sp[3];
+    SphereBox b;
+    b.x0 = (int)floor(X - rad) - 2;
+    b.y0 = (int)floor(Y - rad) - 2;
+    b.ex = min((int)floor(X + rad) + 2 - b.x0 + 1, d.nx);
+    b.ey = min((int)floor(Y + rad) + 2 - b.y0 + 1, d.ny);
+    b.z0 = max((int)floor(Z - rad) - 2, 0);
+    b.ez = max(min((int)floor(Z + rad) + 2, d.nz - 1) - b.z0 + 1, 0);
+    return b;
+}
+
+// cell k of the walk over box b, and the mask of its links into sphere q
+__device__ __forceinline__ uint32_t box_links(const Dev &d, const SphereBox &b, int q, int k, int &c)
+{
+    const int x = ((b.x0 + k % b.ex) % d.nx + d.nx) % d.nx;
+    const int y = ((b.y0 + (k / b.ex) % b.ey) % d.ny + d.ny) % d.ny;
+    const int z = b.z0 + k / (b.ex * b.ey);
+    c = x + d.nx * (y + d.ny * z);
+    if ((d.flags[c] & T_MASK) == T_SOLID) return 0u;
+    const uint32_t sm = d.smask[c];
+    uint32_t m = 0u;
+    if (sm == 0u) return 0u;
+    const Cell pc{x, y, z};
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST || !((sm >> j) & 1u)) continue;
+        const int s = nb_of(d, pc, opp(j));
+        if (s >= 0 && d.owner[s] == q) m |= 1u << j;
+    }
+    return m;
+}
+
+// entries per sphere (one block per sphere)
+__global__ __launch_bounds__(256) void k_mem_count(Dev d, int32_t *counts)
+{
+    __shared__ int s_cnt[4];
+    const int q = blockIdx.x;
+    const SphereBox b = sphere_box(d, q);
+    const int ncell = b.ex * b.ey * b.ez;
+    int n = 0;
+    for (int k = (int)threadIdx.x; k < ncell; k += 256) {
+        int c;
+        n += box_links(d, b, q, k, c) != 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    if (__lane_id() == 0) s_cnt[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[q] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+// the entries, in walk order, from offs[q] on (one block per sphere)
+__global__ __launch_bounds__(256) void k_mem_fill(Dev d, const int32_t *offs, int2 *ent)
+{
+    __shared__ int s_cnt[4];
+    const int q = blockIdx.x;
+    const SphereBox b = sphere_box(d, q);
+    const int ncell = b.ex * b.ey * b.ez;
+    int base = offs[q];
+    const int w = (int)threadIdx.x >> 6, lane = __lane_id();
+    for (int k0 = 0; k0 < ncell; k0 += 256) {
+        const int k = k0 + (int)threadIdx.x;
+        int c = 0;
+        const uint32_t m = k < ncell ? box_links(d, b, q, k, c) : 0u;
+        const uint64_t bal = __ballot(m != 0u);
+        if (lane == 0) s_cnt[w] = (int)__popcll(bal);
+        __syncthreads();
+        int pos = base;
+        for (int i = 0; i < w; ++i) pos += s_cnt[i];
+        if (m != 0u) ent[pos + (int)__popcll(bal & ((1ull << lane) - 1ull))] = make_int2(c, (int)m);
+        base += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        __syncthreads();
     }
 }
 
-// cells with at least one link into a sphere get a record slot
+template <class S>
+__global__ __launch_bounds__(256) void k_mem(Dev d, int p, const int32_t *offs, const int2 *ent, double *out)
+{
+    __shared__ double sh[6][256];
+    const int q = blockIdx.x;
+    const double *sp = d.sph + 10 * q;
+    const double X = sp[0], Y = sp[1], Z = sp[2];
+    const int nx = d.nx, ny = d.ny;
+    const S *pdf = (const S *)d.pdf[p];
+    const size_t N = (size_t)d.N;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int e1 = offs[q + 1];
+    for (int e = offs[q] + (int)threadIdx.x; e < e1; e += 256) {
+        const int2 en = ent[e];
+        const int c = en.x;
+        const uint8_t ty = d.flags[c] & T_MASK;
+        if (ty != T_LIQ && ty != T_IF) continue;
+        const uint32_t m = (uint32_t)en.y;
+        const int x = c % nx, y = (c / nx) % ny, z = c / (nx * ny);
+        for (int j = 0; j < 27; ++j) {
+            if (!((m >> j) & 1u)) continue;
+            const double rx = min_image((x + 0.5 - 0.5 * cx(j)) - X, nx);
+            const double ry = min_image((y + 0.5 - 0.5 * cy(j)) - Y, ny);
+            const double rz = (z + 0.5 - 0.5 * cz(j)) - Z;
+            const double ux = sp[4] + (sp[8] * rz - sp[9] * ry);
+            const double uy = sp[5] + (sp[9] * rx - sp[7] * rz);
+            const double uz = sp[6] + (sp[7] * ry - sp[8] * rx);
+            const double fout = wgt(opp(j)) + (double)ld(pdf + (size_t)opp(j) * N + c);
+            const double fin = fout + 6.0 * wgt(j) * (cx(j) * ux + cy(j) * uy + cz(j) * uz);
+            const double Fx = (-cx(j) - ux) * fout - (cx(j) - ux) * fin;
+            const double Fy = (-cy(j) - uy) * fout - (cy(j) - uy) * fin;
+            const double Fz = (-cz(j) - uz) * fout - (cz(j) - uz) * fin;
+            acc[0] += Fx;
+            acc[1] += Fy;
+            acc[2] += Fz;
+            acc[3] += ry * Fz - rz * Fy;
+            acc[4] += rz * Fx - rx * Fz;
+            acc[5] += rx * Fy - ry * Fx;
+        }
+    }
+    for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[6 * (size_t)q + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st)
+{
+    if (nsph > 0) k_mem_count<<<nsph, 256, 0, st>>>(d, counts);
+}
+
+void launch_mem_fill(const Dev &d, int nsph, const int32_t *offs, int2 *ent, hipStream_t st)
+{
+    if (nsph > 0) k_mem_fill<<<nsph, 256, 0, st>>>(d, offs, ent);
+}
+
+template <class S>
+void launch_mem(const Dev &d, int p, int nsph, const int32_t *offs, const int2 *ent, double *out,
+                hipStream_t st)
+{
+    if (nsph > 0) k_mem<S><<<nsph, 256, 0, st>>>(d, p, offs, ent, out);
+}
+template void launch_mem<double>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
+template void launch_mem<float>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
+template void launch_mem<_Float16>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
+
+// Cells with links into spheres get a record: compact when the links reach
+// at most two spheres, full otherwise.
 __global__ void k_bb_slots(Dev d)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -276,10 +535,19 @@ __global__ void k_bb_slots(Dev d)
     const uint32_t sm = d.smask[c];
     if (sm != 0 && (d.flags[c] & T_MASK) != T_SOLID) {
         const Cell pc = cell_xyz(d, c);
-        bool sphere = false;
-        for (int j = 0; j < 27 && !sphere; ++j)
-            if (j != REST && ((sm >> j) & 1u)) sphere = nb_of(d, pc, opp(j)) >= 0;
-        if (sphere) slot = atomicAdd(&d.cnt[4], 1);
+        int q1 = -1, q2 = -1;
+        bool more = false;
+        for (int j = 0; j < 27; ++j) {
+            if (j == REST || !((sm >> j) & 1u)) continue;
+            const int s = nb_of(d, pc, opp(j));
+            if (s < 0) continue;
+            const int q = d.owner[s];
+            if (q1 < 0 || q == q1) q1 = q;
+            else if (q2 < 0 || q == q2) q2 = q;
+            else more = true;
+            if (!same_image(d, q, pc, j)) more = true;
+        }
+        if (q1 >= 0) slot = (more || !d.rec_compact) ? -2 - atomicAdd(&d.cnt[5], 1) : atomicAdd(&d.cnt[4], 1);
     }
     d.bbslot[c] = slot;
 }
@@ -332,11 +600,30 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
         fl[i] = at(d.flags, a);
         ph[i] = at(d.phi, a);
     }
+    // stage 2 loads follow at once (they depend on nothing loaded above) and
+    // arrive while the geometry is evaluated: the cell's own post-collision
+    // PDFs and the pulled ones
+    R own[27], pulled[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        own[i] = ld_at(src + (size_t)i * N, (uint32_t)c);
+        // source of incoming i is x - c_i = neighbour opp(i)
+        const int s = nb(opp(i));
+        pulled[i] = ld_at(src + (size_t)i * N, (uint32_t)(s < 0 ? c : s));
+    }
+    double mq0 = d.mq[c];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         keep(fl[i]);
         keep(ph[i]);
     }
+    // moving-wall terms of the links into spheres (zero for walls); the
+    // record slot has arrived with the stencil
+    uint4 rv[28 * sizeof(R) / 16];
+    load_record<R>(d, slot, rv);
+    R rec[28];
+    __builtin_memcpy(rec, rv, sizeof(rv));
     uint64_t tyb = 0;
     double sv[27];
 #pragma unroll
@@ -356,16 +643,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // stage 2: the cell's own post-collision PDFs and the pulled ones
-    R own[27], pulled[27];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        own[i] = ld_at(src + (size_t)i * N, (uint32_t)c);
-        // source of incoming i is x - c_i = neighbour opp(i)
-        const int s = nb(opp(i));
-        pulled[i] = ld_at(src + (size_t)i * N, (uint32_t)(s < 0 ? c : s));
-    }
-    double mq0 = d.mq[c];
+    // stage 2 values
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         keep(own[i]);
@@ -384,20 +662,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // stage 3: moving-wall terms of the links into spheres (zero for walls)
-    R rec[28];
-#pragma unroll
-    for (int j = 0; j < 28; ++j) rec[j] = R(0);
-    if (slot >= 0) {
-        constexpr int NV = 28 * (int)sizeof(R) / 16;
-        const uint4 *rp = (const uint4 *)((const R *)d.bbterm + (size_t)slot * 32);
-        uint4 v[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = rp[k];
-        __builtin_memcpy(rec, v, sizeof(v));
-    }
-
-    // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
+    // stage 3: the collision    // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
     // post-collision velocity (formed like the collision's equilibrium
     // part, in FP64 unless the storage is FP16)
     double drho_o = 0.0, jxo = 0.0, jyo = 0.0, jzo = 0.0;
@@ -427,8 +692,11 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
         // incoming j comes from neighbour sj, incoming sj from neighbour j
         const bool rj = tsj == T_GAS || nc < -d.tie;
         const bool rsj = tj == T_GAS || -nc < -d.tie;
-        f[j] = tsj == T_SOLID ? own[sj] + rec[j] : (rj ? R(G - Et(own[sj])) : pulled[j]);
-        f[sj] = tj == T_SOLID ? own[j] + rec[sj] : (rsj ? R(G - Et(own[j])) : pulled[sj]);
+        // wall links (no neighbour) carry no wall term
+        const R tmj = sizeof(S) == 2 ? rec[j] : (nb(sj) < 0 ? R(0) : record_term<R>(rec, slot, j));
+        const R tmsj = sizeof(S) == 2 ? rec[sj] : (nb(j) < 0 ? R(0) : record_term<R>(rec, slot, sj));
+        f[j] = tsj == T_SOLID ? own[sj] + tmj : (rj ? R(G - Et(own[sj])) : pulled[j]);
+        f[sj] = tj == T_SOLID ? own[j] + tmsj : (rsj ? R(G - Et(own[j])) : pulled[sj]);
     }
 
     Et fo[27];

@@ -27,7 +27,7 @@ GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fsl_step",
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
-           "fsl_fd_geometry",
+           "fsl_fd_geometry", "fsl_particle_forces",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
 
@@ -120,6 +120,7 @@ def lib():
         L.fsl_fd_geometry.restype = ctypes.c_int
         L.fsl_fd_geometry.argtypes = [fp, ctypes.c_int64, fp, vp]
         L.fsl_set_estimator.restype = ctypes.c_int
+        L.fsl_particle_forces.argtypes = [vp, dp, i32]
         L.fsl_set_estimator.argtypes = [vp, fp]
         L.fsl_estimator_stats.restype = ctypes.c_int
         L.fsl_estimator_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -170,6 +171,7 @@ class Lattice:
 
         self.params = params
         self.shape = (params.nx, params.ny, params.nz)
+        self.nsph = 0
         self.N = params.nx * params.ny * params.nz
         nbytes = workspace_bytes(params)
         if nbytes == 0:
@@ -200,6 +202,7 @@ class Lattice:
         assert centre.size == 3 * n
         vel, angvel = _f64(vel), _f64(angvel)
         _check(lib().fsl_set_particles(self.h, n, _dp(centre), _dp(radius), _dp(vel), _dp(angvel)))
+        self.nsph = n
 
     def step(self, n=1):
         _check(lib().fsl_step(self.h, int(n)))
@@ -256,6 +259,14 @@ class Lattice:
 
     def timing(self, enable):
         _check(lib().fsl_timing(self.h, 1 if enable else 0))
+
+    def particle_forces(self):
+        """(n, 6) array: force and torque on each sphere by momentum
+        exchange for the streaming of the next step (fsl_particle_forces)."""
+        n = self.nsph
+        out = np.zeros(6 * max(n, 1))
+        _check(lib().fsl_particle_forces(self.h, _dp(out), 0))
+        return out[:6 * n].reshape(n, 6)
 
     def set_estimator(self, weights):
         w = _f32(weights)

@@ -3,7 +3,8 @@
 * The flume 1536 x 40 x 192 (1848 spheres) and the large flume
   3072 x 80 x 256 (9210 spheres): the GPU in FP64 against the FP64 oracle
   after a few steps, over every cell that is fluid in both (the oracle runs
-  its per-cell phases on all host threads).
+  its per-cell phases on all host threads), and the momentum-exchange force
+  and torque on every sphere.
 * The FP32 and FP16 forms on the 1536 x 40 x 192 flume over 200 steps:
   properties that hold at any size -- total mass conserved to 1e-12, no
   liquid cell next to a gas cell, fill levels of interface cells finite,
@@ -33,12 +34,18 @@ def compare_fp64(w, steps):
     g = f.lattice_from_workload(w, "fp64")
     g.step(steps)
     gf = g.read_fields([f.FIELD_TYPE, f.FIELD_VEL, f.FIELD_MASS])
+    gft = g.particle_forces()
     g.destroy()
     to = o.read(O.F_TYPE)
     assert np.array_equal(gf[f.FIELD_TYPE], to)
     fluid = (to == O.LIQUID) | (to == O.INTERFACE)
     dv = np.abs(gf[f.FIELD_VEL][:, fluid] - o.read(O.F_VEL)[:, fluid]).max()
     dm = np.abs(gf[f.FIELD_MASS][fluid] - o.read(O.F_MASS)[fluid]).max()
+    # momentum-exchange force and torque on every sphere
+    oft = o.particle_forces()
+    df = np.abs(gft - oft).max() / max(np.abs(oft).max(), 1.0)
+    print("forces: %d spheres, max relative difference %.2e" % (len(oft), df))
+    assert df < 1e-11
     return dv, dm
 
 
