@@ -963,6 +963,11 @@ void ol_counters(const OlLattice *L, int64_t out[8])
 
 int64_t ol_steps_done(const OlLattice *L) { return L->steps; }
 
+void ol_set_accel(OlLattice *L, const double accel[3])
+{
+    for (int d = 0; d < 3; ++d) L->p.accel[d] = accel[d];
+}
+
 /* Hydrodynamic force and torque on each sphere by momentum exchange
  * (Section 2.2 couples fluid and particles this way and cites Aidun et al.
  * 1998 and Wen et al. 2014; the form here is Wen's Galilean-invariant one).

@@ -110,6 +110,9 @@ double ol_pool(const OlLattice *L);
  * [6] liquid->interface, [7] liquid cells found next to gas (must stay 0) */
 void ol_counters(const OlLattice *L, int64_t out[8]);
 int64_t ol_steps_done(const OlLattice *L);
+/* change the body acceleration between steps (Section 3.1 drives the flow
+ * by a body force controlled to hold the bulk flow rate) */
+void ol_set_accel(OlLattice *L, const double accel[3]);
 /* hydrodynamic force and torque on each sphere by momentum exchange
  * (Galilean-invariant form, link midpoints) for the streaming of the next
  * step; out[6*n]: per sphere Fx, Fy, Fz, Tx, Ty, Tz (torque about the

@@ -78,6 +78,7 @@ def lib():
         L.ol_steps_done.restype = ctypes.c_int64
         L.ol_steps_done.argtypes = [ctypes.c_void_p]
         L.ol_particle_forces.argtypes = [ctypes.c_void_p, dp]
+        L.ol_set_accel.argtypes = [ctypes.c_void_p, dp]
         L.ol_set_threads.argtypes = [ctypes.c_int32]
         L.ol_round_half.restype = ctypes.c_double
         L.ol_round_half.argtypes = [ctypes.c_double]
@@ -252,6 +253,10 @@ class OracleLattice:
     def steps_done(self):
         return lib().ol_steps_done(self.h)
 
+    def set_accel(self, accel):
+        a = _f64(accel).reshape(3)
+        lib().ol_set_accel(self.h, _dp(a))
+
     def particle_forces(self):
         """(n, 6): force and torque on each sphere by momentum exchange for
         the streaming of the next step."""
@@ -291,3 +296,61 @@ def mlp_loss_grad(params, x, target, want_grad=True):
 def mlp_adam(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """In-place Adam step on float64 arrays."""
     lib().ol_mlp_adam(_dp(params), _dp(m), _dp(v), _dp(_f64(grad)), int(t), lr, beta1, beta2, eps)
+
+
+# ------------------------------------------------------------------ flume diagnostics
+def bed_profile(type_field, threshold=0.3):
+    """Section 3.2: the y-averaged solid-volume fraction phi_b(x, z) of every
+    cell column (solid cells over ny) and the bed height h_b(x), the z at
+    which phi_b equals the threshold, interpolated linearly between cell
+    centres (z + 1/2).  The uppermost crossing counts; h_b = 0 without solid
+    cells, nz when the top cell is still at or above the threshold.
+    type_field: (nz, ny, nx).  Returns phi_b (nz, nx), h_b (nx)."""
+    nz, ny, nx = type_field.shape
+    phi = (type_field == SOLID).sum(axis=1) / float(ny)
+    h = np.zeros(nx)
+    for x in range(nx):
+        k = -1
+        for z in range(nz - 1, -1, -1):
+            if phi[z, x] >= threshold:
+                k = z
+                break
+        if k < 0:
+            h[x] = 0.0
+        elif k == nz - 1:
+            h[x] = float(nz)
+        else:
+            h[x] = (k + 0.5) + (phi[k, x] - threshold) / (phi[k, x] - phi[k + 1, x])
+    return phi, h
+
+
+def bulk_velocity(o):
+    """Section 3.1 holds the mean fluid velocity U_x,l at its target: here the
+    fill-weighted mean of the velocity over liquid (fill 1) and interface
+    cells, sum(fill * u) / sum(fill), all three components."""
+    t = o.read(F_TYPE)
+    fill = o.read(F_FILL)
+    vel = o.read(F_VEL)
+    w = np.where((t == LIQUID) | (t == INTERFACE), np.where(t == LIQUID, 1.0, fill), 0.0)
+    return np.array([(w * vel[a]).sum() for a in range(3)]) / w.sum()
+
+
+class FlowController:
+    """Proportional-integral control of the body acceleration a_x so that the
+    bulk velocity reaches `target` (Section 3.1 controls F_x to hold the bulk
+    flow rate; the control law is a reading): every `every` steps,
+    e = target - U_x, I += e, a_x = a0 + kp e + ki I."""
+
+    def __init__(self, target, a0, kp, ki, every):
+        self.target, self.a0, self.kp, self.ki, self.every = target, a0, kp, ki, every
+        self.integral = 0.0
+
+    def run(self, o, steps):
+        ax = self.a0
+        for s in range(0, steps, self.every):
+            o.step(min(self.every, steps - s))
+            e = self.target - bulk_velocity(o)[0]
+            self.integral += e
+            ax = self.a0 + self.kp * e + self.ki * self.integral
+            o.set_accel((ax, 0.0, 0.0))
+        return ax
