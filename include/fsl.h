@@ -226,6 +226,29 @@ FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream)
  * estimate is kept. */
 FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
 
+/* Change the body acceleration g (force density rho g) from the next step
+ * on.  Section 3.1 drives the flume by a body force F_x controlled to hold
+ * the bulk flow rate; the control law is the caller's (see
+ * fsl_bulk_velocity).  FSL_ERR_ARG for NULL or non-finite values. */
+FslStatus fsl_set_accel(FslLattice *lat, const double accel[3]);
+
+/* Bulk velocity of the liquid: the fill-weighted mean of the velocity
+ * u = (sum_i c_i f*_i - rho g / 2) / rho over liquid (weight 1) and
+ * interface cells (weight = fill level); u[0..2] on the host.  FP64 sums in
+ * a fixed order; synchronises the lattice's stream. */
+FslStatus fsl_bulk_velocity(FslLattice *lat, double u[3]);
+
+/* Bed profile (Section 3.2): phi_b[z*nx + x] = solid cells of the column
+ * (x, z) divided by ny (the y-averaged solid-volume fraction on the
+ * lattice), nz*nx values; h_b[x] = the bed height, the uppermost z at which
+ * phi_b equals 0.3, interpolated linearly between cell centres z + 1/2
+ * (0 without solid cells, nz when the top cell is at or above 0.3), nx
+ * values.  Host memory, or device memory when out_on_device != 0.
+ * Synchronises the lattice's stream; do not call it while steps that were
+ * enqueued on another stream still run (host output is staged in a
+ * per-step scratch array of the workspace). */
+FslStatus fsl_bed_profile(FslLattice *lat, double *phi_b, double *h_b, int32_t out_on_device);
+
 /* Hydrodynamic force and torque on every sphere by momentum exchange
  * (Section 2.2 couples fluid and particles this way, citing Aidun et al.
  * 1998 and Wen et al. 2014; this is Wen's Galilean-invariant form).  It is

@@ -127,7 +127,7 @@ static Layout layout(const FslParams *p)
     L.lnew = take(4 * N);
     L.cnt = take(64);
     L.stats = take(8 * 16);
-    L.partial = take(8 * (RED_BLOCKS + 8));
+    L.partial = take(8 * (5 * RED_BLOCKS + 8));
     L.total = off;
     return L;
 }
@@ -351,6 +351,95 @@ __global__ __launch_bounds__(256) void k_pool_partial(Dev d)
     if (threadIdx.x == 0) d.partial[blockIdx.x] = sh[0];
 }
 
+// bulk velocity: per-block partial sums of fill * u (3 components) and of
+// the fill over liquid (fill 1) and interface cells, stored after the
+// mass partials; u = (j* - rho g / 2) / rho as in the read-back
+template <class S>
+__global__ __launch_bounds__(256) void k_bulkvel_partial(Dev d, int p)
+{
+    __shared__ double sh[4][256];
+    const S *pdf = (const S *)d.pdf[p];
+    const size_t N = (size_t)d.N;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) {
+        const uint8_t ty = d.flags[c] & T_MASK;
+        if (ty != T_LIQ && ty != T_IF) continue;
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < 27; ++i) {
+            const double v = (double)ld(pdf + (size_t)i * N + c);
+            r += v;
+            j[0] += cx(i) * v;
+            j[1] += cy(i) * v;
+            j[2] += cz(i) * v;
+        }
+        r += 1.0;
+        const double g[3] = {d.gx, d.gy, d.gz};
+        const double w = ty == T_LIQ ? 1.0 : d.phi[c];
+        for (int a = 0; a < 3; ++a) acc[a] += w * ((j[a] - 0.5 * r * g[a]) / r);
+        acc[3] += w;
+    }
+    for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) d.partial[RED_BLOCKS + 8 + threadIdx.x * RED_BLOCKS + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// the four sums over the block partials, fixed order; u to partial[RED_BLOCKS + 1 .. 3]
+__global__ __launch_bounds__(256) void k_bulkvel_final(Dev d)
+{
+    __shared__ double sh[4][256];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x)
+        for (int a = 0; a < 4; ++a) acc[a] += d.partial[RED_BLOCKS + 8 + a * RED_BLOCKS + i];
+    for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) d.partial[RED_BLOCKS + 1 + threadIdx.x] = sh[3][0] > 0.0 ? sh[threadIdx.x][0] / sh[3][0] : 0.0;
+}
+
+// bed profile: phi_b[z * nx + x] = solid cells of the column (x, z) over ny
+__global__ void k_phib(Dev d, double *phi)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d.nx * d.nz) return;
+    const int x = t % d.nx, z = t / d.nx;
+    int n = 0;
+    for (int y = 0; y < d.ny; ++y) n += (d.flags[x + d.nx * (y + d.ny * z)] & T_MASK) == T_SOLID;
+    phi[t] = (double)n / (double)d.ny;
+}
+
+// bed height: the uppermost z at which phi_b crosses the threshold, linear
+// between cell centres z + 1/2; 0 without solid cells above it, nz when the
+// top cell is at or above it
+__global__ void k_hb(Dev d, const double *phi, double thr, double *h)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= d.nx) return;
+    const int nx = d.nx, nz = d.nz;
+    int k = -1;
+    for (int z = nz - 1; z >= 0; --z)
+        if (phi[z * nx + x] >= thr) {
+            k = z;
+            break;
+        }
+    double v;
+    if (k < 0) v = 0.0;
+    else if (k == nz - 1) v = (double)nz;
+    else {
+        const double a = phi[k * nx + x], b = phi[(k + 1) * nx + x];
+        v = (k + 0.5) + (a - thr) / (a - b);
+    }
+    h[x] = v;
+}
+
 // ---------------------------------------------------------------- read-back
 template <class S, class R4>
 __global__ void k_read(Dev d, int p, int field, void *out)
@@ -447,6 +536,12 @@ template <class S> static void run_mass(FslLattice *L)
 {
     k_mass_partial<S><<<RED_BLOCKS, 256, 0, L->st>>>(L->d, L->parity);
     k_sum_partials<<<1, 256, 0, L->st>>>(L->d, RED_BLOCKS, RED_BLOCKS);
+}
+
+template <class S> static void run_bulkvel(FslLattice *L)
+{
+    k_bulkvel_partial<S><<<RED_BLOCKS, 256, 0, L->st>>>(L->d, L->parity);
+    k_bulkvel_final<<<1, 256, 0, L->st>>>(L->d);
 }
 
 template <class S> static void run_read(FslLattice *L, int field, void *out)
@@ -862,6 +957,51 @@ FslStatus fsl_total_mass(FslLattice *L, double *mass)
     DISPATCH(L, run_mass, L);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(mass, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_set_accel(FslLattice *L, const double accel[3])
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!accel) return fail(FSL_ERR_ARG, "accel is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(accel[a])) return fail(FSL_ERR_ARG, "non-finite acceleration");
+    for (int a = 0; a < 3; ++a) L->P.accel[a] = accel[a];
+    L->d.gx = accel[0];
+    L->d.gy = accel[1];
+    L->d.gz = accel[2];
+    return FSL_OK;
+}
+
+FslStatus fsl_bulk_velocity(FslLattice *L, double u[3])
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!u) return fail(FSL_ERR_ARG, "u is NULL");
+    DISPATCH(L, run_bulkvel, L);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(u, L->d.partial + RED_BLOCKS + 1, 24, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_bed_profile(FslLattice *L, double *phi_b, double *h_b, int32_t out_on_device)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!phi_b || !h_b) return fail(FSL_ERR_ARG, "NULL output");
+    const Dev &d = L->d;
+    const size_t nxz = (size_t)d.nx * d.nz;
+    // host output is staged in the per-step excess-share array (free between
+    // steps; nx*nz + nx <= N since ny >= 3)
+    double *dphi = out_on_device ? phi_b : d.share;
+    double *dh = out_on_device ? h_b : d.share + nxz;
+    k_phib<<<(int)((nxz + 255) / 256), 256, 0, L->st>>>(d, dphi);
+    k_hb<<<(d.nx + 255) / 256, 256, 0, L->st>>>(d, dphi, 0.3, dh);
+    HIP_TRY(hipGetLastError());
+    if (!out_on_device) {
+        HIP_TRY(hipMemcpyAsync(phi_b, dphi, nxz * 8, hipMemcpyDeviceToHost, L->st));
+        HIP_TRY(hipMemcpyAsync(h_b, dh, (size_t)d.nx * 8, hipMemcpyDeviceToHost, L->st));
+    }
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
 }

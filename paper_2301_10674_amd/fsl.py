@@ -27,7 +27,8 @@ GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fsl_step",
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
-           "fsl_fd_geometry", "fsl_particle_forces",
+           "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
+           "fsl_bed_profile",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
 
@@ -121,6 +122,9 @@ def lib():
         L.fsl_fd_geometry.argtypes = [fp, ctypes.c_int64, fp, vp]
         L.fsl_set_estimator.restype = ctypes.c_int
         L.fsl_particle_forces.argtypes = [vp, dp, i32]
+        L.fsl_set_accel.argtypes = [vp, dp]
+        L.fsl_bulk_velocity.argtypes = [vp, dp]
+        L.fsl_bed_profile.argtypes = [vp, dp, dp, i32]
         L.fsl_set_estimator.argtypes = [vp, fp]
         L.fsl_estimator_stats.restype = ctypes.c_int
         L.fsl_estimator_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -259,6 +263,22 @@ class Lattice:
 
     def timing(self, enable):
         _check(lib().fsl_timing(self.h, 1 if enable else 0))
+
+    def set_accel(self, accel):
+        a = _f64(accel).reshape(3)
+        _check(lib().fsl_set_accel(self.h, _dp(a)))
+
+    def bulk_velocity(self):
+        u = np.zeros(3)
+        _check(lib().fsl_bulk_velocity(self.h, _dp(u)))
+        return u
+
+    def bed_profile(self):
+        """(phi_b (nz, nx), h_b (nx)): y-averaged solid fraction and bed height."""
+        nx, ny, nz = self.shape
+        phi, h = np.zeros(nz * nx), np.zeros(nx)
+        _check(lib().fsl_bed_profile(self.h, _dp(phi), _dp(h), 0))
+        return phi.reshape(nz, nx), h
 
     def particle_forces(self):
         """(n, 6) array: force and torque on each sphere by momentum
