@@ -963,6 +963,151 @@ void ol_counters(const OlLattice *L, int64_t out[8])
 
 int64_t ol_steps_done(const OlLattice *L) { return L->steps; }
 
+/* Move the spheres to new centres with new velocities (radii and number
+ * unchanged).  Section 2.2 resolves moving particles on the lattice; the
+ * remapping rules are readings:
+ *   - the owner map is rebuilt (a cell covered by several spheres belongs to
+ *     the lowest index);
+ *   - a fluid cell that a sphere now covers becomes solid and its mass goes
+ *     to the pool, so the total stays exact;
+ *   - a solid cell that no sphere covers any more is typed from its 26
+ *     neighbours: with liquid or interface neighbours and no gas
+ *     neighbour it becomes liquid, with both an interface cell of fill 0,
+ *     with gas neighbours only gas.  Uncovered cells are typed in rounds:
+ *     a round takes every open cell with a neighbour typed before it (the
+ *     lattice after the covering, then earlier rounds) and looks only at
+ *     those; cells no round reaches become gas.  Liquid and interface cells
+ *     get f = f^eq(rho_n, u), rho_n the mean density of those liquid and
+ *     interface neighbours (for cells typed in an earlier round: their
+ *     rho_n), u the rigid velocity of the sphere that covered the cell, at
+ *     its centre; a liquid cell takes its mass rho_n out of the pool.
+ * Returns -1 when no spheres are mapped. */
+int ol_move_particles(OlLattice *L, const double *centre, const double *vel, const double *angvel)
+{
+    const int nx = L->p.nx, ny = L->p.ny, nz = L->p.nz, n = L->nsph;
+    if (n <= 0) return -1;
+    for (int32_t q = 0; q < n; ++q) {
+        double *s = &L->sph[10 * q];
+        s[0] = centre[3 * q] - nx * floor(centre[3 * q] / nx);
+        s[1] = centre[3 * q + 1] - ny * floor(centre[3 * q + 1] / ny);
+        s[2] = centre[3 * q + 2];
+        for (int d = 0; d < 3; ++d) {
+            s[4 + d] = vel ? vel[3 * q + d] : 0.0;
+            s[7 + d] = angvel ? angvel[3 * q + d] : 0.0;
+        }
+    }
+    int32_t *own = (int32_t *)malloc((size_t)L->N * sizeof(int32_t));
+    uint8_t *t0 = (uint8_t *)malloc((size_t)L->N);
+    uint8_t *tn = (uint8_t *)malloc((size_t)L->N);
+    double *rn = (double *)malloc((size_t)L->N * sizeof(double));
+    for (int64_t c = 0; c < L->N; ++c) {
+        own[c] = -1;
+        t0[c] = L->type[c];
+    }
+    for (int32_t q = 0; q < n; ++q) {
+        const double *s = &L->sph[10 * q];
+        const double r = s[3];
+        int x0 = (int)floor(s[0] - r) - 1, x1 = (int)floor(s[0] + r) + 1;
+        int y0 = (int)floor(s[1] - r) - 1, y1 = (int)floor(s[1] + r) + 1;
+        int z0 = (int)floor(s[2] - r) - 1, z1 = (int)floor(s[2] + r) + 1;
+        if (z0 < 0) z0 = 0;
+        if (z1 > nz - 1) z1 = nz - 1;
+        for (int z = z0; z <= z1; ++z)
+            for (int yy = y0; yy <= y1; ++yy)
+                for (int xx = x0; xx <= x1; ++xx) {
+                    const int x = ((xx % nx) + nx) % nx, y = ((yy % ny) + ny) % ny;
+                    const int64_t c = cell_of(L, x, y, z);
+                    if (own[c] >= 0) continue;
+                    const double dx = min_image((x + 0.5) - s[0], nx);
+                    const double dy = min_image((y + 0.5) - s[1], ny);
+                    const double dz = (z + 0.5) - s[2];
+                    if (dx * dx + dy * dy + dz * dz <= r * r) own[c] = q;
+                }
+    }
+    /* covering */
+    for (int64_t c = 0; c < L->N; ++c) {
+        if (own[c] < 0 || t0[c] == OL_SOLID) continue;
+        if (t0[c] == OL_LIQUID || t0[c] == OL_INTERFACE) L->pool += L->m[c];
+        L->type[c] = OL_SOLID;
+        L->m[c] = 0.0;
+        L->phi[c] = 0.0;
+    }
+    /* uncovered cells, in rounds: a round types every open cell that has a
+     * neighbour typed before the round (the covered lattice, then earlier
+     * rounds), from those neighbours only */
+    double *dens = (double *)malloc((size_t)L->N * sizeof(double));
+    uint8_t *tv = (uint8_t *)malloc((size_t)L->N); /* types as seen by the round */
+    for (int64_t c = 0; c < L->N; ++c) {
+        const int open = own[c] < 0 && t0[c] == OL_SOLID;
+        tv[c] = open ? 255 : L->type[c];
+        tn[c] = tv[c];
+        dens[c] = (tv[c] == OL_LIQUID || tv[c] == OL_INTERFACE) ? sum27(&L->f[c * Q]) : 0.0;
+        rn[c] = 1.0;
+    }
+    for (;;) {
+        int64_t typed = 0;
+        for (int64_t c = 0; c < L->N; ++c) {
+            if (tv[c] != 255) continue;
+            int nfl = 0, ngas = 0;
+            double rs = 0.0;
+            for (int i = 0; i < Q; ++i) {
+                if (i == REST) continue;
+                const int64_t y = nbr(L, c, i, 1);
+                if (y < 0) continue;
+                if (tv[y] == OL_LIQUID || tv[y] == OL_INTERFACE) {
+                    ++nfl;
+                    rs += dens[y];
+                } else if (tv[y] == OL_GAS) {
+                    ++ngas;
+                }
+            }
+            if (nfl + ngas == 0) continue;
+            tn[c] = nfl > 0 ? (ngas > 0 ? OL_INTERFACE : OL_LIQUID) : OL_GAS;
+            rn[c] = nfl > 0 ? rs / nfl : 1.0;
+            ++typed;
+        }
+        if (typed == 0) break;
+        for (int64_t c = 0; c < L->N; ++c)
+            if (tv[c] == 255 && tn[c] != 255) {
+                tv[c] = tn[c];
+                dens[c] = rn[c];
+            }
+    }
+    for (int64_t c = 0; c < L->N; ++c)
+        if (tn[c] == 255) tn[c] = OL_GAS; /* enclosed by solid cells */
+    free(dens);
+    free(tv);
+    for (int64_t c = 0; c < L->N; ++c) {
+        if (own[c] >= 0 || t0[c] != OL_SOLID) continue;
+        L->type[c] = tn[c];
+        L->m[c] = 0.0;
+        L->phi[c] = 0.0;
+        if (tn[c] == OL_GAS) continue;
+        /* rigid velocity of the sphere that covered the cell, at its centre */
+        const double *s = &L->sph[10 * L->owner[c]];
+        int x, y, z;
+        cell_xyz(L, c, &x, &y, &z);
+        const double r[3] = {min_image((x + 0.5) - s[0], nx), min_image((y + 0.5) - s[1], ny), (z + 0.5) - s[2]};
+        const double u[3] = {s[4] + (s[8] * r[2] - s[9] * r[1]), s[5] + (s[9] * r[0] - s[7] * r[2]),
+                             s[6] + (s[7] * r[1] - s[8] * r[0])};
+        ol_feq(rn[c], u, &L->f[c * Q]);
+        store_form(L, &L->f[c * Q]);
+        L->rho[c] = rn[c];
+        if (tn[c] == OL_LIQUID) {
+            L->m[c] = rn[c];
+            L->phi[c] = 1.0;
+            L->pool -= rn[c];
+        }
+    }
+    for (int64_t c = 0; c < L->N; ++c) L->owner[c] = own[c];
+    free(own);
+    free(t0);
+    free(tn);
+    free(rn);
+    phase_geometry(L);
+    return 0;
+}
+
 void ol_set_accel(OlLattice *L, const double accel[3])
 {
     for (int d = 0; d < 3; ++d) L->p.accel[d] = accel[d];

@@ -110,6 +110,15 @@ double ol_pool(const OlLattice *L);
  * [6] liquid->interface, [7] liquid cells found next to gas (must stay 0) */
 void ol_counters(const OlLattice *L, int64_t out[8]);
 int64_t ol_steps_done(const OlLattice *L);
+/* move the spheres to new centres and velocities (radii and number kept):
+ * the owner map is rebuilt; covered fluid cells turn solid and give their
+ * mass to the pool; uncovered cells, typed in rounds from neighbours typed
+ * in earlier rounds, become liquid (fluid and no gas neighbours), empty
+ * interface (both) or gas (gas only, or never reached), fluid ones at the
+ * equilibrium of their neighbours' mean density and the sphere's rigid
+ * velocity, liquid ones taking that mass from the pool.  -1 when no spheres
+ * are mapped. */
+int ol_move_particles(OlLattice *L, const double *centre, const double *vel, const double *angvel);
 /* change the body acceleration between steps (Section 3.1 drives the flow
  * by a body force controlled to hold the bulk flow rate) */
 void ol_set_accel(OlLattice *L, const double accel[3]);

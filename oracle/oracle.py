@@ -79,6 +79,8 @@ def lib():
         L.ol_steps_done.argtypes = [ctypes.c_void_p]
         L.ol_particle_forces.argtypes = [ctypes.c_void_p, dp]
         L.ol_set_accel.argtypes = [ctypes.c_void_p, dp]
+        L.ol_move_particles.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.ol_move_particles.restype = ctypes.c_int
         L.ol_set_threads.argtypes = [ctypes.c_int32]
         L.ol_round_half.restype = ctypes.c_double
         L.ol_round_half.argtypes = [ctypes.c_double]
@@ -252,6 +254,15 @@ class OracleLattice:
     @property
     def steps_done(self):
         return lib().ol_steps_done(self.h)
+
+    def move_particles(self, centre, vel=None, angvel=None):
+        n = getattr(self, "nsph", 0)
+        centre = _f64(centre).reshape(-1)
+        assert centre.size == 3 * n
+        v = _f64(np.zeros((n, 3)) if vel is None else vel).reshape(-1)
+        w = _f64(np.zeros((n, 3)) if angvel is None else angvel).reshape(-1)
+        if lib().ol_move_particles(self.h, _dp(centre), _dp(v), _dp(w)) != 0:
+            raise ValueError("no spheres to move")
 
     def set_accel(self, accel):
         a = _f64(accel).reshape(3)
