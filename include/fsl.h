@@ -226,6 +226,27 @@ FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream)
  * estimate is kept. */
 FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
 
+/* Move the spheres of fsl_set_particles() to new centres with new
+ * velocities (radii and count unchanged); centre, vel, angvel: 3 doubles
+ * per sphere (vel/angvel may be NULL: zero).  Section 2.2 resolves moving
+ * particles on the lattice; the remapping is a reading:
+ *   - if no cell changes owner, only the moving-wall terms follow the
+ *     spheres (the common case: particles cross a cell in many steps);
+ *   - otherwise fluid cells now covered turn solid and give their mass to
+ *     the excess-mass pool; uncovered cells are typed in rounds from
+ *     neighbours typed before each round: liquid (liquid or interface
+ *     neighbours, no gas), interface of fill 0 (both), gas (gas only, or
+ *     never reached); liquid and interface cells get the equilibrium at the
+ *     mean density of those neighbours and the sphere's rigid velocity at
+ *     the cell centre, liquid cells taking that mass from the pool, so the
+ *     total of fsl_total_mass() is unchanged; everything derived from the
+ *     cell types is rebuilt.
+ * FSL_ERR_STATE when no spheres are mapped, FSL_ERR_ARG for a NULL centre or
+ * non-finite values.  The first remap allocates a scratch buffer of 13
+ * bytes per cell, kept until fsl_destroy().  Synchronises the stream. */
+FslStatus fsl_move_particles(FslLattice *lat, const double *centre, const double *vel,
+                             const double *angvel);
+
 /* Change the body acceleration g (force density rho g) from the next step
  * on.  Section 3.1 drives the flume by a body force F_x controlled to hold
  * the bulk flow rate; the control law is the caller's (see

@@ -63,6 +63,7 @@ struct FslLattice {
     double *sph_dev = nullptr;
     void *bb_dev = nullptr;   // moving-wall bounce-back records
     void *mem_dev = nullptr;  // momentum exchange: per-sphere entry offsets, then the entries
+    void *move_dev = nullptr; // moving spheres: new owner map, round types and densities, counter
     size_t mem_ent_off = 0;
     float *mlpP = nullptr;    // learned estimator: FP32 weights
     uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
@@ -203,7 +204,7 @@ __global__ void k_liquid_form(Dev d, int p, int to_q)
 }
 
 // sphere -> solid cells; owner = lowest covering sphere index
-__global__ void k_map(Dev d, int nsph)
+__global__ void k_map(Dev d, int nsph, int32_t *own)
 {
     const int q = blockIdx.x;
     if (q >= nsph) return;
@@ -225,14 +226,14 @@ __global__ void k_map(Dev d, int nsph)
         if (dy > 0.5 * d.ny) dy -= d.ny; else if (dy < -0.5 * d.ny) dy += d.ny;
         const double dz = (z + 0.5) - s[2];
         const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-        if (r2 <= __dmul_rn(r, r)) atomicMin(&d.owner[x + d.nx * (y + d.ny * z)], q);
+        if (r2 <= __dmul_rn(r, r)) atomicMin(&own[x + d.nx * (y + d.ny * z)], q);
     }
 }
 
-__global__ void k_owner_reset(Dev d)
+__global__ void k_owner_reset(Dev d, int32_t *own)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < d.N) d.owner[c] = INT_MAX;
+    if (c < d.N) own[c] = INT_MAX;
 }
 
 // cells inside spheres become solid (their mass leaves the system)
@@ -246,6 +247,138 @@ __global__ void k_apply_solid(Dev d)
         d.flags[c] = T_SOLID;
         d.mq[c] = 0.0;
     }
+}
+
+// ---------------------------------------------------------------- moving spheres
+// Flag bits used only while the lattice is remapped: an uncovered cell not
+// typed yet, and one typed in an earlier round.
+constexpr uint8_t F_OPEN = 8, F_NEWC = 16;
+
+// cells whose owner changes with the new map (INT_MAX: no sphere)
+__global__ void k_owner_changes(Dev d, const int32_t *own, int *count)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ch = false;
+    if (c < d.N) ch = (own[c] == INT_MAX ? -1 : own[c]) != d.owner[c];
+    const uint64_t m = __ballot(ch);
+    if (__lane_id() == 0 && m) atomicAdd(count, (int)__popcll(m));
+}
+
+// covered fluid cells turn solid, their mass (m form) into the pool;
+// uncovered cells are marked open
+__global__ void k_cover(Dev d, const int32_t *own)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    const uint8_t ty = d.flags[c] & T_MASK;
+    if (own[c] != INT_MAX && ty != T_SOLID) {
+        if (ty == T_LIQ || ty == T_IF) d.poolc[c] += d.mq[c];
+        d.flags[c] = T_SOLID;
+        d.mq[c] = 0.0;
+        d.phi[c] = 0.0;
+    } else if (own[c] == INT_MAX && ty == T_SOLID) {
+        d.flags[c] = T_SOLID | F_OPEN;
+    }
+}
+
+// One round of typing uncovered cells: an open cell with neighbours typed
+// before this round becomes liquid (liquid/interface neighbours, no gas),
+// interface (both) or gas (gas only); rn = mean density of its
+// liquid/interface neighbours (their rn when they were typed in an earlier
+// round).  tn = 0xFF: not typed this round.
+template <class S>
+__global__ void k_uncover_round(Dev d, int p, uint8_t *tn, double *rn, int *typed)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool did = false;
+    if (c < d.N && (d.flags[c] & F_OPEN)) {
+        const S *pdf = (const S *)d.pdf[p];
+        int nfl = 0, ngas = 0;
+        double rs = 0.0;
+        for (int i = 0; i < 27; ++i) {
+            if (i == REST) continue;
+            const int y = nbr(d, c, i);
+            if (y < 0) continue;
+            const uint8_t fy = d.flags[y];
+            if (fy & F_OPEN) continue;
+            const uint8_t t = fy & T_MASK;
+            if (t == T_LIQ || t == T_IF) {
+                ++nfl;
+                if (fy & F_NEWC) {
+                    rs += rn[y];
+                } else {
+                    double r = 0.0;
+                    for (int k = 0; k < 27; ++k) r += (double)ld(pdf + (size_t)k * d.N + y);
+                    rs += 1.0 + r;
+                }
+            } else if (t == T_GAS) {
+                ++ngas;
+            }
+        }
+        if (nfl + ngas > 0) {
+            tn[c] = nfl > 0 ? (ngas > 0 ? T_IF : T_LIQ) : T_GAS;
+            rn[c] = nfl > 0 ? rs / nfl : 1.0;
+            did = true;
+        } else {
+            tn[c] = 0xFF;
+        }
+    }
+    const uint64_t m = __ballot(did);
+    if (__lane_id() == 0 && m) atomicAdd(typed, (int)__popcll(m));
+}
+
+__global__ void k_uncover_apply(Dev d, const uint8_t *tn)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < d.N && (d.flags[c] & F_OPEN) && tn[c] != 0xFF) d.flags[c] = (uint8_t)(tn[c] | F_NEWC);
+}
+
+// uncovered cells: gas if no round reached them; liquid and interface cells
+// at f^eq(rn, u), u the rigid velocity of the sphere that covered them (old
+// owner, new table) at the cell centre; liquid mass (m form) from the pool
+template <class S>
+__global__ void k_uncover_finish(Dev d, int p, const double *rn)
+{
+    using R = typename Real<S>::type;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.N) return;
+    const uint8_t f = d.flags[c];
+    if (!(f & (F_OPEN | F_NEWC))) return;
+    const uint8_t ty = (f & F_OPEN) ? T_GAS : (f & T_MASK);
+    d.flags[c] = ty;
+    d.mq[c] = 0.0;
+    d.phi[c] = 0.0;
+    if (ty == T_GAS) return;
+    const double *s = d.sph + 10 * d.owner[c];
+    const int x = c % d.nx, y = (c / d.nx) % d.ny, z = c / (d.nx * d.ny);
+    double rx = (x + 0.5) - s[0];
+    if (rx > 0.5 * d.nx) rx -= d.nx; else if (rx < -0.5 * d.nx) rx += d.nx;
+    double ry = (y + 0.5) - s[1];
+    if (ry > 0.5 * d.ny) ry -= d.ny; else if (ry < -0.5 * d.ny) ry += d.ny;
+    const double rz = (z + 0.5) - s[2];
+    const double u[3] = {s[4] + (s[8] * rz - s[9] * ry), s[5] + (s[9] * rx - s[7] * rz),
+                         s[6] + (s[7] * ry - s[8] * rx)};
+    R e[27];
+    feq_dev<R>(R(rn[c] - 1.0), R(u[0]), R(u[1]), R(u[2]), e);
+    S *pdf = (S *)d.pdf[p];
+    for (int i = 0; i < 27; ++i) pdf[(size_t)i * d.N + c] = to_store<S, R>(e[i]);
+    if (ty == T_LIQ) {
+        d.mq[c] = rn[c];
+        d.poolc[c] -= rn[c];
+    } else {
+        d.rho[c] = rn[c];
+    }
+}
+
+__global__ void k_owner_commit(Dev d, const int32_t *own)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < d.N) d.owner[c] = own[c] == INT_MAX ? -1 : own[c];
+}
+
+__global__ void k_zero_int(int *v)
+{
+    if (threadIdx.x == 0) *v = 0;
 }
 
 // solid-link mask (bit j: the source x - c_j of direction j is solid or
@@ -284,10 +417,10 @@ __global__ void k_build_list(Dev d, int which)
     list_append(d.list[which], &d.cnt[which], pred, c);
 }
 
-__global__ void k_zero_counts(Dev d)
+__global__ void k_zero_counts(Dev d, int stats)
 {
     if (threadIdx.x < 6) d.cnt[threadIdx.x] = 0;
-    if (threadIdx.x < 16) d.stats[threadIdx.x] = 0ull;
+    if (stats && threadIdx.x < 16) d.stats[threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------- reductions
@@ -609,15 +742,27 @@ static FslStatus build_mem_lists(FslLattice *L)
     return FSL_OK;
 }
 
+template <class S>
+static void run_uncover_round(FslLattice *L, uint8_t *tn, double *rn, int *typed)
+{
+    k_uncover_round<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, tn, rn, typed);
+}
+
+template <class S>
+static void run_uncover_finish(FslLattice *L, const double *rn)
+{
+    k_uncover_finish<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, rn);
+}
+
 // rebuild everything derived from the cell types: solid-link masks,
 // bounce-back records, the highest fluid row, the interface list and the
 // interface geometry
-static FslStatus finalize(FslLattice *L)
+static FslStatus finalize(FslLattice *L, bool reset_stats = true)
 {
     Dev &d = L->d;
     k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_refresh, L);
-    k_zero_counts<<<1, 64, 0, L->st>>>(d);
+    k_zero_counts<<<1, 64, 0, L->st>>>(d, reset_stats ? 1 : 0);
     k_build_list<<<blocks_for(d.N), 256, 0, L->st>>>(d, L->parity);
     launch_setup_links(d, L->st);
     if (L->P.precision == FSL_FP64)
@@ -836,8 +981,8 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
     d.sph = L->sph_dev;
     // liquid cells back to m, re-map, then the stored form with the new solids
     DISPATCH(L, run_liquid_form, L, 0);
-    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d);
-    if (n > 0) k_map<<<n, 256, 0, L->st>>>(d, n);
+    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, d.owner);
+    if (n > 0) k_map<<<n, 256, 0, L->st>>>(d, n, d.owner);
     k_apply_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_liquid_form, L, 1);
@@ -858,6 +1003,74 @@ FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
     HIP_TRY(hipGetLastError());
     if (!out_on_device)
         HIP_TRY(hipMemcpyAsync(out, buf, (size_t)L->nsph * 6 * 8, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *vel, const double *angvel)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!L->geometry_set || L->nsph == 0) return fail(FSL_ERR_STATE, "no spheres are mapped");
+    if (!centre) return fail(FSL_ERR_ARG, "centre is NULL");
+    const int n = L->nsph, nx = L->P.nx, ny = L->P.ny;
+    std::vector<double> t = L->sph_host;
+    for (int q = 0; q < n; ++q) {
+        double *sp = &t[10 * (size_t)q];
+        for (int a = 0; a < 3; ++a) {
+            const double v = vel ? vel[3 * q + a] : 0.0, w = angvel ? angvel[3 * q + a] : 0.0;
+            if (!std::isfinite(centre[3 * q + a]) || !std::isfinite(v) || !std::isfinite(w))
+                return fail(FSL_ERR_ARG, "non-finite sphere centre or velocity");
+            sp[4 + a] = v;
+            sp[7 + a] = w;
+        }
+        sp[0] = centre[3 * q] - nx * std::floor(centre[3 * q] / nx);
+        sp[1] = centre[3 * q + 1] - ny * std::floor(centre[3 * q + 1] / ny);
+        sp[2] = centre[3 * q + 2];
+    }
+    Dev &d = L->d;
+    const size_t N = (size_t)d.N;
+    if (!L->move_dev) HIP_TRY(hipMalloc(&L->move_dev, N * 4 + N * 8 + N + 64));
+    double *rn = (double *)L->move_dev;
+    int32_t *own = (int32_t *)((char *)L->move_dev + N * 8);
+    uint8_t *tn = (uint8_t *)((char *)L->move_dev + N * 12);
+    int *counter = (int *)((char *)L->move_dev + ((N * 13 + 15) & ~(size_t)15));
+    HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), (size_t)n * 10 * 8, hipMemcpyHostToDevice, L->st));
+    L->sph_host = t;
+    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
+    k_map<<<n, 256, 0, L->st>>>(d, n, own);
+    k_zero_int<<<1, 64, 0, L->st>>>(counter);
+    k_owner_changes<<<blocks_for(d.N), 256, 0, L->st>>>(d, own, counter);
+    HIP_TRY(hipGetLastError());
+    int changes = 0;
+    HIP_TRY(hipMemcpyAsync(&changes, counter, 4, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    if (changes == 0) {
+        // no cell changes owner: only the moving-wall records follow the spheres
+        run_bb_terms(L);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(L->st));
+        return FSL_OK;
+    }
+    DISPATCH(L, run_liquid_form, L, 0);
+    k_cover<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
+    for (int round = 0;; ++round) {
+        if (round > d.N) return fail(FSL_ERR_DEVICE, "uncovered cells: rounds do not end");
+        k_zero_int<<<1, 64, 0, L->st>>>(counter);
+        DISPATCH(L, run_uncover_round, L, tn, rn, counter);
+        HIP_TRY(hipGetLastError());
+        int typed = 0;
+        HIP_TRY(hipMemcpyAsync(&typed, counter, 4, hipMemcpyDeviceToHost, L->st));
+        HIP_TRY(hipStreamSynchronize(L->st));
+        if (typed == 0) break;
+        k_uncover_apply<<<blocks_for(d.N), 256, 0, L->st>>>(d, tn);
+    }
+    DISPATCH(L, run_uncover_finish, L, rn);
+    k_owner_commit<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
+    k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+    DISPATCH(L, run_liquid_form, L, 1);
+    HIP_TRY(hipGetLastError());
+    FslStatus r = finalize(L, false);
+    if (r != FSL_OK) return r;
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
 }
@@ -1236,6 +1449,7 @@ void fsl_destroy(FslLattice *L)
     if (L->sph_dev) (void)hipFree(L->sph_dev);
     if (L->bb_dev) (void)hipFree(L->bb_dev);
     if (L->mem_dev) (void)hipFree(L->mem_dev);
+    if (L->move_dev) (void)hipFree(L->move_dev);
     if (L->mlpP) (void)hipFree(L->mlpP);
     if (L->mlpPk) (void)hipFree(L->mlpPk);
     delete L;

@@ -28,7 +28,7 @@ EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fs
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
            "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
-           "fsl_bed_profile",
+           "fsl_bed_profile", "fsl_move_particles",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
 
@@ -123,6 +123,7 @@ def lib():
         L.fsl_set_estimator.restype = ctypes.c_int
         L.fsl_particle_forces.argtypes = [vp, dp, i32]
         L.fsl_set_accel.argtypes = [vp, dp]
+        L.fsl_move_particles.argtypes = [vp, dp, dp, dp]
         L.fsl_bulk_velocity.argtypes = [vp, dp]
         L.fsl_bed_profile.argtypes = [vp, dp, dp, i32]
         L.fsl_set_estimator.argtypes = [vp, fp]
@@ -263,6 +264,12 @@ class Lattice:
 
     def timing(self, enable):
         _check(lib().fsl_timing(self.h, 1 if enable else 0))
+
+    def move_particles(self, centre, vel=None, angvel=None):
+        centre = _f64(centre)
+        assert centre.size == 3 * self.nsph
+        vel, angvel = _f64(vel), _f64(angvel)
+        _check(lib().fsl_move_particles(self.h, _dp(centre), _dp(vel), _dp(angvel)))
 
     def set_accel(self, accel):
         a = _f64(accel).reshape(3)
