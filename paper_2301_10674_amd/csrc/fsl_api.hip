@@ -62,8 +62,11 @@ struct FslLattice {
     std::vector<double> sph_host;
     double *sph_dev = nullptr;
     void *bb_dev = nullptr;   // moving-wall bounce-back records
+    size_t bb_cap = 0;
     void *mem_dev = nullptr;  // momentum exchange: per-sphere entry offsets, then the entries
     void *move_dev = nullptr; // moving spheres: new owner map, round types and densities, counter
+    size_t mem_cap = 0;
+    bool mem_stale = true;    // link lists must be rebuilt before the next force evaluation
     size_t mem_ent_off = 0;
     float *mlpP = nullptr;    // learned estimator: FP32 weights
     uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
@@ -189,10 +192,10 @@ __global__ void k_closure(Dev d)
 
 // liquid cells: switch between the mass m and the stored form m - own outgoing
 template <class S>
-__global__ void k_liquid_form(Dev d, int p, int to_q)
+__global__ void k_liquid_form(Dev d, int p, int to_q, const uint8_t *mark)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N || (d.flags[c] & T_MASK) != T_LIQ) return;
+    if (c >= d.N || (d.flags[c] & T_MASK) != T_LIQ || (mark && !mark[c])) return;
     const S *pdf = (const S *)d.pdf[p];
     double fluid = 0.0;
     for (int i = 0; i < 27; ++i) {
@@ -254,22 +257,38 @@ __global__ void k_apply_solid(Dev d)
 // typed yet, and one typed in an earlier round.
 constexpr uint8_t F_OPEN = 8, F_NEWC = 16;
 
-// cells whose owner changes with the new map (INT_MAX: no sphere)
-__global__ void k_owner_changes(Dev d, const int32_t *own, int *count)
+// cells whose owner changes with the new map (INT_MAX: no sphere), appended
+// to a list (one atomic per wavefront); count = list length
+__global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own, int *count, int32_t *list)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool ch = false;
-    if (c < d.N) ch = (own[c] == INT_MAX ? -1 : own[c]) != d.owner[c];
+    const bool ch = c < d.N && (own[c] == INT_MAX ? -1 : own[c]) != d.owner[c];
     const uint64_t m = __ballot(ch);
-    if (__lane_id() == 0 && m) atomicAdd(count, (int)__popcll(m));
+    if (m == 0) return;
+    const int lane = __lane_id();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, (int)__popcll(m));
+    base = __shfl(base, 0);
+    if (ch) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = c;
+}
+
+// mark (v = 1) or clear (v = 0) the listed cells and their 26 neighbours
+__global__ void k_mark_around(Dev d, const int32_t *list, int n, uint8_t *mark, uint8_t v)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * 27) return;
+    const int c = list[t / 27];
+    const int y = nbr(d, c, (int)(t % 27));
+    if (y >= 0) mark[y] = v;
 }
 
 // covered fluid cells turn solid, their mass (m form) into the pool;
-// uncovered cells are marked open
-__global__ void k_cover(Dev d, const int32_t *own)
+// uncovered cells are marked open (over the changed cells)
+__global__ void k_cover(Dev d, const int32_t *own, const int32_t *list, int n)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c = list[t];
     const uint8_t ty = d.flags[c] & T_MASK;
     if (own[c] != INT_MAX && ty != T_SOLID) {
         if (ty == T_LIQ || ty == T_IF) d.poolc[c] += d.mq[c];
@@ -287,61 +306,81 @@ __global__ void k_cover(Dev d, const int32_t *own)
 // liquid/interface neighbours (their rn when they were typed in an earlier
 // round).  tn = 0xFF: not typed this round.
 template <class S>
-__global__ void k_uncover_round(Dev d, int p, uint8_t *tn, double *rn, int *typed)
+__global__ __launch_bounds__(256) void k_uncover_round(Dev d, int p, const int32_t *list, int n, uint8_t *tn,
+                                                       double *rn, int *typed)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool did = false;
-    if (c < d.N && (d.flags[c] & F_OPEN)) {
-        const S *pdf = (const S *)d.pdf[p];
-        int nfl = 0, ngas = 0;
-        double rs = 0.0;
-        for (int i = 0; i < 27; ++i) {
-            if (i == REST) continue;
-            const int y = nbr(d, c, i);
-            if (y < 0) continue;
+    // 32 lanes per listed cell: lane k < 26 looks at neighbour k
+    __shared__ int s_n[4];
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+    const int k = (int)threadIdx.x & 31;
+    int did = 0;
+    int c = -1;
+    if (t < n) c = list[t];
+    const bool open = c >= 0 && (d.flags[c] & F_OPEN);
+    int nfl = 0, ngas = 0;
+    double rs = 0.0;
+    if (open && k < 26) {
+        const int i = k < REST ? k : k + 1;
+        const int y = nbr(d, c, i);
+        if (y >= 0) {
             const uint8_t fy = d.flags[y];
-            if (fy & F_OPEN) continue;
-            const uint8_t t = fy & T_MASK;
-            if (t == T_LIQ || t == T_IF) {
-                ++nfl;
-                if (fy & F_NEWC) {
-                    rs += rn[y];
-                } else {
-                    double r = 0.0;
-                    for (int k = 0; k < 27; ++k) r += (double)ld(pdf + (size_t)k * d.N + y);
-                    rs += 1.0 + r;
+            const uint8_t ty = fy & T_MASK;
+            if (!(fy & F_OPEN)) {
+                if (ty == T_LIQ || ty == T_IF) {
+                    nfl = 1;
+                    if (fy & F_NEWC) {
+                        rs = rn[y];
+                    } else {
+                        const S *pdf = (const S *)d.pdf[p];
+                        double r = 0.0;
+                        for (int q = 0; q < 27; ++q) r += (double)ld(pdf + (size_t)q * d.N + y);
+                        rs = 1.0 + r;
+                    }
+                } else if (ty == T_GAS) {
+                    ngas = 1;
                 }
-            } else if (t == T_GAS) {
-                ++ngas;
             }
         }
+    }
+    // sums over the 32 lanes of the cell, in a fixed order
+    for (int o = 16; o > 0; o >>= 1) {
+        nfl += __shfl_xor(nfl, o);
+        ngas += __shfl_xor(ngas, o);
+        rs += __shfl_xor(rs, o);
+    }
+    if (open && k == 0) {
         if (nfl + ngas > 0) {
             tn[c] = nfl > 0 ? (ngas > 0 ? T_IF : T_LIQ) : T_GAS;
             rn[c] = nfl > 0 ? rs / nfl : 1.0;
-            did = true;
+            did = 1;
         } else {
             tn[c] = 0xFF;
         }
     }
-    const uint64_t m = __ballot(did);
-    if (__lane_id() == 0 && m) atomicAdd(typed, (int)__popcll(m));
+    for (int o = 32; o > 0; o >>= 1) did += __shfl_xor(did, o);
+    if (__lane_id() == 0) s_n[threadIdx.x >> 6] = did;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_n[0] + s_n[1] + s_n[2] + s_n[3]) atomicAdd(typed, s_n[0] + s_n[1] + s_n[2] + s_n[3]);
 }
 
-__global__ void k_uncover_apply(Dev d, const uint8_t *tn)
+__global__ void k_uncover_apply(Dev d, const int32_t *list, int n, const uint8_t *tn)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < d.N && (d.flags[c] & F_OPEN) && tn[c] != 0xFF) d.flags[c] = (uint8_t)(tn[c] | F_NEWC);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c = list[t];
+    if ((d.flags[c] & F_OPEN) && tn[c] != 0xFF) d.flags[c] = (uint8_t)(tn[c] | F_NEWC);
 }
 
 // uncovered cells: gas if no round reached them; liquid and interface cells
 // at f^eq(rn, u), u the rigid velocity of the sphere that covered them (old
 // owner, new table) at the cell centre; liquid mass (m form) from the pool
 template <class S>
-__global__ void k_uncover_finish(Dev d, int p, const double *rn)
+__global__ void k_uncover_finish(Dev d, int p, const int32_t *list, int n, const double *rn)
 {
     using R = typename Real<S>::type;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c = list[t];
     const uint8_t f = d.flags[c];
     if (!(f & (F_OPEN | F_NEWC))) return;
     const uint8_t ty = (f & F_OPEN) ? T_GAS : (f & T_MASK);
@@ -370,10 +409,34 @@ __global__ void k_uncover_finish(Dev d, int p, const double *rn)
     }
 }
 
-__global__ void k_owner_commit(Dev d, const int32_t *own)
+__global__ void k_owner_commit(Dev d, const int32_t *own, const int32_t *list, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c = list[t];
+    d.owner[c] = own[c] == INT_MAX ? -1 : own[c];
+}
+
+// solid-link mask and near-solid bit of the marked cells only
+__global__ void k_near_solid_marked(Dev d, const uint8_t *mark)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < d.N) d.owner[c] = own[c] == INT_MAX ? -1 : own[c];
+    if (c >= d.N || !mark[c]) return;
+    uint32_t m = 0;
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST) continue;
+        const int y = nbr(d, c, opp(j));
+        if (y < 0 || (d.flags[y] & T_MASK) == T_SOLID) m |= 1u << j;
+    }
+    d.smask[c] = m;
+    d.flags[c] = (uint8_t)((d.flags[c] & ~F_NEAR_SOLID) | (m ? F_NEAR_SOLID : 0));
+}
+
+// zero n bytes (16 per thread; n a multiple of 16)
+__global__ void k_zero_bytes(uint4 *p, size_t n16)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 __global__ void k_zero_int(int *v)
@@ -655,9 +718,9 @@ static void run_setup(FslLattice *L, const double *fill, const double *rho, cons
     k_closure<<<blocks_for(d.N), 256, 0, L->st>>>(d);
 }
 
-template <class S> static void run_liquid_form(FslLattice *L, int to_q)
+template <class S> static void run_liquid_form(FslLattice *L, int to_q, const uint8_t *mark = nullptr)
 {
-    k_liquid_form<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, to_q);
+    k_liquid_form<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, to_q, mark);
 }
 
 template <class S> static void run_refresh(FslLattice *L)
@@ -715,10 +778,6 @@ static void run_mem(FslLattice *L, double *out)
 static FslStatus build_mem_lists(FslLattice *L)
 {
     Dev &d = L->d;
-    if (L->mem_dev) {
-        HIP_TRY(hipFree(L->mem_dev));
-        L->mem_dev = nullptr;
-    }
     const int n = L->nsph;
     if (n == 0 || !d.sph) return FSL_OK;
     // the per-sphere counts use the new-cell list as scratch (free between steps; n <= N)
@@ -734,7 +793,14 @@ static FslStatus build_mem_lists(FslLattice *L)
         offs[q + 1] = (int32_t)total;
     }
     L->mem_ent_off = (((size_t)n + 1) * 4 + 255) & ~(size_t)255;
-    HIP_TRY(hipMalloc(&L->mem_dev, L->mem_ent_off + (size_t)std::max<int64_t>(total, 1) * 8));
+    const size_t need = L->mem_ent_off + (size_t)std::max<int64_t>(total, 1) * 8;
+    if (need > L->mem_cap) {
+        if (L->mem_dev) HIP_TRY(hipFree(L->mem_dev));
+        L->mem_dev = nullptr;
+        L->mem_cap = 0;
+        HIP_TRY(hipMalloc(&L->mem_dev, need + need / 8));
+        L->mem_cap = need + need / 8;
+    }
     HIP_TRY(hipMemcpyAsync(L->mem_dev, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, L->st));
     launch_mem_fill(d, n, (const int32_t *)L->mem_dev, (int2 *)((char *)L->mem_dev + L->mem_ent_off), L->st);
     HIP_TRY(hipGetLastError());
@@ -743,24 +809,24 @@ static FslStatus build_mem_lists(FslLattice *L)
 }
 
 template <class S>
-static void run_uncover_round(FslLattice *L, uint8_t *tn, double *rn, int *typed)
+static void run_uncover_round(FslLattice *L, const int32_t *list, int n, uint8_t *tn, double *rn, int *typed)
 {
-    k_uncover_round<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, tn, rn, typed);
+    k_uncover_round<S><<<(int)(((int64_t)n * 32 + 255) / 256), 256, 0, L->st>>>(L->d, L->parity, list, n, tn, rn, typed);
 }
 
 template <class S>
-static void run_uncover_finish(FslLattice *L, const double *rn)
+static void run_uncover_finish(FslLattice *L, const int32_t *list, int n, const double *rn)
 {
-    k_uncover_finish<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, rn);
+    k_uncover_finish<S><<<(n + 255) / 256, 256, 0, L->st>>>(L->d, L->parity, list, n, rn);
 }
 
 // rebuild everything derived from the cell types: solid-link masks,
 // bounce-back records, the highest fluid row, the interface list and the
 // interface geometry
-static FslStatus finalize(FslLattice *L, bool reset_stats = true)
+static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done = false)
 {
     Dev &d = L->d;
-    k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
+    if (!near_done) k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_refresh, L);
     k_zero_counts<<<1, 64, 0, L->st>>>(d, reset_stats ? 1 : 0);
     k_build_list<<<blocks_for(d.N), 256, 0, L->st>>>(d, L->parity);
@@ -773,23 +839,29 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true)
     int32_t nrec[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(nrec, d.cnt + 4, 8, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
-    if (L->bb_dev) {
-        HIP_TRY(hipFree(L->bb_dev));
-        L->bb_dev = nullptr;
-    }
     d.bbterm = nullptr;
     d.bbfull = nullptr;
     if (nrec[0] > 0 || nrec[1] > 0) {
-        // compact records, then the full ones, in one allocation
+        // compact records, then the full ones, in one allocation (kept and
+        // reused while large enough: moving spheres rebuild it often)
         const size_t rs = L->P.precision == FSL_FP64 ? 8 : 4;
         const size_t hb = ((size_t)nrec[0] * 8 * rs + 255) & ~(size_t)255;
-        HIP_TRY(hipMalloc(&L->bb_dev, hb + (size_t)nrec[1] * 32 * rs));
+        const size_t need = hb + (size_t)nrec[1] * 32 * rs;
+        if (need > L->bb_cap) {
+            if (L->bb_dev) HIP_TRY(hipFree(L->bb_dev));
+            L->bb_dev = nullptr;
+            L->bb_cap = 0;
+            HIP_TRY(hipMalloc(&L->bb_dev, need + need / 8));
+            L->bb_cap = need + need / 8;
+        }
         d.bbterm = L->bb_dev;
         d.bbfull = (char *)L->bb_dev + hb;
         run_bb_terms(L);
         HIP_TRY(hipGetLastError());
     }
-    return build_mem_lists(L);
+    // the momentum-exchange link lists follow on the next force evaluation
+    L->mem_stale = true;
+    return FSL_OK;
 }
 
 static bool finite_all(const float *v, size_t n)
@@ -880,6 +952,7 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.bbterm = nullptr;
     d.bbfull = nullptr;
     d.rec_compact = params->precision != FSL_FP16_STORE;
+    d.img_check = 0;
     d.list[0] = (int32_t *)(base + lay.list0);
     d.list[1] = (int32_t *)(base + lay.list1);
     d.lnew = (int32_t *)(base + lay.lnew);
@@ -979,6 +1052,12 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
     L->geometry_set = true;
     Dev &d = L->d;
     d.sph = L->sph_dev;
+    // a cell next to a sphere lies within r + 1.5 of its centre; its link
+    // midpoints and its centre can only see different periodic images when
+    // that reaches half a period
+    d.img_check = 0;
+    for (int q = 0; q < n; ++q)
+        if (2.0 * (t[10 * (size_t)q + 3] + 2.0) >= (double)std::min(nx, ny)) d.img_check = 1;
     // liquid cells back to m, re-map, then the stored form with the new solids
     DISPATCH(L, run_liquid_form, L, 0);
     k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, d.owner);
@@ -997,6 +1076,11 @@ FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
     if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
     if (L->nsph == 0) return FSL_OK;
     if (!out) return fail(FSL_ERR_ARG, "out is NULL");
+    if (L->mem_stale) {
+        FslStatus r = build_mem_lists(L);
+        if (r != FSL_OK) return r;
+        L->mem_stale = false;
+    }
     if (!L->mem_dev) return fail(FSL_ERR_STATE, "sphere link lists missing");
     double *buf = out_on_device ? out : L->sph_dev + (size_t)L->nsph * 10;
     DISPATCH(L, run_mem, L, buf);
@@ -1029,47 +1113,62 @@ FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *
     }
     Dev &d = L->d;
     const size_t N = (size_t)d.N;
-    if (!L->move_dev) HIP_TRY(hipMalloc(&L->move_dev, N * 4 + N * 8 + N + 64));
+    // scratch: densities (8 B), new owners (4 B), changed cells (4 B), round
+    // types (1 B) and marks (1 B) per cell, a counter; marks start zero and
+    // are cleared again after use
+    const size_t nm = (N + 15) & ~(size_t)15;
+    const size_t tn_off = N * 16;
+    if (!L->move_dev) {
+        HIP_TRY(hipMalloc(&L->move_dev, tn_off + nm + nm + 64));
+        k_zero_bytes<<<(int)((nm / 16 + 255) / 256), 256, 0, L->st>>>(
+            (uint4 *)((char *)L->move_dev + tn_off + nm), nm / 16);
+    }
     double *rn = (double *)L->move_dev;
     int32_t *own = (int32_t *)((char *)L->move_dev + N * 8);
-    uint8_t *tn = (uint8_t *)((char *)L->move_dev + N * 12);
-    int *counter = (int *)((char *)L->move_dev + ((N * 13 + 15) & ~(size_t)15));
+    int32_t *chg = (int32_t *)((char *)L->move_dev + N * 12);
+    uint8_t *tn = (uint8_t *)((char *)L->move_dev + tn_off);
+    uint8_t *mark = tn + nm;
+    int *counter = (int *)(mark + nm);
     HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), (size_t)n * 10 * 8, hipMemcpyHostToDevice, L->st));
     L->sph_host = t;
     k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
     k_map<<<n, 256, 0, L->st>>>(d, n, own);
     k_zero_int<<<1, 64, 0, L->st>>>(counter);
-    k_owner_changes<<<blocks_for(d.N), 256, 0, L->st>>>(d, own, counter);
+    k_owner_changes<<<blocks_for(d.N), 256, 0, L->st>>>(d, own, counter, chg);
     HIP_TRY(hipGetLastError());
-    int changes = 0;
-    HIP_TRY(hipMemcpyAsync(&changes, counter, 4, hipMemcpyDeviceToHost, L->st));
+    int nch = 0;
+    HIP_TRY(hipMemcpyAsync(&nch, counter, 4, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
-    if (changes == 0) {
+    if (nch == 0) {
         // no cell changes owner: only the moving-wall records follow the spheres
         run_bb_terms(L);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(L->st));
         return FSL_OK;
     }
-    DISPATCH(L, run_liquid_form, L, 0);
-    k_cover<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
+    const int gch = (nch + 255) / 256, gmk = (int)(((int64_t)nch * 27 + 255) / 256);
+    // only the changed cells and their neighbours change type or solid neighbours
+    k_mark_around<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, 1);
+    DISPATCH(L, run_liquid_form, L, 0, mark);
+    k_cover<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
     for (int round = 0;; ++round) {
-        if (round > d.N) return fail(FSL_ERR_DEVICE, "uncovered cells: rounds do not end");
+        if (round > nch) return fail(FSL_ERR_DEVICE, "uncovered cells: rounds do not end");
         k_zero_int<<<1, 64, 0, L->st>>>(counter);
-        DISPATCH(L, run_uncover_round, L, tn, rn, counter);
+        DISPATCH(L, run_uncover_round, L, chg, nch, tn, rn, counter);
         HIP_TRY(hipGetLastError());
         int typed = 0;
         HIP_TRY(hipMemcpyAsync(&typed, counter, 4, hipMemcpyDeviceToHost, L->st));
         HIP_TRY(hipStreamSynchronize(L->st));
         if (typed == 0) break;
-        k_uncover_apply<<<blocks_for(d.N), 256, 0, L->st>>>(d, tn);
+        k_uncover_apply<<<gch, 256, 0, L->st>>>(d, chg, nch, tn);
     }
-    DISPATCH(L, run_uncover_finish, L, rn);
-    k_owner_commit<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
-    k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
-    DISPATCH(L, run_liquid_form, L, 1);
+    DISPATCH(L, run_uncover_finish, L, chg, nch, rn);
+    k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
+    k_near_solid_marked<<<blocks_for(d.N), 256, 0, L->st>>>(d, mark);
+    DISPATCH(L, run_liquid_form, L, 1, mark);
+    k_mark_around<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, 0);
     HIP_TRY(hipGetLastError());
-    FslStatus r = finalize(L, false);
+    FslStatus r = finalize(L, false, true);
     if (r != FSL_OK) return r;
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;

@@ -33,6 +33,8 @@ struct Dev {
                               // cell in the FP16-storage form): the moving-wall term of each
                               // direction, 32 Real values each
     int rec_compact;          // 1: compact records where they suffice (FP64, FP32 storage)
+    int img_check;            // 1: some sphere nearly spans the periodic box, so a link
+                              // midpoint and its cell centre may see different images
     int32_t *list[2];         // interface cells, current / next step
     int32_t *lnew;            // cells that become interface cells this step
     int32_t *cnt;             // [0],[1] list lengths, [2] lnew length, [3] highest fluid z,

@@ -526,13 +526,18 @@ template void launch_mem<float>(const Dev &, int, int, const int32_t *, const in
 template void launch_mem<_Float16>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
 
 // Cells with links into spheres get a record: compact when the links reach
-// at most two spheres, full otherwise.
-__global__ void k_bb_slots(Dev d)
+// at most two spheres, full otherwise.  Three passes without contended
+// atomics: each cell's kind (0 none, 1 compact, 2 full) and per-block
+// counts; exclusive prefix sums of the counts; slots from the kinds (compact
+// records count up from 0 in cell order, full ones from -2 down).
+constexpr int SLOT_THREADS = 1024;
+
+__global__ __launch_bounds__(SLOT_THREADS) void k_slot_kinds(Dev d, uint8_t *kind, int32_t *bc, int32_t *bf)
 {
+    __shared__ int s_c[SLOT_THREADS / 64], s_f[SLOT_THREADS / 64];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N) return;
-    int slot = -1;
-    const uint32_t sm = d.smask[c];
+    uint8_t k = 0;
+    const uint32_t sm = c < d.N ? d.smask[c] : 0u;
     if (sm != 0 && (d.flags[c] & T_MASK) != T_SOLID) {
         const Cell pc = cell_xyz(d, c);
         int q1 = -1, q2 = -1;
@@ -545,20 +550,99 @@ __global__ void k_bb_slots(Dev d)
             if (q1 < 0 || q == q1) q1 = q;
             else if (q2 < 0 || q == q2) q2 = q;
             else more = true;
-            if (!same_image(d, q, pc, j)) more = true;
+            if (d.img_check && !same_image(d, q, pc, j)) more = true;
         }
-        if (q1 >= 0) slot = (more || !d.rec_compact) ? -2 - atomicAdd(&d.cnt[5], 1) : atomicAdd(&d.cnt[4], 1);
+        if (q1 >= 0) k = (more || !d.rec_compact) ? 2 : 1;
     }
-    d.bbslot[c] = slot;
+    if (c < d.N) kind[c] = k;
+    const uint64_t mc = __ballot(k == 1), mf = __ballot(k == 2);
+    if (__lane_id() == 0) {
+        s_c[threadIdx.x >> 6] = (int)__popcll(mc);
+        s_f[threadIdx.x >> 6] = (int)__popcll(mf);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tc = 0, tf = 0;
+        for (int i = 0; i < SLOT_THREADS / 64; ++i) {
+            tc += s_c[i];
+            tf += s_f[i];
+        }
+        bc[blockIdx.x] = tc;
+        bf[blockIdx.x] = tf;
+    }
+}
+
+// exclusive prefix sum of n counts in place (one block); the total to *total
+__global__ __launch_bounds__(1024) void k_scan_counts(int32_t *v, int n, int32_t *total)
+{
+    __shared__ int s_w[16];
+    __shared__ int s_carry;
+    const int lane = __lane_id(), w = (int)threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int x = i < n ? v[i] : 0;
+        int sc = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(sc, o);
+            if (lane >= o) sc += y;
+        }
+        if (lane == 63) s_w[w] = sc;
+        __syncthreads();
+        int off = s_carry;
+        for (int k = 0; k < w; ++k) off += s_w[k];
+        if (i < n) v[i] = off + sc - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = off + sc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = s_carry;
+}
+
+__global__ __launch_bounds__(SLOT_THREADS) void k_slot_write(Dev d, const uint8_t *kind, const int32_t *bc,
+                                                             const int32_t *bf)
+{
+    __shared__ int s_c[SLOT_THREADS / 64], s_f[SLOT_THREADS / 64];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint8_t k = c < d.N ? kind[c] : 0;
+    const uint64_t mc = __ballot(k == 1), mf = __ballot(k == 2);
+    const int lane = __lane_id(), w = (int)threadIdx.x >> 6;
+    if (lane == 0) {
+        s_c[w] = (int)__popcll(mc);
+        s_f[w] = (int)__popcll(mf);
+    }
+    __syncthreads();
+    int oc = bc[blockIdx.x], of = bf[blockIdx.x];
+    for (int i = 0; i < w; ++i) {
+        oc += s_c[i];
+        of += s_f[i];
+    }
+    const uint64_t below = (1ull << lane) - 1ull;
+    int slot = -1;
+    if (k == 1) slot = oc + (int)__popcll(mc & below);
+    else if (k == 2) slot = -2 - (of + (int)__popcll(mf & below));
+    if (c < d.N) d.bbslot[c] = slot;
 }
 
 // highest z that holds a liquid or interface cell
-__global__ void k_zmax(Dev d)
+// (grid-stride; a maximum per block, then one atomic per block)
+__global__ __launch_bounds__(256) void k_zmax(Dev d)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N) return;
-    const uint8_t ty = d.flags[c] & T_MASK;
-    if (ty == T_LIQ || ty == T_IF) atomicMax(&d.cnt[3], c / (d.nx * d.ny));
+    __shared__ int s_max[4];
+    int zm = -1;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) {
+        const uint8_t ty = d.flags[c] & T_MASK;
+        if (ty == T_LIQ || ty == T_IF) zm = max(zm, c / (d.nx * d.ny));
+    }
+    for (int o = 32; o > 0; o >>= 1) zm = max(zm, __shfl_xor(zm, o));
+    if (__lane_id() == 0) s_max[threadIdx.x >> 6] = zm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int m = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+        if (m >= 0) atomicMax(&d.cnt[3], m);
+    }
 }
 
 // ---------------------------------------------------------------- interface
@@ -1093,11 +1177,20 @@ void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st)
 template void launch_geom<double>(const Dev &, int, int, hipStream_t);
 template void launch_geom<float>(const Dev &, int, int, hipStream_t);
 
+// record slots and the highest fluid row.  Scratch: the per-cell kinds in
+// the excess-share array and the per-block counts in the new-cell list
+// (both free between steps; 2 * blocks <= N)
 void launch_setup_links(const Dev &d, hipStream_t st)
 {
     const int b = (d.N + 255) / 256;
-    k_bb_slots<<<b, 256, 0, st>>>(d);
-    k_zmax<<<b, 256, 0, st>>>(d);
+    const int bs = (d.N + SLOT_THREADS - 1) / SLOT_THREADS;
+    uint8_t *kind = (uint8_t *)d.share;
+    int32_t *bc = d.lnew, *bf = d.lnew + bs;
+    k_slot_kinds<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf);
+    k_scan_counts<<<1, 1024, 0, st>>>(bc, bs, d.cnt + 4);
+    k_scan_counts<<<1, 1024, 0, st>>>(bf, bs, d.cnt + 5);
+    k_slot_write<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf);
+    k_zmax<<<b < 1024 ? b : 1024, 256, 0, st>>>(d);
 }
 
 template <class R>
