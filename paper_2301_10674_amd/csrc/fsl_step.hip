@@ -147,7 +147,9 @@ __device__ __forceinline__ typename Real<S>::type ld_at(const S *base, uint32_t 
 template <class S>
 __device__ __forceinline__ void st_at(S *base, uint32_t e, S v)
 {
-    *(S *)((char *)base + e * (uint32_t)sizeof(S)) = v;
+    // non-temporal: the new PDFs stream out and are not read again in this
+    // pass, so they should not displace lines the pulls still use
+    __builtin_nontemporal_store(v, (S *)((char *)base + e * (uint32_t)sizeof(S)));
 }
 // Ties a loaded value to this point (an empty asm statement that reads and
 // writes the register; no instruction is emitted).  Placed after all loads
