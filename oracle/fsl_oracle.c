@@ -30,6 +30,8 @@
  *   conversion  -- thresholds (1+eps) rho and -eps rho, isolated-cell rules,
  *                  fill -> cancel -> empty order (Thuerey 2007); excess mass
  *                  shared evenly among interface neighbours, a pool otherwise;
+ *   variants    -- (optional, OL_VAR_*) Thuerey's flux modifiers between
+ *                  interface cells and his normal-weighted excess mass;
  *   geometry    -- Parker-Youngs normal, mean curvature from the finite-
  *                  difference Hessian of the same 3x3x3 fill stencil.
  * The two per-cell phases (stream-collide, geometry) may run their cells on
@@ -351,7 +353,7 @@ void ol_normal_curvature(const double phi[27], double n[3], double *kappa)
 /* ------------------------------------------------------------------------ */
 
 enum { MK_TO_LIQ = 1, MK_TO_GAS = 2, MK_EMPTY = 4, MK_NEW_FROM_GAS = 8,
-       MK_NEW_FROM_LIQ = 16, MK_RULE_ISO = 32 };
+       MK_NEW_FROM_LIQ = 16, MK_RULE_ISO = 32, MK_WEIGHTED = 64 };
 
 struct OlLattice {
     OlParams p;
@@ -511,6 +513,7 @@ OlLattice *ol_create(const OlParams *p, const double *fill, const double *rho,
     if (!p || !fill || !rho) return NULL;
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return NULL;
     if (!(p->omega > 0.0 && p->omega < 2.0)) return NULL;
+    if (p->variants & ~(OL_VAR_FLUX_MODIFIERS | OL_VAR_NORMAL_EXCESS)) return NULL;
     OlLattice *L = (OlLattice *)calloc(1, sizeof(OlLattice));
     L->p = *p;
     int64_t N = (int64_t)p->nx * p->ny * p->nz;
@@ -647,6 +650,28 @@ static void phase_stream_collide(OlLattice *L)
         mnew[c] = L->m[c];
     }
     int64_t liquid_next_to_gas = 0;
+    /* flux-modifier class of each interface cell from the types at the start
+     * of the step: 0 with gas but no liquid neighbours (it may only lose mass
+     * to other interface cells), 2 with liquid but no gas neighbours (it may
+     * only gain), 1 otherwise */
+    uint8_t *cls = NULL;
+    if (p->variants & OL_VAR_FLUX_MODIFIERS) {
+        cls = (uint8_t *)malloc((size_t)N);
+        for (int64_t c = 0; c < N; ++c) {
+            cls[c] = 1;
+            if (L->type[c] != OL_INTERFACE) continue;
+            int has_gas = 0, has_liq = 0;
+            for (int i = 0; i < Q; ++i) {
+                if (i == REST) continue;
+                int64_t y = nbr(L, c, i, +1);
+                if (y < 0) continue;
+                if (L->type[y] == OL_GAS) has_gas = 1;
+                if (L->type[y] == OL_LIQUID) has_liq = 1;
+            }
+            if (has_gas && !has_liq) cls[c] = 0;
+            else if (has_liq && !has_gas) cls[c] = 2;
+        }
+    }
 
 #pragma omp parallel for schedule(static) reduction(+ : liquid_next_to_gas)
     for (int64_t c = 0; c < N; ++c) {
@@ -708,7 +733,13 @@ static void phase_stream_collide(OlLattice *L)
             double s = (t == OL_INTERFACE && ty == OL_INTERFACE)
                            ? 0.5 * (clamp01(L->phi[c]) + clamp01(L->phi[y]))
                            : 1.0;
-            dm += s * (L->f[y * Q + opp(i)] - fo[i]);
+            double in = L->f[y * Q + opp(i)], out = fo[i];
+            if (cls && t == OL_INTERFACE && ty == OL_INTERFACE) {
+                /* between classes mass moves only from the lower to the higher */
+                if (cls[c] < cls[y]) in = 0.0;
+                else if (cls[c] > cls[y]) out = 0.0;
+            }
+            dm += s * (in - out);
         }
         mnew[c] = L->m[c] + dm;
 
@@ -717,6 +748,7 @@ static void phase_stream_collide(OlLattice *L)
         L->rho[c] = sum27(&fnew[c * Q]);
     }
     L->cnt[7] += liquid_next_to_gas;
+    free(cls);
     free(L->f);
     free(L->m);
     L->f = fnew;
@@ -840,12 +872,24 @@ static void phase_convert(OlLattice *L)
 }
 
 /* ---- phase 4: excess mass ------------------------------------------------ */
+/* weight of the link c_i from a converted cell with normal n (liquid to gas)
+ * in the normal-weighted variant: a filled cell sends its excess along n, an
+ * emptied one against it; projections up to the normal tie count as zero */
+static double excess_weight(const OlLattice *L, const double n[3], int i, int filled)
+{
+    double nc = n[0] * CV[i][0] + n[1] * CV[i][1] + n[2] * CV[i][2];
+    if (!filled) nc = -nc;
+    return nc > L->p.normal_tie ? nc : 0.0;
+}
+
 static void phase_excess(OlLattice *L)
 {
     const int64_t N = L->N;
     uint8_t *mk = L->mark;
+    const int weighted = (L->p.variants & OL_VAR_NORMAL_EXCESS) != 0;
     for (int64_t c = 0; c < N; ++c) {
         L->share[c] = 0.0;
+        mk[c] &= (uint8_t)~MK_WEIGHTED;
         int filled = (mk[c] & MK_TO_LIQ) != 0, emptied = (mk[c] & MK_EMPTY) != 0;
         if (!filled && !emptied) continue;
         double e;
@@ -857,23 +901,39 @@ static void phase_excess(OlLattice *L)
             L->m[c] = 0.0;
         }
         int recv = 0;
+        double wsum = 0.0;
         for (int i = 0; i < Q; ++i) {
             if (i == REST) continue;
             int64_t y = nbr(L, c, i, +1);
-            if (y >= 0 && L->type[y] == OL_INTERFACE) recv++;
+            if (y >= 0 && L->type[y] == OL_INTERFACE) {
+                recv++;
+                if (weighted) wsum += excess_weight(L, &L->n[3 * c], i, filled);
+            }
         }
-        if (recv > 0) L->share[c] = e / recv;
-        else L->pool += e;
+        if (wsum > 0.0) {
+            /* receiver y = c + c_i takes share * weight of c_i */
+            L->share[c] = e / wsum;
+            mk[c] |= MK_WEIGHTED;
+        } else if (recv > 0) {
+            L->share[c] = e / recv;
+        } else {
+            L->pool += e;
+        }
     }
     /* every interface cell gathers the shares of its converted neighbours in
-     * direction order */
+     * direction order; seen from the neighbour y = c + c_i, c lies along
+     * -c_i */
     for (int64_t c = 0; c < N; ++c) {
         if (L->type[c] != OL_INTERFACE) continue;
         double add = 0.0;
         for (int i = 0; i < Q; ++i) {
             if (i == REST) continue;
             int64_t y = nbr(L, c, i, +1);
-            if (y >= 0 && (mk[y] & (MK_TO_LIQ | MK_EMPTY))) add += L->share[y];
+            if (y < 0 || !(mk[y] & (MK_TO_LIQ | MK_EMPTY))) continue;
+            if (mk[y] & MK_WEIGHTED)
+                add += L->share[y] * excess_weight(L, &L->n[3 * y], opp(i), (mk[y] & MK_TO_LIQ) != 0);
+            else
+                add += L->share[y];
         }
         L->m[c] += add;
     }

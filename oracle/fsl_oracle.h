@@ -45,7 +45,19 @@ typedef struct {
     int32_t store;              /* storage form: 0 FP64; 1 and 2: every stored PDF is
                                    w_i + (f_i - w_i) rounded to the nearest FP32 (1) or FP16 (2)
                                    value, as the reduced-precision forms store deviations */
+    int32_t variants;           /* OL_VAR_* bits; 0 is the model described above */
 } OlParams;
+
+/* Free-surface variants of the cited method (Thuerey 2007):
+ *   OL_VAR_FLUX_MODIFIERS  interface cells with no liquid neighbour only give
+ *     mass to other interface cells, those with no gas neighbour only take
+ *     it (the exchange between two interface cells of different classes
+ *     keeps one of its two PDF terms);
+ *   OL_VAR_NORMAL_EXCESS   a converted cell shares its excess mass among its
+ *     interface neighbours in proportion to the projection of its normal on
+ *     the link (along the normal when filled, against it when emptied),
+ *     evenly when no link has a positive projection. */
+enum { OL_VAR_FLUX_MODIFIERS = 1, OL_VAR_NORMAL_EXCESS = 2 };
 
 typedef struct OlLattice OlLattice;
 

@@ -23,6 +23,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS = range(10)
+VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS = 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -47,6 +48,7 @@ class _Params(ctypes.Structure):
         ("sigma", ctypes.c_double), ("rho_gas", ctypes.c_double),
         ("conv_eps", ctypes.c_double), ("normal_tie", ctypes.c_double),
         ("rule_isolated", ctypes.c_int32), ("store", ctypes.c_int32),
+        ("variants", ctypes.c_int32),
     ]
 
 
@@ -166,7 +168,8 @@ class OracleLattice:
 
     def __init__(self, shape, omega, accel=(0.0, 0.0, 0.0), sigma=0.0, rho_gas=1.0,
                  conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
-                 omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None, store="fp64"):
+                 omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None, store="fp64",
+                 flux_modifiers=False, normal_excess=False):
         nx, ny, nz = shape
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -178,6 +181,8 @@ class OracleLattice:
         p.sigma, p.rho_gas, p.conv_eps, p.normal_tie = sigma, rho_gas, conv_eps, normal_tie
         p.rule_isolated = 1 if rule_isolated else 0
         p.store = {"fp64": 0, "fp32": 1, "fp16": 2}[store]
+        # free-surface variants of Thuerey 2007 (bits of the C header)
+        p.variants = (VAR_FLUX_MODIFIERS if flux_modifiers else 0) | (VAR_NORMAL_EXCESS if normal_excess else 0)
         self._p = p
         fill = _f64(np.ones((nz, ny, nx)) if fill is None else fill).reshape(-1)
         rho = _f64(np.ones((nz, ny, nx)) if rho is None else rho).reshape(-1)

@@ -30,7 +30,7 @@ MUTANTS = {
                        "test_oracle_flow.py", "cylinder"),
     "flux_weight": ("? 0.5 * (clamp01(L->phi[c]) + clamp01(L->phi[y]))", "? clamp01(L->phi[c])",
                     "test_oracle_flow.py", "channel_film_mass"),
-    "flux_index": ("dm += s * (L->f[y * Q + opp(i)] - fo[i]);", "dm += s * (L->f[y * Q + i] - fo[i]);",
+    "flux_index": ("double in = L->f[y * Q + opp(i)], out = fo[i];", "double in = L->f[y * Q + i], out = fo[i];",
                    "test_oracle_flow.py", "tracks_density"),
     "reconstruction": ("fin[j] = feqG[j] + feqG[opp(j)] - fo[opp(j)];",
                        "fin[j] = 2.0 * feqG[j] - fo[opp(j)];",
@@ -39,14 +39,25 @@ MUTANTS = {
                     "test_oracle_flow.py", "gravity_driven_film"),
     "no_cancel": ("if (near_fill) {\n            L->cnt[4]++;", "if (0) {\n            L->cnt[4]++;",
                   "test_oracle_conversion.py", "rule_text"),
-    "excess_to_liquid": ("if (y >= 0 && L->type[y] == OL_INTERFACE) recv++;",
-                         "if (y >= 0 && L->type[y] != OL_GAS && L->type[y] != OL_SOLID) recv++;",
+    "excess_to_liquid": ("if (y >= 0 && L->type[y] == OL_INTERFACE) {\n                recv++;",
+                         "if (y >= 0 && L->type[y] != OL_GAS && L->type[y] != OL_SOLID) {\n                recv++;",
                          "test_oracle_conversion.py", "rule_text"),
     "mean_includes_emptying": ("if (mk[y] & MK_TO_GAS) continue;", "if (0) continue;",
                                "test_oracle_conversion.py", "rule_text"),
     "parker_youngs_weight": ("static const double Wpy[3] = {1.0, 2.0, 1.0};",
                              "static const double Wpy[3] = {1.0, 1.0, 1.0};",
                              "test_oracle_geometry.py", "quadratic"),
+    "flux_modifier_direction": ("if (cls[c] < cls[y]) in = 0.0;", "if (cls[c] > cls[y]) in = 0.0;",
+                                "test_oracle_variants.py", "flux_modifiers_direct"),
+    "flux_modifier_class": ("if (has_gas && !has_liq) cls[c] = 0;", "if (has_liq && !has_gas) cls[c] = 0;",
+                            "test_oracle_variants.py", "flux_modifiers_direct"),
+    "excess_weight_side": ("if (!filled) nc = -nc;", "if (filled) nc = -nc;",
+                           "test_oracle_variants.py", "diagonal"),
+    "excess_receiver_link": ("excess_weight(L, &L->n[3 * y], opp(i),", "excess_weight(L, &L->n[3 * y], i,",
+                             "test_oracle_variants.py", "diagonal"),
+    "excess_no_fallback": ("} else if (recv > 0) {\n            L->share[c] = e / recv;",
+                           "} else if (0) {\n            L->share[c] = e / recv;",
+                           "test_oracle_variants.py", "falls_back"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
