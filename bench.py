@@ -186,7 +186,10 @@ def run_form(w, form, steps, warmup):
     from paper_2301_10674_amd import fsl
 
     precision, learned = form.split("-")[0], form.endswith("-learned")
-    lat = fsl.lattice_from_workload(w, precision, normals=1 if learned else 0)
+    # "-variants": Thuerey's flux modifiers and normal-weighted excess mass
+    variants = form.endswith("-variants")
+    lat = fsl.lattice_from_workload(w, precision, normals=1 if learned else 0,
+                                    flux_modifiers=variants, normal_excess=variants)
     est = None
     if learned:
         weights, est = learned_weights(lat, fsl)
@@ -307,9 +310,10 @@ def main():
     ap.add_argument("--nx", type=int, default=1536)
     ap.add_argument("--ny", type=int, default=40)
     ap.add_argument("--nz", type=int, default=192)
-    ap.add_argument("--forms", default="fp16,fp64,fp32-learned",
+    ap.add_argument("--forms", default="fp16,fp64,fp32-learned,fp32-variants",
                     help="other forms timed on the same workload ('' for none): fp16, fp64, fp32, "
-                         "fp32-learned (estimator trained in the run, see train.py)")
+                         "fp32-learned (estimator trained in the run, see train.py), "
+                         "fp32-variants (flux modifiers and normal-weighted excess mass)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 counter runs of this command and exit")

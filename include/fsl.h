@@ -79,8 +79,23 @@ typedef struct {
     int32_t normals;        /* 0: finite-difference normal and curvature,
                                1: learned estimator with finite-difference fallback */
     int32_t check_every;    /* watchdog interval in steps (0: never) */
-    int32_t reserved;       /* must be 0 */
+    int32_t variants;       /* FSL_VAR_* bits; 0 is the free-surface model of
+                               Section 2.1 as the cited FSLBM defines it */
 } FslParams;
+
+/* Optional free-surface variants (Thuerey 2007), bits of FslParams.variants:
+ *   FSL_VAR_FLUX_MODIFIERS  between two interface cells, mass moves only
+ *     from a cell with gas but no liquid neighbours (which may only lose)
+ *     and towards a cell with liquid but no gas neighbours (which may only
+ *     gain); the classes come from the cell types at the start of the step.
+ *   FSL_VAR_NORMAL_EXCESS   a cell that fills (empties) shares its excess
+ *     mass among its interface neighbours in proportion to the positive
+ *     part of n . c_i (of -n . c_i), n its normal from liquid to gas,
+ *     projections up to normal_tie counting as zero; evenly when no link
+ *     has a positive weight, and the pool takes it when there is no
+ *     interface neighbour at all.
+ * Unknown bits make fsl_create_lattice fail with FSL_ERR_ARG. */
+enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2 };
 
 /* field ids for fsl_read_fields(); bit k of the mask selects field k */
 enum {

@@ -78,6 +78,9 @@ struct FslLattice {
 // ---------------------------------------------------------------- workspace
 static size_t store_bytes(int prec) { return prec == FSL_FP64 ? 8 : (prec == FSL_FP32 ? 4 : 2); }
 
+static_assert(FSL_VAR_FLUX_MODIFIERS == VAR_FLUX_MODIFIERS && FSL_VAR_NORMAL_EXCESS == VAR_NORMAL_EXCESS,
+              "variant bits of the header and the kernels differ");
+
 static bool params_ok(const FslParams *p, std::string &why)
 {
     if (!p) { why = "params is NULL"; return false; }
@@ -93,7 +96,8 @@ static bool params_ok(const FslParams *p, std::string &why)
     if (!(p->conv_eps >= 0.0 && p->conv_eps < 1.0)) { why = "conv_eps must lie in [0, 1)"; return false; }
     if (!(p->normal_tie >= 0.0)) { why = "normal_tie must be >= 0"; return false; }
     if (p->normals != 0 && p->normals != 1) { why = "normals must be 0 or 1"; return false; }
-    if (p->check_every < 0 || p->reserved != 0) { why = "check_every < 0 or reserved != 0"; return false; }
+    if (p->check_every < 0) { why = "check_every must be >= 0"; return false; }
+    if (p->variants & ~(FSL_VAR_FLUX_MODIFIERS | FSL_VAR_NORMAL_EXCESS)) { why = "unknown variant bits"; return false; }
     return true;
 }
 
@@ -969,6 +973,7 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.eps = params->conv_eps;
     d.tie = params->normal_tie;
     d.rule_iso = params->rule_isolated;
+    d.variants = params->variants;
     L->list_blocks = (int)std::min<size_t>(2048, std::max<size_t>(64, N / 4096));
 
     // stage the host inputs

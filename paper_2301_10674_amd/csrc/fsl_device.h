@@ -23,9 +23,13 @@ __host__ __device__ constexpr int MI(int a, int b, int c) { return a + 3 * b + 9
 constexpr int REST = 13;
 
 // cell types (low two bits of the flag byte) and static flag bits
-enum : uint8_t { T_GAS = 0, T_LIQ = 1, T_IF = 2, T_SOLID = 3, T_MASK = 3, F_NEAR_SOLID = 4 };
+enum : uint8_t { T_GAS = 0, T_LIQ = 1, T_IF = 2, T_SOLID = 3, T_MASK = 3, F_NEAR_SOLID = 4,
+                 // flux-modifier class of an interface cell (set only when that
+                 // variant is on): gas but no liquid neighbours / liquid but no gas
+                 F_CLS_LOSE = 32, F_CLS_GAIN = 64 };
 // conversion marks (low byte of the epoch-stamped mark word)
-enum : uint32_t { MK_TO_LIQ = 1, MK_TO_GAS = 2, MK_EMPTY = 4, MK_NEW = 8, MK_ISO = 16 };
+enum : uint32_t { MK_TO_LIQ = 1, MK_TO_GAS = 2, MK_EMPTY = 4, MK_NEW = 8, MK_ISO = 16,
+                  MK_WEIGHTED = 32 /* excess shared by normal weights */ };
 
 __device__ __forceinline__ uint32_t mark_bits(uint32_t mk, uint32_t epoch)
 {

@@ -44,7 +44,12 @@ struct Dev {
     double *partial;          // reduction partials
     double omega, gx, gy, gz, sigma, rho_gas, eps, tie;
     int rule_iso;
+    int variants;             // VAR_* bits
 };
+
+// free-surface variants (Thuerey 2007): flux modifiers between interface
+// cells, normal-weighted excess mass
+constexpr int VAR_FLUX_MODIFIERS = 1, VAR_NORMAL_EXCESS = 2;
 
 constexpr int BULK_THREADS = 256;
 constexpr int BULK_MAX_BLOCKS = 2048;

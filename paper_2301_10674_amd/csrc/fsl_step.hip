@@ -5,6 +5,8 @@
 //   k_bulk    dense over the liquid rows: pull streaming, bounce-back next
 //             to walls and spheres, mass bookkeeping, cumulant collision,
 //             store.  This is the HBM-bound hot kernel.
+//   k_classes (flux-modifier variant only) interface list: the class of
+//             each interface cell from its neighbours' types.
 //   k_iface   interface list: the same plus the interface normal and
 //             curvature (finite differences on the fill stencil),
 //             reconstruction of PDFs from the gas side, the fill-weighted
@@ -654,6 +656,14 @@ __global__ __launch_bounds__(256) void k_zmax(Dev d)
 // the conversion marks.  GI: the normal and curvature are evaluated here
 // from the fill stencil (finite differences); otherwise they are read from
 // the geometry array (learned estimator).
+// flux-modifier rank of an interface cell from its flag byte: 0 may only
+// lose mass to other interface cells, 2 may only gain, 1 both (every cell
+// when the variant is off, since the class bits are then never set)
+__device__ __forceinline__ uint32_t fm_rank(uint32_t f)
+{
+    return 1u + ((f >> 6) & 1u) - ((f >> 5) & 1u);
+}
+
 template <class S, bool GI>
 __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
                                            int c, uint32_t epoch)
@@ -710,16 +720,18 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     load_record<R>(d, slot, rv);
     R rec[28];
     __builtin_memcpy(rec, rv, sizeof(rv));
-    uint64_t tyb = 0;
+    uint64_t tyb = 0, rkb = 0;
     double sv[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const uint32_t t = nb(i) < 0 ? (uint32_t)T_SOLID : (fl[i] & T_MASK);
         const double pv = ph[i] < 0.0 ? 0.0 : (ph[i] > 1.0 ? 1.0 : ph[i]);
         tyb |= (uint64_t)t << (2 * i);
+        rkb |= (uint64_t)fm_rank(fl[i]) << (2 * i);
         sv[i] = i == REST ? phicl : (t == T_LIQ ? 1.0 : (t == T_GAS ? 0.0 : (t == T_IF ? pv : phicl)));
     }
     auto ty = [&](int i) { return (uint32_t)(tyb >> (2 * i)) & 3u; };
+    auto rk = [&](int i) { return (uint32_t)(rkb >> (2 * i)) & 3u; };
     double4 gn;
     if constexpr (GI) {
         gn = fd_geometry(sv);
@@ -737,14 +749,29 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     }
     keep(mq0);
 
-    // mass flux from the stored PDFs: s_i (f*_{-i}(x+c_i) - f*_i(x))
+    // mass flux from the stored PDFs: s_i (f*_{-i}(x+c_i) - f*_i(x)); with
+    // the flux modifiers, between interface cells of different ranks only
+    // the term that moves mass from the lower to the higher rank is kept
     double dm = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const uint32_t t = ty(i);
         if (i == REST || t == T_SOLID || t == T_GAS) continue;
         const double sw = t == T_IF ? 0.5 * (phicl + sv[i]) : 1.0;
-        dm += sw * ((double)pulled[opp(i)] - (double)own[i]);
+        double in = (double)pulled[opp(i)], out = (double)own[i];
+        if (t == T_IF) {
+            // a single kept term is a whole PDF: the stored deviations get
+            // their weight back (w_{-i} = w_i), which the difference of two
+            // terms cancels
+            if (rk(REST) < rk(i)) {
+                in = 0.0;
+                out += wgt(i);
+            } else if (rk(REST) > rk(i)) {
+                out = 0.0;
+                in += wgt(i);
+            }
+        }
+        dm += sw * (in - out);
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -817,6 +844,43 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
         else if (!has_liq && has_gas) bits = MK_TO_GAS | MK_ISO;
     }
     d.mark[c] = (epoch << 8) | bits;
+    if constexpr (GI) {
+        // the normal-weighted excess of a converting cell needs its normal
+        if ((d.variants & VAR_NORMAL_EXCESS) && (bits & (MK_TO_LIQ | MK_TO_GAS))) {
+            R4 g;
+            g.x = R(gn.x);
+            g.y = R(gn.y);
+            g.z = R(gn.z);
+            g.w = R(gn.w);
+            ((R4 *)d.geom)[c] = g;
+        }
+    }
+}
+
+// Flux-modifier classes of the interface cells from the cell types at the
+// start of the step (Thuerey 2007): F_CLS_LOSE with gas but no liquid
+// neighbours, F_CLS_GAIN with liquid but no gas neighbours.  Only the class
+// bits of the cell's own flag byte change, so concurrent readers of its type
+// are unaffected.
+__global__ __launch_bounds__(LIST_THREADS) void k_classes(Dev d, int p)
+{
+    const int32_t *list = d.list[p];
+    const int count = d.cnt[p];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int c = list[t];
+        const Cell pc = cell_xyz(d, c);
+        bool g = false, q = false;
+        for (int i = 0; i < 27; ++i) {
+            if (i == REST) continue;
+            const int y = nb_of(d, pc, i);
+            if (y < 0) continue;
+            const uint8_t ty = d.flags[y] & T_MASK;
+            g |= ty == T_GAS;
+            q |= ty == T_LIQ;
+        }
+        const uint8_t cls = (g && !q) ? F_CLS_LOSE : ((q && !g) ? F_CLS_GAIN : 0);
+        d.flags[c] = (uint8_t)((d.flags[c] & ~(F_CLS_LOSE | F_CLS_GAIN)) | cls);
+    }
 }
 
 // Interface list of the step (one cell per thread).  Block 0 starts the
@@ -972,6 +1036,27 @@ __device__ __forceinline__ bool interface_after(const Dev &d, int y, uint32_t ep
     return (d.flags[y] & T_MASK) == T_IF && !(mk & (MK_TO_LIQ | MK_EMPTY));
 }
 
+// weight of the link c_i from a converted cell with normal n (liquid to gas)
+// when the excess is shared by normal weights: along n for a filled cell,
+// against it for an emptied one; projections up to the normal tie are zero
+__device__ __forceinline__ double excess_weight(const double (&n)[3], int i, bool filled, double tie)
+{
+    double nc = n[0] * cx(i) + n[1] * cy(i) + n[2] * cz(i);
+    if (!filled) nc = -nc;
+    return nc > tie ? nc : 0.0;
+}
+
+template <class S>
+__device__ __forceinline__ void load_normal(const Dev &d, int c, double (&n)[3])
+{
+    using R = typename Real<S>::type;
+    using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+    const R4 g = ((const R4 *)d.geom)[c];
+    n[0] = (double)g.x;
+    n[1] = (double)g.y;
+    n[2] = (double)g.z;
+}
+
 // excess mass of an interface cell that fills or empties this step
 template <class S>
 __device__ __forceinline__ void conv3_cell(const Dev &d, int p, uint32_t epoch, int c)
@@ -992,13 +1077,24 @@ __device__ __forceinline__ void conv3_cell(const Dev &d, int p, uint32_t epoch, 
             e = d.mq[c];
             d.mq[c] = 0.0;
         }
+        const bool weighted = (d.variants & VAR_NORMAL_EXCESS) != 0;
+        double n[3] = {0.0, 0.0, 0.0};
+        if (weighted) load_normal<S>(d, c, n);
         int recv = 0;
+        double wsum = 0.0;
         for (int i = 0; i < 27; ++i) {
             if (i == REST) continue;
             const int y = nb_of(d, pc, i);
-            if (y >= 0 && interface_after(d, y, epoch)) ++recv;
+            if (y >= 0 && interface_after(d, y, epoch)) {
+                ++recv;
+                if (weighted) wsum += excess_weight(n, i, filled, d.tie);
+            }
         }
-        if (recv > 0) {
+        if (wsum > 0.0) {
+            // the receiver along c_i takes share * weight of c_i
+            d.share[c] = e / wsum;
+            atomicOr(&d.mark[c], MK_WEIGHTED);
+        } else if (recv > 0) {
             d.share[c] = e / recv;
         } else {
             d.share[c] = 0.0;
@@ -1043,6 +1139,7 @@ __device__ __forceinline__ void block_append(int32_t *list, int32_t *counter, bo
     __syncthreads();
 }
 
+template <class S>
 __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t epoch)
 {
     const int32_t *list = d.list[p];
@@ -1088,10 +1185,22 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv4(Dev d, int p, uint32_t e
             for (int i = 0; i < 27; ++i) keep(mk[i]);
             keep(mq0);
             keep(rho0);
+            // seen from the converted neighbour y = c + c_i, this cell lies
+            // along -c_i
             double add = 0.0;
 #pragma unroll
-            for (int i = 0; i < 27; ++i)
-                if (nb[i] >= 0 && (mark_bits(mk[i], epoch) & (MK_TO_LIQ | MK_EMPTY))) add += d.share[nb[i]];
+            for (int i = 0; i < 27; ++i) {
+                if (nb[i] < 0) continue;
+                const uint32_t b = mark_bits(mk[i], epoch);
+                if (!(b & (MK_TO_LIQ | MK_EMPTY))) continue;
+                double s = d.share[nb[i]];
+                if (b & MK_WEIGHTED) {
+                    double n[3];
+                    load_normal<S>(d, nb[i], n);
+                    s *= excess_weight(n, opp(i), (b & MK_TO_LIQ) != 0, d.tie);
+                }
+                add += s;
+            }
             const double m = mq0 + add;
             d.mq[c] = m;
             d.phi[c] = m / rho0;
@@ -1154,13 +1263,14 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
     if (ev0) (void)hipEventRecord(ev0, st);
     k_bulk<S><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
+    if (d.variants & VAR_FLUX_MODIFIERS) k_classes<<<list_blocks, LIST_THREADS, 0, st>>>(d, p);
     if (mlpP)
         k_iface<S, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     else
         k_iface<S, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv23<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_conv4<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    k_conv4<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     if (mlpP) launch_geom_mlp<R>(d, p ^ 1, list_blocks, mlpP, mlpPk, st);
 }
 

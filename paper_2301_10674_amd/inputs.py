@@ -213,3 +213,29 @@ def droplet(n: int = 40, radius: float = 10.0, sigma: float = 1e-3, omega: float
         sigma=sigma, fill=fill, rho=np.ones((n, n, n)), vel=np.zeros((3, n, n, n)),
         centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
         sphere_angvel=np.zeros((0, 3)), meta={"radius": radius})
+
+
+def splash(shape=(48, 32, 40), seed: int = 4, sigma: float = 1e-3) -> Workload:
+    """A falling blob over a rough pool: liquid up to z = nz/3 with a noisy
+    surface, a ball of radius nz/6 centred at 0.62 nz moving down at 0.04
+    with a random swirl, gravity 2e-4 down.  The blob's edge and the pool's
+    surface carry interface cells with only gas or only liquid neighbours,
+    and the impact fills and empties many cells a step."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    h = nz / 3.0 + 0.8 * rng.standard_normal((ny, nx))
+    fill = height_fill(shape, h)
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    r = np.sqrt((x - 0.5 * nx) ** 2 + (y - 0.5 * ny) ** 2 + (z - 0.62 * nz) ** 2)
+    ball = np.clip(nz / 6.0 + 0.5 - r, 0.0, 1.0)
+    fill = np.clip(fill + ball, 0.0, 1.0)
+    edge = (fill > 0) & (fill < 1)
+    fill = np.where(edge, np.clip(fill + 0.15 * rng.standard_normal(fill.shape), 0.0, 1.0), fill)
+    vel = np.zeros((3, nz, ny, nx))
+    inball = r < nz / 6.0 + 1.0
+    vel[2] = np.where(inball, -0.04, 0.0)
+    vel += 0.01 * rng.standard_normal((3, nz, ny, nx)) * inball
+    return Workload(name="splash_%dx%dx%d" % shape, shape=shape, omega=1.6, accel=(0.0, 0.0, -2e-4),
+                    sigma=sigma, fill=fill, rho=np.ones((nz, ny, nx)), vel=vel,
+                    centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+                    sphere_angvel=np.zeros((0, 3)))

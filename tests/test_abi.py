@@ -54,5 +54,14 @@ def test_bad_params_rejected(lib, kw):
     assert len(lib.fsl_last_error()) > 0
 
 
+def test_variant_bits(lib):
+    p = F.make_params((16, 8, 8), "fp32", omega=1.5, flux_modifiers=True, normal_excess=True)
+    assert p.variants == F.FSL_VAR_FLUX_MODIFIERS | F.FSL_VAR_NORMAL_EXCESS
+    assert F.workspace_bytes(p) > 0
+    p.variants = 4
+    assert F.workspace_bytes(p) == 0
+    assert "variant" in lib.fsl_last_error().decode()
+
+
 def test_bad_shape_rejected(lib):
     assert F.workspace_bytes(F.make_params((2, 8, 8), "fp32", omega=1.5)) == 0
