@@ -146,6 +146,34 @@ void ol_set_threads(int32_t n);
 double ol_round_half(double x);
 int32_t ol_threads(void);
 
+/* --- particles (dem_oracle.c) --------------------------------------------- */
+typedef struct {
+    int32_t nx, ny, nz;         /* periodic x in [0, nx), y in [0, ny); walls z = 0, z = nz */
+    double density;             /* particle density over fluid density */
+    double restitution;         /* dry coefficient of restitution, (0, 1] */
+    double collision_time;      /* duration of a free binary collision */
+    double poisson;             /* Poisson's ratio, [0, 0.5) */
+    double friction;            /* Coulomb friction coefficient */
+    double viscosity;           /* fluid kinematic viscosity (fluid density 1) */
+    double lub_cut;             /* lubrication acts for gaps below this (0: off) */
+    double lub_min;             /* smallest gap the lubrication force uses */
+    double accel[3];            /* acceleration of every particle (gravity) */
+    double dt;                  /* time advanced by one ol_dem_step */
+    int32_t substeps;           /* sub-steps per ol_dem_step */
+} OlDemParams;
+
+typedef struct OlDem OlDem;
+
+/* centre, vel, angvel: 3 per sphere (vel, angvel may be NULL: zero); fixed:
+ * n flags (NULL: none; fixed spheres never move).  NULL on bad arguments. */
+OlDem *ol_dem_create(const OlDemParams *p, int32_t n, const double *centre, const double *radius,
+                     const double *vel, const double *angvel, const uint8_t *fixed);
+void ol_dem_destroy(OlDem *D);
+/* one lattice step of particle motion under hydro[6 n] (force, torque per
+ * sphere, held over the sub-steps; NULL: none) */
+void ol_dem_step(OlDem *D, const double *hydro);
+void ol_dem_read(const OlDem *D, double *centre, double *vel, double *angvel);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fsl_oracle.c")
 MLP_SRC = os.path.join(HERE, "mlp_oracle.c")
+DEM_SRC = os.path.join(HERE, "dem_oracle.c")
 HDR = os.path.join(HERE, "fsl_oracle.h")
 LIB = os.path.join(HERE, "liboracle.so")
 
@@ -29,15 +30,26 @@ VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS = 1, 2
 def build(force: bool = True) -> str:
     """Compile ``liboracle.so`` next to its source."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
-        os.path.getmtime(SRC), os.path.getmtime(HDR), os.path.getmtime(MLP_SRC)
+        os.path.getmtime(SRC), os.path.getmtime(HDR), os.path.getmtime(MLP_SRC), os.path.getmtime(DEM_SRC)
     ):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, MLP_SRC, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, MLP_SRC, DEM_SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+class _DemParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("density", ctypes.c_double), ("restitution", ctypes.c_double),
+        ("collision_time", ctypes.c_double), ("poisson", ctypes.c_double),
+        ("friction", ctypes.c_double), ("viscosity", ctypes.c_double),
+        ("lub_cut", ctypes.c_double), ("lub_min", ctypes.c_double),
+        ("accel", ctypes.c_double * 3), ("dt", ctypes.c_double), ("substeps", ctypes.c_int32),
+    ]
 
 
 class _Params(ctypes.Structure):
@@ -98,6 +110,11 @@ def lib():
         L.ol_mlp_loss_grad.argtypes = [dp, ctypes.c_int32, dp, dp, dp]
         L.ol_mlp_adam.argtypes = [dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.ol_dem_create.restype = ctypes.c_void_p
+        L.ol_dem_create.argtypes = [ctypes.POINTER(_DemParams), ctypes.c_int32, dp, dp, dp, dp, ctypes.c_void_p]
+        L.ol_dem_destroy.argtypes = [ctypes.c_void_p]
+        L.ol_dem_step.argtypes = [ctypes.c_void_p, dp]
+        L.ol_dem_read.argtypes = [ctypes.c_void_p, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -370,3 +387,54 @@ class FlowController:
             ax = self.a0 + self.kp * e + self.ki * self.integral
             o.set_accel((ax, 0.0, 0.0))
         return ax
+
+
+# ------------------------------------------------------------------ particles
+class OracleDem:
+    """FP64 reference of the particle motion (dem_oracle.c): rigid spheres
+    with contacts, lubrication, gravity and a given hydrodynamic load."""
+
+    def __init__(self, box, centre, radius, vel=None, angvel=None, fixed=None, density=2.5,
+                 restitution=0.97, collision_time=40.0, poisson=0.22, friction=0.5, viscosity=0.0,
+                 lub_cut=0.0, lub_min=1e-3, accel=(0.0, 0.0, 0.0), dt=1.0, substeps=10):
+        p = _DemParams()
+        p.nx, p.ny, p.nz = (int(v) for v in box)
+        p.density, p.restitution, p.collision_time = density, restitution, collision_time
+        p.poisson, p.friction, p.viscosity = poisson, friction, viscosity
+        p.lub_cut, p.lub_min, p.dt, p.substeps = lub_cut, lub_min, dt, int(substeps)
+        for d in range(3):
+            p.accel[d] = accel[d]
+        centre = _f64(centre).reshape(-1, 3)
+        self.n = n = centre.shape[0]
+        self._keep = [_f64(centre).reshape(-1), _f64(radius).reshape(-1)]
+        v = None if vel is None else _f64(vel).reshape(-1)
+        w = None if angvel is None else _f64(angvel).reshape(-1)
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8).reshape(-1)
+        self._keep += [v, w, fx]
+        L = lib()
+        h = L.ol_dem_create(ctypes.byref(p), n, _dp(self._keep[0]), _dp(self._keep[1]),
+                            _dp(v) if v is not None else None, _dp(w) if w is not None else None,
+                            fx.ctypes.data if fx is not None else None)
+        if not h:
+            raise ValueError("oracle rejected the particle parameters")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().ol_dem_destroy(h)
+            self.h = None
+
+    def step(self, hydro=None, n=1):
+        hp = None
+        if hydro is not None:
+            self._hydro = _f64(hydro).reshape(-1)
+            assert self._hydro.size == 6 * self.n
+            hp = _dp(self._hydro)
+        for _ in range(int(n)):
+            lib().ol_dem_step(self.h, hp)
+
+    def state(self):
+        out = [np.zeros((self.n, 3)) for _ in range(3)]
+        lib().ol_dem_read(self.h, *[_dp(o) for o in out])
+        return out

@@ -58,6 +58,21 @@ MUTANTS = {
     "excess_no_fallback": ("} else if (recv > 0) {\n            L->share[c] = e / recv;",
                            "} else if (0) {\n            L->share[c] = e / recv;",
                            "test_oracle_variants.py", "falls_back"),
+    "dem_damping_sign": ("const double gn = -2.0 * meff * lne / p->collision_time;",
+                         "const double gn = 2.0 * meff * lne / p->collision_time;",
+                         "test_oracle_dem.py", "head_on", "dem_oracle.c"),
+    "dem_effective_mass": ("else meff = D->m[a] * D->m[b] / (D->m[a] + D->m[b]);", "else meff = D->m[a];",
+                           "test_oracle_dem.py", "head_on", "dem_oracle.c"),
+    "dem_contact_point": ("const double la = ra - 0.5 * delta, lb = rb - 0.5 * delta;",
+                          "const double la = ra, lb = rb;", "test_oracle_dem.py", "oblique", "dem_oracle.c"),
+    "dem_friction_cap": ("lim = p->friction * fabs(fn);", "lim = 2.0 * p->friction * fabs(fn);",
+                         "test_oracle_dem.py", "sliding", "dem_oracle.c"),
+    "dem_lubrication_radius": ("const double reff = ra * rb / (ra + rb);", "const double reff = 0.5 * (ra + rb);",
+                               "test_oracle_dem.py", "lubrication", "dem_oracle.c"),
+    "dem_wall_torque": ("cross3(arm, ft, t);", "cross3(ft, arm, t);", "test_oracle_dem.py", "sliding",
+                        "dem_oracle.c"),
+    "dem_inertia": ("D->inertia[i] = 0.4 * D->m[i] * r * r;", "D->inertia[i] = 0.5 * D->m[i] * r * r;",
+                    "test_oracle_dem.py", "hydrodynamic", "dem_oracle.c"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
@@ -65,17 +80,20 @@ MUTANTS = {
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_is_caught(name, tmp_path):
-    old, new, target, sel = MUTANTS[name]
-    src = open(SRC).read()
-    assert src.count(old) >= 1, "mutation site not found: " + name
+    old, new, target, sel = MUTANTS[name][:4]
+    mutated = MUTANTS[name][4] if len(MUTANTS[name]) > 4 else "fsl_oracle.c"
     mdir = tmp_path / "oracle"
     mdir.mkdir()
-    (mdir / "fsl_oracle.c").write_text(src.replace(old, new, 1))
-    for extra in ("fsl_oracle.h", "mlp_oracle.c"):
-        (mdir / extra).write_text(open(os.path.join(ROOT, "oracle", extra)).read())
+    for f in ("fsl_oracle.c", "fsl_oracle.h", "mlp_oracle.c", "dem_oracle.c"):
+        src = open(os.path.join(ROOT, "oracle", f)).read()
+        if f == mutated:
+            assert src.count(old) >= 1, "mutation site not found: " + name
+            src = src.replace(old, new, 1)
+        (mdir / f).write_text(src)
     so = str(mdir / "liboracle.so")
     subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                    "-o", so, str(mdir / "fsl_oracle.c"), str(mdir / "mlp_oracle.c"), "-lm"],
+                    "-o", so, str(mdir / "fsl_oracle.c"), str(mdir / "mlp_oracle.c"),
+                    str(mdir / "dem_oracle.c"), "-lm"],
                    check=True)
     env = dict(os.environ, FSL_ORACLE_LIB=so)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
