@@ -180,7 +180,49 @@ def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=10,
     return w, rep
 
 
-def run_form(w, form, steps, warmup):
+def time_particles(w, lat, fsl, steps=20, coupled_steps=10):
+    """Particle motion on the flume's spheres (lowest layer fixed, 10
+    sub-steps per lattice step, the paper's collision parameters, gravity
+    of the flume, lubrication below 2/3 cell) under the lattice's
+    momentum-exchange load, then whole coupled steps (fluid step, forces,
+    particle sub-steps, remap).  The generated bed overlaps (it is a
+    jittered packing for the lattice), so the spheres first push apart: the
+    timings are those of a bed with every sphere in contact."""
+    import torch
+
+    from paper_2301_10674_amd.couple import Coupled
+
+    c, r = w.centre, w.radius
+    fixed = (c[:, 2] < c[:, 2].min() + 2.0).astype(np.uint8)
+    nu = (1.0 / w.omega - 0.5) / 3.0
+    out = {"spheres": int(len(r)), "fixed": int(fixed.sum()), "substeps": 10}
+    try:
+        dem = fsl.Dem(w.shape, c, r, w.sphere_vel, w.sphere_angvel, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
+                      accel=w.accel, substeps=10, skin=1.0)
+        hydro = lat.particle_forces()
+        dem.step(hydro)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dem.step(hydro)
+        out["dem_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
+        dem.destroy()
+        dem = fsl.Dem(w.shape, c, r, w.sphere_vel, w.sphere_angvel, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
+                      accel=w.accel, substeps=10, skin=1.0)
+        run = Coupled(lat, dem)
+        run.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.step(coupled_steps)
+        torch.cuda.synchronize()
+        out["coupled_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / coupled_steps
+        dem.destroy()
+    except fsl.FslError as e:
+        out["error"] = str(e)
+    return out
+
+
+def run_form(w, form, steps, warmup, main_form=None):
     import torch
 
     from paper_2301_10674_amd import fsl
@@ -231,6 +273,8 @@ def run_form(w, form, steps, warmup):
     if learned:
         used1 = lat.estimator_stats()
         res["estimator"] = dict(est, network_cells=used1[0] - used0[0], fallback_cells=used1[1] - used0[1])
+    if len(w.radius) and form == main_form:
+        res["particles"] = time_particles(w, lat, fsl)
     # momentum-exchange force and torque on every sphere (outside the timed
     # steps; the coupling would call it once per step)
     if len(w.radius):
@@ -342,7 +386,7 @@ def main():
     w = inputs.flume(nx=args.nx, ny=args.ny, nz=args.nz, seed=2)
     log("spheres %d, bed height %.2f, surface %.2f" % (w.meta["spheres"], w.meta["bed_height"],
                                                       w.meta["surface"]))
-    main_res = run_form(w, args.precision, args.steps, args.warmup)
+    main_res = run_form(w, args.precision, args.steps, args.warmup, main_form=args.precision)
     log("main form:", json.dumps(main_res))
     forms = {args.precision: main_res}
     for p in [f for f in args.forms.split(",") if f and f != args.precision]:
@@ -376,7 +420,7 @@ def main():
         "mlups_all_cells": r["mlups_all"],
         "mass_drift": r["mass_drift"],
         "forms": {k: {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_gbs", "mass_drift",
-                                          "interface_error", "estimator", "particle_forces_ms") if kk in v}
+                                          "interface_error", "estimator", "particle_forces_ms", "particles") if kk in v}
                   for k, v in forms.items()},
     }
     print(json.dumps(out), flush=True)

@@ -305,6 +305,74 @@ FslStatus fsl_particle_forces(FslLattice *lat, double *out, int32_t out_on_devic
 /* Interface-cell updates since creation that used the network / fell back. */
 FslStatus fsl_estimator_stats(FslLattice *lat, int64_t *learned, int64_t *fallback);
 
+/* ---- particle motion (Section 2.2) -------------------------------------
+ * Rigid spheres advanced by the Newton-Euler equations under a hydrodynamic
+ * load (e.g. fsl_particle_forces), gravity, collisions and lubrication, with
+ * several sub-steps per lattice step.  Section 2.2 parameterises the
+ * collision model by e_dry, T_c, nu_p and mu_p and adds lubrication
+ * corrections; the model details are readings of the cited coupling paper:
+ *   normal contact: linear spring-dashpot on the overlap delta with
+ *     k_n = m_eff (pi^2 + ln^2 e)/T_c^2, gamma_n = -2 m_eff ln(e)/T_c
+ *     (a free binary collision rebounds with restitution e after T_c);
+ *     m_eff = m_i m_j/(m_i + m_j), the free sphere's mass against a fixed
+ *     sphere or a wall;
+ *   tangential: a spring on the accumulated tangential displacement plus a
+ *     dashpot, k_t = kappa k_n, gamma_t = sqrt(kappa) gamma_n with
+ *     kappa = 2(1 - nu)/(2 - nu), capped by Coulomb friction mu |F_n|;
+ *     forces act at the middle of the overlap;
+ *   lubrication: -6 pi nu_f R_eff^2 u_n (1/s - 1/s_c) along the line of
+ *     centres for gaps 0 < s < s_c (s taken >= s_min), R_eff = r_i r_j /
+ *     (r_i + r_j) (r_i against a wall), u_n the normal approach speed;
+ *   time: symplectic Euler per sub-step (forces from the sub-step's start,
+ *     then velocities, then positions); x and y periodic, walls z = 0 and
+ *     z = nz (the lattice's bounce-back planes); m = density 4/3 pi r^3,
+ *     I = 2/5 m r^2; fixed spheres never move. */
+typedef struct {
+    int32_t nx, ny, nz;     /* box: periodic x in [0, nx), y in [0, ny); walls at z = 0, nz */
+    double density;         /* particle density over fluid density (> 0) */
+    double restitution;     /* e_dry in (0, 1] */
+    double collision_time;  /* T_c (> 0), time units of the lattice */
+    double poisson;         /* nu_p in [0, 0.5) */
+    double friction;        /* mu_p >= 0 */
+    double viscosity;       /* fluid kinematic viscosity nu_f (lubrication; fluid density 1) */
+    double lub_cut;         /* s_c: lubrication for gaps below it (0: off) */
+    double lub_min;         /* s_min > 0 */
+    double accel[3];        /* acceleration of every sphere (gravity) */
+    double dt;              /* time per step (> 0; one lattice step: 1) */
+    int32_t substeps;       /* sub-steps per step (>= 1) */
+    double skin;            /* > 0: neighbour lists hold spheres within r_i + r_j + s_c + skin */
+} FslDemParams;
+
+typedef struct FslDem FslDem;  /* opaque */
+
+/* Create the particle state for n >= 1 spheres: centre, vel, angvel are 3
+ * host doubles per sphere (vel/angvel may be NULL: zero), radius n doubles
+ * (> 0), fixed n bytes or NULL.  Allocates about (36 + 6*32) doubles and
+ * 66 int32 per sphere of device memory with hipMalloc (freed by
+ * fsl_dem_destroy); all work runs on hip_stream (NULL: default).
+ * FSL_ERR_ARG for invalid parameters or state, FSL_ERR_NOMEM. */
+FslStatus fsl_dem_create(const FslDemParams *params, void *hip_stream, int32_t n,
+                         const double *centre, const double *radius, const double *vel,
+                         const double *angvel, const uint8_t *fixed, FslDem **out);
+
+/* Advance nsteps steps of dt, each in `substeps` sub-steps, under hydro:
+ * 6 doubles per sphere (force, torque; the order of fsl_particle_forces),
+ * held over all sub-steps; host memory, or device memory when
+ * hydro_on_device != 0; NULL for none.  Each step rebuilds the neighbour
+ * lists; a sphere with more than 32 spheres within reach gives
+ * FSL_ERR_NOMEM, a sphere that moves more than skin/2 within one step
+ * FSL_ERR_UNSTABLE (the state stays readable; later steps report the same
+ * error).  Forces sum in a fixed order (deterministic).  Synchronises the
+ * stream. */
+FslStatus fsl_dem_step(FslDem *dem, const double *hydro, int32_t hydro_on_device, int32_t nsteps);
+
+/* Copy the state out: 3 doubles per sphere each (any may be NULL), centres
+ * wrapped into [0, nx) x [0, ny); host memory, or device memory when
+ * out_on_device != 0.  Synchronises the stream. */
+FslStatus fsl_dem_read(FslDem *dem, double *centre, double *vel, double *angvel, int32_t out_on_device);
+
+void fsl_dem_destroy(FslDem *dem);
+
 /* Thread-local text of the last error (never NULL). */
 const char *fsl_last_error(void);
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfsl.so")
-SOURCES = ["fsl_step.hip", "fsl_mlp.hip", "fsl_api.hip"]
+SOURCES = ["fsl_step.hip", "fsl_mlp.hip", "fsl_dem.hip", "fsl_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -42,6 +42,11 @@ static FslStatus fail(FslStatus s, const std::string &msg)
     return s;
 }
 
+namespace fsl {
+// the error text of the other entry points of the library (particles)
+FslStatus set_error(FslStatus s, const std::string &msg) { return fail(s, msg); }
+}  // namespace fsl
+
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
         hipError_t e_ = (expr);                                                         \

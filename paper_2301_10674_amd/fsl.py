@@ -30,7 +30,8 @@ EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fs
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
            "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
            "fsl_bed_profile", "fsl_move_particles",
-           "fsl_set_estimator", "fsl_estimator_stats", "fsl_last_error", "fsl_destroy")
+           "fsl_set_estimator", "fsl_estimator_stats", "fsl_dem_create", "fsl_dem_step",
+           "fsl_dem_read", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
 
 
@@ -49,6 +50,18 @@ class FslParams(ctypes.Structure):
         ("normal_tie", ctypes.c_double), ("rule_isolated", ctypes.c_int32),
         ("normals", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("variants", ctypes.c_int32),
+    ]
+
+
+class FslDemParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("density", ctypes.c_double), ("restitution", ctypes.c_double),
+        ("collision_time", ctypes.c_double), ("poisson", ctypes.c_double),
+        ("friction", ctypes.c_double), ("viscosity", ctypes.c_double),
+        ("lub_cut", ctypes.c_double), ("lub_min", ctypes.c_double),
+        ("accel", ctypes.c_double * 3), ("dt", ctypes.c_double), ("substeps", ctypes.c_int32),
+        ("skin", ctypes.c_double),
     ]
 
 
@@ -132,6 +145,15 @@ def lib():
         L.fsl_set_estimator.argtypes = [vp, fp]
         L.fsl_estimator_stats.restype = ctypes.c_int
         L.fsl_estimator_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.fsl_dem_create.restype = ctypes.c_int
+        L.fsl_dem_create.argtypes = [ctypes.POINTER(FslDemParams), vp, i32, dp, dp, dp, dp, vp,
+                                     ctypes.POINTER(vp)]
+        L.fsl_dem_step.restype = ctypes.c_int
+        L.fsl_dem_step.argtypes = [vp, vp, i32, i32]
+        L.fsl_dem_read.restype = ctypes.c_int
+        L.fsl_dem_read.argtypes = [vp, dp, dp, dp, i32]
+        L.fsl_dem_destroy.restype = None
+        L.fsl_dem_destroy.argtypes = [vp]
         L.fsl_last_error.restype = ctypes.c_char_p
         L.fsl_last_error.argtypes = []
         L.fsl_destroy.restype = None
@@ -367,3 +389,60 @@ def fd_geometry(x):
     y = np.zeros(4 * n, dtype=np.float32)
     _check(lib().fsl_fd_geometry(_fp(x), n, _fp(y), _stream()))
     return y.reshape(n, 4)
+
+
+class Dem:
+    """Rigid spheres on the GPU (fsl_dem_*): Newton-Euler motion under a
+    hydrodynamic load, gravity, collisions and lubrication, sub-stepped per
+    lattice step.  Defaults are the paper's collision parameters (e_dry 0.97,
+    T_c = 4 d50 for d50 = 10 cells, nu_p 0.22, mu_p 0.5) and the density
+    ratio of its gravel (2.55)."""
+
+    def __init__(self, box, centre, radius, vel=None, angvel=None, fixed=None, density=2.55,
+                 restitution=0.97, collision_time=40.0, poisson=0.22, friction=0.5, viscosity=0.0,
+                 lub_cut=0.0, lub_min=1e-3, accel=(0.0, 0.0, 0.0), dt=1.0, substeps=10, skin=1.0,
+                 stream=None):
+        p = FslDemParams()
+        p.nx, p.ny, p.nz = (int(v) for v in box)
+        p.density, p.restitution, p.collision_time = density, restitution, collision_time
+        p.poisson, p.friction, p.viscosity = poisson, friction, viscosity
+        p.lub_cut, p.lub_min, p.dt, p.substeps, p.skin = lub_cut, lub_min, dt, int(substeps), skin
+        for d in range(3):
+            p.accel[d] = float(accel[d])
+        c = _f64(centre)
+        self.n = n = c.size // 3
+        r, v, w = _f64(radius), _f64(vel), _f64(angvel)
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8).reshape(-1)
+        h = ctypes.c_void_p()
+        _check(lib().fsl_dem_create(ctypes.byref(p), stream, n, _dp(c), _dp(r), _dp(v), _dp(w),
+                                    None if fx is None else fx.ctypes.data, ctypes.byref(h)))
+        self.h = h
+
+    def step(self, hydro=None, n=1):
+        """hydro: (n, 6) host array, a CUDA tensor of 6 n float64, or None"""
+        if hydro is None:
+            _check(lib().fsl_dem_step(self.h, None, 0, int(n)))
+        elif hasattr(hydro, "data_ptr"):
+            assert hydro.is_cuda and hydro.numel() == 6 * self.n and hydro.is_contiguous()
+            _check(lib().fsl_dem_step(self.h, ctypes.c_void_p(hydro.data_ptr()), 1, int(n)))
+        else:
+            a = _f64(hydro)
+            assert a.size == 6 * self.n
+            _check(lib().fsl_dem_step(self.h, a.ctypes.data, 0, int(n)))
+
+    def state(self):
+        """(centre, vel, angvel), each (n, 3) host arrays"""
+        out = [np.zeros(3 * self.n) for _ in range(3)]
+        _check(lib().fsl_dem_read(self.h, *[_dp(o) for o in out], 0))
+        return [o.reshape(self.n, 3) for o in out]
+
+    def destroy(self):
+        if self.h:
+            lib().fsl_dem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

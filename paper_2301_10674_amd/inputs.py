@@ -239,3 +239,43 @@ def splash(shape=(48, 32, 40), seed: int = 4, sigma: float = 1e-3) -> Workload:
                     sigma=sigma, fill=fill, rho=np.ones((nz, ny, nx)), vel=vel,
                     centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
                     sphere_angvel=np.zeros((0, 3)))
+
+
+def sphere_cluster(box=(48, 36, 30), seed: int = 6):
+    """60 spheres of radius 2.5-4 on a jittered 5 x 4 x 3 grid (spacing
+    9.6 x 9 x 9, jitter +-1.2: close pairs that collide soon), with
+    random velocities (0.03) and spins (0.002); the first six fixed."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = box
+    g = np.stack(np.meshgrid((np.arange(5) + 0.5) * nx / 5, (np.arange(4) + 0.5) * ny / 4,
+                             5.0 + 9.0 * np.arange(3), indexing="ij"), axis=-1).reshape(-1, 3)
+    n = len(g)
+    c = g + rng.uniform(-1.2, 1.2, (n, 3))
+    r = rng.uniform(2.5, 4.0, n)
+    v = 0.03 * rng.standard_normal((n, 3))
+    w = 0.002 * rng.standard_normal((n, 3))
+    fixed = np.zeros(n, dtype=np.uint8)
+    fixed[: n // 10] = 1
+    v[fixed == 1] = 0.0
+    w[fixed == 1] = 0.0
+    return c, r, v, w, fixed
+
+
+def settling_box(shape=(24, 20, 28), seed: int = 8) -> Workload:
+    """Liquid at rest to z = 20 under gravity 1e-3 down, three spheres of
+    radius 3 moving down at 0.02 (one 0.3 cells above the bottom wall, one
+    a few cells above it, one at the surface), for the coupled fluid-particle
+    step."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    h = np.full((ny, nx), 20.0)
+    fill = height_fill(shape, h)
+    g = 1e-3
+    z = np.arange(nz, dtype=np.float64)[:, None, None] + 0.5
+    rho = np.exp(3.0 * g * (20.0 - np.minimum(z, 20.0))) * np.ones((nz, ny, nx))
+    centre = np.array([[6.0, 5.0, 3.3], [15.5, 12.0, 9.0], [10.0, 15.0, 19.0]])
+    centre[:, :2] += rng.uniform(-0.5, 0.5, (3, 2))
+    return Workload(name="settling_%dx%dx%d" % shape, shape=shape, omega=1.5, accel=(0.0, 0.0, -g),
+                    sigma=0.0, fill=fill, rho=rho, vel=np.zeros((3, nz, ny, nx)), centre=centre,
+                    radius=np.full(3, 3.0), sphere_vel=np.tile([0.0, 0.0, -0.02], (3, 1)),
+                    sphere_angvel=np.zeros((3, 3)))

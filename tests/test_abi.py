@@ -63,5 +63,18 @@ def test_variant_bits(lib):
     assert "variant" in lib.fsl_last_error().decode()
 
 
+@pytest.mark.parametrize("kw", [dict(restitution=0.0), dict(restitution=1.5), dict(collision_time=0.0),
+                                dict(poisson=0.5), dict(friction=-1.0), dict(lub_min=0.0),
+                                dict(substeps=0), dict(skin=0.0), dict(dt=-1.0)])
+def test_bad_particle_params_rejected(lib, kw):
+    # rejected before any device work
+    with pytest.raises(F.FslError) as e:
+        F.Dem((10, 10, 10), [[5, 5, 5]], [1.0], **kw)
+    assert e.value.status == F.FSL_ERR_ARG
+    with pytest.raises(F.FslError) as e:
+        F.Dem((10, 10, 10), [[5, 5, 5]], [-1.0])
+    assert e.value.status == F.FSL_ERR_ARG
+
+
 def test_bad_shape_rejected(lib):
     assert F.workspace_bytes(F.make_params((2, 8, 8), "fp32", omega=1.5)) == 0
