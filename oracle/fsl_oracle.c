@@ -31,7 +31,9 @@
  *                  fill -> cancel -> empty order (Thuerey 2007); excess mass
  *                  shared evenly among interface neighbours, a pool otherwise;
  *   variants    -- (optional, OL_VAR_*) Thuerey's flux modifiers between
- *                  interface cells and his normal-weighted excess mass;
+ *                  interface cells, his normal-weighted excess mass, and a
+ *                  curvature from the divergence of corner normals
+ *                  (Brackbill et al. 1992);
  *   geometry    -- Parker-Youngs normal, mean curvature from the finite-
  *                  difference Hessian of the same 3x3x3 fill stencil.
  * The two per-cell phases (stream-collide, geometry) may run their cells on
@@ -444,6 +446,44 @@ static double stencil_phi(const OlLattice *L, int64_t y, double centre)
     }
 }
 
+/* Curvature in the manner of Brackbill et al. 1992 (continuum surface
+ * force): half the divergence of the unit normal n = -grad(phi)/|grad(phi)|,
+ * with the gradient taken at the 8 corners of the cell (differences of the
+ * 2x2x2 cells around each corner) and the divergence from the corner
+ * normals (differences between the four corners on either side). */
+void ol_csf_curvature(const double phi[27], double *kappa)
+{
+    double div = 0.0;
+    double nc[2][2][2][3];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const int sx = 2 * a - 1, sy = 2 * b - 1, sz = 2 * c - 1;
+                double g[3] = {0.0, 0.0, 0.0};
+                for (int p = 0; p < 2; ++p)
+                    for (int q = 0; q < 2; ++q) {
+                        /* across x: the cells at x-offset sx and 0, over the
+                         * two y and two z layers next to the corner */
+                        g[0] += st(phi, sx, p * sy, q * sz) - st(phi, 0, p * sy, q * sz);
+                        g[1] += st(phi, p * sx, sy, q * sz) - st(phi, p * sx, 0, q * sz);
+                        g[2] += st(phi, p * sx, q * sy, sz) - st(phi, p * sx, q * sy, 0);
+                    }
+                g[0] *= 0.25 * sx;
+                g[1] *= 0.25 * sy;
+                g[2] *= 0.25 * sz;
+                const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                for (int d = 0; d < 3; ++d) nc[a][b][c][d] = gn < 1e-12 ? 0.0 : -g[d] / gn;
+            }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                div += 0.25 * (2 * a - 1) * nc[a][b][c][0];
+                div += 0.25 * (2 * b - 1) * nc[a][b][c][1];
+                div += 0.25 * (2 * c - 1) * nc[a][b][c][2];
+            }
+    *kappa = 0.5 * div;
+}
+
 static void geometry_cell(OlLattice *L, int64_t c)
 {
     double st27[Q];
@@ -451,6 +491,7 @@ static void geometry_cell(OlLattice *L, int64_t c)
     for (int i = 0; i < Q; ++i)
         st27[i] = (i == REST) ? centre : stencil_phi(L, nbr(L, c, i, +1), centre);
     ol_normal_curvature(st27, &L->n[3 * c], &L->kappa[c]);
+    if (L->p.variants & OL_VAR_CSF_CURVATURE) ol_csf_curvature(st27, &L->kappa[c]);
 }
 
 static void phase_geometry(OlLattice *L)
@@ -513,7 +554,7 @@ OlLattice *ol_create(const OlParams *p, const double *fill, const double *rho,
     if (!p || !fill || !rho) return NULL;
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return NULL;
     if (!(p->omega > 0.0 && p->omega < 2.0)) return NULL;
-    if (p->variants & ~(OL_VAR_FLUX_MODIFIERS | OL_VAR_NORMAL_EXCESS)) return NULL;
+    if (p->variants & ~(OL_VAR_FLUX_MODIFIERS | OL_VAR_NORMAL_EXCESS | OL_VAR_CSF_CURVATURE)) return NULL;
     OlLattice *L = (OlLattice *)calloc(1, sizeof(OlLattice));
     L->p = *p;
     int64_t N = (int64_t)p->nx * p->ny * p->nz;

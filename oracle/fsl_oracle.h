@@ -56,8 +56,11 @@ typedef struct {
  *   OL_VAR_NORMAL_EXCESS   a converted cell shares its excess mass among its
  *     interface neighbours in proportion to the projection of its normal on
  *     the link (along the normal when filled, against it when emptied),
- *     evenly when no link has a positive projection. */
-enum { OL_VAR_FLUX_MODIFIERS = 1, OL_VAR_NORMAL_EXCESS = 2 };
+ *     evenly when no link has a positive projection;
+ *   OL_VAR_CSF_CURVATURE   the curvature is half the divergence of the unit
+ *     normal, from normals at the 8 cell corners (Brackbill et al. 1992),
+ *     instead of the Hessian form; the normal stays Parker-Youngs. */
+enum { OL_VAR_FLUX_MODIFIERS = 1, OL_VAR_NORMAL_EXCESS = 2, OL_VAR_CSF_CURVATURE = 4 };
 
 typedef struct OlLattice OlLattice;
 
@@ -77,6 +80,8 @@ void ol_feq(double rho, const double u[3], double feq[27]);
 /* Parker-Youngs normal and mean curvature from a 3x3x3 fill-level stencil in
  * direction order (entry i is the cell at offset c_i) */
 void ol_normal_curvature(const double phi[27], double n[3], double *kappa);
+/* curvature of the same stencil as half the divergence of corner normals */
+void ol_csf_curvature(const double phi[27], double *kappa);
 
 /* --- lattice -------------------------------------------------------------- */
 /* fill, rho: nx*ny*nz values; vel: 3*nx*ny*nz values (component-major:

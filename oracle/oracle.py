@@ -24,7 +24,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS = range(10)
-VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS = 1, 2
+VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS, VAR_CSF_CURVATURE = 1, 2, 4
 
 
 def build(force: bool = True) -> str:
@@ -103,6 +103,7 @@ def lib():
         L.ol_cumulants.argtypes = [dp, dp, dp]
         L.ol_feq.argtypes = [ctypes.c_double, dp, dp]
         L.ol_normal_curvature.argtypes = [dp, dp, dp]
+        L.ol_csf_curvature.argtypes = [dp, dp]
         L.ol_velocities.argtypes = [ctypes.c_void_p, dp]
         L.ol_mlp_nparam.restype = ctypes.c_int32
         L.ol_mlp_forward.argtypes = [dp, ctypes.c_int32, dp, dp]
@@ -171,6 +172,15 @@ def feq(rho, u):
     return out
 
 
+def csf_curvature(phi27):
+    """Curvature of a 3x3x3 stencil as half the divergence of the unit
+    normals at the cell corners (Brackbill et al. 1992)."""
+    p = _f64(phi27).reshape(27)
+    k = np.zeros(1)
+    lib().ol_csf_curvature(_dp(p), _dp(k))
+    return float(k[0])
+
+
 def normal_curvature(phi27):
     phi = _f64(phi27)
     n = np.zeros(3)
@@ -186,7 +196,7 @@ class OracleLattice:
     def __init__(self, shape, omega, accel=(0.0, 0.0, 0.0), sigma=0.0, rho_gas=1.0,
                  conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
                  omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None, store="fp64",
-                 flux_modifiers=False, normal_excess=False):
+                 flux_modifiers=False, normal_excess=False, csf_curvature=False):
         nx, ny, nz = shape
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -199,7 +209,8 @@ class OracleLattice:
         p.rule_isolated = 1 if rule_isolated else 0
         p.store = {"fp64": 0, "fp32": 1, "fp16": 2}[store]
         # free-surface variants of Thuerey 2007 (bits of the C header)
-        p.variants = (VAR_FLUX_MODIFIERS if flux_modifiers else 0) | (VAR_NORMAL_EXCESS if normal_excess else 0)
+        p.variants = (VAR_FLUX_MODIFIERS if flux_modifiers else 0) | (VAR_NORMAL_EXCESS if normal_excess else 0) | \
+            (VAR_CSF_CURVATURE if csf_curvature else 0)
         self._p = p
         fill = _f64(np.ones((nz, ny, nx)) if fill is None else fill).reshape(-1)
         rho = _f64(np.ones((nz, ny, nx)) if rho is None else rho).reshape(-1)

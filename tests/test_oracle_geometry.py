@@ -7,6 +7,10 @@ difference Hessian of the same 3x3x3 fill stencil.  Both are exact for a
 quadratic fill field, which gives a closed-form pin:
     phi = a + b.x + x.A.x/2  ->  grad = b, Hessian = A,
     n = -b/|b|, kappa = -(tr A - b^.A.b^) / (2 |b|).
+The variant curvature (half the divergence of corner normals, Brackbill et
+al. 1992) is pinned by planes (zero), spheres and cylinders (1/R and
+1/(2R), second-order convergence), the complement field (opposite sign)
+and the 48 symmetries of the cube.
 """
 import numpy as np
 
@@ -82,3 +86,43 @@ def test_lattice_geometry_of_flat_film():
     top = itf & (k == 6)
     assert np.allclose(n[2][top], 1.0) and np.allclose(n[0][top], 0) and np.allclose(n[1][top], 0)
     assert np.max(np.abs(kap[itf])) < 1e-14
+
+
+# ---- curvature from corner normals (Brackbill et al. 1992), a variant ----
+def test_csf_planes_have_zero_curvature():
+    rng = np.random.default_rng(14)
+    for _ in range(50):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        phi = stencil(lambda x: 0.5 - 0.1 * d @ x)
+        assert abs(O.csf_curvature(phi)) < 1e-14
+
+
+def test_csf_sphere_and_cylinder():
+    """Half the divergence of the unit normal: 1/R on a sphere, 1/(2R) on a
+    cylinder, converging as the radius grows; a bubble (the complement
+    field) has exactly the opposite curvature."""
+    errs = []
+    for R in (8.0, 16.0, 32.0, 64.0):
+        centre = np.array([R, 0.3, -0.2])
+        phi = stencil(lambda x: 0.5 - 0.1 * (np.linalg.norm(x - centre) - R))
+        k = O.csf_curvature(phi)
+        errs.append(abs(k * R - 1.0))
+        assert abs(O.csf_curvature(1.0 - phi) + k) < 1e-14 * abs(k)
+        axis = np.array([0.0, 0.0, 1.0])
+        cyl = stencil(lambda x: 0.5 - 0.1 * (np.linalg.norm((x - centre) - ((x - centre) @ axis) * axis) - R))
+        assert abs(O.csf_curvature(cyl) * 2 * R - 1.0) < 4.0 / R
+    # second order: the error falls about fourfold per doubling of R
+    assert errs[-1] < 2e-4 and all(b < 0.3 * a for a, b in zip(errs, errs[1:]))
+
+
+def test_csf_is_invariant_under_the_cube_symmetries():
+    rng = np.random.default_rng(15)
+    phi = np.clip(rng.uniform(0, 1, 27), 0, 1)
+    k0 = O.csf_curvature(phi)
+    assert abs(k0) > 1e-3
+    grid = phi.reshape(3, 3, 3)   # [z, y, x]
+    for perm in ((0, 2, 1), (1, 0, 2), (2, 1, 0)):
+        assert abs(O.csf_curvature(np.transpose(grid, perm).reshape(27)) - k0) < 1e-14
+    for ax in range(3):
+        assert abs(O.csf_curvature(np.flip(grid, ax).reshape(27)) - k0) < 1e-14

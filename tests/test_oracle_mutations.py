@@ -73,6 +73,11 @@ MUTANTS = {
                         "dem_oracle.c"),
     "dem_inertia": ("D->inertia[i] = 0.4 * D->m[i] * r * r;", "D->inertia[i] = 0.5 * D->m[i] * r * r;",
                     "test_oracle_dem.py", "hydrodynamic", "dem_oracle.c"),
+    "csf_corner_gradient": ("g[2] += st(phi, p * sx, q * sy, sz) - st(phi, p * sx, q * sy, 0);",
+                            "g[2] += st(phi, p * sx, q * sy, sz) - st(phi, p * sx, q * sy, -sz);",
+                            "test_oracle_geometry.py", "csf"),
+    "csf_divergence_sign": ("div += 0.25 * (2 * c - 1) * nc[a][b][c][2];", "div -= 0.25 * (2 * c - 1) * nc[a][b][c][2];",
+                            "test_oracle_geometry.py", "csf"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
