@@ -94,8 +94,14 @@ typedef struct {
  *     projections up to normal_tie counting as zero; evenly when no link
  *     has a positive weight, and the pool takes it when there is no
  *     interface neighbour at all.
+ *   FSL_VAR_CSF_CURVATURE   the curvature of the finite-difference estimator
+ *     is half the divergence of the unit normal, from normals at the 8 cell
+ *     corners of the 3x3x3 fill stencil (Brackbill et al. 1992; a corner
+ *     gradient g below 0.01 gives the shortened normal -g/0.01, so that the
+ *     curvature is continuous in the fill levels), instead of the Hessian
+ *     form; needs normals == 0.
  * Unknown bits make fsl_create_lattice fail with FSL_ERR_ARG. */
-enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2 };
+enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2, FSL_VAR_CSF_CURVATURE = 4 };
 
 /* field ids for fsl_read_fields(); bit k of the mask selects field k */
 enum {

@@ -450,7 +450,12 @@ static double stencil_phi(const OlLattice *L, int64_t y, double centre)
  * force): half the divergence of the unit normal n = -grad(phi)/|grad(phi)|,
  * with the gradient taken at the 8 corners of the cell (differences of the
  * 2x2x2 cells around each corner) and the divergence from the corner
- * normals (differences between the four corners on either side). */
+ * normals (differences between the four corners on either side).  A corner
+ * gradient below CSF_GMIN gets the shortened normal -grad/CSF_GMIN: the
+ * unit normal of a vanishing gradient is undefined, and without the floor a
+ * rounding-level change of one fill level would turn a corner's normal from
+ * zero to a unit vector. */
+#define CSF_GMIN 1e-2
 void ol_csf_curvature(const double phi[27], double *kappa)
 {
     double div = 0.0;
@@ -472,7 +477,7 @@ void ol_csf_curvature(const double phi[27], double *kappa)
                 g[1] *= 0.25 * sy;
                 g[2] *= 0.25 * sz;
                 const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-                for (int d = 0; d < 3; ++d) nc[a][b][c][d] = gn < 1e-12 ? 0.0 : -g[d] / gn;
+                for (int d = 0; d < 3; ++d) nc[a][b][c][d] = -g[d] / (gn > CSF_GMIN ? gn : CSF_GMIN);
             }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)

@@ -58,7 +58,8 @@ typedef struct {
  *     the link (along the normal when filled, against it when emptied),
  *     evenly when no link has a positive projection;
  *   OL_VAR_CSF_CURVATURE   the curvature is half the divergence of the unit
- *     normal, from normals at the 8 cell corners (Brackbill et al. 1992),
+ *     normal, from normals at the 8 cell corners (Brackbill et al. 1992;
+ *     corner gradients below 0.01 give shortened normals -grad/0.01),
  *     instead of the Hessian form; the normal stays Parker-Youngs. */
 enum { OL_VAR_FLUX_MODIFIERS = 1, OL_VAR_NORMAL_EXCESS = 2, OL_VAR_CSF_CURVATURE = 4 };
 

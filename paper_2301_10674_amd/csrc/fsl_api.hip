@@ -83,7 +83,8 @@ struct FslLattice {
 // ---------------------------------------------------------------- workspace
 static size_t store_bytes(int prec) { return prec == FSL_FP64 ? 8 : (prec == FSL_FP32 ? 4 : 2); }
 
-static_assert(FSL_VAR_FLUX_MODIFIERS == VAR_FLUX_MODIFIERS && FSL_VAR_NORMAL_EXCESS == VAR_NORMAL_EXCESS,
+static_assert(FSL_VAR_FLUX_MODIFIERS == VAR_FLUX_MODIFIERS && FSL_VAR_NORMAL_EXCESS == VAR_NORMAL_EXCESS &&
+                  FSL_VAR_CSF_CURVATURE == VAR_CSF_CURVATURE,
               "variant bits of the header and the kernels differ");
 
 static bool params_ok(const FslParams *p, std::string &why)
@@ -102,7 +103,14 @@ static bool params_ok(const FslParams *p, std::string &why)
     if (!(p->normal_tie >= 0.0)) { why = "normal_tie must be >= 0"; return false; }
     if (p->normals != 0 && p->normals != 1) { why = "normals must be 0 or 1"; return false; }
     if (p->check_every < 0) { why = "check_every must be >= 0"; return false; }
-    if (p->variants & ~(FSL_VAR_FLUX_MODIFIERS | FSL_VAR_NORMAL_EXCESS)) { why = "unknown variant bits"; return false; }
+    if (p->variants & ~(FSL_VAR_FLUX_MODIFIERS | FSL_VAR_NORMAL_EXCESS | FSL_VAR_CSF_CURVATURE)) {
+        why = "unknown variant bits";
+        return false;
+    }
+    if ((p->variants & FSL_VAR_CSF_CURVATURE) && p->normals != 0) {
+        why = "the corner-normal curvature variant needs the finite-difference estimator (normals = 0)";
+        return false;
+    }
     return true;
 }
 

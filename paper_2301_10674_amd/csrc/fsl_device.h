@@ -296,6 +296,47 @@ __device__ __forceinline__ double4 fd_geometry(const double s[27])
     return o;
 }
 
+// Curvature as half the divergence of the unit normal (Brackbill et al.
+// 1992): normals -grad/|grad| at the 8 cell corners from the 2x2x2 cells
+// around each corner, divergence from the differences between the four
+// corners on either side.  Corner gradients below 0.01 give the shortened
+// normal -grad/0.01, which keeps the curvature continuous where a corner's
+// gradient vanishes.  The free-surface variant that replaces the Hessian
+// curvature above.
+__device__ __forceinline__ double csf_curvature(const double s[27])
+{
+    double div = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                // offsets 0 or the corner's side (-1 or +1), as stencil indices
+                const int X = 2 * a, Y = 2 * b, Z = 2 * c;
+                double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int py = p ? Y : 1, qz = q ? Z : 1, px = p ? X : 1, qy = q ? Y : 1;
+                        gx += s[MI(X, py, qz)] - s[MI(1, py, qz)];
+                        gy += s[MI(px, Y, qz)] - s[MI(px, 1, qz)];
+                        gz += s[MI(px, qy, Z)] - s[MI(px, qy, 1)];
+                    }
+                gx *= 0.25 * (2 * a - 1);
+                gy *= 0.25 * (2 * b - 1);
+                gz *= 0.25 * (2 * c - 1);
+                const double gn = sqrt(gx * gx + gy * gy + gz * gz);
+                const double gd = gn > 1e-2 ? gn : 1e-2;
+                const double nx = -gx / gd, ny = -gy / gd, nz = -gz / gd;
+                div += 0.25 * (2 * a - 1) * nx;
+                div += 0.25 * (2 * b - 1) * ny;
+                div += 0.25 * (2 * c - 1) * nz;
+            }
+    return 0.5 * div;
+}
+
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int wrap_m(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_p(int v, int n) { return v == n - 1 ? 0 : v + 1; }

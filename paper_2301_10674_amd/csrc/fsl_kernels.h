@@ -47,9 +47,10 @@ struct Dev {
     int variants;             // VAR_* bits
 };
 
-// free-surface variants (Thuerey 2007): flux modifiers between interface
-// cells, normal-weighted excess mass
-constexpr int VAR_FLUX_MODIFIERS = 1, VAR_NORMAL_EXCESS = 2;
+// free-surface variants: flux modifiers between interface cells and
+// normal-weighted excess mass (Thuerey 2007), curvature from corner normals
+// (Brackbill et al. 1992)
+constexpr int VAR_FLUX_MODIFIERS = 1, VAR_NORMAL_EXCESS = 2, VAR_CSF_CURVATURE = 4;
 
 constexpr int BULK_THREADS = 256;
 constexpr int BULK_MAX_BLOCKS = 2048;

@@ -735,6 +735,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     double4 gn;
     if constexpr (GI) {
         gn = fd_geometry(sv);
+        if (d.variants & VAR_CSF_CURVATURE) gn.w = csf_curvature(sv);
     } else {
         const R4 g = ((const R4 *)d.geom)[c];
         gn = make_double4((double)g.x, (double)g.y, (double)g.z, (double)g.w);
@@ -1241,7 +1242,8 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
         double s[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) s[i] = i == REST ? centre : stencil_value<double>(d, nb_of(d, pc, i), centre);
-        const double4 o = fd_geometry(s);
+        double4 o = fd_geometry(s);
+        if (d.variants & VAR_CSF_CURVATURE) o.w = csf_curvature(s);
         R4 out;
         out.x = R(o.x);
         out.y = R(o.y);

@@ -78,6 +78,8 @@ MUTANTS = {
                             "test_oracle_geometry.py", "csf"),
     "csf_divergence_sign": ("div += 0.25 * (2 * c - 1) * nc[a][b][c][2];", "div -= 0.25 * (2 * c - 1) * nc[a][b][c][2];",
                             "test_oracle_geometry.py", "csf"),
+    "csf_no_floor": ("-g[d] / (gn > CSF_GMIN ? gn : CSF_GMIN)", "-g[d] / (gn > 1e-12 ? gn : 1.0)",
+                     "test_oracle_geometry.py", "continuous"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
