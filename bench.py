@@ -216,6 +216,7 @@ def time_particles(w, lat, fsl, steps=20, coupled_steps=10):
         run.step(coupled_steps)
         torch.cuda.synchronize()
         out["coupled_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / coupled_steps
+        out["bedload_rate"] = dem.bedload()      # Eq. (1) after the coupled steps
         dem.destroy()
     except fsl.FslError as e:
         out["error"] = str(e)

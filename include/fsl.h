@@ -377,6 +377,12 @@ FslStatus fsl_dem_step(FslDem *dem, const double *hydro, int32_t hydro_on_device
  * out_on_device != 0.  Synchronises the stream. */
 FslStatus fsl_dem_read(FslDem *dem, double *centre, double *vel, double *angvel, int32_t out_on_device);
 
+/* Bedload transport rate of Eq. (1) (Section 3.2): the sum over all spheres
+ * of the streamwise velocity times the sphere volume 4/3 pi r^3, over the
+ * bed area nx * ny; one double on the host.  Fixed-order sum
+ * (deterministic); synchronises the stream.  FSL_ERR_ARG for a NULL qb. */
+FslStatus fsl_dem_bedload(FslDem *dem, double *qb);
+
 void fsl_dem_destroy(FslDem *dem);
 
 /* Thread-local text of the last error (never NULL). */

@@ -326,3 +326,15 @@ void ol_dem_read(const OlDem *D, double *centre, double *vel, double *angvel)
     if (vel) memcpy(vel, D->v, b);
     if (angvel) memcpy(angvel, D->w, b);
 }
+
+/* Bedload transport rate of Eq. (1): the sum over all particles of the
+ * streamwise velocity times the particle volume, over the bed area Lx Ly. */
+double ol_dem_bedload(const OlDem *D)
+{
+    double q = 0.0;
+    for (int32_t i = 0; i < D->n; ++i) {
+        const double r = D->r[i];
+        q += D->v[3 * i] * ((4.0 / 3.0) * PI * r * r * r);
+    }
+    return q / ((double)D->p.nx * (double)D->p.ny);
+}

@@ -179,6 +179,8 @@ void ol_dem_destroy(OlDem *D);
  * sphere, held over the sub-steps; NULL: none) */
 void ol_dem_step(OlDem *D, const double *hydro);
 void ol_dem_read(const OlDem *D, double *centre, double *vel, double *angvel);
+/* bedload transport rate, Eq. (1): sum_i u_x,i V_i / (Lx Ly) */
+double ol_dem_bedload(const OlDem *D);
 
 #ifdef __cplusplus
 }

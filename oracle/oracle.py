@@ -116,6 +116,8 @@ def lib():
         L.ol_dem_destroy.argtypes = [ctypes.c_void_p]
         L.ol_dem_step.argtypes = [ctypes.c_void_p, dp]
         L.ol_dem_read.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.ol_dem_bedload.restype = ctypes.c_double
+        L.ol_dem_bedload.argtypes = [ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -449,3 +451,7 @@ class OracleDem:
         out = [np.zeros((self.n, 3)) for _ in range(3)]
         lib().ol_dem_read(self.h, *[_dp(o) for o in out])
         return out
+
+    def bedload(self):
+        """bedload transport rate q_b of Eq. (1)"""
+        return lib().ol_dem_bedload(self.h)

@@ -320,6 +320,25 @@ __global__ __launch_bounds__(DEM_THREADS) void k_dem_check(DemDev D, int s)
     if (!(dx * dx + dy * dy + dz * dz <= 0.25 * D.skin * D.skin)) atomicOr(D.err, 2);
 }
 
+// Bedload transport rate of Eq. (1), sum_i u_x,i V_i / (Lx Ly): one block;
+// each thread sums a strided share in index order, then a fixed tree.
+__global__ __launch_bounds__(DEM_THREADS) void k_dem_bedload(DemDev D, int s, double *out)
+{
+    __shared__ double part[DEM_THREADS];
+    double q = 0.0;
+    for (int i = (int)threadIdx.x; i < D.n; i += DEM_THREADS) {
+        const double r = D.r[i];
+        q += D.v[s][3 * i] * ((4.0 / 3.0) * PI * r * r * r);
+    }
+    part[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = DEM_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0] / (D.Lx * D.Ly);
+}
+
 }  // namespace
 
 struct FslDem {
@@ -496,6 +515,18 @@ FslStatus fsl_dem_read(FslDem *D, double *centre, double *vel, double *angvel, i
     if (centre) DEM_TRY(hipMemcpyAsync(centre, D->d.x[D->s], b, k, D->st));
     if (vel) DEM_TRY(hipMemcpyAsync(vel, D->d.v[D->s], b, k, D->st));
     if (angvel) DEM_TRY(hipMemcpyAsync(angvel, D->d.w[D->s], b, k, D->st));
+    DEM_TRY(hipStreamSynchronize(D->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_dem_bedload(FslDem *D, double *qb)
+{
+    if (!D) return set_error(FSL_ERR_STATE, "particle state is NULL");
+    if (!qb) return set_error(FSL_ERR_ARG, "qb is NULL");
+    // the staging area of host hydrodynamic loads holds the result
+    k_dem_bedload<<<1, DEM_THREADS, 0, D->st>>>(D->d, D->s, D->hbuf);
+    DEM_TRY(hipGetLastError());
+    DEM_TRY(hipMemcpyAsync(qb, D->hbuf, sizeof(double), hipMemcpyDeviceToHost, D->st));
     DEM_TRY(hipStreamSynchronize(D->st));
     return FSL_OK;
 }

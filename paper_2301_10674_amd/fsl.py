@@ -31,7 +31,7 @@ EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fs
            "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
            "fsl_bed_profile", "fsl_move_particles",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_dem_create", "fsl_dem_step",
-           "fsl_dem_read", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy")
+           "fsl_dem_read", "fsl_dem_bedload", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
 
 
@@ -152,6 +152,8 @@ def lib():
         L.fsl_dem_step.argtypes = [vp, vp, i32, i32]
         L.fsl_dem_read.restype = ctypes.c_int
         L.fsl_dem_read.argtypes = [vp, dp, dp, dp, i32]
+        L.fsl_dem_bedload.restype = ctypes.c_int
+        L.fsl_dem_bedload.argtypes = [vp, dp]
         L.fsl_dem_destroy.restype = None
         L.fsl_dem_destroy.argtypes = [vp]
         L.fsl_last_error.restype = ctypes.c_char_p
@@ -435,6 +437,12 @@ class Dem:
         out = [np.zeros(3 * self.n) for _ in range(3)]
         _check(lib().fsl_dem_read(self.h, *[_dp(o) for o in out], 0))
         return [o.reshape(self.n, 3) for o in out]
+
+    def bedload(self):
+        """bedload transport rate q_b of Eq. (1)"""
+        q = np.zeros(1)
+        _check(lib().fsl_dem_bedload(self.h, _dp(q)))
+        return float(q[0])
 
     def destroy(self):
         if self.h:

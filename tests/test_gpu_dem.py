@@ -5,7 +5,8 @@ fluid-particle step against the FP64 oracle, through the C-ABI.
   under gravity, a constant hydrodynamic load, collisions with friction,
   walls and lubrication, 40 lattice steps of 10 sub-steps: positions,
   velocities and spins agree to 1e-12 of their scale (both sides evaluate
-  each pair in the same order with the same roundings).
+  each pair in the same order with the same roundings); the bedload rate of
+  Eq. (1) to 1e-13.
 * The flume bed (1,848 spheres of the benchmark, the lowest layer fixed)
   settling under gravity for 5 steps: the same bound.
 * Coupled steps (fluid step, momentum-exchange forces, particle sub-steps,
@@ -56,6 +57,9 @@ def test_cluster_fp64():
         err = compare(g.state(), o.state(), 1e-12, "after %d steps" % (10 * (k + 1)))
         print("after %d steps: max relative difference %.3e" % (10 * (k + 1), err))
     x, vv, ww = g.state()
+    qg, qo = g.bedload(), o.bedload()
+    print("bedload rate %.6e (oracle %.6e)" % (qg, qo))
+    assert abs(qg - qo) <= 1e-13 * max(abs(qo), 1e-30) and abs(qo) > 0
     assert np.abs(vv - v).max() > 1e-3            # collisions happened
     assert np.array_equal(x[fixed == 1], c[fixed == 1])
     g.destroy()

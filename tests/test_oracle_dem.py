@@ -19,7 +19,9 @@ Closed forms and invariants, none retyping the oracle's formulas:
   lubrication range follow the integral of m du = 6 pi mu R_eff^2 (1/s -
   1/s_c) ds, u(s) = u0 - 6 pi mu R_eff^2/m_eff (ln(s0/s) - (s0 - s)/s_c);
 * a constant hydrodynamic force and torque accelerate a sphere of mass
-  rho_p 4/3 pi r^3 and moment of inertia 2/5 m r^2 uniformly.
+  rho_p 4/3 pi r^3 and moment of inertia 2/5 m r^2 uniformly;
+* the bedload rate of Eq. (1) for spheres moving together, opposite pairs,
+  fixed spheres and scaled velocities.
 """
 import math
 
@@ -173,3 +175,23 @@ def test_hydrodynamic_load_and_fixed_spheres():
     assert np.allclose(v[0], F[0, :3] * 10 / m, rtol=1e-13, atol=0)
     assert np.allclose(w[0], F[0, 3:] * 10 / (0.4 * m * r[0] ** 2), rtol=1e-13, atol=0)
     assert np.array_equal(x[1], [70, 70, 50]) and not v[1].any() and not w[1].any()
+
+
+def test_bedload_rate():
+    """Eq. (1): q_b = sum_i u_x,i V_i / (Lx Ly).  Spheres moving together at
+    u give u times their total volume over the bed area; a sphere moving
+    against the stream cancels an equal one moving with it; fixed spheres
+    (at rest) add nothing; the rate is linear in the velocities."""
+    box = (60, 20, 40)
+    r = np.array([2.0, 3.0, 2.0, 4.0])
+    c = np.array([[10, 5, 10], [25, 10, 10], [40, 5, 10], [50, 15, 25]], float)
+    u = 0.013
+    d = O.OracleDem(box, c, r, vel=np.tile([u, 0.002, -0.001], (4, 1)), density=RHO, substeps=1)
+    vol = 4.0 / 3.0 * math.pi * (r ** 3).sum()
+    assert abs(d.bedload() - u * vol / (60 * 20)) < 1e-15
+    v = np.zeros((4, 3))
+    v[0, 0], v[2, 0], v[1, 0] = 0.01, -0.01, 0.004
+    d = O.OracleDem(box, c, r, vel=v, fixed=[0, 0, 0, 1], density=RHO, substeps=1)
+    assert abs(d.bedload() - 0.004 * 4.0 / 3.0 * math.pi * 27.0 / 1200) < 1e-16
+    d2 = O.OracleDem(box, c, r, vel=2.5 * v, fixed=[0, 0, 0, 1], density=RHO, substeps=1)
+    assert abs(d2.bedload() - 2.5 * d.bedload()) < 1e-16
