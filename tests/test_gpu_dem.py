@@ -109,6 +109,22 @@ def test_coupled_settling_fp64():
     dem.destroy()
 
 
+def test_collision_across_the_periodic_seam_fp64():
+    kw = dict(KW, dt=0.05, substeps=1)
+    c = [[34.9, 20, 20], [5.1, 20.3, 19.8]]
+    v = [[0.02, 0.001, 0], [-0.02, 0, 0.001]]
+    w = [[0, 0, 0.003], [0.002, 0, 0]]
+    g = F().Dem((40, 40, 40), c, [5.0, 5.0], v, w, None, skin=1.0, **kw)
+    o = O.OracleDem((40, 40, 40), c, [5.0, 5.0], v, w, None, **kw)
+    g.step(None, n=2000)
+    o.step(None, n=2000)
+    err = compare(g.state(), o.state(), 1e-12, "seam")
+    x, vv, _ = g.state()
+    assert vv[1, 0] > 0.0 and (x[:, 0] >= 0).all() and (x[:, 0] < 40).all()
+    print("collision across x = 0: max relative difference %.3e" % err)
+    g.destroy()
+
+
 def test_error_paths():
     f = F()
     # 60 small spheres in a cube of side 0.8: every other sphere is within
