@@ -4,12 +4,15 @@
   3072 x 80 x 256 (9210 spheres): the GPU in FP64 against the FP64 oracle
   after a few steps, over every cell that is fluid in both (the oracle runs
   its per-cell phases on all host threads), and the momentum-exchange force
-  and torque on every sphere.
+  and torque on every sphere; the particle step on the large flume's bed
+  (bit-identical to the oracle's all-pairs evaluation).
 * The FP32 and FP16 forms on the 1536 x 40 x 192 flume over 200 steps:
   properties that hold at any size -- total mass conserved to 1e-12, no
   liquid cell next to a gas cell, fill levels of interface cells finite,
   every interface normal a unit vector or zero.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -55,10 +58,36 @@ def test_flume_full_size_fp64():
     assert dv < 1e-13 and dm < 1e-12
 
 
+@functools.lru_cache(maxsize=1)
+def large_flume():
+    return I.flume(nx=3072, ny=80, nz=256, seed=5)
+
+
 def test_large_flume_full_size_fp64():
-    dv, dm = compare_fp64(I.flume(nx=3072, ny=80, nz=256, seed=5), 2)
+    dv, dm = compare_fp64(large_flume(), 2)
     print("3072x80x256, 2 steps: max |du| %.2e, max |dm| %.2e" % (dv, dm))
     assert dv < 1e-13 and dm < 1e-12
+
+
+def test_large_flume_bed_particles_fp64():
+    """The particle step on the large flume's 9,210 spheres (lowest layer
+    fixed), 2 lattice steps of 10 sub-steps under gravity with lubrication,
+    against the oracle's all-pairs evaluation."""
+    w = large_flume()
+    c, r = w.centre, w.radius
+    fixed = (c[:, 2] < c[:, 2].min() + 2.0).astype(np.uint8)
+    kw = dict(density=2.55, restitution=0.97, collision_time=40.0, poisson=0.22, friction=0.5,
+              viscosity=1e-3, lub_cut=0.6, lub_min=1e-3, accel=(0, 0, -1e-4), dt=1.0, substeps=10)
+    g = F().Dem(w.shape, c, r, None, None, fixed, skin=1.0, **kw)
+    o = O.OracleDem(w.shape, c, r, None, None, fixed, **kw)
+    g.step(None, n=2)
+    o.step(None, n=2)
+    worst = 0.0
+    for a, b in zip(g.state(), o.state()):
+        worst = max(worst, np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+    print("3072x80x256 bed, %d spheres: max relative difference %.3e" % (len(r), worst))
+    assert worst <= 1e-12
+    g.destroy()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
