@@ -180,14 +180,17 @@ def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=10,
     return w, rep
 
 
-def time_particles(w, lat, fsl, steps=20, coupled_steps=10):
+def time_particles(w, fsl, precision, steps=20, coupled_steps=20):
     """Particle motion on the flume's spheres (lowest layer fixed, 10
     sub-steps per lattice step, the paper's collision parameters, gravity
     of the flume, lubrication below 2/3 cell) under the lattice's
     momentum-exchange load, then whole coupled steps (fluid step, forces,
-    particle sub-steps, remap).  The generated bed overlaps (it is a
-    jittered packing for the lattice), so the spheres first push apart: the
-    timings are those of a bed with every sphere in contact."""
+    particle sub-steps, remap).  The generated bed is a jittered packing
+    whose spheres overlap, so it is first relaxed without fluid (restitution
+    0.1, gravity 1e-3, 300 steps) and the lattice is built on the relaxed
+    bed."""
+    import dataclasses
+
     import torch
 
     from paper_2301_10674_amd.couple import Coupled
@@ -197,7 +200,16 @@ def time_particles(w, lat, fsl, steps=20, coupled_steps=10):
     nu = (1.0 / w.omega - 0.5) / 3.0
     out = {"spheres": int(len(r)), "fixed": int(fixed.sum()), "substeps": 10}
     try:
-        dem = fsl.Dem(w.shape, c, r, w.sphere_vel, w.sphere_angvel, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
+        relax = fsl.Dem(w.shape, c, r, None, None, fixed, restitution=0.1, friction=0.5,
+                        accel=(0.0, 0.0, -1e-3), substeps=10, skin=1.0)
+        relax.step(None, n=300)
+        c2, v2, _ = relax.state()
+        relax.destroy()
+        out["relaxed_max_speed"] = float(np.abs(v2).max())
+        wr = dataclasses.replace(w, centre=c2, sphere_vel=np.zeros_like(c2), sphere_angvel=np.zeros_like(c2))
+        lat = fsl.lattice_from_workload(wr, precision)
+        lat.step(5)
+        dem = fsl.Dem(w.shape, c2, r, None, None, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
                       accel=w.accel, substeps=10, skin=1.0)
         hydro = lat.particle_forces()
         dem.step(hydro)
@@ -207,7 +219,7 @@ def time_particles(w, lat, fsl, steps=20, coupled_steps=10):
             dem.step(hydro)
         out["dem_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
         dem.destroy()
-        dem = fsl.Dem(w.shape, c, r, w.sphere_vel, w.sphere_angvel, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
+        dem = fsl.Dem(w.shape, c2, r, None, None, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
                       accel=w.accel, substeps=10, skin=1.0)
         run = Coupled(lat, dem)
         run.step(1)
@@ -216,8 +228,25 @@ def time_particles(w, lat, fsl, steps=20, coupled_steps=10):
         run.step(coupled_steps)
         torch.cuda.synchronize()
         out["coupled_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / coupled_steps
+        # the same sequence phase by phase (each phase synchronised)
+        ph = np.zeros(4)
+        for _ in range(coupled_steps):
+            t = [time.perf_counter()]
+            lat.step(1)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter())
+            hydro = lat.particle_forces()
+            t.append(time.perf_counter())
+            dem.step(hydro)
+            t.append(time.perf_counter())
+            lat.move_particles(*dem.state())
+            t.append(time.perf_counter())
+            ph += np.diff(t)
+        out["coupled_phases_ms"] = dict(zip(("fluid_step", "forces", "particle_substeps", "remap"),
+                                            (1e3 * ph / coupled_steps).round(4).tolist()))
         out["bedload_rate"] = dem.bedload()      # Eq. (1) after the coupled steps
         dem.destroy()
+        lat.destroy()
     except fsl.FslError as e:
         out["error"] = str(e)
     return out
@@ -276,7 +305,7 @@ def run_form(w, form, steps, warmup, main_form=None):
         used1 = lat.estimator_stats()
         res["estimator"] = dict(est, network_cells=used1[0] - used0[0], fallback_cells=used1[1] - used0[1])
     if len(w.radius) and form == main_form:
-        res["particles"] = time_particles(w, lat, fsl)
+        res["particles"] = time_particles(w, fsl, precision)
     # momentum-exchange force and torque on every sphere (outside the timed
     # steps; the coupling would call it once per step)
     if len(w.radius):
