@@ -114,7 +114,7 @@ def trace_summary(d):
     print("| kernel | calls | avg µs | min µs | max µs | total ms | % |")
     print("|---|---:|---:|---:|---:|---:|---:|")
     for r in rows:
-        name = re.sub(r"\(.*", "", r["Name"]).replace("void ", "")
+        name = re.sub(r"\(.*", "", r["Name"].replace("(anonymous namespace)::", "")).replace("void ", "")
         print("| %s | %s | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
             name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
             float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))

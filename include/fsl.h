@@ -268,6 +268,15 @@ FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
 FslStatus fsl_move_particles(FslLattice *lat, const double *centre, const double *vel,
                              const double *angvel);
 
+/* The same move with centre, vel and angvel in device memory (3 doubles per
+ * sphere; vel/angvel may be NULL: zero), e.g. the particle state of
+ * fsl_dem_read(..., out_on_device = 1), so that a coupled step keeps the
+ * sphere state on the GPU.  The values are checked on the device before
+ * anything changes (FSL_ERR_ARG for a non-finite value); then as
+ * fsl_move_particles.  Synchronises the stream. */
+FslStatus fsl_move_particles_device(FslLattice *lat, const double *centre, const double *vel,
+                                    const double *angvel);
+
 /* Change the body acceleration g (force density rho g) from the next step
  * on.  Section 3.1 drives the flume by a body force F_x controlled to hold
  * the bulk flow rate; the control law is the caller's (see
@@ -305,7 +314,10 @@ FslStatus fsl_bed_profile(FslLattice *lat, double *phi_b, double *h_b, int32_t o
  * Fx, Fy, Fz, Tx, Ty, Tz (lattice units); host memory, or device memory when
  * out_on_device != 0.  Sums run in FP64 in a fixed order (deterministic).
  * Nothing is written when no spheres are mapped; FSL_ERR_ARG for a NULL out
- * otherwise.  Allocates nothing; synchronises the lattice's stream. */
+ * otherwise.  The first call after set-up or after a remap that changed
+ * cells rebuilds per-sphere lists of the cells with links into each sphere
+ * (in a library buffer that grows with hipMalloc when needed and is kept
+ * until fsl_destroy); synchronises the lattice's stream. */
 FslStatus fsl_particle_forces(FslLattice *lat, double *out, int32_t out_on_device);
 
 /* Interface-cell updates since creation that used the network / fell back. */

@@ -22,6 +22,17 @@ class Coupled:
         self.lat, self.dem = lat, dem
 
     def step(self, n: int = 1):
+        """n coupled steps; the sphere state stays in device memory (the
+        forces, the particle state and the remap's input are CUDA tensors)"""
+        for _ in range(int(n)):
+            self.lat.step(1)
+            hydro = self.lat.particle_forces_device()
+            self.dem.step(hydro)
+            c, v, w = self.dem.state_device()
+            self.lat.move_particles_device(c, v, w)
+
+    def step_host(self, n: int = 1):
+        """the same through host arrays (fsl_move_particles)"""
         for _ in range(int(n)):
             self.lat.step(1)
             hydro = self.lat.particle_forces()

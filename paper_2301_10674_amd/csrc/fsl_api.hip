@@ -65,7 +65,9 @@ struct FslLattice {
     int nsph = 0;
     bool geometry_set = false;
     std::vector<double> sph_host;
-    double *sph_dev = nullptr;
+    double *sph_dev = nullptr;     // sphere table (10 per sphere), one force evaluation
+                                   // (6 per sphere), a staging table (10 per sphere), a flag
+    bool sph_host_stale = false;   // the table was last written from device arrays
     void *bb_dev = nullptr;   // moving-wall bounce-back records
     size_t bb_cap = 0;
     void *mem_dev = nullptr;  // momentum exchange: per-sphere entry offsets, then the entries
@@ -881,6 +883,43 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     return FSL_OK;
 }
 
+// bring the host copy of the sphere table up to date after moves from
+// device arrays
+static FslStatus sync_sph_host(FslLattice *L)
+{
+    if (!L->sph_host_stale) return FSL_OK;
+    HIP_TRY(hipMemcpyAsync(L->sph_host.data(), L->sph_dev, L->sph_host.size() * 8, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    L->sph_host_stale = false;
+    return FSL_OK;
+}
+
+// New centres and velocities from device arrays into the staging table
+// (radii kept); flag = 1 for a non-finite value.  One thread per sphere.
+__global__ void k_sph_stage(const double *table, double *stage, int n, const double *centre, const double *vel,
+                            const double *angvel, double nx, double ny, int *flag)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    double t[10];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        const double c = centre[3 * q + a], v = vel ? vel[3 * q + a] : 0.0, w = angvel ? angvel[3 * q + a] : 0.0;
+        ok = ok && isfinite(c) && isfinite(v) && isfinite(w);
+        t[a] = c;
+        t[4 + a] = v;
+        t[7 + a] = w;
+    }
+    if (!ok) {
+        atomicOr(flag, 1);
+        return;
+    }
+    t[0] -= nx * floor(t[0] / nx);
+    t[1] -= ny * floor(t[1] / ny);
+    t[3] = table[10 * q + 3];
+    for (int k = 0; k < 10; ++k) stage[10 * q + k] = t[k];
+}
+
 static bool finite_all(const float *v, size_t n)
 {
     for (size_t i = 0; i < n; ++i)
@@ -1047,6 +1086,8 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
         }
     }
     if (L->geometry_set) {
+        FslStatus hs = sync_sph_host(L);
+        if (hs != FSL_OK) return hs;
         // the geometry is mapped once; later calls may only change velocities
         bool same = n == L->nsph;
         for (int q = 0; same && q < n; ++q)
@@ -1062,8 +1103,9 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
         return FSL_OK;
     }
     if (L->steps > 0) return fail(FSL_ERR_STATE, "spheres must be mapped before the first step");
-    // the sphere table, then room for one force/torque evaluation (6 per sphere)
-    HIP_TRY(hipMalloc(&L->sph_dev, t.size() * 8 + (size_t)std::max(n, 1) * 6 * 8));
+    // the sphere table, room for one force/torque evaluation (6 per sphere),
+    // a staging table for moves from device arrays and its flag
+    HIP_TRY(hipMalloc(&L->sph_dev, 2 * t.size() * 8 + (size_t)std::max(n, 1) * 6 * 8 + 64));
     HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), t.size() * 8, hipMemcpyHostToDevice, L->st));
     L->sph_host = t;
     L->nsph = n;
@@ -1109,26 +1151,11 @@ FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
     return FSL_OK;
 }
 
-FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *vel, const double *angvel)
+// The spheres of the lattice move to the state in the device table: remap
+// owners, cover and uncover cells, rebuild what follows from the cell types.
+static FslStatus remap(FslLattice *L)
 {
-    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
-    if (!L->geometry_set || L->nsph == 0) return fail(FSL_ERR_STATE, "no spheres are mapped");
-    if (!centre) return fail(FSL_ERR_ARG, "centre is NULL");
-    const int n = L->nsph, nx = L->P.nx, ny = L->P.ny;
-    std::vector<double> t = L->sph_host;
-    for (int q = 0; q < n; ++q) {
-        double *sp = &t[10 * (size_t)q];
-        for (int a = 0; a < 3; ++a) {
-            const double v = vel ? vel[3 * q + a] : 0.0, w = angvel ? angvel[3 * q + a] : 0.0;
-            if (!std::isfinite(centre[3 * q + a]) || !std::isfinite(v) || !std::isfinite(w))
-                return fail(FSL_ERR_ARG, "non-finite sphere centre or velocity");
-            sp[4 + a] = v;
-            sp[7 + a] = w;
-        }
-        sp[0] = centre[3 * q] - nx * std::floor(centre[3 * q] / nx);
-        sp[1] = centre[3 * q + 1] - ny * std::floor(centre[3 * q + 1] / ny);
-        sp[2] = centre[3 * q + 2];
-    }
+    const int n = L->nsph;
     Dev &d = L->d;
     const size_t N = (size_t)d.N;
     // scratch: densities (8 B), new owners (4 B), changed cells (4 B), round
@@ -1147,8 +1174,6 @@ FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *
     uint8_t *tn = (uint8_t *)((char *)L->move_dev + tn_off);
     uint8_t *mark = tn + nm;
     int *counter = (int *)(mark + nm);
-    HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), (size_t)n * 10 * 8, hipMemcpyHostToDevice, L->st));
-    L->sph_host = t;
     k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
     k_map<<<n, 256, 0, L->st>>>(d, n, own);
     k_zero_int<<<1, 64, 0, L->st>>>(counter);
@@ -1190,6 +1215,55 @@ FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *
     if (r != FSL_OK) return r;
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
+}
+
+FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *vel, const double *angvel)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!L->geometry_set || L->nsph == 0) return fail(FSL_ERR_STATE, "no spheres are mapped");
+    if (!centre) return fail(FSL_ERR_ARG, "centre is NULL");
+    FslStatus hs = sync_sph_host(L);
+    if (hs != FSL_OK) return hs;
+    const int n = L->nsph, nx = L->P.nx, ny = L->P.ny;
+    std::vector<double> t = L->sph_host;
+    for (int q = 0; q < n; ++q) {
+        double *sp = &t[10 * (size_t)q];
+        for (int a = 0; a < 3; ++a) {
+            const double v = vel ? vel[3 * q + a] : 0.0, w = angvel ? angvel[3 * q + a] : 0.0;
+            if (!std::isfinite(centre[3 * q + a]) || !std::isfinite(v) || !std::isfinite(w))
+                return fail(FSL_ERR_ARG, "non-finite sphere centre or velocity");
+            sp[4 + a] = v;
+            sp[7 + a] = w;
+        }
+        sp[0] = centre[3 * q] - nx * std::floor(centre[3 * q] / nx);
+        sp[1] = centre[3 * q + 1] - ny * std::floor(centre[3 * q + 1] / ny);
+        sp[2] = centre[3 * q + 2];
+    }
+    HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), (size_t)n * 10 * 8, hipMemcpyHostToDevice, L->st));
+    L->sph_host = t;
+    return remap(L);
+}
+
+FslStatus fsl_move_particles_device(FslLattice *L, const double *centre, const double *vel, const double *angvel)
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!L->geometry_set || L->nsph == 0) return fail(FSL_ERR_STATE, "no spheres are mapped");
+    if (!centre) return fail(FSL_ERR_ARG, "centre is NULL");
+    const int n = L->nsph;
+    const size_t tsz = L->sph_host.size();
+    double *stage = L->sph_dev + tsz + (size_t)std::max(n, 1) * 6;
+    int *flag = (int *)(stage + tsz);
+    k_zero_int<<<1, 64, 0, L->st>>>(flag);
+    k_sph_stage<<<(n + 255) / 256, 256, 0, L->st>>>(L->sph_dev, stage, n, centre, vel, angvel, (double)L->P.nx,
+                                                     (double)L->P.ny, flag);
+    HIP_TRY(hipGetLastError());
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    if (bad) return fail(FSL_ERR_ARG, "non-finite sphere centre or velocity");
+    HIP_TRY(hipMemcpyAsync(L->sph_dev, stage, (size_t)n * 10 * 8, hipMemcpyDeviceToDevice, L->st));
+    L->sph_host_stale = true;
+    return remap(L);
 }
 
 static FslStatus check_mass(FslLattice *L)

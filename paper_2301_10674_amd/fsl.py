@@ -29,7 +29,7 @@ EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fs
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
            "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
-           "fsl_bed_profile", "fsl_move_particles",
+           "fsl_bed_profile", "fsl_move_particles", "fsl_move_particles_device",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_dem_create", "fsl_dem_step",
            "fsl_dem_read", "fsl_dem_bedload", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy")
 MLP_NPARAM = 6212
@@ -140,6 +140,7 @@ def lib():
         L.fsl_particle_forces.argtypes = [vp, dp, i32]
         L.fsl_set_accel.argtypes = [vp, dp]
         L.fsl_move_particles.argtypes = [vp, dp, dp, dp]
+        L.fsl_move_particles_device.argtypes = [vp, vp, vp, vp]
         L.fsl_bulk_velocity.argtypes = [vp, dp]
         L.fsl_bed_profile.argtypes = [vp, dp, dp, i32]
         L.fsl_set_estimator.argtypes = [vp, fp]
@@ -162,6 +163,11 @@ def lib():
         L.fsl_destroy.argtypes = [vp]
         _lib = L
     return _lib
+
+
+def _torch():
+    import torch
+    return torch
 
 
 def _check(status):
@@ -298,6 +304,15 @@ class Lattice:
         vel, angvel = _f64(vel), _f64(angvel)
         _check(lib().fsl_move_particles(self.h, _dp(centre), _dp(vel), _dp(angvel)))
 
+    def move_particles_device(self, centre, vel=None, angvel=None):
+        """the same with CUDA float64 tensors of 3 values per sphere"""
+        def ptr(t):
+            if t is None:
+                return None
+            assert t.is_cuda and t.dtype == _torch().float64 and t.is_contiguous() and t.numel() == 3 * self.nsph
+            return ctypes.c_void_p(t.data_ptr())
+        _check(lib().fsl_move_particles_device(self.h, ptr(centre), ptr(vel), ptr(angvel)))
+
     def set_accel(self, accel):
         a = _f64(accel).reshape(3)
         _check(lib().fsl_set_accel(self.h, _dp(a)))
@@ -321,6 +336,13 @@ class Lattice:
         out = np.zeros(6 * max(n, 1))
         _check(lib().fsl_particle_forces(self.h, _dp(out), 0))
         return out[:6 * n].reshape(n, 6)
+
+    def particle_forces_device(self):
+        """(n, 6) CUDA float64 tensor of the same force and torque"""
+        torch = _torch()
+        out = torch.empty((max(self.nsph, 1), 6), dtype=torch.float64, device="cuda")
+        _check(lib().fsl_particle_forces(self.h, ctypes.cast(out.data_ptr(), ctypes.POINTER(ctypes.c_double)), 1))
+        return out[:self.nsph]
 
     def set_estimator(self, weights):
         w = _f32(weights)
@@ -437,6 +459,13 @@ class Dem:
         out = [np.zeros(3 * self.n) for _ in range(3)]
         _check(lib().fsl_dem_read(self.h, *[_dp(o) for o in out], 0))
         return [o.reshape(self.n, 3) for o in out]
+
+    def state_device(self):
+        """(centre, vel, angvel) as (n, 3) CUDA float64 tensors"""
+        torch = _torch()
+        out = [torch.empty((self.n, 3), dtype=torch.float64, device="cuda") for _ in range(3)]
+        _check(lib().fsl_dem_read(self.h, *[ctypes.cast(o.data_ptr(), ctypes.POINTER(ctypes.c_double)) for o in out], 1))
+        return out
 
     def bedload(self):
         """bedload transport rate q_b of Eq. (1)"""
