@@ -164,6 +164,25 @@ def test_coupled_device_path_matches_host_path():
         assert np.array_equal(fa[k], fb[k]), k
 
 
+@pytest.mark.parametrize("case", ["single", "between_walls"])
+def test_small_cases_fp64(case):
+    """One free sphere falling onto the bottom wall and bouncing; a sphere
+    that touches both walls of a box only slightly taller than it is wide
+    (both wall contacts at once)."""
+    if case == "single":
+        box, c, r, v = (20, 20, 20), [[10.0, 10.0, 6.0]], [5.0], [[0.003, -0.002, -0.03]]
+    else:
+        box, c, r, v = (20, 20, 10), [[10.0, 10.0, 5.0]], [5.05], [[0.01, 0.0, 0.002]]
+    kw = dict(KW, viscosity=0.02, lub_cut=0.6, lub_min=1e-3, accel=(0, 0, -1e-4), dt=1.0, substeps=10)
+    g = F().Dem(box, c, r, v, [[0, 0.001, 0]], None, skin=1.0, **kw)
+    o = O.OracleDem(box, c, r, v, [[0, 0.001, 0]], None, **kw)
+    g.step(None, n=100)
+    o.step(None, n=100)
+    err = compare(g.state(), o.state(), 1e-12, case)
+    print(case, "max relative difference %.3e" % err)
+    g.destroy()
+
+
 def test_error_paths():
     f = F()
     # 60 small spheres in a cube of side 0.8: every other sphere is within

@@ -10,6 +10,7 @@ al.) against the FP64 oracle, through the C-ABI.
 * FP32 and FP16 storage with all variants on the channel film with surface
   tension: the velocity error against the FP64 oracle within the storage
   forms' targets, mass conserved.
+* Ragged and tiny lattices, an all-liquid box (empty interface list).
 * The variants change the result (the splash with and without differs).
 """
 import dataclasses
@@ -101,6 +102,42 @@ def test_film_reduced_storage(prec, target):
     # FP16-rounded densities, which costs the default model ~1e-2 here; the
     # variants must not add to the storage error
     assert errs["both"] <= max(target, 1.5 * errs["default"]), errs
+
+
+@pytest.mark.parametrize("shape,h", [((300, 3, 7), 3.4), ((3, 3, 3), 1.6), ((257, 5, 9), 5.0)])
+def test_ragged_and_tiny_lattices_fp64(shape, h):
+    """All variants on ragged x tails (300 and 257 cells over 256-wide
+    blocks), the smallest lattice and a surface exactly on a cell face."""
+    nx, ny, nz = shape
+    xc = np.arange(nx) + 0.5
+    hh = h + 0.7 * np.sin(2 * np.pi * xc / nx)
+    fill = I.height_fill(shape, np.broadcast_to(hh[None, :], (ny, nx)))
+    rng = np.random.default_rng(5)
+    w = I.Workload(name="rag", shape=shape, omega=1.3, accel=(1e-4, 0, -1e-4), sigma=1e-3,
+                   fill=fill, rho=np.ones((nz, ny, nx)), vel=0.01 * rng.standard_normal((3, nz, ny, nx)),
+                   centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+                   sphere_angvel=np.zeros((0, 3)))
+    g, o = pair(w, "fp64", VARIANTS["both"])
+    M0 = o.total_mass()
+    g.step(20)
+    o.step(20)
+    assert_fp64_parity(gpu_fields(g), oracle_fields(o), 1e-12, str(shape))
+    assert abs(g.total_mass() - M0) <= 1e-12 * M0
+    g.destroy()
+
+
+def test_all_liquid_box_with_variants():
+    nx, ny, nz = 64, 4, 6
+    w = I.Workload(name="liq", shape=(nx, ny, nz), omega=1.5, accel=(1e-5, 0, 0), sigma=1e-3,
+                   fill=np.ones((nz, ny, nx)), rho=np.ones((nz, ny, nx)), vel=np.zeros((3, nz, ny, nx)),
+                   centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+                   sphere_angvel=np.zeros((0, 3)))
+    g, o = pair(w, "fp64", VARIANTS["both"])
+    assert g.info()[1] == 0
+    g.step(10)
+    o.step(10)
+    assert_fp64_parity(gpu_fields(g), oracle_fields(o), 1e-13, "liquid box")
+    g.destroy()
 
 
 def test_variants_change_the_result():
