@@ -867,20 +867,29 @@ __global__ __launch_bounds__(LIST_THREADS) void k_classes(Dev d, int p)
 {
     const int32_t *list = d.list[p];
     const int count = d.cnt[p];
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
         const int c = list[t];
-        const Cell pc = cell_xyz(d, c);
+        const int x = c % nx, row = c / nx, y = row % ny, z = row / ny;
+        const int OX[3] = {x == 0 ? nx - 1 : -1, 0, x == nx - 1 ? 1 - nx : 1};
+        const int OY[3] = {y == 0 ? (ny - 1) * nx : -nx, 0, y == ny - 1 ? (1 - ny) * nx : nx};
+        const int OZ[3] = {z == 0 ? 0 : -nxy, 0, z == nz - 1 ? 0 : nxy};
+        const bool WZ[3] = {z == 0, false, z == nz - 1};
+        // every neighbour's flag byte at once (beyond a wall: the cell's own,
+        // ignored below)
+        uint32_t f[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) f[i] = at(d.flags, (uint32_t)(c + OX[i % 3] + OY[(i / 3) % 3] + OZ[i / 9]));
         bool g = false, q = false;
+#pragma unroll
         for (int i = 0; i < 27; ++i) {
-            if (i == REST) continue;
-            const int y = nb_of(d, pc, i);
-            if (y < 0) continue;
-            const uint8_t ty = d.flags[y] & T_MASK;
+            if (i == REST || WZ[i / 9]) continue;
+            const uint32_t ty = f[i] & T_MASK;
             g |= ty == T_GAS;
             q |= ty == T_LIQ;
         }
         const uint8_t cls = (g && !q) ? F_CLS_LOSE : ((q && !g) ? F_CLS_GAIN : 0);
-        d.flags[c] = (uint8_t)((d.flags[c] & ~(F_CLS_LOSE | F_CLS_GAIN)) | cls);
+        d.flags[c] = (uint8_t)((f[REST] & ~(F_CLS_LOSE | F_CLS_GAIN)) | cls);
     }
 }
 
