@@ -9,8 +9,8 @@
  *
  * The paper needs the local curvature kappa only inside the Laplace pressure
  * 2 sigma kappa (Section 2.1) and does not say how it is estimated; the
- * network is this build's learned alternative to the finite-difference
- * estimate, not part of the paper.
+ * network is a learned alternative to the finite-difference estimate, not
+ * part of the paper.
  *
  * Layout of the flat parameter vector (double, 6212 entries):
  *   W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
