@@ -30,6 +30,13 @@
  *                      R_eff = r1 r2/(r1 + r2), applied for gaps 0 < s < s_c
  *                      as -6 pi mu R_eff^2 u_n (1/s - 1/s_c) so that it
  *                      vanishes at the cut-off, s limited below by s_min;
+ *                      and the leading tangential force -6 pi mu R_t
+ *                      ln(1/s) v_t on the tangential slip v_t of the facing
+ *                      surfaces, R_t = 4 r1 r2 (2 r1^2 + r1 r2 + 2 r2^2) /
+ *                      (15 (r1 + r2)^3) (Jeffrey and Onishi 1984: r/6 for
+ *                      equal spheres; 8 r/15 against a wall, Goldman, Cox
+ *                      and Brenner 1967), applied as ln(s_c/s) at the
+ *                      middle of the gap;
  *   integration     -- symplectic Euler per sub-step: forces from the state
  *                      at the start of the sub-step, then velocities, then
  *                      positions from the new velocities.
@@ -162,12 +169,13 @@ static void forget(OlDem *D, int32_t lo, int32_t hi)
  *   delta   overlap (> 0 in contact; -delta is the gap otherwise)
  *   vrel    velocity of a's surface point relative to b's, at the contact
  *   ucen    normal approach speed of the centres, (v_a - v_b) . n
- *   meff, reff   effective mass and radius
+ *   meff, reff   effective mass and radius (normal lubrication)
+ *   rt      radius of the tangential lubrication force
  *   xi      tangential displacement record (updated), NULL for no contact
  * Returns the force on a in F and its tangential part in Ft (zero without
  * contact). */
 static void pair_force(const OlDemParams *p, double h, const double n[3], double delta,
-                       const double vrel[3], double ucen, double meff, double reff, double *xi,
+                       const double vrel[3], double ucen, double meff, double reff, double rt, double *xi,
                        double F[3], double Ft[3])
 {
     F[0] = F[1] = F[2] = 0.0;
@@ -201,7 +209,12 @@ static void pair_force(const OlDemParams *p, double h, const double n[3], double
         double s = -delta;
         if (s < p->lub_min) s = p->lub_min;
         const double f = -6.0 * PI * p->viscosity * reff * reff * ucen * (1.0 / s - 1.0 / p->lub_cut);
-        for (int d = 0; d < 3; ++d) F[d] = f * n[d];
+        const double un = dot3(vrel, n);
+        const double g = -6.0 * PI * p->viscosity * rt * log(p->lub_cut / s);
+        for (int d = 0; d < 3; ++d) {
+            Ft[d] = g * (vrel[d] - un * n[d]);
+            F[d] = f * n[d] + Ft[d];
+        }
     }
 }
 
@@ -239,6 +252,8 @@ static void substep(OlDem *D, const double *hydro, double h)
             else if (D->fixed[b]) meff = D->m[a];
             else meff = D->m[a] * D->m[b] / (D->m[a] + D->m[b]);
             const double reff = ra * rb / (ra + rb);
+            const double rt = 4.0 * ra * rb * (2.0 * ra * ra + ra * rb + 2.0 * rb * rb) /
+                              (15.0 * (ra + rb) * (ra + rb) * (ra + rb));
             /* contact point in the middle of the overlap */
             const double la = ra - 0.5 * delta, lb = rb - 0.5 * delta;
             double wa[3], wb[3], arm_a[3] = {la * nv[0], la * nv[1], la * nv[2]};
@@ -255,7 +270,7 @@ static void substep(OlDem *D, const double *hydro, double h)
             if (delta > 0.0) xi = history(D, a, b);
             else forget(D, a, b);
             double f[3], ft[3];
-            pair_force(p, h, nv, delta, vrel, ucen, meff, reff, xi, f, ft);
+            pair_force(p, h, nv, delta, vrel, ucen, meff, reff, rt, xi, f, ft);
             /* b takes the opposite force; both torques come from the
              * tangential force at the common contact point (the normal part
              * has no lever about either centre) */
@@ -290,7 +305,8 @@ static void substep(OlDem *D, const double *hydro, double h)
             const double ucen = D->v[3 * i + 2] * nv[2];
             if (delta <= 0.0) xi[0] = xi[1] = xi[2] = 0.0;
             double f[3], ft[3], t[3];
-            pair_force(p, h, nv, delta, vrel, ucen, D->m[i], D->r[i], delta > 0.0 ? xi : NULL, f, ft);
+            pair_force(p, h, nv, delta, vrel, ucen, D->m[i], D->r[i], 8.0 * D->r[i] / 15.0,
+                       delta > 0.0 ? xi : NULL, f, ft);
             cross3(arm, ft, t);
             for (int d = 0; d < 3; ++d) {
                 F[3 * i + d] += f[d];

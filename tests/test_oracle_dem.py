@@ -18,6 +18,10 @@ Closed forms and invariants, none retyping the oracle's formulas:
 * two spheres (or a sphere and the wall) approaching inside the
   lubrication range follow the integral of m du = 6 pi mu R_eff^2 (1/s -
   1/s_c) ds, u(s) = u0 - 6 pi mu R_eff^2/m_eff (ln(s0/s) - (s0 - s)/s_c);
+* a sphere sliding along the wall inside the lubrication range ends
+  rolling (angular momentum about the gap's midpoint is conserved) and its
+  slip decays at the rate the tangential coefficient 8 r/15 gives; two equal
+  spheres sliding past each other at the rate of r/6;
 * a constant hydrodynamic force and torque accelerate a sphere of mass
   rho_p 4/3 pi r^3 and moment of inertia 2/5 m r^2 uniformly;
 * the bedload rate of Eq. (1) for spheres moving together, opposite pairs,
@@ -214,3 +218,56 @@ def test_collision_across_the_periodic_seam():
     assert abs(v[1, 0] / u - 0.97) < 5e-4 and abs(inside[1, 0] / u - 0.97) < 5e-4
     assert v[0, 0] == -v[1, 0] and not v[:, 1:].any()
     assert (x[:, 0] >= 0).all() and (x[:, 0] < 40).all()
+
+
+def _slip_decay(d, slip, t1, h):
+    """decay rate of the slip velocity over [0, t1]"""
+    s0 = slip(d.state())
+    for _ in range(int(round(t1 / h))):
+        d.step()
+    return -math.log(slip(d.state()) / s0) / t1
+
+
+def test_tangential_lubrication_against_the_wall():
+    """A sphere sliding along the wall inside the lubrication range (no
+    contact, no gravity): the tangential force acts at the middle of the gap,
+    so angular momentum about that point is conserved and the sphere ends
+    rolling at v0 / (1 + I/(m l^2)), l = r + s/2; the slip v - l w decays
+    at 6 pi mu (8 r/15) ln(s_c/s) (1/m + l^2/I) (Goldman, Cox and Brenner's
+    coefficient for a sphere translating past a wall)."""
+    r, s, mu, sc, v0, h = 5.0, 0.1, 0.1, 0.6, 0.01, 0.02
+    ell = r + s / 2
+    m = mass(r)
+    inertia = 0.4 * m * r * r
+    d = O.OracleDem((400, 50, 50), [[20, 25, r + s]], [r], vel=[[v0, 0, 0]], density=RHO, viscosity=mu,
+                    lub_cut=sc, lub_min=1e-4, dt=h, substeps=1)
+    slip = lambda st: st[1][0, 0] - ell * st[2][0, 1]      # noqa: E731
+    k = _slip_decay(d, slip, 10.0, h)
+    want = 6 * math.pi * mu * (8 * r / 15) * math.log(sc / s) * (1 / m + ell ** 2 / inertia)
+    assert abs(k / want - 1) < 2e-3, (k, want)
+    for _ in range(40000):
+        d.step()
+    x, v, w = d.state()
+    assert abs(x[0, 2] - (r + s)) < 1e-12                 # the gap stays
+    assert abs(v[0, 0] / v0 - 1 / (1 + inertia / (m * ell ** 2))) < 1e-4
+    assert abs(ell * w[0, 1] / v[0, 0] - 1) < 1e-4
+
+
+def test_tangential_lubrication_between_spheres():
+    """Two equal spheres sliding past each other at a fixed gap: momentum is
+    conserved and the slip decays at 6 pi mu (r/6) ln(s_c/s) (2/m + 2 l^2/I)
+    (Jeffrey and Onishi's coefficient for equal spheres)."""
+    r, s, mu, sc, v0, h = 5.0, 0.1, 0.1, 0.6, 0.01, 0.02
+    ell = r + s / 2
+    m = mass(r)
+    inertia = 0.4 * m * r * r
+    d = O.OracleDem((200, 200, 200), [[100, 100, 100], [100, 100, 100 + 2 * r + s]], [r, r],
+                    vel=[[v0, 0, 0], [-v0, 0, 0]], density=RHO, viscosity=mu, lub_cut=sc, lub_min=1e-4,
+                    dt=h, substeps=1)
+    # slip of sphere 0's top point against sphere 1's bottom point
+    slip = lambda st: (st[1][0, 0] + ell * st[2][0, 1]) - (st[1][1, 0] - ell * st[2][1, 1])  # noqa: E731
+    k = _slip_decay(d, slip, 10.0, h)
+    want = 6 * math.pi * mu * (r / 6) * math.log(sc / s) * (2 / m + 2 * ell ** 2 / inertia)
+    assert abs(k / want - 1) < 2e-3, (k, want)
+    x, v, w = d.state()
+    assert abs(v[:, 0].sum()) < 1e-17 and abs(v[:, 2].sum()) < 1e-17

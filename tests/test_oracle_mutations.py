@@ -80,6 +80,10 @@ MUTANTS = {
                             "test_oracle_geometry.py", "csf"),
     "csf_no_floor": ("-g[d] / (gn > CSF_GMIN ? gn : CSF_GMIN)", "-g[d] / (gn > 1e-12 ? gn : 1.0)",
                      "test_oracle_geometry.py", "continuous"),
+    "dem_tangential_lubrication": ("(15.0 * (ra + rb) * (ra + rb) * (ra + rb))", "(10.0 * (ra + rb) * (ra + rb) * (ra + rb))",
+                                   "test_oracle_dem.py", "tangential_lubrication_between", "dem_oracle.c"),
+    "dem_tangential_lub_wall": ("8.0 * D->r[i] / 15.0", "8.0 * D->r[i] / 12.0",
+                                "test_oracle_dem.py", "tangential_lubrication_against", "dem_oracle.c"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
