@@ -340,7 +340,10 @@ FslStatus fsl_estimator_stats(FslLattice *lat, int64_t *learned, int64_t *fallba
  *     forces act at the middle of the overlap;
  *   lubrication: -6 pi nu_f R_eff^2 u_n (1/s - 1/s_c) along the line of
  *     centres for gaps 0 < s < s_c (s taken >= s_min), R_eff = r_i r_j /
- *     (r_i + r_j) (r_i against a wall), u_n the normal approach speed;
+ *     (r_i + r_j) (r_i against a wall), u_n the normal approach speed; and
+ *     -6 pi nu_f R_t ln(s_c/s) v_t on the tangential slip v_t of the facing
+ *     surfaces at the middle of the gap, R_t = 4 r_i r_j (2 r_i^2 + r_i r_j +
+ *     2 r_j^2) / (15 (r_i + r_j)^3) (8 r_i/15 against a wall);
  *   time: symplectic Euler per sub-step (forces from the sub-step's start,
  *     then velocities, then positions); x and y periodic, walls z = 0 and
  *     z = nz (the lattice's bounce-back planes); m = density 4/3 pi r^3,

@@ -11,8 +11,11 @@
 // sqrt(kappa) gamma_n with Mindlin's kappa = 2(1-nu)/(2-nu), capped by
 // Coulomb friction mu |F_n|; forces act at the middle of the overlap;
 // Brenner's leading-order normal lubrication force -6 pi mu R_eff^2 u_n
-// (1/s - 1/s_c) for gaps 0 < s < s_c (s >= s_min); walls z = 0 and z = nz
-// as bodies of infinite radius and mass; symplectic Euler per sub-step.
+// (1/s - 1/s_c) and the leading tangential one -6 pi mu R_t ln(s_c/s) v_t,
+// R_t = 4 r1 r2 (2 r1^2 + r1 r2 + 2 r2^2) / (15 (r1 + r2)^3) (Jeffrey and
+// Onishi; 8 r/15 against a wall, Goldman, Cox and Brenner), for gaps
+// 0 < s < s_c (s >= s_min); walls z = 0 and z = nz as bodies of infinite
+// radius and mass; symplectic Euler per sub-step.
 //
 // Layout: one wavefront per sphere for the lists, one lane per (sphere,
 // list slot) for the forces.  Each call first rebuilds every sphere's
@@ -144,7 +147,8 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 // Force F on body a (tangential part Ft) from body b: contact (delta > 0,
 // xi updated) or lubrication (gap -delta below the cut-off).
 __device__ void pair_force(const DemDev &D, const double n[3], double delta, const double vrel[3],
-                           double ucen, double meff, double reff, double *xi, double F[3], double Ft[3])
+                           double ucen, double meff, double reff, double rt, double *xi, double F[3],
+                           double Ft[3])
 {
     F[0] = F[1] = F[2] = 0.0;
     Ft[0] = Ft[1] = Ft[2] = 0.0;
@@ -172,7 +176,12 @@ __device__ void pair_force(const DemDev &D, const double n[3], double delta, con
         double s = -delta;
         if (s < D.lub_min) s = D.lub_min;
         const double f = -6.0 * PI * D.visc * reff * reff * ucen * (1.0 / s - 1.0 / D.lub_cut);
-        for (int d = 0; d < 3; ++d) F[d] = f * n[d];
+        const double un = dot3(vrel, n);
+        const double g = -6.0 * PI * D.visc * rt * log(D.lub_cut / s);
+        for (int d = 0; d < 3; ++d) {
+            Ft[d] = g * (vrel[d] - un * n[d]);
+            F[d] = f * n[d] + Ft[d];
+        }
     }
 }
 
@@ -213,6 +222,8 @@ __global__ __launch_bounds__(DEM_THREADS) void k_dem_sub(DemDev D, int s, int l)
             else if (D.fixed[b]) meff = D.m[a];
             else meff = D.m[a] * D.m[b] / (D.m[a] + D.m[b]);
             const double reff = ra * rb / (ra + rb);
+            const double rt = 4.0 * ra * rb * (2.0 * ra * ra + ra * rb + 2.0 * rb * rb) /
+                              (15.0 * (ra + rb) * (ra + rb) * (ra + rb));
             const double la = ra - 0.5 * delta, lb = rb - 0.5 * delta;
             const double arm_a[3] = {la * nv[0], la * nv[1], la * nv[2]};
             const double arm_b[3] = {-lb * nv[0], -lb * nv[1], -lb * nv[2]};
@@ -227,7 +238,7 @@ __global__ __launch_bounds__(DEM_THREADS) void k_dem_sub(DemDev D, int s, int l)
             const double ucen = dot3(vc, nv);
             if (delta <= 0.0) xi[0] = xi[1] = xi[2] = 0.0;
             double f[3], ft[3], t[3];
-            pair_force(D, nv, delta, vrel, ucen, meff, reff, delta > 0.0 ? xi : nullptr, f, ft);
+            pair_force(D, nv, delta, vrel, ucen, meff, reff, rt, delta > 0.0 ? xi : nullptr, f, ft);
             if (i == a) {
                 cross3(arm_a, ft, t);
             } else {
@@ -281,7 +292,8 @@ __global__ __launch_bounds__(DEM_THREADS) void k_dem_sub(DemDev D, int s, int l)
             const double ucen = V[3 * i + 2] * nv[2];
             if (delta <= 0.0) xi[0] = xi[1] = xi[2] = 0.0;
             double f[3], ft[3], t[3];
-            pair_force(D, nv, delta, vrel, ucen, mi, D.r[i], delta > 0.0 ? xi : nullptr, f, ft);
+            pair_force(D, nv, delta, vrel, ucen, mi, D.r[i], 8.0 * D.r[i] / 15.0, delta > 0.0 ? xi : nullptr, f,
+                       ft);
             cross3(arm, ft, t);
             for (int d = 0; d < 3; ++d) {
                 F[d] += f[d];

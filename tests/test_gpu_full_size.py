@@ -5,7 +5,7 @@
   after a few steps, over every cell that is fluid in both (the oracle runs
   its per-cell phases on all host threads), and the momentum-exchange force
   and torque on every sphere; the particle step on the large flume's bed
-  (bit-identical to the oracle's all-pairs evaluation).
+  (to 1e-12 of the oracle's all-pairs evaluation).
 * The FP32 and FP16 forms on the 1536 x 40 x 192 flume over 200 steps:
   properties that hold at any size -- total mass conserved to 1e-12, no
   liquid cell next to a gas cell, fill levels of interface cells finite,
