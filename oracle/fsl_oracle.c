@@ -17,7 +17,7 @@
  * Where the paper delegates to cited methods, the readings used are:
  *   collision   -- Geier et al. 2015 cumulant transform (chimera passes,
  *                  cumulants with first-order central moments taken as zero),
- *                  no Galilean correction terms; force by shifting the
+ *                  Galilean correction terms only as a variant; force by shifting the
  *                  velocity by F/(2 rho) and negating the first-order central
  *                  moments in the collision;
  *   walls       -- halfway bounce-back, Ladd's moving-wall term with rho_w=1;
@@ -33,7 +33,8 @@
  *   variants    -- (optional, OL_VAR_*) Thuerey's flux modifiers between
  *                  interface cells, his normal-weighted excess mass, and a
  *                  curvature from the divergence of corner normals
- *                  (Brackbill et al. 1992);
+ *                  (Brackbill et al. 1992), and the Galilean-invariance
+ *                  correction of the cumulant collision;
  *   geometry    -- Parker-Youngs normal, mean curvature from the finite-
  *                  difference Hessian of the same 3x3x3 fill stencil.
  * The two per-cell phases (stream-collide, geometry) may run their cells on
@@ -248,7 +249,7 @@ void ol_cumulants(const double fin[27], const double g[3], double C[27])
 }
 
 void ol_collide(const double fin[27], const double g[3], double omega,
-                double omega_bulk, double omega_high, double fout[27])
+                double omega_bulk, double omega_high, int32_t galilean, double fout[27])
 {
     double rho, u[3], M[Q], k[Q], C[Q], Cs[Q], ks[Q];
     macro(fin, g, &rho, u);
@@ -267,6 +268,23 @@ void ol_collide(const double fin[27], const double g[3], double omega,
     double D1 = (1.0 - omega) * (C_(2, 0, 0) - C_(0, 2, 0));
     double D2 = (1.0 - omega) * (C_(2, 0, 0) - C_(0, 0, 2));
     double T = (1.0 - omega_bulk) * (C_(2, 0, 0) + C_(0, 2, 0) + C_(0, 0, 2)) + omega_bulk * 1.0;
+    if (galilean) {
+        /* Galilean-invariance correction (Geier et al. 2015).  The first-
+         * order non-equilibrium of the second-order cumulants is
+         * -(2/(3 w)) times the strain rate, w the rate of that part; solving
+         * the deviator (rate omega) and the trace (rate omega_bulk) for the
+         * normal strain rates gives d_a u_a.  The cubic moment the lattice
+         * cannot hold would add 3 u_a^2 d_a u_a to the momentum flux; it is
+         * removed as a source term with the usual (1 - w/2) factor. */
+        const double trace_neq = C_(2, 0, 0) + C_(0, 2, 0) + C_(0, 0, 2) - 1.0;
+        const double dxu = -0.5 * omega * (2.0 * C_(2, 0, 0) - C_(0, 2, 0) - C_(0, 0, 2)) - 0.5 * omega_bulk * trace_neq;
+        const double dyv = -0.5 * omega * (2.0 * C_(0, 2, 0) - C_(2, 0, 0) - C_(0, 0, 2)) - 0.5 * omega_bulk * trace_neq;
+        const double dzw = -0.5 * omega * (2.0 * C_(0, 0, 2) - C_(2, 0, 0) - C_(0, 2, 0)) - 0.5 * omega_bulk * trace_neq;
+        const double ex = u[0] * u[0] * dxu, ey = u[1] * u[1] * dyv, ez = u[2] * u[2] * dzw;
+        D1 -= 3.0 * (1.0 - 0.5 * omega) * (ex - ey);
+        D2 -= 3.0 * (1.0 - 0.5 * omega) * (ex - ez);
+        T -= 3.0 * (1.0 - 0.5 * omega_bulk) * (ex + ey + ez);
+    }
     Cs[K(2, 0, 0)] = (T + D1 + D2) / 3.0;
     Cs[K(0, 2, 0)] = (T - 2.0 * D1 + D2) / 3.0;
     Cs[K(0, 0, 2)] = (T + D1 - 2.0 * D2) / 3.0;
@@ -559,7 +577,8 @@ OlLattice *ol_create(const OlParams *p, const double *fill, const double *rho,
     if (!p || !fill || !rho) return NULL;
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return NULL;
     if (!(p->omega > 0.0 && p->omega < 2.0)) return NULL;
-    if (p->variants & ~(OL_VAR_FLUX_MODIFIERS | OL_VAR_NORMAL_EXCESS | OL_VAR_CSF_CURVATURE)) return NULL;
+    if (p->variants & ~(OL_VAR_FLUX_MODIFIERS | OL_VAR_NORMAL_EXCESS | OL_VAR_CSF_CURVATURE | OL_VAR_GALILEAN))
+        return NULL;
     OlLattice *L = (OlLattice *)calloc(1, sizeof(OlLattice));
     L->p = *p;
     int64_t N = (int64_t)p->nx * p->ny * p->nz;
@@ -789,7 +808,8 @@ static void phase_stream_collide(OlLattice *L)
         }
         mnew[c] = L->m[c] + dm;
 
-        ol_collide(fin, p->accel, p->omega, p->omega_bulk, p->omega_high, &fnew[c * Q]);
+        ol_collide(fin, p->accel, p->omega, p->omega_bulk, p->omega_high, (p->variants & OL_VAR_GALILEAN) != 0,
+                   &fnew[c * Q]);
         store_form(L, &fnew[c * Q]);
         L->rho[c] = sum27(&fnew[c * Q]);
     }

@@ -60,8 +60,16 @@ typedef struct {
  *   OL_VAR_CSF_CURVATURE   the curvature is half the divergence of the unit
  *     normal, from normals at the 8 cell corners (Brackbill et al. 1992;
  *     corner gradients below 0.01 give shortened normals -grad/0.01),
- *     instead of the Hessian form; the normal stays Parker-Youngs. */
-enum { OL_VAR_FLUX_MODIFIERS = 1, OL_VAR_NORMAL_EXCESS = 2, OL_VAR_CSF_CURVATURE = 4 };
+ *     instead of the Hessian form; the normal stays Parker-Youngs.
+ * And of the collision (Geier et al. 2015):
+ *   OL_VAR_GALILEAN        Galilean-invariance correction of the second-order
+ *     cumulants: D3Q27 cannot hold the cubic velocity moments, which leaves
+ *     an error of 3 rho u_a^2 d_a u_a in the normal stresses; the correction
+ *     subtracts 3 (1 - w/2) u_a^2 d_a u_a from the relaxed diagonal cumulants
+ *     (w = omega for the deviator, omega_bulk for the trace), with the
+ *     strain rates d_a u_a estimated from the cell's own non-equilibrium
+ *     second-order cumulants. */
+enum { OL_VAR_FLUX_MODIFIERS = 1, OL_VAR_NORMAL_EXCESS = 2, OL_VAR_CSF_CURVATURE = 4, OL_VAR_GALILEAN = 8 };
 
 typedef struct OlLattice OlLattice;
 
@@ -69,9 +77,10 @@ typedef struct OlLattice OlLattice;
 void ol_velocities(int32_t c[27][3], double w[27]);
 
 /* --- single-cell operators ------------------------------------------------ */
-/* collision of one cell; g = body acceleration; returns post-collision f */
+/* collision of one cell; g = body acceleration; galilean = 1 adds the
+ * Galilean-invariance correction (OL_VAR_GALILEAN); returns post-collision f */
 void ol_collide(const double fin[27], const double g[3], double omega,
-                double omega_bulk, double omega_high, double fout[27]);
+                double omega_bulk, double omega_high, int32_t galilean, double fout[27]);
 /* the normalised pre-collision cumulants of one cell (index a+3b+9c for
  * C_{abc}); entry 0 holds rho, entries 1,3,9 hold the first-order central
  * moments (which the higher cumulants treat as zero) */

@@ -24,7 +24,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS = range(10)
-VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS, VAR_CSF_CURVATURE = 1, 2, 4
+VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS, VAR_CSF_CURVATURE, VAR_GALILEAN = 1, 2, 4, 8
 
 
 def build(force: bool = True) -> str:
@@ -99,7 +99,7 @@ def lib():
         L.ol_round_half.restype = ctypes.c_double
         L.ol_round_half.argtypes = [ctypes.c_double]
         L.ol_threads.restype = ctypes.c_int32
-        L.ol_collide.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.ol_collide.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32, dp]
         L.ol_cumulants.argtypes = [dp, dp, dp]
         L.ol_feq.argtypes = [ctypes.c_double, dp, dp]
         L.ol_normal_curvature.argtypes = [dp, dp, dp]
@@ -151,11 +151,11 @@ def velocities():
     return c, w
 
 
-def collide(f, g=(0.0, 0.0, 0.0), omega=1.0, omega_bulk=1.0, omega_high=1.0):
+def collide(f, g=(0.0, 0.0, 0.0), omega=1.0, omega_bulk=1.0, omega_high=1.0, galilean=False):
     f = _f64(f)
     g = _f64(g)
     out = np.zeros(27)
-    lib().ol_collide(_dp(f), _dp(g), omega, omega_bulk, omega_high, _dp(out))
+    lib().ol_collide(_dp(f), _dp(g), omega, omega_bulk, omega_high, int(bool(galilean)), _dp(out))
     return out
 
 
@@ -198,7 +198,7 @@ class OracleLattice:
     def __init__(self, shape, omega, accel=(0.0, 0.0, 0.0), sigma=0.0, rho_gas=1.0,
                  conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
                  omega_bulk=1.0, omega_high=1.0, fill=None, rho=None, vel=None, store="fp64",
-                 flux_modifiers=False, normal_excess=False, csf_curvature=False):
+                 flux_modifiers=False, normal_excess=False, csf_curvature=False, galilean=False):
         nx, ny, nz = shape
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -210,9 +210,9 @@ class OracleLattice:
         p.sigma, p.rho_gas, p.conv_eps, p.normal_tie = sigma, rho_gas, conv_eps, normal_tie
         p.rule_isolated = 1 if rule_isolated else 0
         p.store = {"fp64": 0, "fp32": 1, "fp16": 2}[store]
-        # free-surface variants of Thuerey 2007 (bits of the C header)
+        # variants of the free-surface model and of the collision (bits of the C header)
         p.variants = (VAR_FLUX_MODIFIERS if flux_modifiers else 0) | (VAR_NORMAL_EXCESS if normal_excess else 0) | \
-            (VAR_CSF_CURVATURE if csf_curvature else 0)
+            (VAR_CSF_CURVATURE if csf_curvature else 0) | (VAR_GALILEAN if galilean else 0)
         self._p = p
         fill = _f64(np.ones((nz, ny, nx)) if fill is None else fill).reshape(-1)
         rho = _f64(np.ones((nz, ny, nx)) if rho is None else rho).reshape(-1)

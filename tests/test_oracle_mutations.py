@@ -84,6 +84,16 @@ MUTANTS = {
                                    "test_oracle_dem.py", "tangential_lubrication_between", "dem_oracle.c"),
     "dem_tangential_lub_wall": ("8.0 * D->r[i] / 15.0", "8.0 * D->r[i] / 12.0",
                                 "test_oracle_dem.py", "tangential_lubrication_against", "dem_oracle.c"),
+    "galilean_sign": ("D1 -= 3.0 * (1.0 - 0.5 * omega) * (ex - ey);", "D1 += 3.0 * (1.0 - 0.5 * omega) * (ex - ey);",
+                      "test_oracle_galilean.py", "sound_wave"),
+    "galilean_source_factor": ("T -= 3.0 * (1.0 - 0.5 * omega_bulk) * (ex + ey + ez);",
+                               "T -= 3.0 * (1.0 - omega_bulk) * (ex + ey + ez);",
+                               "test_oracle_galilean.py", "sound_wave"),
+    "galilean_dropped_term": ("D2 -= 3.0 * (1.0 - 0.5 * omega) * (ex - ez);", "D2 -= 3.0 * (1.0 - 0.5 * omega) * (ex);",
+                              "test_oracle_galilean.py", "sound_wave or cube"),
+    "galilean_strain_rate": ("- 0.5 * omega_bulk * trace_neq;\n        const double dyv",
+                             "- 0.5 * omega * trace_neq;\n        const double dyv",
+                             "test_oracle_galilean.py", "sound_wave or cube"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
