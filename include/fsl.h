@@ -79,11 +79,12 @@ typedef struct {
     int32_t normals;        /* 0: finite-difference normal and curvature,
                                1: learned estimator with finite-difference fallback */
     int32_t check_every;    /* watchdog interval in steps (0: never) */
-    int32_t variants;       /* FSL_VAR_* bits; 0 is the free-surface model of
-                               Section 2.1 as the cited FSLBM defines it */
+    int32_t variants;       /* FSL_VAR_* bits; 0 is the model of Section 2.1
+                               as the cited FSLBM and collision define it */
 } FslParams;
 
-/* Optional free-surface variants (Thuerey 2007), bits of FslParams.variants:
+/* Optional variants of the free surface (Thuerey 2007) and of the collision
+ * (Geier et al. 2015), bits of FslParams.variants:
  *   FSL_VAR_FLUX_MODIFIERS  between two interface cells, mass moves only
  *     from a cell with gas but no liquid neighbours (which may only lose)
  *     and towards a cell with liquid but no gas neighbours (which may only
@@ -100,8 +101,15 @@ typedef struct {
  *     gradient g below 0.01 gives the shortened normal -g/0.01, so that the
  *     curvature is continuous in the fill levels), instead of the Hessian
  *     form; needs normals == 0.
+ *   FSL_VAR_GALILEAN        Galilean-invariance correction of the cumulant
+ *     collision: D3Q27 cannot hold the cubic velocity moments, which puts an
+ *     error of 3 rho u_a^2 d_a u_a into the normal stresses; the relaxed
+ *     diagonal second-order cumulants lose 3 (1 - w/2) u_a^2 d_a u_a
+ *     (w = omega for the deviator, 1 for the trace), the strain rates d_a u_a
+ *     estimated from the cell's non-equilibrium second-order cumulants.
+ *     Applies to every fluid cell (liquid and interface).
  * Unknown bits make fsl_create_lattice fail with FSL_ERR_ARG. */
-enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2, FSL_VAR_CSF_CURVATURE = 4 };
+enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2, FSL_VAR_CSF_CURVATURE = 4, FSL_VAR_GALILEAN = 8 };
 
 /* field ids for fsl_read_fields(); bit k of the mask selects field k */
 enum {

@@ -86,7 +86,7 @@ struct FslLattice {
 static size_t store_bytes(int prec) { return prec == FSL_FP64 ? 8 : (prec == FSL_FP32 ? 4 : 2); }
 
 static_assert(FSL_VAR_FLUX_MODIFIERS == VAR_FLUX_MODIFIERS && FSL_VAR_NORMAL_EXCESS == VAR_NORMAL_EXCESS &&
-                  FSL_VAR_CSF_CURVATURE == VAR_CSF_CURVATURE,
+                  FSL_VAR_CSF_CURVATURE == VAR_CSF_CURVATURE && FSL_VAR_GALILEAN == VAR_GALILEAN,
               "variant bits of the header and the kernels differ");
 
 static bool params_ok(const FslParams *p, std::string &why)
@@ -105,7 +105,7 @@ static bool params_ok(const FslParams *p, std::string &why)
     if (!(p->normal_tie >= 0.0)) { why = "normal_tie must be >= 0"; return false; }
     if (p->normals != 0 && p->normals != 1) { why = "normals must be 0 or 1"; return false; }
     if (p->check_every < 0) { why = "check_every must be >= 0"; return false; }
-    if (p->variants & ~(FSL_VAR_FLUX_MODIFIERS | FSL_VAR_NORMAL_EXCESS | FSL_VAR_CSF_CURVATURE)) {
+    if (p->variants & ~(FSL_VAR_FLUX_MODIFIERS | FSL_VAR_NORMAL_EXCESS | FSL_VAR_CSF_CURVATURE | FSL_VAR_GALILEAN)) {
         why = "unknown variant bits";
         return false;
     }

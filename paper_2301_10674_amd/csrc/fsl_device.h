@@ -137,10 +137,15 @@ __device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
 }
 
 // Cumulant collision (Geier et al. 2015, as chosen in Section 2.1: shear
-// rate omega, bulk and all higher-order rates 1, no Galilean correction) on
-// PDF deviations d_i = f_i - w_i, in place.  g is the body acceleration:
-// the velocity is shifted by F/(2 rho) and the first-order central moments
-// leave the collision as +F/(2 rho) = g/2.
+// rate omega, bulk and all higher-order rates 1) on PDF deviations
+// d_i = f_i - w_i, in place.  g is the body acceleration: the velocity is
+// shifted by F/(2 rho) and the first-order central moments leave the
+// collision as +F/(2 rho) = g/2.  gc adds the Galilean-invariance
+// correction of the same paper (a variant): the lattice lacks the cubic
+// velocity moments, which puts 3 u_a^2 d_a u_a into the normal stresses;
+// the relaxed diagonal second-order cumulants lose 3 (1 - w/2) u_a^2 d_a u_a
+// (w = omega for the deviator, 1 for the trace), with the strain rates
+// d_a u_a read from the cell's non-equilibrium second-order cumulants.
 //
 // With every higher-order rate equal to 1 the post-collision cumulants of
 // order >= 3 vanish, so the post-collision central moments are the Gaussian
@@ -149,7 +154,7 @@ __device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
 // is carried as a deviation from the rest state (rho = 1, u = 0, K = I/3) so
 // FP32 keeps the small quantities exact enough.
 template <class R, class E>
-__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27])
+__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27], bool gc = false)
 {
     // Raw moments of the deviations, passes x, y, z of (sum, odd, even), in
     // FP64 in every form: the non-equilibrium second moments are small
@@ -205,7 +210,21 @@ __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz
     // relaxation: deviator with omega, trace to equilibrium
     const R om1 = R(1) - omega;
     const R tr3 = (Kxx + Kyy + Kzz) * third;
-    const R ax = om1 * (Kxx - tr3), ay = om1 * (Kyy - tr3), az = om1 * (Kzz - tr3);
+    R ax = om1 * (Kxx - tr3), ay = om1 * (Kyy - tr3), az = om1 * (Kzz - tr3);
+    if (gc) {
+        // first-order non-equilibrium K = -(2/(3 w)) x strain rate, solved
+        // for the normal strain rates from the deviator (w = omega) and the
+        // trace (w = 1); the correction enters as a source with (1 - w/2)
+        const R hw = R(0.5) * omega, trn = Kxx + Kyy + Kzz;
+        const R ex = ux * ux * (-hw * (R(2) * Kxx - Kyy - Kzz) - R(0.5) * trn);
+        const R ey = uy * uy * (-hw * (R(2) * Kyy - Kxx - Kzz) - R(0.5) * trn);
+        const R ez = uz * uz * (-hw * (R(2) * Kzz - Kxx - Kyy) - R(0.5) * trn);
+        const R es = ex + ey + ez, cw = R(3) - R(3) * hw;
+        // deviator part: -cw (e_a - es/3); trace part: -(3/2) es over 3 axes
+        ax -= cw * (ex - es * third) + R(0.5) * es;
+        ay -= cw * (ey - es * third) + R(0.5) * es;
+        az -= cw * (ez - es * third) + R(0.5) * es;
+    }
     const R bxy = om1 * Kxy, bxz = om1 * Kxz, byz = om1 * Kyz;
     // post-collision central moments minus their rest values
     R k[27];

@@ -47,10 +47,10 @@ struct Dev {
     int variants;             // VAR_* bits
 };
 
-// free-surface variants: flux modifiers between interface cells and
-// normal-weighted excess mass (Thuerey 2007), curvature from corner normals
-// (Brackbill et al. 1992)
-constexpr int VAR_FLUX_MODIFIERS = 1, VAR_NORMAL_EXCESS = 2, VAR_CSF_CURVATURE = 4;
+// variants: flux modifiers between interface cells and normal-weighted
+// excess mass (Thuerey 2007), curvature from corner normals (Brackbill et al.
+// 1992), Galilean correction of the cumulant collision (Geier et al. 2015)
+constexpr int VAR_FLUX_MODIFIERS = 1, VAR_NORMAL_EXCESS = 2, VAR_CSF_CURVATURE = 4, VAR_GALILEAN = 8;
 
 constexpr int BULK_THREADS = 256;
 constexpr int BULK_MAX_BLOCKS = 2048;

@@ -177,7 +177,7 @@ __device__ __forceinline__ T at(const T *base, uint32_t e)
 // NEAR: the wavefront holds a cell next to a solid or a wall (the other
 // lanes run the same code with an empty solid mask); without it the code
 // has no bounce-back part at all.
-template <class S, bool NEAR>
+template <class S, bool NEAR, bool GC>
 __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
                                           int x, int row, uint8_t fl)
 {
@@ -242,7 +242,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 
     using E = typename Eq<S>::type;
     E fo[27];
-    collide<R, E>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
+    collide<R, E>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, GC);
 
     double out_sum = 0.0;
 #pragma unroll
@@ -262,7 +262,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 // XCD, so the segments of one row (which share cache lines at their edges)
 // meet in one L2 while the liquid/gas split in z stays balanced over the
 // XCDs.
-template <class S>
+template <class S, bool GC>
 __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
                                            int b, int nblocks)
 {
@@ -299,11 +299,11 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
         seg(s + step, rowd, xd, fld);
         const bool la = (fla & T_MASK) == T_LIQ, lb = (flb & T_MASK) == T_LIQ;
         if (__ballot((la && (fla & F_NEAR_SOLID)) || (lb && (flb & F_NEAR_SOLID))) != 0) {
-            if (la) bulk_cell<S, true>(d, src, dst, xa, rowa, fla);
-            if (lb) bulk_cell<S, true>(d, src, dst, xb, rowb, flb);
+            if (la) bulk_cell<S, true, GC>(d, src, dst, xa, rowa, fla);
+            if (lb) bulk_cell<S, true, GC>(d, src, dst, xb, rowb, flb);
         } else if (__ballot(la || lb) != 0) {
-            if (la) bulk_cell<S, false>(d, src, dst, xa, rowa, fla);
-            if (lb) bulk_cell<S, false>(d, src, dst, xb, rowb, flb);
+            if (la) bulk_cell<S, false, GC>(d, src, dst, xa, rowa, fla);
+            if (lb) bulk_cell<S, false, GC>(d, src, dst, xb, rowb, flb);
         }
         rowa = rowc;
         xa = xc;
@@ -814,7 +814,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     }
 
     Et fo[27];
-    collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
+    collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, (d.variants & VAR_GALILEAN) != 0);
 
     double rs = 0.0;
 #pragma unroll
@@ -910,11 +910,12 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
         iface_cell<S, GI>(d, src, dst, list[t], epoch);
 }
 
-// Dense stream-collide over the liquid rows.
-template <class S>
+// Dense stream-collide over the liquid rows; GC: with the Galilean
+// correction of the collision.
+template <class S, bool GC>
 __global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
 {
-    dense_rows<S>(d, (const S *)d.pdf[p], (S *)d.pdf[p ^ 1], (int)blockIdx.x, (int)gridDim.x);
+    dense_rows<S, GC>(d, (const S *)d.pdf[p], (S *)d.pdf[p ^ 1], (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------- conversion
@@ -1272,7 +1273,10 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
     if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
     if (d.xcd_map) gb &= ~7;
     if (ev0) (void)hipEventRecord(ev0, st);
-    k_bulk<S><<<gb, BULK_THREADS, 0, st>>>(d, p);
+    if (d.variants & VAR_GALILEAN)
+        k_bulk<S, true><<<gb, BULK_THREADS, 0, st>>>(d, p);
+    else
+        k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
     if (d.variants & VAR_FLUX_MODIFIERS) k_classes<<<list_blocks, LIST_THREADS, 0, st>>>(d, p);
     if (mlpP)

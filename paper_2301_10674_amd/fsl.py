@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfsl.so")
 FSL_OK, FSL_ERR_ARG, FSL_ERR_STATE, FSL_ERR_DEVICE, FSL_ERR_NOMEM, FSL_ERR_UNSTABLE = range(6)
 FP64, FP32, FP16_STORE = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORE}
-FSL_VAR_FLUX_MODIFIERS, FSL_VAR_NORMAL_EXCESS, FSL_VAR_CSF_CURVATURE = 1, 2, 4   # FslParams.variants bits
+FSL_VAR_FLUX_MODIFIERS, FSL_VAR_NORMAL_EXCESS, FSL_VAR_CSF_CURVATURE, FSL_VAR_GALILEAN = 1, 2, 4, 8  # variants bits
 (FIELD_TYPE, FIELD_MASS, FIELD_FILL, FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_NORMAL,
  FIELD_CURV, FIELD_OWNER) = range(9)
 NFIELDS = 9
@@ -73,7 +73,8 @@ class FslTrainParams(ctypes.Structure):
 
 def make_params(shape, precision="fp64", omega=1.0, accel=(0.0, 0.0, 0.0), sigma=0.0,
                 rho_gas=1.0, conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
-                normals=0, check_every=0, flux_modifiers=False, normal_excess=False, csf_curvature=False):
+                normals=0, check_every=0, flux_modifiers=False, normal_excess=False, csf_curvature=False,
+                galilean=False):
     p = FslParams()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -85,7 +86,8 @@ def make_params(shape, precision="fp64", omega=1.0, accel=(0.0, 0.0, 0.0), sigma
     p.rule_isolated = 1 if rule_isolated else 0
     p.normals, p.check_every = int(normals), int(check_every)
     p.variants = (FSL_VAR_FLUX_MODIFIERS if flux_modifiers else 0) | \
-        (FSL_VAR_NORMAL_EXCESS if normal_excess else 0) | (FSL_VAR_CSF_CURVATURE if csf_curvature else 0)
+        (FSL_VAR_NORMAL_EXCESS if normal_excess else 0) | (FSL_VAR_CSF_CURVATURE if csf_curvature else 0) | \
+        (FSL_VAR_GALILEAN if galilean else 0)
     return p
 
 

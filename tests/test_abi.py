@@ -58,7 +58,10 @@ def test_variant_bits(lib):
     p = F.make_params((16, 8, 8), "fp32", omega=1.5, flux_modifiers=True, normal_excess=True)
     assert p.variants == F.FSL_VAR_FLUX_MODIFIERS | F.FSL_VAR_NORMAL_EXCESS
     assert F.workspace_bytes(p) > 0
-    p.variants = 8
+    p = F.make_params((16, 8, 8), "fp32", omega=1.5, galilean=True)
+    assert p.variants == F.FSL_VAR_GALILEAN == 8
+    assert F.workspace_bytes(p) > 0
+    p.variants = 16
     assert F.workspace_bytes(p) == 0
     assert "variant" in lib.fsl_last_error().decode()
     p = F.make_params((16, 8, 8), "fp32", omega=1.5, csf_curvature=True, normals=1)
