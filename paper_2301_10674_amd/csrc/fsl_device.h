@@ -140,7 +140,7 @@ __device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
 // rate omega, bulk and all higher-order rates 1) on PDF deviations
 // d_i = f_i - w_i, in place.  g is the body acceleration: the velocity is
 // shifted by F/(2 rho) and the first-order central moments leave the
-// collision as +F/(2 rho) = g/2.  gc adds the Galilean-invariance
+// collision as +F/(2 rho) = g/2.  GC adds the Galilean-invariance
 // correction of the same paper (a variant): the lattice lacks the cubic
 // velocity moments, which puts 3 u_a^2 d_a u_a into the normal stresses;
 // the relaxed diagonal second-order cumulants lose 3 (1 - w/2) u_a^2 d_a u_a
@@ -153,8 +153,8 @@ __device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
 // rho, the momentum and the second moments of the input matter.  Everything
 // is carried as a deviation from the rest state (rho = 1, u = 0, K = I/3) so
 // FP32 keeps the small quantities exact enough.
-template <class R, class E>
-__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27], bool gc = false)
+template <class R, class E, bool GC = false>
+__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27])
 {
     // Raw moments of the deviations, passes x, y, z of (sum, odd, even), in
     // FP64 in every form: the non-equilibrium second moments are small
@@ -211,7 +211,7 @@ __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz
     const R om1 = R(1) - omega;
     const R tr3 = (Kxx + Kyy + Kzz) * third;
     R ax = om1 * (Kxx - tr3), ay = om1 * (Kyy - tr3), az = om1 * (Kzz - tr3);
-    if (gc) {
+    if constexpr (GC) {
         // first-order non-equilibrium K = -(2/(3 w)) x strain rate, solved
         // for the normal strain rates from the deviator (w = omega) and the
         // trace (w = 1); the correction enters as a source with (1 - w/2)

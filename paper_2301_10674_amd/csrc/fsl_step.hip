@@ -242,7 +242,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 
     using E = typename Eq<S>::type;
     E fo[27];
-    collide<R, E>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, GC);
+    collide<R, E, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
 
     double out_sum = 0.0;
 #pragma unroll
@@ -664,7 +664,7 @@ __device__ __forceinline__ uint32_t fm_rank(uint32_t f)
     return 1u + ((f >> 6) & 1u) - ((f >> 5) & 1u);
 }
 
-template <class S, bool GI>
+template <class S, bool GI, bool GC>
 __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
                                            int c, uint32_t epoch)
 {
@@ -814,7 +814,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     }
 
     Et fo[27];
-    collide<R, Et>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, (d.variants & VAR_GALILEAN) != 0);
+    collide<R, Et, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
 
     double rs = 0.0;
 #pragma unroll
@@ -894,8 +894,10 @@ __global__ __launch_bounds__(LIST_THREADS) void k_classes(Dev d, int p)
 }
 
 // Interface list of the step (one cell per thread).  Block 0 starts the
-// next list and the new-cell list empty.
-template <class S, bool GI>
+// next list and the new-cell list empty.  GC: with the Galilean correction
+// of the collision (a compile-time flag, as in the dense kernel, so that the
+// instance without it keeps its own code).
+template <class S, bool GI, bool GC>
 __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t epoch)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -907,7 +909,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
     const int32_t *list = d.list[p];
     const int count = d.cnt[p];
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x)
-        iface_cell<S, GI>(d, src, dst, list[t], epoch);
+        iface_cell<S, GI, GC>(d, src, dst, list[t], epoch);
 }
 
 // Dense stream-collide over the liquid rows; GC: with the Galilean
@@ -1279,10 +1281,15 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
         k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
     if (d.variants & VAR_FLUX_MODIFIERS) k_classes<<<list_blocks, LIST_THREADS, 0, st>>>(d, p);
-    if (mlpP)
-        k_iface<S, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    const bool gc = (d.variants & VAR_GALILEAN) != 0;
+    if (mlpP && gc)
+        k_iface<S, false, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    else if (mlpP)
+        k_iface<S, false, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    else if (gc)
+        k_iface<S, true, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     else
-        k_iface<S, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+        k_iface<S, true, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv23<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv4<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
