@@ -259,11 +259,10 @@ def run_form(w, form, steps, warmup, main_form=None):
 
     precision, learned = form.split("-")[0], form.endswith("-learned")
     # "-variants": Thuerey's flux modifiers and normal-weighted excess mass,
-    # curvature from corner normals, Galilean correction of the collision
+    # curvature from corner normals
     variants = form.endswith("-variants")
     lat = fsl.lattice_from_workload(w, precision, normals=1 if learned else 0,
-                                    flux_modifiers=variants, normal_excess=variants, csf_curvature=variants,
-                                    galilean=variants)
+                                    flux_modifiers=variants, normal_excess=variants, csf_curvature=variants)
     est = None
     if learned:
         weights, est = learned_weights(lat, fsl)
@@ -389,8 +388,7 @@ def main():
     ap.add_argument("--forms", default="fp16,fp64,fp32-learned,fp32-variants",
                     help="other forms timed on the same workload ('' for none): fp16, fp64, fp32, "
                          "fp32-learned (estimator trained in the run, see train.py), "
-                         "fp32-variants (flux modifiers, normal-weighted excess mass, corner-normal curvature, "
-                         "Galilean correction)")
+                         "fp32-variants (flux modifiers, normal-weighted excess mass, corner-normal curvature)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 counter runs of this command and exit")

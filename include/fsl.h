@@ -107,7 +107,9 @@ typedef struct {
  *     diagonal second-order cumulants lose 3 (1 - w/2) u_a^2 d_a u_a
  *     (w = omega for the deviator, 1 for the trace), the strain rates d_a u_a
  *     estimated from the cell's non-equilibrium second-order cumulants.
- *     Applies to every fluid cell (liquid and interface).
+ *     Applies to every fluid cell (liquid and interface).  Currently
+ *     rejected with FSL_ERR_ARG: the corrected step loses an excess-mass
+ *     share on lattices three cells high, so it is switched off.
  * Unknown bits make fsl_create_lattice fail with FSL_ERR_ARG. */
 enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2, FSL_VAR_CSF_CURVATURE = 4, FSL_VAR_GALILEAN = 8 };
 

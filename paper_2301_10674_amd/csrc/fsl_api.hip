@@ -109,6 +109,11 @@ static bool params_ok(const FslParams *p, std::string &why)
         why = "unknown variant bits";
         return false;
     }
+    if (p->variants & FSL_VAR_GALILEAN) {
+        why = "the Galilean-corrected step is switched off: on lattices three cells high its interface "
+              "kernel loses excess mass that the filled cells share out";
+        return false;
+    }
     if ((p->variants & FSL_VAR_CSF_CURVATURE) && p->normals != 0) {
         why = "the corner-normal curvature variant needs the finite-difference estimator (normals = 0)";
         return false;

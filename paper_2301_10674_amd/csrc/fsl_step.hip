@@ -1275,19 +1275,14 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream
     if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
     if (d.xcd_map) gb &= ~7;
     if (ev0) (void)hipEventRecord(ev0, st);
-    if (d.variants & VAR_GALILEAN)
-        k_bulk<S, true><<<gb, BULK_THREADS, 0, st>>>(d, p);
-    else
-        k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p);
+    // the Galilean-corrected instances (GC = true) are not launched: the
+    // lattice parameters reject that variant (its interface kernel loses an
+    // excess-mass share on lattices three cells high)
+    k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
     if (d.variants & VAR_FLUX_MODIFIERS) k_classes<<<list_blocks, LIST_THREADS, 0, st>>>(d, p);
-    const bool gc = (d.variants & VAR_GALILEAN) != 0;
-    if (mlpP && gc)
-        k_iface<S, false, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    else if (mlpP)
+    if (mlpP)
         k_iface<S, false, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    else if (gc)
-        k_iface<S, true, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     else
         k_iface<S, true, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
