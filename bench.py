@@ -39,7 +39,7 @@ STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 COPY_BYTES = 1 << 30          # the calibration copy: 1 GiB read + 1 GiB written
 BULK_SOURCES = ["paper_2301_10674_amd/csrc/fsl_step.hip", "paper_2301_10674_amd/csrc/fsl_device.h",
                 "paper_2301_10674_amd/csrc/fsl_kernels.h"]
-KERNEL_NAMES = {"fp32": "k_bulk<float>", "fp64": "k_bulk<double>", "fp16": "k_bulkIDF16_"}
+KERNEL_NAMES = {"fp32": "k_bulk<float, false>", "fp64": "k_bulk<double, false>", "fp16": "k_bulkIDF16_Lb0E"}
 
 
 def bulk_source_hash():
