@@ -191,3 +191,30 @@ def test_galilean_correction_in_a_fast_channel(prec, tol):
     rel = np.sqrt((d ** 2).sum() / (out[False][F().FIELD_VEL] ** 2).sum())
     print("the correction changes the velocity by %.3e relative" % rel)
     assert rel > 50 * tol
+
+
+@pytest.mark.parametrize("shape,h", [((3, 3, 3), 1.6), ((6, 3, 3), 1.6), ((3, 3, 5), 2.6)])
+def test_tiny_lattices_default_model_fp64(shape, h):
+    """The default model on lattices three and five cells high with x and y
+    periods of 3 and 6, where every cell neighbours every cell of the next
+    row: the conversions cascade (one filled cell turns the whole gas row
+    into interface cells) and the excess mass of filled cells is shared by
+    a whole row; every field element by element after 20 steps."""
+    nx, ny, nz = shape
+    xc = np.arange(nx) + 0.5
+    hh = h + 0.7 * np.sin(2 * np.pi * xc / nx)
+    fill = I.height_fill(shape, np.broadcast_to(hh[None, :], (ny, nx)))
+    rng = np.random.default_rng(5)
+    w = I.Workload(name="tiny", shape=shape, omega=1.3, accel=(1e-4, 0, -1e-4), sigma=1e-3,
+                   fill=fill, rho=np.ones((nz, ny, nx)), vel=0.01 * rng.standard_normal((3, nz, ny, nx)),
+                   centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+                   sphere_angvel=np.zeros((0, 3)))
+    g, o = pair(w, "fp64", {})
+    M0 = o.total_mass()
+    for k in range(4):
+        g.step(5)
+        o.step(5)
+        assert_fp64_parity(gpu_fields(g), oracle_fields(o), 1e-12, "%s after %d steps" % (shape, 5 * (k + 1)))
+    assert np.array_equal(g.counters()[:7], o.counters()[:7])
+    assert abs(g.total_mass() - M0) <= 1e-12 * M0
+    g.destroy()
