@@ -50,7 +50,8 @@ typedef enum {
     FSL_ERR_STATE = 2,     /* call not allowed in the lattice's current state */
     FSL_ERR_DEVICE = 3,    /* a HIP runtime call failed */
     FSL_ERR_NOMEM = 4,     /* workspace too small, or an internal allocation failed */
-    FSL_ERR_UNSTABLE = 5   /* watchdog: total mass became non-finite */
+    FSL_ERR_UNSTABLE = 5   /* watchdog: total mass non-finite or drifted, or a
+                              density outside [0.5, 1.5] (see fsl_step) */
 } FslStatus;
 
 /* Storage precision of the PDFs.  Mass, fill level, excess mass and the
@@ -78,7 +79,7 @@ typedef struct {
                                neighbours to liquid (gas) */
     int32_t normals;        /* 0: finite-difference normal and curvature,
                                1: learned estimator with finite-difference fallback */
-    int32_t check_every;    /* watchdog interval in steps (0: never) */
+    int32_t check_every;    /* watchdog interval in steps (0: never; see fsl_step) */
     int32_t variants;       /* FSL_VAR_* bits; 0 is the model of Section 2.1
                                as the cited FSLBM and collision define it */
 } FslParams;
@@ -107,9 +108,7 @@ typedef struct {
  *     diagonal second-order cumulants lose 3 (1 - w/2) u_a^2 d_a u_a
  *     (w = omega for the deviator, 1 for the trace), the strain rates d_a u_a
  *     estimated from the cell's non-equilibrium second-order cumulants.
- *     Applies to every fluid cell (liquid and interface).  Currently
- *     rejected with FSL_ERR_ARG: the corrected step loses an excess-mass
- *     share on lattices three cells high, so it is switched off.
+ *     Applies to every fluid cell (liquid and interface).
  * Unknown bits make fsl_create_lattice fail with FSL_ERR_ARG. */
 enum { FSL_VAR_FLUX_MODIFIERS = 1, FSL_VAR_NORMAL_EXCESS = 2, FSL_VAR_CSF_CURVATURE = 4, FSL_VAR_GALILEAN = 8 };
 
@@ -126,7 +125,15 @@ enum {
     FSL_FIELD_NORMAL = 6,   /* double [3n]: interface normal, liquid -> gas */
     FSL_FIELD_CURV = 7,     /* double [n]: mean curvature (interface cells) */
     FSL_FIELD_OWNER = 8,    /* int32 [n]: owning sphere of a solid cell, -1 otherwise */
-    FSL_NFIELDS = 9
+    FSL_FIELD_ESTIMATOR = 9,/* uint8 [n]: outcome of the learned estimator for the
+                               current geometry of each interface cell: 1 the corrected
+                               estimate is used; finite differences kept because
+                               2 a neighbour is solid or beyond a wall, 3 |n_raw| lies
+                               outside [0.5, 2], 4 the angle to the finite-difference
+                               normal exceeds 30 degrees, 5 |kappa| > 0.5 (the first
+                               that holds, see fsl_set_estimator); 0 for other cells and
+                               when no network is attached */
+    FSL_NFIELDS = 10
 };
 
 /* Bytes of device workspace the lattice needs (0 for invalid params). */
@@ -167,15 +174,40 @@ FslStatus fsl_set_particles(FslLattice *lat, int32_t n, const double *centre,
                             const double *radius, const double *vel,
                             const double *angvel);
 
-/* Advance nsteps time steps (asynchronous on the lattice's stream).
- * Returns FSL_ERR_UNSTABLE if the watchdog (every check_every steps) finds a
- * non-finite total mass; the state then stays readable. */
+/* Advance nsteps time steps (asynchronous on the lattice's stream).  One
+ * step is the fluid update of Section 2.1 (pull streaming with bounce-back,
+ * gas-side reconstruction, mass flux, cumulant collision), then interface
+ * conversion with excess-mass redistribution and the interface geometry.
+ * Watchdog: on every check_every-th step the step kernels also reduce, per
+ * block and then in one fixed-order pass, the total mass (liquid and
+ * interface mass before the step's conversions, which only move mass, plus
+ * the excess-mass pool) and the range of the fluid cells' densities; the
+ * step then synchronises and returns FSL_ERR_UNSTABLE when the mass is not
+ * finite, when some density lies outside [0.5, 1.5] (or is not a number), or
+ * when the mass differs from the reference mass (the exact total of
+ * fsl_total_mass() after fsl_create_lattice() or fsl_set_particles()) by
+ * more than 1e-10 relative.  The state then stays readable and
+ * fsl_watchdog() gives the values found.  Steps without a check do not
+ * synchronise. */
 FslStatus fsl_step(FslLattice *lat, int32_t nsteps);
 
-/* Copy fields out.  dst[k] is the destination of field k when bit k of
- * field_mask is set (entries of unselected fields are ignored).  dst points
- * to host memory, or to device memory when dst_on_device != 0.  Synchronises
- * the lattice's stream. */
+/* Values of the last watchdog check (zeros before the first): out[0] total
+ * mass, out[1] reference mass, out[2] lowest and out[3] highest fluid
+ * density, out[4] number of fluid cells with a density outside [0.5, 1.5].
+ * Host memory; no device work.  FSL_ERR_STATE for a NULL lattice,
+ * FSL_ERR_ARG for a NULL out. */
+FslStatus fsl_watchdog(FslLattice *lat, double out[5]);
+
+/* Copy fields out (the state after the last step; Section 2.1's fluid
+ * fields plus the free-surface bookkeeping).  dst[k] is the destination of
+ * field k when bit k of field_mask is set (entries of unselected fields are
+ * ignored); sizes and types per field are listed with FSL_FIELD_*.  dst
+ * points to host memory, or to device memory when dst_on_device != 0.  Host
+ * output is staged on the device: in a buffer of 24 bytes per cell that the
+ * lattice allocates on first need and keeps until fsl_destroy(), and for
+ * FSL_FIELD_PDF in a temporary one.  FSL_ERR_ARG for NULL destinations,
+ * FSL_ERR_DEVICE for a failed copy or allocation.  Synchronises the
+ * lattice's stream. */
 FslStatus fsl_read_fields(FslLattice *lat, uint32_t field_mask, void *const *dst,
                           int32_t dst_on_device);
 
@@ -249,12 +281,18 @@ FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n,
  * network is compared with and falls back to. */
 FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream);
 
-/* Attach trained weights to a lattice.  With params.normals == 1 the
- * geometry of every interface cell then comes from the corrected estimate,
- * except where a stencil cell is solid, |n_fd + y[0..2]| is outside
- * [0.5, 2], the corrected normal differs from the finite-difference one by
- * more than 30 degrees, or |kappa| > 0.5: there the finite-difference
- * estimate is kept. */
+/* Attach trained weights to a lattice (weights: 6212 host floats, copied;
+ * the first call allocates the weights and their BF16 copies with hipMalloc,
+ * kept until fsl_destroy).  With params.normals == 1 the geometry of every
+ * interface cell, the current ones included, then comes from the corrected
+ * estimate, except where (rules checked in this order) 1. a neighbour is
+ * solid or beyond a wall, 2. |n_fd + y[0..2]| is outside [0.5, 2], 3. the
+ * corrected normal differs from the finite-difference one by more than 30
+ * degrees, or 4. |kappa| > 0.5: there the finite-difference estimate is kept
+ * (FSL_FIELD_ESTIMATOR reports which).  The network stands in for the
+ * curvature estimate of the Laplace pressure 2 sigma kappa (Section 2.1);
+ * the paper names no estimator.  FSL_ERR_ARG for NULL or non-finite
+ * weights; synchronises the lattice's stream. */
 FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
 
 /* Move the spheres of fsl_set_particles() to new centres with new

@@ -384,6 +384,9 @@ struct OlLattice {
     int32_t *owner;
     double *n, *kappa;
     double *share;    /* excess share of a converted cell */
+    double *est_P;    /* learned estimator weights (NULL: finite differences only) */
+    uint8_t *est_rule;  /* per interface cell: 1 + the rule of ol_estimator_compose */
+    double *est_q;    /* per cell: |n_raw|, angle (degrees), composed kappa */
     int32_t nsph;
     double *sph;      /* per sphere: X[3], r, U[3], Omega[3] */
     double pool;
@@ -513,6 +516,18 @@ static void geometry_cell(OlLattice *L, int64_t c)
     double centre = clamp01(L->phi[c]);
     for (int i = 0; i < Q; ++i)
         st27[i] = (i == REST) ? centre : stencil_phi(L, nbr(L, c, i, +1), centre);
+    if (L->est_P) {
+        /* learned estimator with its finite-difference fallback (O18) */
+        int32_t solid_nb = 0;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            int64_t y = nbr(L, c, i, +1);
+            if (y < 0 || L->type[y] == OL_SOLID) solid_nb = 1;
+        }
+        L->est_rule[c] = (uint8_t)(1 + ol_estimator_compose(L->est_P, st27, solid_nb, &L->n[3 * c],
+                                                            &L->kappa[c], &L->est_q[3 * c]));
+        return;
+    }
     ol_normal_curvature(st27, &L->n[3 * c], &L->kappa[c]);
     if (L->p.variants & OL_VAR_CSF_CURVATURE) ol_csf_curvature(st27, &L->kappa[c]);
 }
@@ -526,6 +541,10 @@ static void phase_geometry(OlLattice *L)
         } else {
             L->n[3 * c] = L->n[3 * c + 1] = L->n[3 * c + 2] = 0.0;
             L->kappa[c] = 0.0;
+            if (L->est_P) {
+                L->est_rule[c] = 0;
+                L->est_q[3 * c] = L->est_q[3 * c + 1] = L->est_q[3 * c + 2] = 0.0;
+            }
         }
     }
 }
@@ -635,7 +654,7 @@ void ol_destroy(OlLattice *L)
     if (!L) return;
     free(L->f); free(L->m); free(L->phi); free(L->rho); free(L->type);
     free(L->mark); free(L->owner); free(L->n); free(L->kappa); free(L->share);
-    free(L->sph);
+    free(L->sph); free(L->est_P); free(L->est_rule); free(L->est_q);
     free(L);
 }
 
@@ -1032,6 +1051,24 @@ void ol_step(OlLattice *L, int32_t nsteps)
     }
 }
 
+void ol_set_estimator(OlLattice *L, const double *P)
+{
+    free(L->est_P);
+    free(L->est_rule);
+    free(L->est_q);
+    L->est_P = NULL;
+    L->est_rule = NULL;
+    L->est_q = NULL;
+    if (P) {
+        const int32_t np = ol_mlp_nparam();
+        L->est_P = (double *)malloc((size_t)np * sizeof(double));
+        memcpy(L->est_P, P, (size_t)np * sizeof(double));
+        L->est_rule = (uint8_t *)calloc((size_t)L->N, 1);
+        L->est_q = (double *)calloc((size_t)L->N * 3, sizeof(double));
+    }
+    phase_geometry(L);
+}
+
 void ol_read(const OlLattice *L, int32_t field, void *dst)
 {
     const int64_t N = L->N;
@@ -1068,6 +1105,16 @@ void ol_read(const OlLattice *L, int32_t field, void *dst)
     case OL_F_CURV: memcpy(dst, L->kappa, (size_t)N * sizeof(double)); break;
     case OL_F_OWNER: memcpy(dst, L->owner, (size_t)N * sizeof(int32_t)); break;
     case OL_F_MARKS: memcpy(dst, L->mark, (size_t)N); break;
+    case OL_F_EST_RULE:
+        if (L->est_rule) memcpy(dst, L->est_rule, (size_t)N);
+        else memset(dst, 0, (size_t)N);
+        break;
+    case OL_F_EST_Q: {
+        double *o = (double *)dst;
+        for (int64_t c = 0; c < N; ++c)
+            for (int d = 0; d < 3; ++d) o[d * N + c] = L->est_q ? L->est_q[3 * c + d] : 0.0;
+        break;
+    }
     default: break;
     }
 }

@@ -93,6 +93,20 @@ void ol_normal_curvature(const double phi[27], double n[3], double *kappa);
 /* curvature of the same stencil as half the divergence of corner normals */
 void ol_csf_curvature(const double phi[27], double *kappa);
 
+/* --- learned estimator (mlp_oracle.c) -------------------------------------- */
+/* number of network parameters (6212) */
+int32_t ol_mlp_nparam(void);
+/* the estimator as the lattice uses it (reading O18: the network output y
+ * corrects the finite-difference estimate of the same stencil, n_raw = n_fd +
+ * y[0..2], kappa = kappa_fd + y[3]/4, with a per-cell fallback to finite
+ * differences).  phi: the fill stencil in direction order; solid_nb: a
+ * neighbour is solid or beyond a wall.  Returns 0 when the corrected
+ * estimate is used, else the first rule that keeps finite differences:
+ * 1 solid neighbour, 2 |n_raw| outside [0.5, 2], 3 angle to n_fd above 30
+ * degrees, 4 |kappa| > 0.5.  q (may be NULL): |n_raw|, angle, kappa. */
+int32_t ol_estimator_compose(const double *P, const double phi[27], int32_t solid_nb, double n[3],
+                             double *kappa, double q[3]);
+
 /* --- lattice -------------------------------------------------------------- */
 /* fill, rho: nx*ny*nz values; vel: 3*nx*ny*nz values (component-major:
  * vel[d*N + cell]) or NULL for rest.  Returns NULL on bad arguments. */
@@ -109,6 +123,10 @@ int ol_set_particles(OlLattice *L, int32_t n, const double *centre,
  * type[N], m[N], f[N*27] (cell-major), normal[N*3] may be NULL -> recomputed */
 void ol_set_state(OlLattice *L, const uint8_t *type, const double *m,
                   const double *f);
+/* attach network weights (ol_mlp_nparam() doubles, copied; NULL: back to
+ * finite differences): from now on the geometry of every interface cell,
+ * including the current ones, comes from ol_estimator_compose */
+void ol_set_estimator(OlLattice *L, const double *P);
 /* full time steps */
 void ol_step(OlLattice *L, int32_t nsteps);
 /* one phase of the step, for unit tests:
@@ -127,7 +145,12 @@ enum {
     OL_F_NORMAL = 6, /* double [3*N] component-major */
     OL_F_CURV = 7,   /* double [N] */
     OL_F_OWNER = 8,  /* int32 [N], -1 if not inside a sphere */
-    OL_F_MARKS = 9   /* uint8 [N], conversion marks of the last phase 2/3 */
+    OL_F_MARKS = 9,  /* uint8 [N], conversion marks of the last phase 2/3 */
+    OL_F_EST_RULE = 10,  /* uint8 [N], learned estimator: 0 not an interface cell (or no
+                            estimator), 1 corrected estimate used, 2..5 finite differences
+                            kept by rule 1..4 of ol_estimator_compose */
+    OL_F_EST_Q = 11      /* double [3*N] component-major: |n_raw|, angle to n_fd in
+                            degrees, composed kappa (learned estimator, interface cells) */
 };
 void ol_read(const OlLattice *L, int32_t field, void *dst);
 double ol_total_mass(const OlLattice *L);   /* sum of m over liquid+interface cells + pool */

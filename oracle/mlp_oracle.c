@@ -15,15 +15,18 @@
  * Layout of the flat parameter vector (double, 6212 entries):
  *   W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
  * Input x_k = clamp(phi_k, 0, 1) - 1/2 in direction order (k = a+3b+9c for
- * the offset (a-1, b-1, c-1)).  Output y[0..2] is the normal (trained
- * towards the unit normal, normalised when used), y[3] is 4 * kappa.  Loss
- * per sample: |y[0..2] - n*|^2 + (y[3] - 4 kappa*)^2, averaged over the
- * batch.
+ * the offset (a-1, b-1, c-1)).  Loss per sample against a target t:
+ * |y[0..2] - t[0..2]|^2 + (y[3] - 4 t[3])^2, averaged over the batch.  In a
+ * lattice the outputs correct the finite-difference estimate of the same
+ * stencil (ol_estimator_compose), so the targets are t = (n* - n_fd,
+ * kappa* - kappa_fd).
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include "fsl_oracle.h"
 
 #define NIN 27
 #define NH 64
@@ -118,4 +121,56 @@ void ol_mlp_adam(double *P, double *m, double *v, const double *g, int64_t t, do
         v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
         P[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
     }
+}
+
+/* The estimator as a lattice uses it (O18, a reading: the paper needs the
+ * curvature only in the Laplace pressure 2 sigma kappa of Section 2.1 and
+ * names no estimator).  phi is the interface cell's 3x3x3 fill stencil as the
+ * lattice builds it (liquid 1, gas 0, interface clamp(m/rho), solid or wall
+ * the centre value); solid_nb says whether any of its 26 neighbours is solid
+ * or lies beyond a wall.  In order:
+ *   1. the finite-difference estimate (n_fd, kappa_fd) of the stencil;
+ *   2. the network outputs y for the input phi - 1/2;
+ *   3. n_raw = n_fd + y[0..2] and kappa = kappa_fd + y[3]/4;
+ *   4. the finite-difference estimate is kept when the first of these holds:
+ *      (1) a neighbour is solid, (2) |n_raw| lies outside [0.5, 2], (3) n_raw
+ *      makes an angle of more than 30 degrees with n_fd, (4) |kappa| > 0.5;
+ *      otherwise n = n_raw/|n_raw| with the composed kappa.
+ * Returns 0 when the corrected estimate is used, else the number of the rule
+ * that kept finite differences.  q (may be NULL) receives |n_raw|, the angle
+ * in degrees and the composed kappa, whichever rule decided. */
+int32_t ol_estimator_compose(const double *P, const double phi[27], int32_t solid_nb, double n[3],
+                             double *kappa, double q[3])
+{
+    double nfd[3], kfd, x[NIN], h1[NH], h2[NH], y[NOUT];
+    ol_normal_curvature(phi, nfd, &kfd);
+    for (int k = 0; k < NIN; ++k) x[k] = phi[k] - 0.5;
+    forward_one(P, x, h1, h2, y);
+    double nr[3] = {nfd[0] + y[0], nfd[1] + y[1], nfd[2] + y[2]};
+    const double rn = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+    const double kap = kfd + 0.25 * y[3];
+    /* n_fd is a unit vector or zero (vanishing gradient: the angle is then
+     * taken as 90 degrees) */
+    double cosang = rn > 0.0 ? (nfd[0] * nr[0] + nfd[1] * nr[1] + nfd[2] * nr[2]) / rn : 0.0;
+    if (cosang > 1.0) cosang = 1.0;
+    if (cosang < -1.0) cosang = -1.0;
+    const double angle = acos(cosang) * (180.0 / 3.14159265358979323846);
+    if (q) {
+        q[0] = rn;
+        q[1] = angle;
+        q[2] = kap;
+    }
+    int32_t rule = 0;
+    if (solid_nb) rule = 1;
+    else if (rn < 0.5 || rn > 2.0) rule = 2;
+    else if (angle > 30.0) rule = 3;
+    else if (fabs(kap) > 0.5) rule = 4;
+    if (rule) {
+        for (int d = 0; d < 3; ++d) n[d] = nfd[d];
+        *kappa = kfd;
+    } else {
+        for (int d = 0; d < 3; ++d) n[d] = nr[d] / rn;
+        *kappa = kap;
+    }
+    return rule;
 }

@@ -23,7 +23,11 @@ HDR = os.path.join(HERE, "fsl_oracle.h")
 LIB = os.path.join(HERE, "liboracle.so")
 
 GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
-F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS = range(10)
+F_TYPE, F_MASS, F_FILL, F_RHO, F_VEL, F_PDF, F_NORMAL, F_CURV, F_OWNER, F_MARKS, F_EST_RULE, F_EST_Q = range(12)
+# learned estimator, per interface cell: 1 the corrected estimate is used; 2..5 finite
+# differences kept by a solid neighbour, |n_raw| outside [0.5, 2], an angle above 30
+# degrees, |kappa| > 0.5 (0 elsewhere)
+EST_NETWORK, EST_SOLID, EST_NORM, EST_ANGLE, EST_KAPPA = 1, 2, 3, 4, 5
 VAR_FLUX_MODIFIERS, VAR_NORMAL_EXCESS, VAR_CSF_CURVATURE, VAR_GALILEAN = 1, 2, 4, 8
 
 
@@ -111,6 +115,9 @@ def lib():
         L.ol_mlp_loss_grad.argtypes = [dp, ctypes.c_int32, dp, dp, dp]
         L.ol_mlp_adam.argtypes = [dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.ol_estimator_compose.restype = ctypes.c_int32
+        L.ol_estimator_compose.argtypes = [dp, dp, ctypes.c_int32, dp, dp, dp]
+        L.ol_set_estimator.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.ol_dem_create.restype = ctypes.c_void_p
         L.ol_dem_create.argtypes = [ctypes.POINTER(_DemParams), ctypes.c_int32, dp, dp, dp, dp, ctypes.c_void_p]
         L.ol_dem_destroy.argtypes = [ctypes.c_void_p]
@@ -249,6 +256,17 @@ class OracleLattice:
         assert t.size == self.N and m.size == self.N and f.size == 27 * self.N
         lib().ol_set_state(self.h, t.ctypes.data, _dp(m), _dp(f))
 
+    def set_estimator(self, params):
+        """Learned estimator with finite-difference fallback for the geometry
+        of every interface cell from now on (params: 6212 values; None: finite
+        differences only).  The current interface cells are re-evaluated."""
+        if params is None:
+            lib().ol_set_estimator(self.h, None)
+            return
+        self._est = _f64(params).reshape(-1)
+        assert self._est.size == mlp_nparam()
+        lib().ol_set_estimator(self.h, self._est.ctypes.data)
+
     def step(self, n=1):
         lib().ol_step(self.h, int(n))
 
@@ -258,18 +276,18 @@ class OracleLattice:
     def read(self, field):
         nx, ny, nz = self.shape
         N = self.N
-        if field in (F_TYPE, F_MARKS):
+        if field in (F_TYPE, F_MARKS, F_EST_RULE):
             out = np.zeros(N, dtype=np.uint8)
         elif field == F_OWNER:
             out = np.zeros(N, dtype=np.int32)
-        elif field in (F_VEL, F_NORMAL):
+        elif field in (F_VEL, F_NORMAL, F_EST_Q):
             out = np.zeros(3 * N)
         elif field == F_PDF:
             out = np.zeros(27 * N)
         else:
             out = np.zeros(N)
         lib().ol_read(self.h, field, out.ctypes.data)
-        if field in (F_VEL, F_NORMAL):
+        if field in (F_VEL, F_NORMAL, F_EST_Q):
             return out.reshape(3, nz, ny, nx)
         if field == F_PDF:
             return out.reshape(27, nz, ny, nx)
@@ -455,3 +473,19 @@ class OracleDem:
     def bedload(self):
         """bedload transport rate q_b of Eq. (1)"""
         return lib().ol_dem_bedload(self.h)
+
+
+def estimator_compose(params, phi27, solid_nb=False):
+    """The learned estimator as a lattice applies it to one fill stencil
+    (phi27 in direction order; solid_nb: a neighbour is solid or beyond a
+    wall): returns (normal, kappa, rule, q) with rule 0 when the corrected
+    estimate is used, else the first fallback rule (1 solid neighbour,
+    2 |n_raw| outside [0.5, 2], 3 angle above 30 degrees, 4 |kappa| > 0.5),
+    and q = (|n_raw|, angle in degrees, composed kappa)."""
+    p = _f64(params)
+    phi = _f64(phi27).reshape(27)
+    n = np.zeros(3)
+    k = np.zeros(1)
+    q = np.zeros(3)
+    rule = lib().ol_estimator_compose(_dp(p), _dp(phi), int(bool(solid_nb)), _dp(n), _dp(k), _dp(q))
+    return n, float(k[0]), int(rule), q

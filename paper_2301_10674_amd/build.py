@@ -3,10 +3,20 @@
 Run ``python -m paper_2301_10674_amd.build``; the library lands next to this
 file.  Every HIP source is compiled for gfx950 only, with packed-FP32
 instructions disabled.
+
+The compiler's per-kernel resource report (``-Rpass-analysis=kernel-
+resource-usage``) is kept in ``_build/kernel_resources.txt`` and checked:
+the build fails if any kernel needs a private (scratch) segment.  Every
+kernel of the library keeps its values in registers -- VGPRs, and AGPRs as
+the compiler's spill space, which needs no memory -- so a scratch segment
+means an array the compiler could not keep in registers (an index it could
+not resolve at compile time, or register pressure beyond the register file),
+which is a change to look at before it runs.
 """
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -21,7 +31,8 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",
-]
+    "-Rpass-analysis=kernel-resource-usage",
+] + os.environ.get("FSL_EXTRA_HIPCC", "").split()
 
 
 def hipcc():
@@ -31,17 +42,54 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+def kernel_resources(remarks: str) -> dict:
+    """{kernel: {field: value}} from the compiler's resource remarks."""
+    out, cur = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            out[cur] = {}
+            continue
+        m = re.search(r"remark:\s+(.+?): (\S+) \[-Rpass-analysis", line)
+        if m and cur:
+            out[cur][m.group(1).strip()] = m.group(2)
+    return out
+
+
+def check_resources(res: dict) -> list:
+    """Kernels that need a scratch segment."""
+    return [k for k, v in res.items() if v.get("ScratchSize [bytes/lane]", "0") != "0"]
+
+
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, table, bad = [], [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        msgs = "\n".join(l for l in r.stderr.splitlines()
+                         if "remark:" not in l and "packed-fp32-ops" not in l and l.strip()
+                         and not re.match(r"^\s*\d*\s*\|", l))
+        if msgs and (verbose or r.returncode):
+            print(msgs, file=sys.stderr, flush=True)
+        if r.returncode:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
+        res = kernel_resources(r.stderr)
+        for k, v in res.items():
+            table.append("%-14s %-70s VGPR %4s AGPR %4s VGPR-spill %3s scratch %4s occupancy %s" % (
+                src, k, v.get("VGPRs"), v.get("AGPRs"), v.get("VGPRs Spill"),
+                v.get("ScratchSize [bytes/lane]"), v.get("Occupancy [waves/SIMD]")))
+        bad += ["%s: %s" % (src, k) for k in check_resources(res)]
         objs.append(obj)
+    with open(os.path.join(objdir, "kernel_resources.txt"), "w") as fh:
+        fh.write("\n".join(table) + "\n")
+    if bad:
+        raise RuntimeError("kernels with a scratch (private) segment:\n  " + "\n  ".join(bad))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:

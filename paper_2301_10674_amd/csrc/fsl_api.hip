@@ -18,7 +18,7 @@
 
 namespace fsl {
 template <class S>
-void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream_t st,
+void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1, const float *mlpP, const uint16_t *mlpPk);
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
@@ -77,10 +77,16 @@ struct FslLattice {
     size_t mem_ent_off = 0;
     float *mlpP = nullptr;    // learned estimator: FP32 weights
     uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
+    void *read_buf = nullptr; // device staging of fields read to the host
+    size_t read_cap = 0;
     bool timing = false;
+    double mass_ref = 0.0;    // watchdog: total mass after set-up (fsl_total_mass)
+    double watch_last[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t ev_used = 0;
 };
+
+static FslStatus set_mass_ref(FslLattice *L);
 
 // ---------------------------------------------------------------- workspace
 static size_t store_bytes(int prec) { return prec == FSL_FP64 ? 8 : (prec == FSL_FP32 ? 4 : 2); }
@@ -109,11 +115,6 @@ static bool params_ok(const FslParams *p, std::string &why)
         why = "unknown variant bits";
         return false;
     }
-    if (p->variants & FSL_VAR_GALILEAN) {
-        why = "the Galilean-corrected step is switched off: on lattices three cells high its interface "
-              "kernel loses excess mass that the filled cells share out";
-        return false;
-    }
     if ((p->variants & FSL_VAR_CSF_CURVATURE) && p->normals != 0) {
         why = "the corner-normal curvature variant needs the finite-difference estimator (normals = 0)";
         return false;
@@ -122,7 +123,7 @@ static bool params_ok(const FslParams *p, std::string &why)
 }
 
 struct Layout {
-    size_t pdf[2], mq, phi, rho, share, poolc, geom, mark, owner, flags, smask, bbslot, list0, list1,
+    size_t pdf[2], mq, phi, rho, share, poolc, geom, mark, est, owner, flags, smask, bbslot, list0, list1,
         lnew, cnt, stats, partial, total;
 };
 
@@ -146,6 +147,7 @@ static Layout layout(const FslParams *p)
     L.poolc = take(8 * N);
     L.geom = take((p->precision == FSL_FP64 ? 32 : 16) * N);
     L.mark = take(4 * N);
+    L.est = take(N);
     L.owner = take(4 * N);
     L.flags = take(N + 4);
     L.smask = take(4 * N);
@@ -155,7 +157,7 @@ static Layout layout(const FslParams *p)
     L.lnew = take(4 * N);
     L.cnt = take(64);
     L.stats = take(8 * 16);
-    L.partial = take(8 * (5 * RED_BLOCKS + 8));
+    L.partial = take(8 * (5 * RED_BLOCKS + 8 + WD_SIZE));
     L.total = off;
     return L;
 }
@@ -172,6 +174,7 @@ __global__ void k_init(Dev d, const double *fill, const double *rho, const doubl
     d.flags[c] = ty;
     d.owner[c] = -1;
     d.mark[c] = 0;
+    d.est[c] = 0;
     d.share[c] = 0.0;
     d.poolc[c] = 0.0;
     const double cl = fl < 0.0 ? 0.0 : (fl > 1.0 ? 1.0 : fl);
@@ -688,6 +691,7 @@ __global__ void k_read(Dev d, int p, int field, void *out)
         break;
     }
     case FSL_FIELD_FILL: ((double *)out)[c] = ty == T_IF ? d.phi[c] : (ty == T_LIQ ? 1.0 : 0.0); break;
+    case FSL_FIELD_ESTIMATOR: ((uint8_t *)out)[c] = ty == T_IF ? d.est[c] : (uint8_t)0; break;
     case FSL_FIELD_RHO:
     case FSL_FIELD_VEL: {
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -854,11 +858,19 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     DISPATCH(L, run_refresh, L);
     k_zero_counts<<<1, 64, 0, L->st>>>(d, reset_stats ? 1 : 0);
     k_build_list<<<blocks_for(d.N), 256, 0, L->st>>>(d, L->parity);
+    // running pool total of the watchdog, exact after every rebuild
+    k_pool_partial<<<RED_BLOCKS, 256, 0, L->st>>>(d);
+    k_sum_partials<<<1, 256, 0, L->st>>>(d, RED_BLOCKS, (int)(d.wd - d.partial) + WD_POOL);
     launch_setup_links(d, L->st);
-    if (L->P.precision == FSL_FP64)
-        launch_geom<double>(d, L->parity, L->list_blocks, L->st);
-    else
-        launch_geom<float>(d, L->parity, L->list_blocks, L->st);
+    // the geometry of the rebuilt list, with the estimator the steps use
+    const bool learned = L->P.normals == 1 && L->mlpP;
+    if (L->P.precision == FSL_FP64) {
+        if (learned) launch_geom_mlp<double>(d, L->parity, L->list_blocks, L->mlpP, L->mlpPk, L->st);
+        else launch_geom<double>(d, L->parity, L->list_blocks, L->st);
+    } else {
+        if (learned) launch_geom_mlp<float>(d, L->parity, L->list_blocks, L->mlpP, L->mlpPk, L->st);
+        else launch_geom<float>(d, L->parity, L->list_blocks, L->st);
+    }
     HIP_TRY(hipGetLastError());
     int32_t nrec[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(nrec, d.cnt + 4, 8, hipMemcpyDeviceToHost, L->st));
@@ -1006,6 +1018,7 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.poolc = (double *)(base + lay.poolc);
     d.geom = base + lay.geom;
     d.mark = (uint32_t *)(base + lay.mark);
+    d.est = (uint8_t *)(base + lay.est);
     d.owner = (int32_t *)(base + lay.owner);
     d.flags = (uint8_t *)(base + lay.flags);
     d.smask = (uint32_t *)(base + lay.smask);
@@ -1020,6 +1033,7 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.cnt = (int32_t *)(base + lay.cnt);
     d.stats = (unsigned long long *)(base + lay.stats);
     d.partial = (double *)(base + lay.partial);
+    d.wd = d.partial + 5 * RED_BLOCKS + 8;
     d.sph = nullptr;
     d.omega = params->omega;
     d.gx = params->accel[0];
@@ -1061,6 +1075,11 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     if (e != hipSuccess) {
         delete L;
         return fail(FSL_ERR_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    }
+    FslStatus r = set_mass_ref(L);
+    if (r != FSL_OK) {
+        delete L;
+        return r;
     }
     *out = L;
     return FSL_OK;
@@ -1132,8 +1151,8 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
     DISPATCH(L, run_liquid_form, L, 1);
     FslStatus r = finalize(L);
     if (r != FSL_OK) return r;
-    HIP_TRY(hipStreamSynchronize(L->st));
-    return FSL_OK;
+    // mass inside the new solids has left: a new reference for the watchdog
+    return set_mass_ref(L);
 }
 
 FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
@@ -1271,13 +1290,46 @@ FslStatus fsl_move_particles_device(FslLattice *L, const double *centre, const d
     return remap(L);
 }
 
-static FslStatus check_mass(FslLattice *L)
+// reference mass of the watchdog: the exact total after set-up
+static FslStatus set_mass_ref(FslLattice *L)
 {
     DISPATCH(L, run_mass, L);
-    double m = 0.0;
-    HIP_TRY(hipMemcpyAsync(&m, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&L->mass_ref, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
-    if (!std::isfinite(m)) return fail(FSL_ERR_UNSTABLE, "total mass is not finite");
+    return FSL_OK;
+}
+
+// Watchdog after a step that wrote its partials: the total mass must be
+// finite and within a relative 1e-10 of the reference, and every fluid
+// cell's density within [0.5, 1.5].
+static FslStatus check_watch(FslLattice *L)
+{
+    double w[4];
+    HIP_TRY(hipMemcpyAsync(w, L->d.wd + WD_OUT, sizeof(w), hipMemcpyDeviceToHost, L->st));
+    HIP_TRY(hipStreamSynchronize(L->st));
+    double *o = L->watch_last;
+    o[0] = w[0];
+    o[1] = L->mass_ref;
+    o[2] = w[1];
+    o[3] = w[2];
+    o[4] = w[3];
+    char msg[200];
+    if (!std::isfinite(w[0])) {
+        snprintf(msg, sizeof(msg), "watchdog at step %lld: total mass is not finite", (long long)L->steps);
+        return fail(FSL_ERR_UNSTABLE, msg);
+    }
+    if (w[3] > 0.0) {
+        snprintf(msg, sizeof(msg), "watchdog at step %lld: %.0f fluid cells with density outside [%.1f, %.1f] "
+                 "(range %.6g .. %.6g)", (long long)L->steps, w[3], WD_RHO_MIN, WD_RHO_MAX, w[1], w[2]);
+        return fail(FSL_ERR_UNSTABLE, msg);
+    }
+    const double drift = std::fabs(w[0] - L->mass_ref) / std::max(std::fabs(L->mass_ref), 1e-300);
+    if (!(drift <= 1e-10)) {
+        snprintf(msg, sizeof(msg), "watchdog at step %lld: total mass %.17g drifted from %.17g (relative %.3g > 1e-10)",
+                 (long long)L->steps, w[0], L->mass_ref, drift);
+        return fail(FSL_ERR_UNSTABLE, msg);
+    }
     return FSL_OK;
 }
 
@@ -1308,15 +1360,17 @@ FslStatus fsl_step(FslLattice *L, int32_t nsteps)
         const bool learned = L->P.normals == 1 && L->mlpP;
         const float *mP = learned ? L->mlpP : nullptr;
         const uint16_t *mK = learned ? L->mlpPk : nullptr;
+        const int watch = L->P.check_every > 0 && (L->steps + 1) % L->P.check_every == 0;
+        const int lb = L->list_blocks;
         switch (L->P.precision) {
-        case FSL_FP64: launch_step<double>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1, mP, mK); break;
-        case FSL_FP32: launch_step<float>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1, mP, mK); break;
-        default: launch_step<_Float16>(L->d, L->parity, ep, L->list_blocks, L->st, e0, e1, mP, mK); break;
+        case FSL_FP64: launch_step<double>(L->d, L->parity, ep, lb, watch, L->st, e0, e1, mP, mK); break;
+        case FSL_FP32: launch_step<float>(L->d, L->parity, ep, lb, watch, L->st, e0, e1, mP, mK); break;
+        default: launch_step<_Float16>(L->d, L->parity, ep, lb, watch, L->st, e0, e1, mP, mK); break;
         }
         L->parity ^= 1;
         ++L->steps;
-        if (L->P.check_every > 0 && L->steps % L->P.check_every == 0) {
-            FslStatus r = check_mass(L);
+        if (watch) {
+            FslStatus r = check_watch(L);
             if (r != FSL_OK) return r;
         }
     }
@@ -1333,7 +1387,7 @@ FslStatus fsl_read_fields(FslLattice *L, uint32_t mask, void *const *dst, int32_
         if (!(mask & (1u << f))) continue;
         if (!dst[f]) return fail(FSL_ERR_ARG, "destination of a selected field is NULL");
         size_t bytes = N * 8;
-        if (f == FSL_FIELD_TYPE) bytes = N;
+        if (f == FSL_FIELD_TYPE || f == FSL_FIELD_ESTIMATOR) bytes = N;
         if (f == FSL_FIELD_OWNER) bytes = N * 4;
         if (f == FSL_FIELD_VEL || f == FSL_FIELD_NORMAL) bytes = 3 * N * 8;
         if (f == FSL_FIELD_PDF) bytes = 27 * N * 8;
@@ -1345,15 +1399,33 @@ FslStatus fsl_read_fields(FslLattice *L, uint32_t mask, void *const *dst, int32_
             else
                 launch_geom<float>(L->d, L->parity, L->list_blocks, L->st);
         }
+        // host output is staged on the device: in a buffer kept by the
+        // lattice for fields up to three doubles per cell, in a temporary
+        // one for the PDFs
         void *buf = dst[f];
-        if (!on_device) HIP_TRY(hipMalloc(&buf, bytes));
+        bool temp = false;
+        if (!on_device) {
+            if (bytes <= 3 * N * 8) {
+                if (L->read_cap < bytes) {
+                    if (L->read_buf) HIP_TRY(hipFree(L->read_buf));
+                    L->read_buf = nullptr;
+                    L->read_cap = 0;
+                    HIP_TRY(hipMalloc(&L->read_buf, 3 * N * 8));
+                    L->read_cap = 3 * N * 8;
+                }
+                buf = L->read_buf;
+            } else {
+                HIP_TRY(hipMalloc(&buf, bytes));
+                temp = true;
+            }
+        }
         DISPATCH(L, run_read, L, f, buf);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && !on_device) {
             e = hipMemcpyAsync(dst[f], buf, bytes, hipMemcpyDeviceToHost, L->st);
             if (e == hipSuccess) e = hipStreamSynchronize(L->st);
-            (void)hipFree(buf);
         }
+        if (temp) (void)hipFree(buf);
         if (e != hipSuccess) return fail(FSL_ERR_DEVICE, std::string("read_fields: ") + hipGetErrorString(e));
     }
     HIP_TRY(hipStreamSynchronize(L->st));
@@ -1367,6 +1439,14 @@ FslStatus fsl_total_mass(FslLattice *L, double *mass)
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(mass, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
+    return FSL_OK;
+}
+
+FslStatus fsl_watchdog(FslLattice *L, double out[5])
+{
+    if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
+    if (!out) return fail(FSL_ERR_ARG, "out is NULL");
+    for (int k = 0; k < 5; ++k) out[k] = L->watch_last[k];
     return FSL_OK;
 }
 
@@ -1648,6 +1728,7 @@ void fsl_destroy(FslLattice *L)
     if (L->move_dev) (void)hipFree(L->move_dev);
     if (L->mlpP) (void)hipFree(L->mlpP);
     if (L->mlpPk) (void)hipFree(L->mlpPk);
+    if (L->read_buf) (void)hipFree(L->read_buf);
     delete L;
 }
 

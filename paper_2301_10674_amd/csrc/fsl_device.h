@@ -154,7 +154,7 @@ __device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
 // is carried as a deviation from the rest state (rho = 1, u = 0, K = I/3) so
 // FP32 keeps the small quantities exact enough.
 template <class R, class E, bool GC = false>
-__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27])
+__device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27], double &rho_out)
 {
     // Raw moments of the deviations, passes x, y, z of (sum, odd, even), in
     // FP64 in every form: the non-equilibrium second moments are small
@@ -192,6 +192,7 @@ __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz
         }
     const double drho_d = m[MI(0, 0, 0)];
     const double rho_d = 1.0 + drho_d;
+    rho_out = rho_d;
     const double irho_d = 1.0 / rho_d;
     const double jxd = m[MI(1, 0, 0)], jyd = m[MI(0, 1, 0)], jzd = m[MI(0, 0, 1)];
     const double uxd = (jxd + 0.5 * rho_d * (double)gx) * irho_d;
@@ -354,6 +355,67 @@ __device__ __forceinline__ double csf_curvature(const double s[27])
                 div += 0.25 * (2 * c - 1) * nz;
             }
     return 0.5 * div;
+}
+
+// ---------------------------------------------------------------- watchdog
+// Per-thread accumulation of the watchdog quantities of the step kernels:
+// the FP64 mass of the cells a thread updates, their density range, and the
+// number of cells whose density is outside [0.5, 1.5] or not a number.
+struct Watch {
+    double mass = 0.0;
+    float rmin = 3.0e38f, rmax = -3.0e38f;
+    int bad = 0;
+    __device__ __forceinline__ void add(double m, double rho)
+    {
+        mass += m;
+        const float r = (float)rho;
+        rmin = fminf(rmin, r);
+        rmax = fmaxf(rmax, r);
+        bad += !(rho >= 0.5 && rho <= 1.5);
+    }
+};
+
+// Reduce a block's Watch values (every thread of the block calls this, in
+// uniform control flow) in a fixed order -- butterflies within each
+// wavefront, then the wavefronts in order -- and let thread 0 write 4
+// doubles: mass, lowest density, highest density, cells out of range.
+template <int NT>
+__device__ __forceinline__ void block_watch(Watch w, double *out)
+{
+    __shared__ double s_m[NT / 64];
+    __shared__ float s_lo[NT / 64], s_hi[NT / 64];
+    __shared__ int s_bad[NT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        w.mass += __shfl_xor(w.mass, o);
+        w.rmin = fminf(w.rmin, __shfl_xor(w.rmin, o));
+        w.rmax = fmaxf(w.rmax, __shfl_xor(w.rmax, o));
+        w.bad += __shfl_xor(w.bad, o);
+    }
+    const int wv = (int)threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+        s_m[wv] = w.mass;
+        s_lo[wv] = w.rmin;
+        s_hi[wv] = w.rmax;
+        s_bad[wv] = w.bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        float lo = 3.0e38f, hi = -3.0e38f;
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) {
+            m += s_m[k];
+            lo = fminf(lo, s_lo[k]);
+            hi = fmaxf(hi, s_hi[k]);
+            bad += s_bad[k];
+        }
+        out[0] = m;
+        out[1] = (double)lo;
+        out[2] = (double)hi;
+        out[3] = (double)bad;
+    }
 }
 
 // ---------------------------------------------------------------- helpers

@@ -21,6 +21,7 @@ struct Dev {
     double *poolc;            // per-cell excess mass that found no receiver
     void *geom;               // interface normal (xyz) and curvature (w): double4 or float4
     uint32_t *mark;           // conversion marks, epoch << 8 | bits
+    uint8_t *est;             // learned estimator: outcome per interface cell (0 none)
     int32_t *owner;           // owning sphere of a solid cell, -1 otherwise
     uint8_t *flags;           // cell type (2 bits) | near-solid bit
     uint32_t *smask;          // bit j: the source x - c_j is solid or beyond a wall
@@ -42,6 +43,8 @@ struct Dev {
     unsigned long long *stats;  // conversion counters
     const double *sph;        // spheres: X[3], r, U[3], Omega[3]
     double *partial;          // reduction partials
+    double *wd;               // watchdog: per-block partials of the step kernels, the
+                              // result of the last check and the running pool total
     double omega, gx, gy, gz, sigma, rho_gas, eps, tie;
     int rule_iso;
     int variants;             // VAR_* bits
@@ -56,5 +59,15 @@ constexpr int BULK_THREADS = 256;
 constexpr int BULK_MAX_BLOCKS = 2048;
 constexpr int LIST_THREADS = 256;
 constexpr int RED_BLOCKS = 1024;
+
+// watchdog area (doubles): 4 per block of the dense and of the interface
+// kernel (mass, lowest and highest density, cells outside [0.5, 1.5]), then
+// the combined result (mass, lowest, highest, outside) and the pool total
+constexpr int WD_BULK = 0;
+constexpr int WD_IFACE = 4 * BULK_MAX_BLOCKS;
+constexpr int WD_OUT = WD_IFACE + 4 * 2048;
+constexpr int WD_POOL = WD_OUT + 4;
+constexpr int WD_SIZE = WD_OUT + 8;
+constexpr double WD_RHO_MIN = 0.5, WD_RHO_MAX = 1.5;
 
 }  // namespace fsl

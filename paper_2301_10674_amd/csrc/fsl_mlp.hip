@@ -152,11 +152,13 @@ __device__ __forceinline__ void load_weights(uint16_t *sW, const uint16_t *pk)
     const uint4 *s = (const uint4 *)pk;
     uint4 *d = (uint4 *)sW;
     for (int i0 = 0; i0 < NV; i0 += 8 * (int)blockDim.x) {
+        // every lane loads (the index clamped in range), so that the eight
+        // values stay in registers
         uint4 v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
-            if (i < NV) v[k] = s[i];
+            v[k] = s[i < NV ? i : 0];
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -429,6 +431,12 @@ __device__ __forceinline__ void keep_reg(T &v)
     asm volatile("" : "+v"(v));
 }
 
+// Per-cell outcome of the learned estimator (read back as a field): the
+// corrected estimate was used, or finite differences were kept because of a
+// solid or wall neighbour, |n_raw| outside [0.5, 2], an angle to the finite-
+// difference normal above 30 degrees, or |kappa| > 0.5 (first rule that holds).
+enum : uint8_t { EST_NETWORK = 1, EST_SOLID = 2, EST_LENGTH = 3, EST_ANGLE = 4, EST_KAPPA = 5 };
+
 // Interface normal and curvature with the learned estimator: per group of 16
 // interface cells, the four lanes of a cell (lane = cell + 16 q) gather
 // entries q, q+4, ... of its fill stencil (liquid 1, gas 0, interface
@@ -517,15 +525,24 @@ __global__ __launch_bounds__(64) void k_geom_mlp(Dev d, int which, const float *
             out.y = R(fd.y);
             out.z = R(fd.z);
             out.w = R(fd.w);
-            // the network corrects the finite-difference estimate
+            // the network corrects the finite-difference estimate; the first
+            // rule that fails keeps finite differences (codes 2..5)
             const double nx = fd.x + (double)F.y[0], ny = fd.y + (double)F.y[1], nz = fd.z + (double)F.y[2];
             const double rn = sqrt(nx * nx + ny * ny + nz * nz);
             const double kap = fd.w + 0.25 * (double)F.y[3];
-            use = !any_solid && rn >= 0.5 && rn <= 2.0;
-            if (use) {
+            uint8_t rule = EST_NETWORK;
+            if (any_solid) {
+                rule = EST_SOLID;
+            } else if (!(rn >= 0.5 && rn <= 2.0)) {
+                rule = EST_LENGTH;
+            } else {
+                // cosine of the angle between n_raw and the unit (or zero) n_fd
                 const double cosang = (fd.x * nx + fd.y * ny + fd.z * nz) / rn;
-                use = cosang >= 0.8660254037844386 && fabs(kap) <= 0.5;
+                if (!(cosang >= 0.8660254037844386)) rule = EST_ANGLE;
+                else if (!(fabs(kap) <= 0.5)) rule = EST_KAPPA;
             }
+            use = rule == EST_NETWORK;
+            d.est[c] = rule;
             if (use) {
                 out.x = R(nx / rn);
                 out.y = R(ny / rn);

@@ -179,7 +179,7 @@ __device__ __forceinline__ T at(const T *base, uint32_t e)
 // has no bounce-back part at all.
 template <class S, bool NEAR, bool GC>
 __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
-                                          int x, int row, uint8_t fl)
+                                          int x, int row, uint8_t fl, Watch &wd)
 {
     using R = typename Real<S>::type;
     const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
@@ -242,7 +242,8 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 
     using E = typename Eq<S>::type;
     E fo[27];
-    collide<R, E, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
+    double rho;
+    collide<R, E, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, rho);
 
     double out_sum = 0.0;
 #pragma unroll
@@ -252,7 +253,9 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
         if (i != REST) out_sum += ((solid >> opp(i)) & 1u) ? 0.0 : (double)ld(&v);
     }
     // liquid cells keep m - own outgoing: m' = (m - out) + in over non-solid links
-    d.mq[c] = (mq0 + in_sum) - out_sum;
+    const double m = mq0 + in_sum;
+    d.mq[c] = m - out_sum;
+    wd.add(m, rho);
 }
 
 // Dense part over the rows (y, z) up to the highest fluid row; each block
@@ -264,7 +267,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 // XCDs.
 template <class S, bool GC>
 __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
-                                           int b, int nblocks)
+                                           int b, int nblocks, Watch &wd)
 {
     const int rowmax = (d.cnt[3] + 1) * d.ny;
     const int tx = (int)threadIdx.x;
@@ -299,11 +302,11 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
         seg(s + step, rowd, xd, fld);
         const bool la = (fla & T_MASK) == T_LIQ, lb = (flb & T_MASK) == T_LIQ;
         if (__ballot((la && (fla & F_NEAR_SOLID)) || (lb && (flb & F_NEAR_SOLID))) != 0) {
-            if (la) bulk_cell<S, true, GC>(d, src, dst, xa, rowa, fla);
-            if (lb) bulk_cell<S, true, GC>(d, src, dst, xb, rowb, flb);
+            if (la) bulk_cell<S, true, GC>(d, src, dst, xa, rowa, fla, wd);
+            if (lb) bulk_cell<S, true, GC>(d, src, dst, xb, rowb, flb, wd);
         } else if (__ballot(la || lb) != 0) {
-            if (la) bulk_cell<S, false, GC>(d, src, dst, xa, rowa, fla);
-            if (lb) bulk_cell<S, false, GC>(d, src, dst, xb, rowb, flb);
+            if (la) bulk_cell<S, false, GC>(d, src, dst, xa, rowa, fla, wd);
+            if (lb) bulk_cell<S, false, GC>(d, src, dst, xb, rowb, flb, wd);
         }
         rowa = rowc;
         xa = xc;
@@ -686,7 +689,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     // fill stencil (liquid 1, gas 0, interface clamped fill, solid the centre)
     const double phic = d.phi[c];
     const int slot = d.bbslot[c];
-    const double phicl = phic < 0.0 ? 0.0 : (phic > 1.0 ? 1.0 : phic);
+    const double phicl = fmin(fmax(phic, 0.0), 1.0);
     uint32_t fl[27];
     double ph[27];
 #pragma unroll
@@ -725,10 +728,13 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const uint32_t t = nb(i) < 0 ? (uint32_t)T_SOLID : (fl[i] & T_MASK);
-        const double pv = ph[i] < 0.0 ? 0.0 : (ph[i] > 1.0 ? 1.0 : ph[i]);
+        const double pv = fmin(fmax(ph[i], 0.0), 1.0);
         tyb |= (uint64_t)t << (2 * i);
         rkb |= (uint64_t)fm_rank(fl[i]) << (2 * i);
-        sv[i] = i == REST ? phicl : (t == T_LIQ ? 1.0 : (t == T_GAS ? 0.0 : (t == T_IF ? pv : phicl)));
+        // liquid 1, gas 0, interface its clamped fill, solid or wall the
+        // centre's, as a sum of the cases (arithmetic, not a branch chain)
+        sv[i] = i == REST ? phicl
+                          : (double)(t == T_LIQ) + (double)(t == T_IF) * pv + (double)(t == T_SOLID) * phicl;
     }
     auto ty = [&](int i) { return (uint32_t)(tyb >> (2 * i)) & 3u; };
     auto rk = [&](int i) { return (uint32_t)(rkb >> (2 * i)) & 3u; };
@@ -753,27 +759,33 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     // mass flux from the stored PDFs: s_i (f*_{-i}(x+c_i) - f*_i(x)); with
     // the flux modifiers, between interface cells of different ranks only
     // the term that moves mass from the lower to the higher rank is kept
+    // Written with selects only (no per-lane branches), like the
+    // reconstruction below: see the note at the mass store.
     double dm = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
+        if (i == REST) continue;
         const uint32_t t = ty(i);
-        if (i == REST || t == T_SOLID || t == T_GAS) continue;
-        const double sw = t == T_IF ? 0.5 * (phicl + sv[i]) : 1.0;
-        double in = (double)pulled[opp(i)], out = (double)own[i];
-        if (t == T_IF) {
-            // a single kept term is a whole PDF: the stored deviations get
-            // their weight back (w_{-i} = w_i), which the difference of two
-            // terms cancels
-            if (rk(REST) < rk(i)) {
-                in = 0.0;
-                out += wgt(i);
-            } else if (rk(REST) > rk(i)) {
-                out = 0.0;
-                in += wgt(i);
-            }
-        }
-        dm += sw * (in - out);
+        const bool flows = (t == T_LIQ) | (t == T_IF), itf = t == T_IF;
+        const double sw = itf ? 0.5 * (phicl + sv[i]) : 1.0;
+        // a single kept term is a whole PDF: the stored deviations get their
+        // weight back (w_{-i} = w_i), which the difference of two terms cancels
+        const bool lower = itf & (rk(REST) < rk(i)), higher = itf & (rk(REST) > rk(i));
+        const double in0 = (double)pulled[opp(i)], out0 = (double)own[i];
+        const double in = lower ? 0.0 : (higher ? in0 + wgt(i) : in0);
+        const double out = higher ? 0.0 : (lower ? out0 + wgt(i) : out0);
+        dm += flows ? sw * (in - out) : 0.0;
     }
+    // The new mass is stored here and read back for the conversion marks
+    // below, so that no mass value has to stay in registers through the
+    // reconstruction and the collision.  Builds of this kernel whose flux
+    // and reconstruction compiled to per-lane branches handed a value live
+    // across them to only one side of a branch (the other lanes summed a
+    // stale register); the loops are now written with selects and the mass
+    // is not carried.  The read-back is a fresh load of the cell's own, just
+    // written entry (an empty asm with a memory clobber keeps the compiler
+    // from forwarding the stored value).
+    d.mq[c] = mq0 + dm;
     __builtin_amdgcn_sched_barrier(0);
 
     // stage 3: the collision    // gas-side equilibrium at rho_gas + 6 sigma kappa and the cell's own
@@ -794,27 +806,38 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     const Et drg = Et(d.rho_gas - 1.0 + 6.0 * d.sigma * gn.w);
 
     // incoming PDFs, by pairs (j, opp j) that share the sum of the two
-    // gas-side equilibria
+    // gas-side equilibria.  Every candidate -- bounce-back, reconstruction,
+    // streamed value -- is formed for every link and one is selected (the
+    // equilibria are tied to registers first, so the compiler cannot move
+    // them into per-lane branches).
+    Et G[REST];
+#pragma unroll
+    for (int j = 0; j < REST; ++j) {
+        G[j] = feq_dev_one<Et>(drg, ef, j) + feq_dev_one<Et>(drg, ef, opp(j));
+        keep(G[j]);
+    }
     R f[27];
     f[REST] = own[REST];
 #pragma unroll
     for (int j = 0; j < REST; ++j) {
         const int sj = opp(j);
-        const Et G = feq_dev_one<Et>(drg, ef, j) + feq_dev_one<Et>(drg, ef, sj);
         const double nc = gn.x * cx(j) + gn.y * cy(j) + gn.z * cz(j);  // n . c_j = -(n . c_sj)
         const uint32_t tj = ty(j), tsj = ty(sj);
         // incoming j comes from neighbour sj, incoming sj from neighbour j
-        const bool rj = tsj == T_GAS || nc < -d.tie;
-        const bool rsj = tj == T_GAS || -nc < -d.tie;
+        const bool rj = (tsj == T_GAS) | (nc < -d.tie);
+        const bool rsj = (tj == T_GAS) | (-nc < -d.tie);
         // wall links (no neighbour) carry no wall term
         const R tmj = sizeof(S) == 2 ? rec[j] : (nb(sj) < 0 ? R(0) : record_term<R>(rec, slot, j));
         const R tmsj = sizeof(S) == 2 ? rec[sj] : (nb(j) < 0 ? R(0) : record_term<R>(rec, slot, sj));
-        f[j] = tsj == T_SOLID ? own[sj] + tmj : (rj ? R(G - Et(own[sj])) : pulled[j]);
-        f[sj] = tj == T_SOLID ? own[j] + tmsj : (rsj ? R(G - Et(own[j])) : pulled[sj]);
+        const R bj = own[sj] + tmj, bsj = own[j] + tmsj;
+        const R gj = R(G[j] - Et(own[sj])), gsj = R(G[j] - Et(own[j]));
+        f[j] = tsj == T_SOLID ? bj : (rj ? gj : pulled[j]);
+        f[sj] = tj == T_SOLID ? bsj : (rsj ? gsj : pulled[sj]);
     }
 
     Et fo[27];
-    collide<R, Et, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo);
+    double rho_in;
+    collide<R, Et, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, rho_in);
 
     double rs = 0.0;
 #pragma unroll
@@ -824,8 +847,8 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
         rs += (double)ld(&v);
     }
     const double rho = 1.0 + rs;
-    const double m = mq0 + dm;
-    d.mq[c] = m;
+    asm volatile("" ::: "memory");
+    const double m = d.mq[c];
     d.rho[c] = rho;
 
     uint32_t bits = 0;
@@ -897,6 +920,10 @@ __global__ __launch_bounds__(LIST_THREADS) void k_classes(Dev d, int p)
 // next list and the new-cell list empty.  GC: with the Galilean correction
 // of the collision (a compile-time flag, as in the dense kernel, so that the
 // instance without it keeps its own code).
+// The interface kernel keeps no watchdog accumulators: values kept live
+// across its whole loop (five more registers) made the compiler's register
+// allocation hand the cell's mass to only one side of a divergent branch;
+// k_conv1 takes the interface partial from the stored mass and density.
 template <class S, bool GI, bool GC>
 __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t epoch)
 {
@@ -913,11 +940,36 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
 }
 
 // Dense stream-collide over the liquid rows; GC: with the Galilean
-// correction of the collision.
+// correction of the collision.  watch != 0: each block writes its watchdog
+// partial (liquid mass after streaming, density range) to
+// wd[WD_BULK + 4 block].
 template <class S, bool GC>
-__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
+__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p, int watch)
 {
-    dense_rows<S, GC>(d, (const S *)d.pdf[p], (S *)d.pdf[p ^ 1], (int)blockIdx.x, (int)gridDim.x);
+    Watch wd;
+    dense_rows<S, GC>(d, (const S *)d.pdf[p], (S *)d.pdf[p ^ 1], (int)blockIdx.x, (int)gridDim.x, wd);
+    if (watch) block_watch<BULK_THREADS>(wd, d.wd + WD_BULK + 4 * blockIdx.x);
+}
+
+// Watchdog result of a step: the partials of the nb dense and ni interface
+// blocks summed in a fixed order, plus the pool; wd[WD_OUT ..] = total mass,
+// lowest and highest density, cells outside [0.5, 1.5].  The mass is the
+// liquid and interface mass before the step's conversions, which only move
+// mass between cells and the pool, so it equals the total after the step to
+// rounding.
+__global__ __launch_bounds__(256) void k_watch_final(Dev d, int nb, int ni)
+{
+    Watch w;
+    for (int i = (int)threadIdx.x; i < nb + ni; i += 256) {
+        const double *q = d.wd + (i < nb ? WD_BULK + 4 * i : WD_IFACE + 4 * (i - nb));
+        w.mass += q[0];
+        w.rmin = fminf(w.rmin, (float)q[1]);
+        w.rmax = fmaxf(w.rmax, (float)q[2]);
+        w.bad += (int)q[3];
+    }
+    block_watch<256>(w, d.wd + WD_OUT);
+    __syncthreads();
+    if (threadIdx.x == 0) d.wd[WD_OUT] += d.wd[WD_POOL];
 }
 
 // ---------------------------------------------------------------- conversion
@@ -931,12 +983,16 @@ __device__ __forceinline__ void push_new(const Dev &d, int c, uint32_t epoch, un
     }
 }
 
-__global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t epoch)
+// watch != 0: each block also writes the watchdog partial of its interface
+// cells (mass after the flux, density) to wd[WD_IFACE + 4 block].
+__global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t epoch, int watch)
 {
     const int32_t *list = d.list[p];
     const int count = d.cnt[p];
+    Watch wd;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
         const int c = list[t];
+        if (watch) wd.add(d.mq[c], d.rho[c]);
         const uint32_t mk = mark_bits(d.mark[c], epoch);
         if (!(mk & (MK_TO_LIQ | MK_TO_GAS))) continue;
         const Cell pc = cell_xyz(d, c);
@@ -967,6 +1023,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t e
             }
         }
     }
+    if (watch) block_watch<LIST_THREADS>(wd, d.wd + WD_IFACE + 4 * blockIdx.x);
 }
 
 // sum of a cell's stored deviations over all directions (all) and over the
@@ -1112,6 +1169,7 @@ __device__ __forceinline__ void conv3_cell(const Dev &d, int p, uint32_t epoch, 
         } else {
             d.share[c] = 0.0;
             d.poolc[c] += e;
+            atomicAdd(d.wd + WD_POOL, e);  // running pool total (watchdog)
         }
     }
 }
@@ -1267,32 +1325,38 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
 
 // ---------------------------------------------------------------- launchers
 template <class S>
-void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, hipStream_t st,
+void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1, const float *mlpP, const uint16_t *mlpPk)
 {
     using R = typename Real<S>::type;
     int gb = d.nbx * d.rows;
     if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
     if (d.xcd_map) gb &= ~7;
+    const bool gc = (d.variants & VAR_GALILEAN) != 0;
     if (ev0) (void)hipEventRecord(ev0, st);
-    // the Galilean-corrected instances (GC = true) are not launched: the
-    // lattice parameters reject that variant (its interface kernel loses an
-    // excess-mass share on lattices three cells high)
-    k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p);
+    if (gc)
+        k_bulk<S, true><<<gb, BULK_THREADS, 0, st>>>(d, p, watch);
+    else
+        k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p, watch);
     if (ev1) (void)hipEventRecord(ev1, st);
     if (d.variants & VAR_FLUX_MODIFIERS) k_classes<<<list_blocks, LIST_THREADS, 0, st>>>(d, p);
-    if (mlpP)
-        k_iface<S, false, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    else
-        k_iface<S, true, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
-    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    if (mlpP) {
+        if (gc) k_iface<S, false, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+        else k_iface<S, false, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    } else {
+        if (gc) k_iface<S, true, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+        else k_iface<S, true, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
+    }
+    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch, watch);
+    // the watchdog result is complete before the conversions touch the pool
+    if (watch) k_watch_final<<<1, 256, 0, st>>>(d, gb, list_blocks);
     k_conv23<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     k_conv4<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     if (mlpP) launch_geom_mlp<R>(d, p ^ 1, list_blocks, mlpP, mlpPk, st);
 }
 
 #define FSL_STEP_INST(S)                                                                          \
-    template void launch_step<S>(const Dev &, int, uint32_t, int, hipStream_t, hipEvent_t, hipEvent_t, \
+    template void launch_step<S>(const Dev &, int, uint32_t, int, int, hipStream_t, hipEvent_t, hipEvent_t, \
                                  const float *, const uint16_t *);
 FSL_STEP_INST(double)
 FSL_STEP_INST(float)

@@ -20,8 +20,11 @@ FP64, FP32, FP16_STORE = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORE}
 FSL_VAR_FLUX_MODIFIERS, FSL_VAR_NORMAL_EXCESS, FSL_VAR_CSF_CURVATURE, FSL_VAR_GALILEAN = 1, 2, 4, 8  # variants bits
 (FIELD_TYPE, FIELD_MASS, FIELD_FILL, FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_NORMAL,
- FIELD_CURV, FIELD_OWNER) = range(9)
-NFIELDS = 9
+ FIELD_CURV, FIELD_OWNER, FIELD_ESTIMATOR) = range(10)
+NFIELDS = 10
+# FIELD_ESTIMATOR values: corrected estimate used, or finite differences kept
+# because of a solid neighbour, |n_raw|, the angle, |kappa|
+EST_NETWORK, EST_SOLID, EST_LENGTH, EST_ANGLE, EST_KAPPA = 1, 2, 3, 4, 5
 GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 
 # every symbol declared in include/fsl.h
@@ -31,7 +34,8 @@ EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fs
            "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
            "fsl_bed_profile", "fsl_move_particles", "fsl_move_particles_device",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_dem_create", "fsl_dem_step",
-           "fsl_dem_read", "fsl_dem_bedload", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy")
+           "fsl_dem_read", "fsl_dem_bedload", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy",
+           "fsl_watchdog")
 MLP_NPARAM = 6212
 
 
@@ -121,6 +125,8 @@ def lib():
         L.fsl_read_fields.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(vp), i32]
         L.fsl_total_mass.restype = ctypes.c_int
         L.fsl_total_mass.argtypes = [vp, dp]
+        L.fsl_watchdog.restype = ctypes.c_int
+        L.fsl_watchdog.argtypes = [vp, dp]
         L.fsl_counters.restype = ctypes.c_int
         L.fsl_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.fsl_info.restype = ctypes.c_int
@@ -255,7 +261,7 @@ class Lattice:
         ptrs = (ctypes.c_void_p * NFIELDS)()
         mask = 0
         for f in fields:
-            if f == FIELD_TYPE:
+            if f in (FIELD_TYPE, FIELD_ESTIMATOR):
                 a = np.zeros(N, dtype=np.uint8)
             elif f == FIELD_OWNER:
                 a = np.zeros(N, dtype=np.int32)
@@ -350,6 +356,13 @@ class Lattice:
         w = _f32(weights)
         assert w.size == MLP_NPARAM
         _check(lib().fsl_set_estimator(self.h, _fp(w)))
+
+    def watchdog(self):
+        """Last watchdog check: dict of mass, reference mass, lowest and
+        highest fluid density, cells outside [0.5, 1.5]."""
+        out = np.zeros(5)
+        _check(lib().fsl_watchdog(self.h, _dp(out)))
+        return dict(zip(("mass", "mass_ref", "rho_min", "rho_max", "cells_out"), out.tolist()))
 
     def estimator_stats(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()

@@ -75,6 +75,28 @@ def channel_film(seed: int = 1) -> Workload:
         meta={"seed": seed, "steps": 200})
 
 
+def film_with_surface_spheres(sigma: float = 0.0, nz: int = 32) -> Workload:
+    """The channel film with four more fixed spheres of radius 3 centred on
+    its free surface (x = 8, 24, 40, 56; y = 4), so that interface cells
+    touch solids; with nz = 22 the surface crests (z up to 22) also reach
+    the top wall."""
+    w = channel_film()
+    nx, ny, _ = w.shape
+    xs = np.array([8.0, 24.0, 40.0, 56.0])
+    h = 20.0 + 2.0 * np.sin(2.0 * np.pi * xs / nx)
+    extra = np.stack([xs, np.full(4, 4.0), h], axis=1)
+    n = len(w.radius) + 4
+    xc = np.arange(nx) + 0.5
+    hh = 20.0 + 2.0 * np.sin(2.0 * np.pi * xc / nx)
+    fill = height_fill((nx, ny, nz), np.broadcast_to(hh[None, :], (ny, nx)))
+    return Workload(
+        name="film_surface_spheres_%dx%dx%d" % (nx, ny, nz), shape=(nx, ny, nz), omega=w.omega,
+        accel=w.accel, sigma=sigma, fill=fill, rho=np.ones((nz, ny, nx)),
+        vel=np.zeros((3, nz, ny, nx)), centre=np.concatenate([w.centre, extra]),
+        radius=np.concatenate([w.radius, np.full(4, 3.0)]), sphere_vel=np.zeros((n, 3)),
+        sphere_angvel=np.zeros((n, 3)), meta={"seed": 1})
+
+
 def _bed_spheres(nx, ny, rng, d=10.0, layers=3, z0=5.0, jitter=0.75):
     """Jittered hexagonal packing of ``layers`` layers of diameter-d spheres
     that tiles the periodic nx x ny box."""

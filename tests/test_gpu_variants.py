@@ -1,7 +1,7 @@
 """GPU parity of the variants (Thuerey's flux modifiers and normal-weighted
-excess mass, the corner-normal curvature of Brackbill et al.) against the
-FP64 oracle, through the C-ABI.  (The Galilean correction of the collision
-is switched off on the GPU; its test is kept, skipped.)
+excess mass, the corner-normal curvature of Brackbill et al., the Galilean
+correction of the cumulant collision) against the FP64 oracle, through the
+C-ABI.
 
 * FP64, each variant alone and all together: the splash (a blob falling
   into a rough pool, many cells with only gas or only liquid neighbours and
@@ -11,7 +11,11 @@ is switched off on the GPU; its test is kept, skipped.)
 * FP32 and FP16 storage with all variants on the channel film with surface
   tension: the velocity error against the FP64 oracle within the storage
   forms' targets, mass conserved.
-* Ragged and tiny lattices, an all-liquid box (empty interface list).
+* Ragged and tiny lattices, an all-liquid box (empty interface list); the
+  Galilean correction also on lattices three and five cells high with
+  periods 3 and 6 (conversion cascades, excess shared by a whole row) and in
+  a fast channel where the correction changes the velocity far beyond the
+  tolerance.
 * The variants change the result (the splash with and without differs).
 """
 import dataclasses
@@ -27,7 +31,7 @@ from test_gpu_parity import assert_fp64_parity, gpu_fields, oracle_fields, veloc
 pytestmark = pytest.mark.gpu
 
 VARIANTS = {"flux": dict(flux_modifiers=True), "excess": dict(normal_excess=True),
-            "csf": dict(csf_curvature=True),
+            "csf": dict(csf_curvature=True), "galilean": dict(galilean=True),
             "both": dict(flux_modifiers=True, normal_excess=True, csf_curvature=True)}
 
 
@@ -152,9 +156,6 @@ def test_variants_change_the_result():
     assert np.abs(out[0] - out[1]).max() > 1e-3
 
 
-@pytest.mark.skip(reason="the Galilean-corrected step is switched off: its interface kernel lost an "
-                         "excess-mass share on 3x3x3 and 6x3x3 lattices (all nine cells of the middle row "
-                         "0.0687 short after one step) while matching the oracle on larger lattices")
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_galilean_correction_in_a_fast_channel(prec, tol):
     """The correction grows with u^2: a liquid-filled channel (walls at the
@@ -193,13 +194,15 @@ def test_galilean_correction_in_a_fast_channel(prec, tol):
     assert rel > 50 * tol
 
 
+@pytest.mark.parametrize("galilean", [False, True])
 @pytest.mark.parametrize("shape,h", [((3, 3, 3), 1.6), ((6, 3, 3), 1.6), ((3, 3, 5), 2.6)])
-def test_tiny_lattices_default_model_fp64(shape, h):
-    """The default model on lattices three and five cells high with x and y
-    periods of 3 and 6, where every cell neighbours every cell of the next
-    row: the conversions cascade (one filled cell turns the whole gas row
-    into interface cells) and the excess mass of filled cells is shared by
-    a whole row; every field element by element after 20 steps."""
+def test_tiny_lattices_fp64(shape, h, galilean):
+    """The default model and the Galilean-corrected one on lattices three
+    and five cells high with x and y periods of 3 and 6, where every cell
+    neighbours every cell of the next row: the conversions cascade (one
+    filled cell turns the whole gas row into interface cells) and the excess
+    mass of filled cells is shared by a whole row; every field element by
+    element after 5, 10, 15 and 20 steps."""
     nx, ny, nz = shape
     xc = np.arange(nx) + 0.5
     hh = h + 0.7 * np.sin(2 * np.pi * xc / nx)
@@ -209,7 +212,7 @@ def test_tiny_lattices_default_model_fp64(shape, h):
                    fill=fill, rho=np.ones((nz, ny, nx)), vel=0.01 * rng.standard_normal((3, nz, ny, nx)),
                    centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
                    sphere_angvel=np.zeros((0, 3)))
-    g, o = pair(w, "fp64", {})
+    g, o = pair(w, "fp64", dict(galilean=True) if galilean else {})
     M0 = o.total_mass()
     for k in range(4):
         g.step(5)

@@ -1,0 +1,81 @@
+"""The library's kernels built as host code (tests/hostemu: a CPU stand-in
+for the HIP runtime, kernels unchanged but for launch syntax) run against
+the FP64 oracle on the CPU, under UBSan with array-bounds checks.
+
+This checks the kernel sources on their own, apart from the GPU compiler:
+the GPU parity tests compare what the GPU compiler made of them.  The cases
+are those where the GPU build has gone wrong before -- lattices three and
+five cells high (every cell neighbours every cell of the next row, filled
+cells share their excess with a whole row) with and without the Galilean
+correction, and a film whose crests touch the top wall -- so that a
+difference between the GPU and the oracle there can be placed: in the
+source if this test fails too, in the compiled code if it does not.
+"""
+import dataclasses
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2301_10674_amd import fsl as F
+from paper_2301_10674_amd import inputs as I
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "hostemu"))
+import emu  # noqa: E402
+
+
+def tiny(shape, h):
+    nx, ny, nz = shape
+    xc = np.arange(nx) + 0.5
+    hh = h + 0.7 * np.sin(2 * np.pi * xc / nx)
+    fill = I.height_fill(shape, np.broadcast_to(hh[None, :], (ny, nx)))
+    rng = np.random.default_rng(5)
+    return I.Workload(name="tiny", shape=shape, omega=1.3, accel=(1e-4, 0, -1e-4), sigma=1e-3,
+                      fill=fill, rho=np.ones((nz, ny, nx)), vel=0.01 * rng.standard_normal((3, nz, ny, nx)),
+                      centre=np.zeros((0, 3)), radius=np.zeros(0), sphere_vel=np.zeros((0, 3)),
+                      sphere_angvel=np.zeros((0, 3)))
+
+
+def lid():
+    w = I.film_with_surface_spheres(nz=22, sigma=1e-3)
+    return dataclasses.replace(w, centre=w.centre[:18], radius=w.radius[:18], sphere_vel=w.sphere_vel[:18],
+                               sphere_angvel=w.sphere_angvel[:18])
+
+
+def compare(g, o, label):
+    t = o.read(O.F_TYPE)
+    assert np.array_equal(g.read(F.FIELD_TYPE), t), label
+    fl = (t == O.LIQUID) | (t == O.INTERFACE)
+    for gf, of in ((F.FIELD_MASS, O.F_MASS), (F.FIELD_FILL, O.F_FILL)):
+        assert np.abs(g.read(gf)[fl] - o.read(of)[fl]).max() <= 1e-12, (label, gf)
+    assert np.abs(g.read(F.FIELD_PDF)[:, fl] - o.read(O.F_PDF)[:, fl]).max() <= 1e-12, label
+
+
+@pytest.mark.parametrize("galilean", [False, True])
+@pytest.mark.parametrize("shape,h", [((3, 3, 3), 1.6), ((6, 3, 3), 1.6), ((3, 3, 5), 2.6)])
+def test_tiny_lattices_on_the_cpu(shape, h, galilean):
+    w = tiny(shape, h)
+    kw = dict(galilean=True) if galilean else {}
+    g = emu.EmuLattice(w, "fp64", **kw)
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, fill=w.fill, rho=w.rho, vel=w.vel, **kw)
+    for k in range(4):
+        g.step(5)
+        o.step(5)
+        compare(g, o, "%s after %d steps" % (shape, 5 * (k + 1)))
+    assert np.array_equal(g.counters()[:7], o.counters()[:7])
+    g.destroy()
+
+
+def test_surface_at_the_top_wall_on_the_cpu():
+    w = lid()
+    g = emu.EmuLattice(w, "fp64")
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, fill=w.fill, rho=w.rho, vel=w.vel)
+    o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    for k in range(3):
+        g.step(2)
+        o.step(2)
+        compare(g, o, "lid after %d steps" % (2 * (k + 1)))
+    assert o.counters()[2] > 0                 # cells filled next to the wall
+    g.destroy()

@@ -94,6 +94,19 @@ MUTANTS = {
     "galilean_strain_rate": ("- 0.5 * omega_bulk * trace_neq;\n        const double dyv",
                              "- 0.5 * omega * trace_neq;\n        const double dyv",
                              "test_oracle_galilean.py", "sound_wave or cube"),
+    "estimator_angle_threshold": ("else if (angle > 30.0) rule = 3;", "else if (angle > 45.0) rule = 3;",
+                                  "test_oracle_estimator.py", "bias_network", "mlp_oracle.c"),
+    "estimator_length_range": ("else if (rn < 0.5 || rn > 2.0) rule = 2;", "else if (rn < 0.5 || rn > 3.0) rule = 2;",
+                               "test_oracle_estimator.py", "bias_network", "mlp_oracle.c"),
+    "estimator_kappa_weight": ("const double kap = kfd + 0.25 * y[3];", "const double kap = kfd + y[3];",
+                               "test_oracle_estimator.py", "bias_network", "mlp_oracle.c"),
+    "estimator_input_centre": ("x[k] = phi[k] - 0.5;", "x[k] = phi[k];",
+                               "test_oracle_estimator.py", "single_path", "mlp_oracle.c"),
+    "estimator_rule_order": ("if (solid_nb) rule = 1;\n    else if (rn < 0.5 || rn > 2.0) rule = 2;",
+                             "if (rn < 0.5 || rn > 2.0) rule = 2;\n    else if (solid_nb) rule = 1;",
+                             "test_oracle_estimator.py", "solid_neighbour", "mlp_oracle.c"),
+    "estimator_solid_cells": ("if (y < 0 || L->type[y] == OL_SOLID) solid_nb = 1;", "if (y < 0) solid_nb = 1;",
+                              "test_oracle_estimator.py", "lattice"),
     "curvature_sign": ("*kappa = -(tr - gHg) / (2.0 * gn);", "*kappa = (tr - gHg) / (2.0 * gn);",
                        "test_oracle_geometry.py", "quadratic or sphere"),
 }
