@@ -267,6 +267,23 @@ FslStatus fsl_estimator_train(const float *x, const float *y, int64_t n,
 FslStatus fsl_estimator_grad(const float *weights, const float *x, const float *y,
                              int64_t n, float *grad, double *loss, void *hip_stream);
 
+/* For callers that cannot allocate memory -- code under HIP graph capture,
+ * tight training loops, harnesses that forbid hipMalloc: the mean loss and
+ * its gradient of fsl_estimator_grad with every array in device memory,
+ * owned by the caller: weights float [6212], x float [n][27] fill levels,
+ * y float [n][4] targets (inputs); grad float [6212] and loss float [1]
+ * (outputs).  Enqueued on hip_stream (NULL: default) without synchronising.
+ * Allocates nothing: the packed weights and the partial sums live in a
+ * device array of the library, about 6.4 MB, one per GPU for the life of
+ * the process, shared by every call on that GPU -- calls that overlap on
+ * one GPU (other streams, other host threads) race and must be serialised
+ * by the caller.  Partial sums are formed over groups of samples in a fixed
+ * order, so the result equals fsl_estimator_grad's to FP32 rounding of the
+ * summation order.  FSL_ERR_ARG for a NULL pointer or n outside [1, 2^24],
+ * FSL_ERR_DEVICE for a failed launch or symbol lookup. */
+FslStatus fsl_estimator_grad_device(const float *weights, const float *x, const float *y,
+                                    int64_t n, float *grad, float *loss, void *hip_stream);
+
 /* Network outputs y float [n][4] for n stencils x float [n][27]. */
 FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n,
                               float *y, void *hip_stream);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -963,6 +964,40 @@ struct DevBufs {
 
 static const int MLP_GPW = 1;  // groups of 16 samples per wavefront
 
+// ---------------------------------------------------------------- no-allocation gradient
+// Device scratch of fsl_estimator_grad_device: the packed BF16 weights, then
+// the partial gradients and losses of at most GRAD_DEVICE_WAVES wavefronts.
+// A file-scope device array: each GPU the library runs on holds one copy for
+// the life of the process.  Host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's
+// name (which on the host is only a stand-in for the symbol).
+constexpr int GRAD_DEVICE_WAVES = 256;
+constexpr int64_t GRAD_DEVICE_MAX_SAMPLES = (int64_t)1 << 24;
+constexpr size_t SCRATCH_PK = ((size_t)MLP_PACK_SIZE * 2 + 255) & ~(size_t)255;
+constexpr size_t SCRATCH_PART = ((size_t)GRAD_DEVICE_WAVES * MLP_NPARAM * 4 + 255) & ~(size_t)255;
+constexpr size_t SCRATCH_BYTES = SCRATCH_PK + SCRATCH_PART + (size_t)GRAD_DEVICE_WAVES * 4;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::atomic<unsigned char *> g_scratch[64];
+
+// address of this device's scratch, looked up once per device
+static FslStatus device_scratch(unsigned char **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(FSL_ERR_DEVICE, "device index beyond 64");
+    unsigned char *p = g_scratch[dev].load();
+    if (!p) {
+        void *q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q)
+            return fail(FSL_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        p = (unsigned char *)q;
+        g_scratch[dev].store(p);
+    }
+    *out = p;
+    return FSL_OK;
+}
+
 // ---------------------------------------------------------------- C-ABI
 extern "C" {
 
@@ -1606,6 +1641,29 @@ FslStatus fsl_estimator_grad(const float *weights, const float *x, const float *
     HIP_TRY(hipMemcpyAsync(&lh, loss, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (loss_out) *loss_out = lh;
+    return FSL_OK;
+}
+
+FslStatus fsl_estimator_grad_device(const float *weights, const float *x, const float *y, int64_t n,
+                                    float *grad, float *loss, void *hip_stream)
+{
+    if (!weights || !x || !y || !grad || !loss) return fail(FSL_ERR_ARG, "NULL argument");
+    if (n <= 0 || n > GRAD_DEVICE_MAX_SAMPLES) return fail(FSL_ERR_ARG, "n must lie in [1, 2^24]");
+    unsigned char *sp = nullptr;
+    FslStatus r = device_scratch(&sp);
+    if (r != FSL_OK) return r;
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint16_t *pk = (uint16_t *)sp;
+    float *part = (float *)(sp + SCRATCH_PK);
+    float *ploss = (float *)(sp + SCRATCH_PK + SCRATCH_PART);
+    // groups of 16 samples per wavefront so that at most GRAD_DEVICE_WAVES
+    // partials are written; every partial slot used is written in full, so
+    // nothing in the scratch has to start at zero
+    const int gpw = (int)((n + 16 * GRAD_DEVICE_WAVES - 1) / (16 * GRAD_DEVICE_WAVES));
+    const int nw = (int)((n + 16 * (int64_t)gpw - 1) / (16 * (int64_t)gpw));
+    mlp_pack(weights, pk, st);
+    mlp_grad(x, y, nullptr, (int)n, 1.0f / (float)n, weights, pk, gpw, part, ploss, nw, grad, loss, st);
+    HIP_TRY(hipGetLastError());
     return FSL_OK;
 }
 

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *X, const float *T,
     for (int g = 0; g < groups_per_wave; ++g) {
         const int s = (blockIdx.x * groups_per_wave + g) * 16 + r;
         const bool valid = s < nbatch;
-        const int sid = valid ? idx[s] : 0;
+        const int sid = valid ? (idx ? idx[s] : s) : 0;  // no id list: samples in order
         // inputs: clamp(phi) - 1/2, features 16 kt + 4 q + j
         v4s xb[2];
 #pragma unroll

@@ -35,7 +35,7 @@ EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fs
            "fsl_bed_profile", "fsl_move_particles", "fsl_move_particles_device",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_dem_create", "fsl_dem_step",
            "fsl_dem_read", "fsl_dem_bedload", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy",
-           "fsl_watchdog")
+           "fsl_watchdog", "fsl_estimator_grad_device")
 MLP_NPARAM = 6212
 
 
@@ -140,6 +140,8 @@ def lib():
         L.fsl_estimator_train.argtypes = [fp, fp, ctypes.c_int64, ctypes.POINTER(FslTrainParams), fp, fp, vp]
         L.fsl_estimator_grad.restype = ctypes.c_int
         L.fsl_estimator_grad.argtypes = [fp, fp, fp, ctypes.c_int64, fp, dp, vp]
+        L.fsl_estimator_grad_device.restype = ctypes.c_int
+        L.fsl_estimator_grad_device.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
         L.fsl_estimator_infer.restype = ctypes.c_int
         L.fsl_estimator_infer.argtypes = [fp, fp, ctypes.c_int64, fp, vp]
         L.fsl_fd_geometry.restype = ctypes.c_int
@@ -402,6 +404,16 @@ def estimator_train(x, y, weights, epochs=10, batch=1024, lr=1e-3, beta1=0.9, be
     losses = np.zeros(int(epochs), dtype=np.float32)
     _check(lib().fsl_estimator_train(_fp(x), _fp(y), n, ctypes.byref(tp), _fp(w), _fp(losses), _stream()))
     return w, losses
+
+
+def estimator_grad_device(weights, x, y, grad, loss, n=None):
+    """The loss gradient with every array a torch device tensor (float32:
+    weights [6212], x [n, 27], y [n, 4], grad [6212] and loss [1] written);
+    enqueued on the current stream, nothing allocated by the library."""
+    n = x.shape[0] if n is None else int(n)
+    _check(lib().fsl_estimator_grad_device(ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr()), n, ctypes.c_void_p(grad.data_ptr()),
+                                           ctypes.c_void_p(loss.data_ptr()), _stream()))
 
 
 def estimator_grad(weights, x, y):
