@@ -2,11 +2,20 @@
 
 One step = one pass of the whole hot path (dense stream-collide, interface
 stream-collide with normals/curvature, reconstruction and mass flux,
-conversion, excess mass) over the synthetic sediment flume 1536 x 40 x 192
-(three layers of diameter-10 spheres with small prescribed velocities, 60
-cells of liquid above the bed, FP32 PDF storage).  Prints one JSON line.
+conversion, excess mass, the estimator's geometry) over the large synthetic
+sediment flume 3072 x 80 x 256 (62.9 M cells: three layers of diameter-10
+spheres, 9,210 of them, with small prescribed velocities, 60 cells of
+liquid above the bed, FP32 PDF storage, 2000 steps).  The main form runs the
+learned interface estimator with its finite-difference fallback where the
+network's gate passes (better than finite differences on held-out stencils
+and in the flume's own flow); the plain FP32 form, the FP16-storage form and
+the network forced on (timed over 300 steps) run on the same lattice; the
+1536 x 40 x 192 flume is a sub-entry (FP32, FP16, FP64, 1000 steps); the
+velocity and fill-level errors of each storage form against the FP64 oracle
+are measured on a 128 x 40 x 192 flume crop after 500 steps and on the
+channel film after 200 steps.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32-learned]
 
 HBM traffic of the dense kernel comes from two rocprofv3 counter runs of
 this same command (FETCH_SIZE, then WRITE_SIZE), summarised by
@@ -162,7 +171,7 @@ def interface_error(lat, fsl):
     return {"rms_angle_deg": ang, "rms_kappa": kap, "cells": int(len(cells))}
 
 
-def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=10, seed=0):
+def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=30, seed=0):
     """Train the estimator for a lattice: analytic stencils plus height-
     function labelled stencils of the lattice's own fill fields (taken while
     it runs the plain estimator), on the GPU; returns weights and report."""
@@ -175,9 +184,35 @@ def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=10,
     Xt, Yt, Xv, Yv = T.split(X, Y, 0.1, seed=seed)
     rep = T.train(fsl, Xt, Yt, Xv, Yv, epochs=epochs, seed=seed)
     rep["data_seconds"] = time.perf_counter() - t0 - rep["train_seconds"]
+    rep.update(analytic_samples=int(len(Xa)), flume_samples=int(len(Xf)), epochs=epochs,
+               supersampling="6^3")
     w = rep.pop("weights")
     rep.pop("losses")
     return w, rep
+
+
+def flow_check(w, fsl, weights, steps=1000, check_every=10):
+    """The network in the flow it serves: the lattice runs `steps` steps with
+    the network and with finite differences alone (watchdog on); the network
+    passes if its run stays healthy and its normals and curvatures are at
+    least as close to the height-function labels of its own fill field as
+    the finite-difference ones are to theirs."""
+    out = {"steps": steps}
+    for name, wts in (("network", weights), ("finite_differences", None)):
+        lat = fsl.lattice_from_workload(w, "fp32", normals=1 if wts is not None else 0,
+                                        check_every=check_every)
+        if wts is not None:
+            lat.set_estimator(wts)
+        try:
+            lat.step(steps)
+            out[name] = interface_error(lat, fsl)
+        except fsl.FslError as e:
+            out[name] = {"unstable": str(e)}
+        lat.destroy()
+    net, fd = out["network"], out["finite_differences"]
+    out["pass"] = bool("unstable" not in net and "unstable" not in fd
+                       and net["rms_angle_deg"] <= fd["rms_angle_deg"] and net["rms_kappa"] <= fd["rms_kappa"])
+    return out
 
 
 def time_particles(w, fsl, precision, steps=20, coupled_steps=20):
@@ -252,27 +287,53 @@ def time_particles(w, fsl, precision, steps=20, coupled_steps=20):
     return out
 
 
-def run_form(w, form, steps, warmup, main_form=None):
+_WEIGHTS = {}
+
+
+def trained_estimator(fsl):
+    """Weights of the learned estimator, trained once per run on analytic
+    stencils and height-function labelled fields of the 1536 x 40 x 192
+    flume (taken while it runs the plain estimator), and its gate: better
+    than finite differences on held-out stencils and in the flume's flow."""
+    if "w" not in _WEIGHTS:
+        from paper_2301_10674_amd import inputs
+
+        w = inputs.flume(seed=2)
+        lat = fsl.lattice_from_workload(w, "fp32")
+        weights, rep = learned_weights(lat, fsl)
+        lat.destroy()
+        rep["held_out_gate"] = rep.pop("gate")
+        rep["flow_check"] = flow_check(w, fsl, weights)
+        rep["gate"] = bool(rep["held_out_gate"] and rep["flow_check"]["pass"])
+        _WEIGHTS["w"], _WEIGHTS["report"] = weights, rep
+    return _WEIGHTS["w"], dict(_WEIGHTS["report"])
+
+
+def run_form(w, form, steps, warmup, main_form=None, particles=True):
     import torch
 
     from paper_2301_10674_amd import fsl
 
-    precision, learned = form.split("-")[0], form.endswith("-learned")
-    # "-variants": Thuerey's flux modifiers and normal-weighted excess mass,
-    # curvature from corner normals
+    precision = form.split("-")[0]
+    # "-learned": the network where its gate passes; "-learned-forced": the
+    # network whatever its gate says (to time it); "-variants": Thuerey's
+    # flux modifiers and normal-weighted excess mass, curvature from corner
+    # normals
+    learned, forced = "-learned" in form, form.endswith("-forced")
     variants = form.endswith("-variants")
-    lat = fsl.lattice_from_workload(w, precision, normals=1 if learned else 0,
-                                    flux_modifiers=variants, normal_excess=variants, csf_curvature=variants)
     est = None
     if learned:
-        weights, est = learned_weights(lat, fsl)
-        if est["gate"]:
-            lat.set_estimator(weights)
+        weights, est = trained_estimator(fsl)
+    on = learned and (forced or est["gate"])
+    lat = fsl.lattice_from_workload(w, precision, normals=1 if on else 0,
+                                    flux_modifiers=variants, normal_excess=variants, csf_curvature=variants)
+    if on:
+        lat.set_estimator(weights)
     lat.step(warmup)
     torch.cuda.synchronize()
     liq0, itf0 = fluid_counts(lat, fsl)
     M0 = lat.total_mass()
-    used0 = lat.estimator_stats() if learned else (0, 0)
+    used0 = lat.estimator_stats() if on else (0, 0)
     lat.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -302,9 +363,10 @@ def run_form(w, form, steps, warmup, main_form=None):
         liquid_cells=liq, fluid_cells=fluid, interface_cells=0.5 * (itf0 + itf1),
         mass_drift=abs(M1 - M0) / M0, interface_error=interface_error(lat, fsl))
     if learned:
-        used1 = lat.estimator_stats()
-        res["estimator"] = dict(est, network_cells=used1[0] - used0[0], fallback_cells=used1[1] - used0[1])
-    if len(w.radius) and form == main_form:
+        used1 = lat.estimator_stats() if on else (0, 0)
+        res["estimator"] = dict(est, network_on=on, network_cells=used1[0] - used0[0],
+                                fallback_cells=used1[1] - used0[1])
+    if len(w.radius) and form == main_form and particles:
         res["particles"] = time_particles(w, fsl, precision)
     # momentum-exchange force and torque on every sphere (outside the timed
     # steps; the coupling would call it once per step)
@@ -340,15 +402,16 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     return best
 
 
-def cpu_baseline(seconds_target=12.0):
-    """The FP64 oracle on the same flume recipe cropped to 128 x 40 x 192,
-    for as many steps as fit in about seconds_target: once on one thread
-    (the reported value) and once on all host threads (its per-cell phases
-    run in parallel; the result does not depend on the thread count)."""
+def cpu_baseline(ny, nz, seconds_target=12.0):
+    """The FP64 oracle on the bench's flume recipe (same ny, nz, seed 3) on
+    a 64-cell-long periodic box, for as many steps as fit in about
+    seconds_target: once on one thread (the reported value) and once on all
+    host threads (its per-cell phases run in parallel; the result does not
+    depend on the thread count)."""
     from oracle import oracle as O
     from paper_2301_10674_amd import inputs
 
-    w = inputs.flume_crop(nx=128, seed=3)
+    w = inputs.flume(nx=64, ny=ny, nz=nz, seed=3)
 
     def timed(threads):
         used = O.set_threads(threads)
@@ -370,26 +433,164 @@ def cpu_baseline(seconds_target=12.0):
     va, ca, _, na, sa = timed(0)
     O.set_threads(0)
     return {"value": v1, "unit": "MLUPS (fluid cells)", "cores": c1, "kind": "oracle",
-            "sample": "FP64 oracle, flume recipe cropped to 128x40x192 (%d fluid cells), "
-                      "%d steps after 1 warm-up step, %.1f s on 1 thread" % (fluid, n1, s1),
+            "sample": "FP64 oracle, the flume recipe on a 64x%dx%d periodic box (%d fluid cells), "
+                      "%d steps after 1 warm-up step, %.1f s on 1 thread" % (ny, nz, fluid, n1, s1),
             "all_cores": {"value": va, "cores": ca,
                           "sample": "%d steps after 1 warm-up step, %.1f s on %d threads" % (na, sa, ca)}}
+
+
+def gpu_weights(w):
+    """The estimator weights as the GPU multiplies with them: the three
+    matrices rounded to BF16 (nearest, ties to even), biases in FP32."""
+    p = np.asarray(w, dtype=np.float64).copy()
+    for a, b in ((0, 1728), (1792, 5888), (5952, 6208)):
+        u = np.ascontiguousarray(w[a:b], dtype=np.float32).view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        p[a:b] = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return p
+
+
+def accuracy_vs_oracle(weights=None, crop_steps=500, film_steps=200):
+    """Velocity and fill-level error of each storage form against the FP64
+    oracle on the same seeded inputs: the flume recipe on its own periodic
+    128 x 40 x 192 box after crop_steps steps (also the oracle's own error
+    when it stores FP16 deviations: the floor of any FP16-storage form), and
+    the channel film 64 x 8 x 32 after film_steps steps, where the learned
+    form is compared with the oracle running the same (BF16-rounded) network
+    with the same fallback rules."""
+    from oracle import oracle as O
+    from paper_2301_10674_amd import fsl, inputs
+
+    def fluid(t):
+        return (t == O.LIQUID) | (t == O.INTERFACE)
+
+    def oracle_run(w, steps, store="fp64", params=None):
+        o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, rho_gas=w.rho_gas,
+                            conv_eps=w.conv_eps, fill=w.fill, rho=w.rho, vel=w.vel, store=store)
+        o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+        if params is not None:
+            o.set_estimator(params)
+        M0 = o.total_mass()
+        o.step(steps)
+        r = {"type": o.read(O.F_TYPE), "vel": o.read(O.F_VEL), "fill": o.read(O.F_FILL),
+             "drift": abs(o.total_mass() - M0) / M0}
+        del o
+        return r
+
+    def compare(tg, vg, fg, ref):
+        both = fluid(tg) & fluid(ref["type"])
+        d = vg[:, both] - ref["vel"][:, both]
+        vel = float(np.sqrt((d ** 2).sum() / (ref["vel"][:, both] ** 2).sum()))
+        bi = (tg == O.INTERFACE) & (ref["type"] == O.INTERFACE)
+        df = np.abs(fg[bi] - ref["fill"][bi])
+        return {"velocity_rel_l2": vel, "fill_max": float(df.max(initial=0.0)),
+                "fill_mean": float(df.mean()) if df.size else 0.0,
+                "type_mismatches": int((tg != ref["type"]).sum())}
+
+    def gpu_run(w, steps, prec, learned=False):
+        g = fsl.lattice_from_workload(w, prec, normals=1 if learned else 0)
+        if learned:
+            g.set_estimator(weights)
+        M0 = g.total_mass()
+        g.step(steps)
+        f = g.read_fields([fsl.FIELD_TYPE, fsl.FIELD_VEL, fsl.FIELD_FILL])
+        drift = abs(g.total_mass() - M0) / M0
+        g.destroy()
+        return f[fsl.FIELD_TYPE], f[fsl.FIELD_VEL], f[fsl.FIELD_FILL], drift
+
+    O.set_threads(0)
+    out = {}
+    w = inputs.flume_crop(nx=128, seed=3)
+    t0 = time.perf_counter()
+    ref = oracle_run(w, crop_steps)
+    floor = oracle_run(w, crop_steps, store="fp16")
+    crop = {"steps": crop_steps, "oracle_seconds": time.perf_counter() - t0,
+            "oracle_fp16_storage": dict(compare(floor["type"], floor["vel"], floor["fill"], ref),
+                                        mass_drift=floor["drift"])}
+    for prec in ("fp64", "fp32", "fp16"):
+        tg, vg, fg, drift = gpu_run(w, crop_steps, prec)
+        crop[prec] = dict(compare(tg, vg, fg, ref), mass_drift=drift)
+    v16 = crop["fp16"]["velocity_rel_l2"]
+    crop["targets"] = {"fp32_velocity_1e-5": crop["fp32"]["velocity_rel_l2"] <= 1e-5,
+                       "fp16_velocity_1e-3": v16 <= 1e-3,
+                       "fp16_within_1.5x_oracle_fp16_floor":
+                           v16 <= 1.5 * crop["oracle_fp16_storage"]["velocity_rel_l2"],
+                       "mass_drift_1e-12": max(crop[p]["mass_drift"] for p in ("fp64", "fp32", "fp16")) <= 1e-12}
+    out[w.name] = crop
+    log("accuracy crop:", json.dumps(crop))
+
+    w = inputs.channel_film()
+    ref = oracle_run(w, film_steps)
+    film = {"steps": film_steps}
+    for prec in ("fp64", "fp32", "fp16"):
+        tg, vg, fg, drift = gpu_run(w, film_steps, prec)
+        film[prec] = dict(compare(tg, vg, fg, ref), mass_drift=drift)
+    if weights is not None:
+        # the oracle runs the network from the same BF16-rounded weights
+        ref_l = oracle_run(w, film_steps, params=gpu_weights(weights))
+        tg, vg, fg, drift = gpu_run(w, film_steps, "fp64", learned=True)
+        film["fp64-learned"] = dict(compare(tg, vg, fg, ref_l), mass_drift=drift)
+        film["learned_vs_plain_oracle"] = compare(ref_l["type"], ref_l["vel"], ref_l["fill"], ref)
+    out[w.name] = film
+    log("accuracy film:", json.dumps(film))
+    return out
+
+
+def dem_only(w, steps=50):
+    """Particle steps alone on the flume's spheres (radius 5, lowest layer
+    fixed, 10 sub-steps, lubrication below 2/3 cell, skin 1 cell, no
+    hydrodynamic load): the command behind the particle kernel trace."""
+    import torch
+
+    from paper_2301_10674_amd import fsl
+
+    c, r = w.centre, w.radius
+    fixed = (c[:, 2] < c[:, 2].min() + 2.0).astype(np.uint8)
+    nu = (1.0 / w.omega - 0.5) / 3.0
+    dem = fsl.Dem(w.shape, c, r, None, None, fixed, viscosity=nu, lub_cut=2.0 / 3.0,
+                  accel=w.accel, substeps=10, skin=1.0)
+    dem.step(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dem.step(None)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    dem.destroy()
+    print(json.dumps({"workload": w.name, "spheres": int(len(r)), "fixed": int(fixed.sum()),
+                      "steps": steps, "substeps": 10, "ms_per_step": ms}), flush=True)
+
+
+def form_summary(v):
+    return {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_us", "bulk_gbs", "mass_drift",
+                                 "interface_error", "estimator", "particle_forces_ms", "particles",
+                                 "steps") if kk in v}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "fp64", "fp32-learned", "fp16-learned"])
-    ap.add_argument("--nx", type=int, default=1536)
-    ap.add_argument("--ny", type=int, default=40)
-    ap.add_argument("--nz", type=int, default=192)
-    ap.add_argument("--forms", default="fp16,fp64,fp32-learned,fp32-variants",
-                    help="other forms timed on the same workload ('' for none): fp16, fp64, fp32, "
-                         "fp32-learned (estimator trained in the run, see train.py), "
-                         "fp32-variants (flux modifiers, normal-weighted excess mass, corner-normal curvature)")
+    ap.add_argument("--precision", default="fp32-learned",
+                    choices=["fp32", "fp16", "fp64", "fp32-learned", "fp16-learned", "fp32-learned-forced"])
+    ap.add_argument("--nx", type=int, default=3072)
+    ap.add_argument("--ny", type=int, default=80)
+    ap.add_argument("--nz", type=int, default=256)
+    ap.add_argument("--forms", default="fp32,fp16,fp32-learned-forced",
+                    help="other forms timed on the same flume ('' for none): fp16, fp64, fp32, "
+                         "fp32-learned (estimator trained in the run, see train.py, used where its gate "
+                         "passes), fp32-learned-forced (the network on whatever its gate says, timed over "
+                         "at most 300 steps), fp32-variants (flux modifiers, normal-weighted excess mass, "
+                         "corner-normal curvature)")
+    ap.add_argument("--sub", default="1536x40x192:fp32,fp16,fp64",
+                    help="a second flume and its forms, NXxNYxNZ:form,form ('' for none)")
+    ap.add_argument("--sub-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy runs against the oracle")
+    ap.add_argument("--no-particles", action="store_true", help="skip the particle and coupled-step timing")
+    ap.add_argument("--dem-only", action="store_true",
+                    help="time particle steps alone on the flume's spheres and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 counter runs of this command and exit")
     ap.add_argument("--trace-summary", metavar="DIR",
@@ -413,24 +614,55 @@ def main():
     fsl.lib()  # fails loudly if the HIP library is missing
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    t_start = time.perf_counter()
     log("building flume %dx%dx%d" % (args.nx, args.ny, args.nz))
     w = inputs.flume(nx=args.nx, ny=args.ny, nz=args.nz, seed=2)
     log("spheres %d, bed height %.2f, surface %.2f" % (w.meta["spheres"], w.meta["bed_height"],
                                                       w.meta["surface"]))
-    main_res = run_form(w, args.precision, args.steps, args.warmup, main_form=args.precision)
+    if args.dem_only:
+        dem_only(w)
+        return
+    meta = dict(w.meta)
+    main_res = run_form(w, args.precision, args.steps, args.warmup, main_form=args.precision,
+                        particles=not args.no_particles)
+    main_res["steps"] = args.steps
     log("main form:", json.dumps(main_res))
     forms = {args.precision: main_res}
     for p in [f for f in args.forms.split(",") if f and f != args.precision]:
-        r = run_form(w, p, max(args.steps // 2, 10), min(args.warmup, 20))
+        k = min(args.steps, 300) if p.endswith("-forced") else args.steps
+        r = run_form(w, p, k, args.warmup)
+        r["steps"] = k
         log("form:", json.dumps(r))
         forms[p] = r
+    del w
+    sub = {}
+    if args.sub:
+        dims, sforms = args.sub.split(":")
+        sx, sy, sz = (int(v) for v in dims.split("x"))
+        ws = inputs.flume(nx=sx, ny=sy, nz=sz, seed=2)
+        entry = {"spheres": ws.meta["spheres"], "cells": ws.ncells, "forms": {}}
+        for p in [f for f in sforms.split(",") if f]:
+            r = run_form(ws, p, args.sub_steps, args.warmup)
+            r["steps"] = args.sub_steps
+            log("sub form %s:" % ws.name, json.dumps(r))
+            entry["forms"][p] = form_summary(r)
+        sub[ws.name] = entry
+        del ws
     copy_gbs = copy_bandwidth()
     log("device copy bandwidth %.0f GB/s" % copy_gbs)
-    cpu = None if args.no_cpu else cpu_baseline()
+    acc = None
+    if not args.no_accuracy:
+        weights = _WEIGHTS.get("w")
+        if weights is None and main_res.get("estimator", {}).get("gate") is not None:
+            weights = trained_estimator(fsl)[0]
+        acc = accuracy_vs_oracle(weights)
+    cpu = None if args.no_cpu else cpu_baseline(args.ny, args.nz)
 
     r = main_res
     base = args.precision.split("-")[0]
-    traffic = stored_traffic(w.name, base)
+    name = "flume_%dx%dx%d" % (args.nx, args.ny, args.nz)
+    traffic = stored_traffic(name, base)
+    est = r.get("estimator")
     out = {
         "metric": "MLUPS free-surface D3Q27 cumulant (FP64/FP32/FP16-store), % HBM roofline",
         "value": r["mlups_fluid"], "unit": "MLUPS (fluid cells)", "n_gpus": 1,
@@ -438,8 +670,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp16": "f16-store/f32", "fp64": "f64"}[base],
         "data": "synthetic seeded flume (no dataset)",
-        "config": {"workload": w.name, "precision": args.precision, "spheres": w.meta["spheres"],
-                   "depth": w.meta["depth"], "cells": w.ncells},
+        "config": {"workload": name, "precision": args.precision,
+                   "estimator": ("finite differences" if not est else
+                                 "learned with finite-difference fallback" if est["network_on"] else
+                                 "learned, gated off (it does not beat finite differences in the flume's "
+                                 "flow): finite differences in every cell"),
+                   "estimator_gate": (est or {}).get("gate"),
+                   "spheres": meta["spheres"], "depth": meta["depth"],
+                   "cells": args.nx * args.ny * args.nz},
         "roofline": {"bound": "hbm", "achieved": r["bulk_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["bulk_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_bulk", "bytes_per_launch": r["bytes_per_launch"],
@@ -450,9 +688,10 @@ def main():
         "cpu_baseline": cpu,
         "mlups_all_cells": r["mlups_all"],
         "mass_drift": r["mass_drift"],
-        "forms": {k: {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_gbs", "mass_drift",
-                                          "interface_error", "estimator", "particle_forces_ms", "particles") if kk in v}
-                  for k, v in forms.items()},
+        "forms": {k: form_summary(v) for k, v in forms.items()},
+        "sub": sub,
+        "accuracy_vs_oracle": acc,
+        "wall_seconds": time.perf_counter() - t_start,
     }
     print(json.dumps(out), flush=True)
 

@@ -15,6 +15,11 @@ Workloads (all lattice units):
   above the bed, hydrostatic density, a parabolic velocity profile above the
   bed with 1 % noise, gravity from Fr = 1.3, slope tan(psi) = 0.044 (Table 2,
   run E1), omega = 1.997 and sigma from We = 15.62 (Table 1, run E1).
+  Fluid pockets that the spheres enclose completely start as gas: the
+  spheres move by prescribed velocities that their cells do not follow, so
+  moving bounce-back on the walls of a closed pocket between spheres of
+  different velocities adds or removes mass there every step, without
+  bound.
 """
 from __future__ import annotations
 
@@ -163,6 +168,75 @@ def bed_height(shape, centre, radius, level=0.3):
     return float(np.mean(hs))
 
 
+def _solid_cells(shape, centre, radius, shrink=1e-9):
+    """Cells whose centre lies within radius - shrink of a sphere centre
+    (periodic in x and y): a subset of the cells the lattice makes solid."""
+    nx, ny, nz = shape
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    zc, yc, xc = (np.arange(n) + 0.5 for n in (nz, ny, nx))
+    for (X, Y, Z), r in zip(centre, radius):
+        r = r - shrink
+        z0, z1 = max(0, int(math.floor(Z - r)) - 1), min(nz, int(math.floor(Z + r)) + 2)
+        yi = np.arange(int(math.floor(Y - r)) - 1, int(math.floor(Y + r)) + 2) % ny
+        xi = np.arange(int(math.floor(X - r)) - 1, int(math.floor(X + r)) + 2) % nx
+        dz = zc[z0:z1, None, None] - Z
+        dy = yc[yi][None, :, None] - Y
+        dy = dy - ny * np.round(dy / ny)
+        dx = xc[xi][None, None, :] - X
+        dx = dx - nx * np.round(dx / nx)
+        inside = dx * dx + dy * dy + dz * dz <= r * r
+        blk = solid[z0:z1][:, yi][:, :, xi] | inside
+        solid[np.ix_(np.arange(z0, z1), yi, xi)] = blk
+    return solid
+
+
+def enclosed_pockets(fill, solid):
+    """Fluid cells (fill > 0, not solid) that no chain of D3Q27 links
+    between fluid cells joins to the free surface (a fluid cell with fill
+    below 1 or with a gas neighbour); the box is periodic in x and y and
+    closed in z.  ``solid`` may miss cells at sphere surfaces: extra fluid
+    cells can only join pockets to the surface, so every cell returned is
+    enclosed."""
+    from scipy import ndimage
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    fluid = (fill > 0.0) & ~solid
+    ball = np.ones((3, 3, 3), dtype=bool)
+    lab, n = ndimage.label(fluid, structure=ball)
+    if n == 0:
+        return np.zeros_like(fluid)
+    # links across the periodic x and y faces (the roll along the face's
+    # other axis wraps too, which covers the links across both at once)
+    a, b = [], []
+    for axis in (2, 1):
+        lo = np.take(lab, 0, axis=axis)
+        hi = np.take(lab, -1, axis=axis)
+        for dz in (-1, 0, 1):
+            for dt in (-1, 0, 1):
+                h = np.roll(hi, dt, axis=1)
+                l2 = lo
+                if dz > 0:
+                    h, l2 = h[dz:], lo[:-dz]
+                elif dz < 0:
+                    h, l2 = h[:dz], lo[-dz:]
+                m = (h > 0) & (l2 > 0)
+                a.append(h[m])
+                b.append(l2[m])
+    a, b = np.concatenate(a), np.concatenate(b)
+    g = coo_matrix((np.ones(len(a)), (a, b)), shape=(n + 1, n + 1))
+    _, comp = connected_components(g, directed=False)
+    gas = (fill <= 0.0) & ~solid
+    near_gas = ndimage.binary_dilation(np.pad(gas, ((0, 0), (1, 1), (1, 1)), mode="wrap"),
+                                       structure=ball)[:, 1:-1, 1:-1]
+    surface = fluid & ((fill < 1.0) | near_gas)
+    if not surface.any():
+        return np.zeros_like(fluid)
+    keep = np.zeros(n + 1, dtype=bool)
+    keep[np.unique(comp[lab[surface]])] = True
+    return fluid & ~keep[comp[lab]]
+
+
 def flume(nx: int = 1536, ny: int = 40, nz: int = 192, seed: int = 2,
           depth: float = 60.0, U: float = 0.02, Fr: float = 1.3,
           We: float = 15.62, slope: float = 0.044, omega: float = 1.997,
@@ -180,6 +254,8 @@ def flume(nx: int = 1536, ny: int = 40, nz: int = 192, seed: int = 2,
     gx = slope * g                       # depth-slope driving, tan(psi)
     sigma = U * U * depth / We           # We = rho U^2 h0 / sigma
     fill = height_fill((nx, ny, nz), np.full((ny, nx), zs))
+    pockets = enclosed_pockets(fill, _solid_cells((nx, ny, nz), centre, radius))
+    fill[pockets] = 0.0
     zc = (np.arange(nz) + 0.5)[:, None, None]
     rho = np.exp(3.0 * g * np.clip(zs - zc, 0.0, None)) * np.ones((1, ny, nx))
     zeta = np.clip((zc - hb) / depth, 0.0, 1.0)
@@ -195,6 +271,7 @@ def flume(nx: int = 1536, ny: int = 40, nz: int = 192, seed: int = 2,
         centre=centre, radius=radius, sphere_vel=svel,
         sphere_angvel=np.zeros((n, 3)),
         meta={"seed": seed, "bed_height": hb, "surface": zs, "spheres": n,
+              "enclosed_cells": int(pockets.sum()),
               "depth": depth, "U": U, "Fr": Fr, "We": We, "slope": slope})
 
 
