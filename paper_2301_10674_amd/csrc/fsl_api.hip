@@ -189,8 +189,8 @@ __global__ void k_init(Dev d, const double *fill, const double *rho, const doubl
     S *pdf0 = (S *)d.pdf[0], *pdf1 = (S *)d.pdf[1];
     for (int i = 0; i < 27; ++i) {
         const S v = to_store<S, R>(e[i]);
-        pdf0[(size_t)i * d.N + c] = v;
-        pdf1[(size_t)i * d.N + c] = v;
+        pdf0[pdf_index(d.nx, i, c)] = v;
+        pdf1[pdf_index(d.nx, i, c)] = v;
     }
 }
 
@@ -229,7 +229,7 @@ __global__ void k_liquid_form(Dev d, int p, int to_q, const uint8_t *mark)
     for (int i = 0; i < 27; ++i) {
         if (i == REST) continue;
         const int y = nbr(d, c, i);
-        if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + (size_t)i * d.N + c);
+        if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + pdf_index(d.nx, i, c));
     }
     d.mq[c] = to_q ? d.mq[c] - fluid : d.mq[c] + fluid;
 }
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void k_uncover_round(Dev d, int p, const int32
                     } else {
                         const S *pdf = (const S *)d.pdf[p];
                         double r = 0.0;
-                        for (int q = 0; q < 27; ++q) r += (double)ld(pdf + (size_t)q * d.N + y);
+                        for (int q = 0; q < 27; ++q) r += (double)ld(pdf + pdf_index(d.nx, q, y));
                         rs = 1.0 + r;
                     }
                 } else if (ty == T_GAS) {
@@ -428,7 +428,7 @@ __global__ void k_uncover_finish(Dev d, int p, const int32_t *list, int n, const
     R e[27];
     feq_dev<R>(R(rn[c] - 1.0), R(u[0]), R(u[1]), R(u[2]), e);
     S *pdf = (S *)d.pdf[p];
-    for (int i = 0; i < 27; ++i) pdf[(size_t)i * d.N + c] = to_store<S, R>(e[i]);
+    for (int i = 0; i < 27; ++i) pdf[pdf_index(d.nx, i, c)] = to_store<S, R>(e[i]);
     if (ty == T_LIQ) {
         d.mq[c] = rn[c];
         d.poolc[c] -= rn[c];
@@ -496,7 +496,7 @@ __global__ void k_refresh_if(Dev d, int p)
     if (c >= d.N || (d.flags[c] & T_MASK) != T_IF) return;
     const S *pdf = (const S *)d.pdf[p];
     double s = 0.0;
-    for (int i = 0; i < 27; ++i) s += (double)ld(pdf + (size_t)i * d.N + c);
+    for (int i = 0; i < 27; ++i) s += (double)ld(pdf + pdf_index(d.nx, i, c));
     d.rho[c] = 1.0 + s;
     d.phi[c] = d.mq[c] / d.rho[c];
 }
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(256) void k_mass_partial(Dev d, int p)
             for (int i = 0; i < 27; ++i) {
                 if (i == REST) continue;
                 const int y = nbr(d, c, i);
-                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + (size_t)i * d.N + c);
+                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + pdf_index(d.nx, i, c));
             }
             m = d.mq[c] + fluid;
         }
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void k_bulkvel_partial(Dev d, int p)
         if (ty != T_LIQ && ty != T_IF) continue;
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < 27; ++i) {
-            const double v = (double)ld(pdf + (size_t)i * N + c);
+            const double v = (double)ld(pdf + pdf_index(d.nx, i, c));
             r += v;
             j[0] += cx(i) * v;
             j[1] += cy(i) * v;
@@ -684,7 +684,7 @@ __global__ void k_read(Dev d, int p, int field, void *out)
             for (int i = 0; i < 27; ++i) {
                 if (i == REST) continue;
                 const int y = nbr(d, c, i);
-                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fl += (double)ld(pdf + (size_t)i * N + c);
+                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fl += (double)ld(pdf + pdf_index(d.nx, i, c));
             }
             m = d.mq[c] + fl;
         }
@@ -698,7 +698,7 @@ __global__ void k_read(Dev d, int p, int field, void *out)
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         if (fluid)
             for (int i = 0; i < 27; ++i) {
-                const double v = (double)ld(pdf + (size_t)i * N + c);
+                const double v = (double)ld(pdf + pdf_index(d.nx, i, c));
                 r += v;
                 j[0] += cx(i) * v;
                 j[1] += cy(i) * v;
@@ -716,7 +716,7 @@ __global__ void k_read(Dev d, int p, int field, void *out)
     }
     case FSL_FIELD_PDF:
         for (int i = 0; i < 27; ++i)
-            ((double *)out)[(size_t)i * N + c] = fluid ? wgt(i) + (double)ld(pdf + (size_t)i * N + c) : 0.0;
+            ((double *)out)[(size_t)i * N + c] = fluid ? wgt(i) + (double)ld(pdf + pdf_index(d.nx, i, c)) : 0.0;
         break;
     case FSL_FIELD_NORMAL: {
         const R4 g = ((const R4 *)d.geom)[c];

@@ -8,7 +8,7 @@ namespace fsl {
 
 // Everything a kernel needs, passed by value.  Per-cell arrays are dense
 // over the whole lattice (cell = x + nx*(y + ny*z)); PDF arrays are
-// direction-major: pdf[i*N + cell].
+// row-interleaved structures of arrays (see pdf_index).
 struct Dev {
     int nx, ny, nz, N;
     int nbx, rows;            // dense grid: x-blocks of 256 cells per (y, z) row
@@ -54,6 +54,22 @@ struct Dev {
 // excess mass (Thuerey 2007), curvature from corner normals (Brackbill et al.
 // 1992), Galilean correction of the cumulant collision (Geier et al. 2015)
 constexpr int VAR_FLUX_MODIFIERS = 1, VAR_NORMAL_EXCESS = 2, VAR_CSF_CURVATURE = 4, VAR_GALILEAN = 8;
+
+// Element of f_i of cell c = x + nx*r (row r = y + ny*z): the 27 direction
+// sub-rows of a row follow one another, f_i(x, r) at (27 r + i) nx + x.
+// Loads along x stay coalesced, and the 27 pulls of a wavefront (from nine
+// rows) and its 27 stores (into its own row) fall into a few pages instead
+// of 54 arrays a whole lattice apart, which would thrash the address
+// translation caches on large lattices.
+__host__ __device__ __forceinline__ size_t pdf_index(int nx, int i, int c)
+{
+    const int r = c / nx;
+    return (size_t)(27 * (size_t)r + (size_t)i) * (size_t)nx + (size_t)(c - r * nx);
+}
+__host__ __device__ __forceinline__ size_t pdf_index(int nx, int i, int r, int x)
+{
+    return (size_t)(27 * (size_t)r + (size_t)i) * (size_t)nx + (size_t)x;
+}
 
 constexpr int BULK_THREADS = 256;
 constexpr int BULK_MAX_BLOCKS = 2048;

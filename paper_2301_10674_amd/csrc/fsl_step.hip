@@ -182,8 +182,9 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
                                           int x, int row, uint8_t fl, Watch &wd)
 {
     using R = typename Real<S>::type;
-    const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
-    const size_t N = (size_t)d.N;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    // the row is the same over the wavefront: its PDF addresses are scalar
+    row = __builtin_amdgcn_readfirstlane(row);
     const int y = row % ny, z = row / ny;
     const int c = x + nx * row;
     const bool near = NEAR && (fl & F_NEAR_SOLID) != 0;
@@ -197,16 +198,16 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
         slot = d.bbslot[c];
     }
 
-    // element offset of the source x - c_i relative to c, per axis and sign
-    // (periodic in x and y; z clamped -- the wall layers are near-solid cells
-    // whose wall links are replaced below)
-    const int DX[3] = {x == nx - 1 ? 1 - nx : 1, 0, x == 0 ? nx - 1 : -1};
-    const int DY[3] = {y == ny - 1 ? (1 - ny) * nx : nx, 0, y == 0 ? (ny - 1) * nx : -nx};
-    const int DZ[3] = {z == nz - 1 ? 0 : nxy, 0, z == 0 ? 0 : -nxy};
+    // source x - c_i: its row (scalar; periodic in y, z clamped -- the wall
+    // layers are near-solid cells whose wall links are replaced below) and
+    // its x (per lane; periodic)
+    const int RY[3] = {y == ny - 1 ? 1 - ny : 1, 0, y == 0 ? ny - 1 : -1};
+    const int RZ[3] = {z == nz - 1 ? 0 : ny, 0, z == 0 ? 0 : -ny};
+    const int XS[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
     R f[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i)
-        f[i] = ld_at(src + (size_t)i * N, (uint32_t)(c + DX[i % 3] + DY[(i / 3) % 3] + DZ[i / 9]));
+        f[i] = ld_at(src + pdf_index(nx, 0, row + RY[(i / 3) % 3] + RZ[i / 9], 0), (uint32_t)(i * nx + XS[i % 3]));
 
     // links whose source is solid or beyond a wall bounce back: the cell's
     // own post-collision value of the opposite direction, plus the
@@ -218,7 +219,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     if (near) {
 #pragma unroll
         for (int j = 0; j < 27; ++j)
-            if (j != REST) fb[j] = ld_at(src + (size_t)opp(j) * N, (uint32_t)c);
+            if (j != REST) fb[j] = ld_at(src + pdf_index(nx, 0, row, 0), (uint32_t)(opp(j) * nx + x));
     }
     load_record<R>(d, slot, rv);
     __builtin_amdgcn_sched_barrier(0);
@@ -249,7 +250,7 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const S v = to_store<S, E>(fo[i]);
-        st_at(dst + (size_t)i * N, (uint32_t)c, v);
+        st_at(dst + pdf_index(nx, 0, row, 0), (uint32_t)(i * nx + x), v);
         if (i != REST) out_sum += ((solid >> opp(i)) & 1u) ? 0.0 : (double)ld(&v);
     }
     // liquid cells keep m - own outgoing: m' = (m - out) + in over non-solid links
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(256) void k_mem(Dev d, int p, const int32_t *offs, 
             const double ux = sp[4] + (sp[8] * rz - sp[9] * ry);
             const double uy = sp[5] + (sp[9] * rx - sp[7] * rz);
             const double uz = sp[6] + (sp[7] * ry - sp[8] * rx);
-            const double fout = wgt(opp(j)) + (double)ld(pdf + (size_t)opp(j) * N + c);
+            const double fout = wgt(opp(j)) + (double)ld(pdf + pdf_index(nx, opp(j), c));
             const double fin = fout + 6.0 * wgt(j) * (cx(j) * ux + cy(j) * uy + cz(j) * uz);
             const double Fx = (-cx(j) - ux) * fout - (cx(j) - ux) * fin;
             const double Fy = (-cy(j) - uy) * fout - (cy(j) - uy) * fin;
@@ -684,6 +685,14 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     const int OZ[3] = {-nxy, 0, nxy};
     const bool WZ[3] = {z == 0, false, z == nz - 1};
     auto nb = [&](int i) { return WZ[i / 9] ? -1 : c + OX[i % 3] + OY[(i / 3) % 3] + OZ[i / 9]; };
+    // PDF element of direction k at the neighbour x + c_i (the cell itself
+    // beyond a z wall)
+    const int RY[3] = {y == 0 ? ny - 1 : -1, 0, y == ny - 1 ? 1 - ny : 1};
+    const int RZ[3] = {-ny, 0, ny};
+    auto pdf_nb = [&](int k, int i) {
+        return WZ[i / 9] ? pdf_index(nx, k, row, x)
+                         : pdf_index(nx, k, row + RY[(i / 3) % 3] + RZ[i / 9], x + OX[i % 3]);
+    };
 
     // stage 1: neighbour types (walls count as solid, 2 bits each) and the
     // fill stencil (liquid 1, gas 0, interface clamped fill, solid the centre)
@@ -705,10 +714,9 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     R own[27], pulled[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        own[i] = ld_at(src + (size_t)i * N, (uint32_t)c);
+        own[i] = ld(src + pdf_index(nx, i, row, x));
         // source of incoming i is x - c_i = neighbour opp(i)
-        const int s = nb(opp(i));
-        pulled[i] = ld_at(src + (size_t)i * N, (uint32_t)(s < 0 ? c : s));
+        pulled[i] = ld(src + pdf_nb(i, opp(i)));
     }
     double mq0 = d.mq[c];
     __builtin_amdgcn_sched_barrier(0);
@@ -843,7 +851,7 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const S v = to_store<S, Et>(fo[i]);
-        st_at(dst + (size_t)i * N, (uint32_t)c, v);
+        __builtin_nontemporal_store(v, dst + pdf_index(nx, i, row, x));
         rs += (double)ld(&v);
     }
     const double rho = 1.0 + rs;
@@ -1036,7 +1044,7 @@ __device__ __forceinline__ void stored_sums(const Dev &d, const S *pdf, int c, c
     all = 0.0;
     fluid = 0.0;
     for (int i = 0; i < 27; ++i) {
-        const double v = (double)ld(pdf + (size_t)i * N + c);
+        const double v = (double)ld(pdf + pdf_index(d.nx, i, c));
         all += v;
         if (i == REST) continue;
         const int y = nb_of(d, pc, i);
@@ -1066,7 +1074,7 @@ __device__ __forceinline__ void conv2_cell(const Dev &d, int p, uint32_t epoch, 
                 if (mark_bits(d.mark[y], epoch) & MK_TO_GAS) continue;
                 double r = 0.0, j[3] = {0.0, 0.0, 0.0};
                 for (int k = 0; k < 27; ++k) {
-                    const double v = (double)ld(pdf + (size_t)k * N + y);
+                    const double v = (double)ld(pdf + pdf_index(d.nx, k, y));
                     r += v;
                     j[0] += cx(k) * v;
                     j[1] += cy(k) * v;
@@ -1084,7 +1092,7 @@ __device__ __forceinline__ void conv2_cell(const Dev &d, int p, uint32_t epoch, 
             double sum = 0.0;
             for (int i = 0; i < 27; ++i) {
                 const S v = to_store<S, Et>(e[i]);
-                pdf[(size_t)i * N + c] = v;
+                pdf[pdf_index(d.nx, i, c)] = v;
                 sum += (double)ld(&v);
             }
             d.mq[c] = 0.0;

@@ -7,6 +7,7 @@ emulation's allocator, and the stream is NULL.
 from __future__ import annotations
 
 import ctypes
+import glob
 import os
 
 import numpy as np
@@ -17,11 +18,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
 
+def _stale(p):
+    """The library is missing or older than a source it is built from."""
+    if not os.path.exists(p):
+        return True
+    root = os.path.dirname(os.path.dirname(HERE))
+    srcs = glob.glob(os.path.join(root, "paper_2301_10674_amd", "csrc", "*"))
+    srcs += glob.glob(os.path.join(HERE, "hip", "*")) + [os.path.join(HERE, f) for f in ("hostemu.cpp", "build.py")]
+    srcs.append(os.path.join(root, "include", "fsl.h"))
+    t = os.path.getmtime(p)
+    return any(os.path.getmtime(f) > t for f in srcs if os.path.isfile(f))
+
+
 def lib(path=None):
     global _lib
     if _lib is None:
         p = path or os.path.join(HERE, "_build", "libfsl_emu.so")
-        if not os.path.exists(p):
+        if path is None and _stale(p):
             import importlib.util
             spec = importlib.util.spec_from_file_location("hostemu_build", os.path.join(HERE, "build.py"))
             mod = importlib.util.module_from_spec(spec)

@@ -30,6 +30,7 @@
 #define __forceinline__ inline
 #define __shared__ static
 #define __launch_bounds__(...)
+#define __align__(n) __attribute__((aligned(n)))
 #define HIP_SYMBOL(x) (&(x))
 
 // ---------------------------------------------------------------- vector types
@@ -144,6 +145,11 @@ template <class T> inline T __shfl_up(T v, unsigned delta, int = 64)
     const int s = l - (int)delta;
     return hipemu::from_bits<T>(hipemu::wave_exchange(hipemu::to_bits(v), s < 0 ? l : s));
 }
+// The library applies readfirstlane only to values that are the same on
+// every lane (it moves them to scalar registers), and may do so inside
+// divergent code, where a lane exchange cannot run: the lane's own value is
+// the wavefront's.
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 inline int __ffsll(unsigned long long v) { return __builtin_ffsll((long long)v); }
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
@@ -228,3 +234,8 @@ hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipGetSymbolAddress(void **p, const void *sym);
+inline hipError_t hipGetDevice(int *dev)
+{
+    *dev = 0;
+    return hipSuccess;
+}

@@ -11,9 +11,10 @@ by more than 1e-10 relative from the exact total after set-up.
   exact fixed-order total to 1e-13 relative;
 * a liquid region created at density 1.6 trips the density check on the
   first checked step, and the state stays readable;
-* mass created by a poke into the stored PDFs (the current PDFs are the 27
-  direction arrays at the start of the workspace before the first step)
-  trips the drift check on the next checked step, not before;
+* mass created by a poke into the stored PDFs (the current PDFs are the
+  first PDF array of the workspace before the first step; f_i of cell
+  (x, y, z) is element (27 (y + ny z) + i) nx + x) trips the drift check on
+  the next checked step, not before;
 * a flow compressed beyond density 1.5 by strong gravity is stopped with
   FSL_ERR_UNSTABLE on the first checked step past it.
 """
@@ -74,7 +75,7 @@ def test_mass_drift_is_caught():
     assert t[z, y, x] == f.LIQUID and (t[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2] == f.LIQUID).all()
     pdf = g.workspace[:27 * N * 8].view(dtype=__import__("torch").float64)
     i = 1 + 3 * 1 + 9 * 2                 # c = (0, 0, +1), pulled by the cell above
-    pdf[i * N + x + nx * (y + ny * z)] += 1e-4
+    pdf[(27 * (y + ny * z) + i) * nx + x] += 1e-4
     g.step(2)                             # no check yet
     with pytest.raises(f.FslError) as e:
         g.step(1)
