@@ -342,8 +342,12 @@ def run_form(w, form, steps, warmup, main_form=None, particles=True):
     t1 = time.perf_counter()
     lat.timing(False)
     bulk_ms, launches = lat.timing_read()
+    # the global mass right after steps (from the last step's partials)
+    t0m = time.perf_counter()
+    for _ in range(10):
+        M1 = lat.total_mass()
+    total_mass_us = 1e6 * (time.perf_counter() - t0m) / 10
     liq1, itf1 = fluid_counts(lat, fsl)
-    M1 = lat.total_mass()
     secs = t1 - t0
     liq = 0.5 * (liq0 + liq1)
     fluid = 0.5 * (liq0 + itf0 + liq1 + itf1)
@@ -361,7 +365,7 @@ def run_form(w, form, steps, warmup, main_form=None, particles=True):
         bulk_gbs=bytes_per_launch / bulk_avg_s / 1e9, bytes_per_launch=bytes_per_launch,
         step_gbs=bytes_per_step / (secs / steps) / 1e9, bytes_per_step=bytes_per_step,
         liquid_cells=liq, fluid_cells=fluid, interface_cells=0.5 * (itf0 + itf1),
-        mass_drift=abs(M1 - M0) / M0, interface_error=interface_error(lat, fsl))
+        mass_drift=abs(M1 - M0) / M0, total_mass_us=total_mass_us, interface_error=interface_error(lat, fsl))
     if learned:
         used1 = lat.estimator_stats() if on else (0, 0)
         res["estimator"] = dict(est, network_on=on, network_cells=used1[0] - used0[0],
@@ -562,7 +566,7 @@ def dem_only(w, steps=50):
 
 
 def form_summary(v):
-    return {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_us", "bulk_gbs", "mass_drift",
+    return {kk: v[kk] for kk in ("mlups_fluid", "ms_per_step", "bulk_us", "bulk_gbs", "mass_drift", "total_mass_us",
                                  "interface_error", "estimator", "particle_forces_ms", "particles",
                                  "steps") if kk in v}
 

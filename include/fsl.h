@@ -178,11 +178,12 @@ FslStatus fsl_set_particles(FslLattice *lat, int32_t n, const double *centre,
  * step is the fluid update of Section 2.1 (pull streaming with bounce-back,
  * gas-side reconstruction, mass flux, cumulant collision), then interface
  * conversion with excess-mass redistribution and the interface geometry.
- * Watchdog: on every check_every-th step the step kernels also reduce, per
- * block and then in one fixed-order pass, the total mass (liquid and
- * interface mass before the step's conversions, which only move mass, plus
- * the excess-mass pool) and the range of the fluid cells' densities; the
- * step then synchronises and returns FSL_ERR_UNSTABLE when the mass is not
+ * Every step's kernels also leave per-block partials of the total mass
+ * (liquid and interface mass before the step's conversions, which only
+ * move mass) and of the range of the fluid cells' densities, and the
+ * excess-mass pool before the conversions (Section 2.1's mass
+ * conservation).  Watchdog: on every check_every-th step the partials are
+ * reduced in one fixed-order pass and the step then synchronises and returns FSL_ERR_UNSTABLE when the mass is not
  * finite, when some density lies outside [0.5, 1.5] (or is not a number), or
  * when the mass differs from the reference mass (the exact total of
  * fsl_total_mass() after fsl_create_lattice() or fsl_set_particles()) by
@@ -213,7 +214,12 @@ FslStatus fsl_read_fields(FslLattice *lat, uint32_t field_mask, void *const *dst
 
 /* Total liquid mass: sum of m over liquid and interface cells plus the pool
  * of excess mass that found no interface neighbour (FP64, fixed summation
- * order).  Synchronises the lattice's stream. */
+ * order; Section 2.1's mass bookkeeping).  Right after fsl_step() it is the
+ * fixed-order sum of the last step's partials (one small kernel); otherwise
+ * (after set-up or a remap that changed cell types) a pass over the
+ * lattice recomputes it from the stored masses and PDFs.  The two agree to
+ * rounding (the step's conversions only move mass).  Synchronises the
+ * lattice's stream. */
 FslStatus fsl_total_mass(FslLattice *lat, double *mass);
 
 /* Cumulative conversion counters since creation: [0] filled by the mass

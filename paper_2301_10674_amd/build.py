@@ -6,12 +6,17 @@ instructions disabled.
 
 The compiler's per-kernel resource report (``-Rpass-analysis=kernel-
 resource-usage``) is kept in ``_build/kernel_resources.txt`` and checked:
-the build fails if any kernel needs a private (scratch) segment.  Every
+the build fails if any kernel accesses a private (scratch) segment.  Every
 kernel of the library keeps its values in registers -- VGPRs, and AGPRs as
-the compiler's spill space, which needs no memory -- so a scratch segment
+the compiler's spill space, which needs no memory -- so a scratch access
 means an array the compiler could not keep in registers (an index it could
 not resolve at compile time, or register pressure beyond the register file),
-which is a change to look at before it runs.
+which is a change to look at before it runs.  A kernel at the edge of the
+register file may be given a segment that no instruction touches (the
+register allocator's emergency slot); for every kernel that reports a
+segment the device assembly is generated and searched for scratch and
+buffer instructions (the library issues none of either otherwise), and only
+an access fails the build.
 """
 from __future__ import annotations
 
@@ -58,8 +63,25 @@ def kernel_resources(remarks: str) -> dict:
 
 
 def check_resources(res: dict) -> list:
-    """Kernels that need a scratch segment."""
+    """Kernels that report a scratch segment."""
     return [k for k, v in res.items() if v.get("ScratchSize [bytes/lane]", "0") != "0"]
+
+
+def scratch_accesses(src: str, kernels: list) -> dict:
+    """{kernel: number of scratch or buffer instructions} in the device
+    assembly of src."""
+    asm = subprocess.run([hipcc(), *[f for f in HIPCC_FLAGS if not f.startswith("-Rpass")], "--offload-device-only",
+                          "-S", src, "-o", "-"], capture_output=True, text=True, check=True).stdout
+    out = {}
+    for k in kernels:
+        i = asm.find("\n" + k + ":")
+        j = asm.find(".Lfunc_end", i)
+        if i < 0 or j < 0:
+            out[k] = -1
+            continue
+        out[k] = sum(1 for l in asm[i:j].splitlines()
+                     if re.match(r"\s+(scratch_|buffer_)", l))
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -84,7 +106,13 @@ def build(verbose: bool = False) -> str:
             table.append("%-14s %-70s VGPR %4s AGPR %4s VGPR-spill %3s scratch %4s occupancy %s" % (
                 src, k, v.get("VGPRs"), v.get("AGPRs"), v.get("VGPRs Spill"),
                 v.get("ScratchSize [bytes/lane]"), v.get("Occupancy [waves/SIMD]")))
-        bad += ["%s: %s" % (src, k) for k in check_resources(res)]
+        seg = check_resources(res)
+        if seg:
+            for k, n in scratch_accesses(os.path.join(CSRC, src), seg).items():
+                if n != 0:
+                    bad.append("%s: %s (%s scratch or buffer instructions)" % (src, k, n if n > 0 else "unknown"))
+                else:
+                    table.append("%-14s %-70s reserves a private segment that no instruction accesses" % (src, k))
         objs.append(obj)
     with open(os.path.join(objdir, "kernel_resources.txt"), "w") as fh:
         fh.write("\n".join(table) + "\n")

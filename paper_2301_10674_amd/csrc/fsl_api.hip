@@ -23,6 +23,7 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch
                  hipEvent_t ev0, hipEvent_t ev1, const float *mlpP, const uint16_t *mlpPk);
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
+void launch_watch_final(const Dev &d, int list_blocks, hipStream_t st);
 void launch_setup_links(const Dev &d, hipStream_t st);
 void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st);
 void launch_mem_fill(const Dev &d, int nsph, const int32_t *offs, int2 *ent, hipStream_t st);
@@ -82,6 +83,7 @@ struct FslLattice {
     size_t read_cap = 0;
     bool timing = false;
     double mass_ref = 0.0;    // watchdog: total mass after set-up (fsl_total_mass)
+    bool mass_fast = false;   // the last call was fsl_step: its mass partials are current
     double watch_last[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t ev_used = 0;
@@ -516,63 +518,63 @@ __global__ void k_zero_counts(Dev d, int stats)
 
 // ---------------------------------------------------------------- reductions
 // total mass, fixed order: block partials, then one block over the partials
+// sum of v over a block of 256 threads in a fixed order (butterflies within
+// each wavefront, then the four wavefronts in order); the result in thread 0
+__device__ __forceinline__ double block_sum256(double v)
+{
+    __shared__ double s_w[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (__lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
+// Exact total mass, in a fixed order: per block, the interface masses, the
+// liquid masses (stored m minus own outgoing, plus the outgoing PDFs over
+// the links that do not end in a solid or beyond a wall: the solid-link
+// mask of the opposite direction) and the per-cell pool; one block sums the
+// block partials.
 template <class S>
 __global__ __launch_bounds__(256) void k_mass_partial(Dev d, int p)
 {
-    __shared__ double sh[256];
     const S *pdf = (const S *)d.pdf[p];
+    const int nx = d.nx;
     double acc = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) {
         const uint8_t ty = d.flags[c] & T_MASK;
-        double m = 0.0;
+        double m = d.poolc[c];
         if (ty == T_IF) {
-            m = d.mq[c];
+            m += d.mq[c];
         } else if (ty == T_LIQ) {
-            double fluid = 0.0;
-            for (int i = 0; i < 27; ++i) {
-                if (i == REST) continue;
-                const int y = nbr(d, c, i);
-                if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + pdf_index(d.nx, i, c));
-            }
-            m = d.mq[c] + fluid;
+            const int row = c / nx;
+            const S *f = pdf + pdf_index(nx, 0, row, c - row * nx);
+            const uint32_t sm = d.smask[c];
+            double out = 0.0;
+            for (int i = 0; i < 27; ++i)
+                if (i != REST && !((sm >> opp(i)) & 1u)) out += (double)ld(f + (size_t)i * nx);
+            m += d.mq[c] + out;
         }
-        acc += m + d.poolc[c];
+        acc += m;
     }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) d.partial[blockIdx.x] = sh[0];
+    acc = block_sum256(acc);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(Dev d, int n, int out_slot)
 {
-    __shared__ double sh[256];
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) acc += d.partial[i];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) d.partial[out_slot] = sh[0];
+    acc = block_sum256(acc);
+    if (threadIdx.x == 0) d.partial[out_slot] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_pool_partial(Dev d)
 {
-    __shared__ double sh[256];
     double acc = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) acc += d.poolc[c];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) d.partial[blockIdx.x] = sh[0];
+    acc = block_sum256(acc);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = acc;
 }
 
 // bulk velocity: per-block partial sums of fill * u (3 components) and of
@@ -855,6 +857,7 @@ static void run_uncover_finish(FslLattice *L, const int32_t *list, int n, const 
 static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done = false)
 {
     Dev &d = L->d;
+    L->mass_fast = false;
     if (!near_done) k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_refresh, L);
     k_zero_counts<<<1, 64, 0, L->st>>>(d, reset_stats ? 1 : 0);
@@ -1404,6 +1407,7 @@ FslStatus fsl_step(FslLattice *L, int32_t nsteps)
         }
         L->parity ^= 1;
         ++L->steps;
+        L->mass_fast = true;
         if (watch) {
             FslStatus r = check_watch(L);
             if (r != FSL_OK) return r;
@@ -1470,9 +1474,18 @@ FslStatus fsl_read_fields(FslLattice *L, uint32_t mask, void *const *dst, int32_
 FslStatus fsl_total_mass(FslLattice *L, double *mass)
 {
     if (!L || !mass) return fail(FSL_ERR_ARG, "NULL argument");
-    DISPATCH(L, run_mass, L);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(mass, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
+    if (L->mass_fast) {
+        // right after steps: the last step's block partials (liquid mass
+        // after streaming, interface mass after the flux) and the pool
+        // before its conversions, which only move mass
+        launch_watch_final(L->d, L->list_blocks, L->st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(mass, L->d.wd + WD_OUT, 8, hipMemcpyDeviceToHost, L->st));
+    } else {
+        DISPATCH(L, run_mass, L);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(mass, L->d.partial + RED_BLOCKS, 8, hipMemcpyDeviceToHost, L->st));
+    }
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
 }

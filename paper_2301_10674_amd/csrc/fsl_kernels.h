@@ -83,6 +83,7 @@ constexpr int WD_BULK = 0;
 constexpr int WD_IFACE = 4 * BULK_MAX_BLOCKS;
 constexpr int WD_OUT = WD_IFACE + 4 * 2048;
 constexpr int WD_POOL = WD_OUT + 4;
+constexpr int WD_POOL_SNAP = WD_OUT + 5;  // the pool total before this step's conversions
 constexpr int WD_SIZE = WD_OUT + 8;
 constexpr double WD_RHO_MIN = 0.5, WD_RHO_MAX = 1.5;
 

@@ -211,7 +211,9 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
 
     // links whose source is solid or beyond a wall bounce back: the cell's
     // own post-collision value of the opposite direction, plus the
-    // precomputed moving-wall term of sphere links (zero for wall links)
+    // precomputed moving-wall term of sphere links (zero for wall links).
+    // In FP32 only the lanes whose link is solid load it (fewer bytes; the
+    // FP16 and FP64 forms run slower with the per-link masks).
     R fb[27];
 #pragma unroll
     for (int j = 0; j < 27; ++j) fb[j] = R(0);
@@ -219,7 +221,8 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     if (near) {
 #pragma unroll
         for (int j = 0; j < 27; ++j)
-            if (j != REST) fb[j] = ld_at(src + pdf_index(nx, 0, row, 0), (uint32_t)(opp(j) * nx + x));
+            if (j != REST && (sizeof(S) != 4 || ((solid >> j) & 1u)))
+                fb[j] = ld_at(src + pdf_index(nx, 0, row, 0), (uint32_t)(opp(j) * nx + x));
     }
     load_record<R>(d, slot, rv);
     __builtin_amdgcn_sched_barrier(0);
@@ -948,15 +951,15 @@ __global__ __launch_bounds__(LIST_THREADS) void k_iface(Dev d, int p, uint32_t e
 }
 
 // Dense stream-collide over the liquid rows; GC: with the Galilean
-// correction of the collision.  watch != 0: each block writes its watchdog
-// partial (liquid mass after streaming, density range) to
-// wd[WD_BULK + 4 block].
+// correction of the collision.  Each block writes its partial of the
+// watchdog and of the global mass (liquid mass after streaming, density
+// range) to wd[WD_BULK + 4 block].
 template <class S, bool GC>
-__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p, int watch)
+__global__ __launch_bounds__(BULK_THREADS) void k_bulk(Dev d, int p)
 {
     Watch wd;
     dense_rows<S, GC>(d, (const S *)d.pdf[p], (S *)d.pdf[p ^ 1], (int)blockIdx.x, (int)gridDim.x, wd);
-    if (watch) block_watch<BULK_THREADS>(wd, d.wd + WD_BULK + 4 * blockIdx.x);
+    block_watch<BULK_THREADS>(wd, d.wd + WD_BULK + 4 * blockIdx.x);
 }
 
 // Watchdog result of a step: the partials of the nb dense and ni interface
@@ -977,7 +980,7 @@ __global__ __launch_bounds__(256) void k_watch_final(Dev d, int nb, int ni)
     }
     block_watch<256>(w, d.wd + WD_OUT);
     __syncthreads();
-    if (threadIdx.x == 0) d.wd[WD_OUT] += d.wd[WD_POOL];
+    if (threadIdx.x == 0) d.wd[WD_OUT] += d.wd[WD_POOL_SNAP];
 }
 
 // ---------------------------------------------------------------- conversion
@@ -991,16 +994,18 @@ __device__ __forceinline__ void push_new(const Dev &d, int c, uint32_t epoch, un
     }
 }
 
-// watch != 0: each block also writes the watchdog partial of its interface
-// cells (mass after the flux, density) to wd[WD_IFACE + 4 block].
-__global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t epoch, int watch)
+// Each block also writes the watchdog and global-mass partial of its
+// interface cells (mass after the flux, density) to wd[WD_IFACE + 4 block],
+// and block 0 keeps the pool total before this step's conversions.
+__global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t epoch)
 {
     const int32_t *list = d.list[p];
     const int count = d.cnt[p];
     Watch wd;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.wd[WD_POOL_SNAP] = d.wd[WD_POOL];
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
         const int c = list[t];
-        if (watch) wd.add(d.mq[c], d.rho[c]);
+        wd.add(d.mq[c], d.rho[c]);
         const uint32_t mk = mark_bits(d.mark[c], epoch);
         if (!(mk & (MK_TO_LIQ | MK_TO_GAS))) continue;
         const Cell pc = cell_xyz(d, c);
@@ -1031,7 +1036,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_conv1(Dev d, int p, uint32_t e
             }
         }
     }
-    if (watch) block_watch<LIST_THREADS>(wd, d.wd + WD_IFACE + 4 * blockIdx.x);
+    block_watch<LIST_THREADS>(wd, d.wd + WD_IFACE + 4 * blockIdx.x);
 }
 
 // sum of a cell's stored deviations over all directions (all) and over the
@@ -1332,20 +1337,33 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
 }
 
 // ---------------------------------------------------------------- launchers
+// workgroups of the persistent dense kernel
+static int bulk_grid(const Dev &d)
+{
+    int gb = d.nbx * d.rows;
+    if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
+    if (d.xcd_map) gb &= ~7;
+    return gb;
+}
+
+// the watchdog result (and global mass) of the last step from its partials
+void launch_watch_final(const Dev &d, int list_blocks, hipStream_t st)
+{
+    k_watch_final<<<1, 256, 0, st>>>(d, bulk_grid(d), list_blocks);
+}
+
 template <class S>
 void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1, const float *mlpP, const uint16_t *mlpPk)
 {
     using R = typename Real<S>::type;
-    int gb = d.nbx * d.rows;
-    if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
-    if (d.xcd_map) gb &= ~7;
+    const int gb = bulk_grid(d);
     const bool gc = (d.variants & VAR_GALILEAN) != 0;
     if (ev0) (void)hipEventRecord(ev0, st);
     if (gc)
-        k_bulk<S, true><<<gb, BULK_THREADS, 0, st>>>(d, p, watch);
+        k_bulk<S, true><<<gb, BULK_THREADS, 0, st>>>(d, p);
     else
-        k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p, watch);
+        k_bulk<S, false><<<gb, BULK_THREADS, 0, st>>>(d, p);
     if (ev1) (void)hipEventRecord(ev1, st);
     if (d.variants & VAR_FLUX_MODIFIERS) k_classes<<<list_blocks, LIST_THREADS, 0, st>>>(d, p);
     if (mlpP) {
@@ -1355,7 +1373,7 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch
         if (gc) k_iface<S, true, true><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
         else k_iface<S, true, false><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     }
-    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch, watch);
+    k_conv1<<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);
     // the watchdog result is complete before the conversions touch the pool
     if (watch) k_watch_final<<<1, 256, 0, st>>>(d, gb, list_blocks);
     k_conv23<S><<<list_blocks, LIST_THREADS, 0, st>>>(d, p, epoch);

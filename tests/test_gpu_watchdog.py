@@ -45,6 +45,41 @@ def test_healthy_run_passes_every_check():
     g.destroy()
 
 
+def test_total_mass_after_steps_matches_oracle():
+    """Right after steps the total mass comes from the last step's block
+    partials (and the pool before its conversions); it equals the oracle's
+    exact total, and the exact recomputation of the set-up state."""
+    from oracle import oracle as O
+
+    f = F()
+    w = I.film_with_surface_spheres(sigma=1e-3)
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, rho_gas=w.rho_gas,
+                        conv_eps=w.conv_eps, fill=w.fill, rho=w.rho, vel=w.vel)
+    o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    g = f.lattice_from_workload(w, "fp64")
+    m0 = g.total_mass()                     # exact pass (nothing stepped yet)
+    assert abs(m0 - o.total_mass()) <= 1e-13 * m0
+    for k in range(3):
+        g.step(7)
+        o.step(7)
+        m = g.total_mass()
+        assert abs(m - o.total_mass()) <= 1e-13 * m, (k, m, o.total_mass())
+        assert abs(m - m0) <= 1e-13 * m0
+    g.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_total_mass_after_steps_is_conserved(prec):
+    f = F()
+    w = I.splash(shape=(24, 16, 20))
+    g = f.lattice_from_workload(w, prec)
+    m0 = g.total_mass()
+    g.step(30)
+    m1 = g.total_mass()
+    assert abs(m1 - m0) <= 1e-12 * m0, (m0, m1)
+    g.destroy()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_density_out_of_range_is_caught(prec):
     f = F()
