@@ -123,18 +123,31 @@ __device__ __forceinline__ void feq_dev(R drho, R ux, R uy, R uz, R out[27])
 
 // ---------------------------------------------------------------- collision
 // One 1D inverse chimera step: central moments (k0,k1,k2) about u ->
-// values at velocities -1, 0, +1.
+// values at velocities -1, 0, +1:
+//   f0 = (1 - u^2) k0 - 2u k1 - k2,
+//   f-/+ = ((u^2 -/+ u) k0 + (2u -/+ 1) k1 + k2) / 2.
+// The coefficients depend on u only and are formed once per pass.
 template <class R>
-__device__ __forceinline__ void inv_chimera(R &a, R &b, R &c, R u)
-{
-    R k0 = a, k1 = b, k2 = c, uu = u * u;
-    R f0 = k0 * (R(1) - uu) - R(2) * u * k1 - k2;
-    R fm = R(0.5) * (k0 * (uu - u) + k1 * (R(2) * u - R(1)) + k2);
-    R fp = R(0.5) * (k0 * (uu + u) + k1 * (R(2) * u + R(1)) + k2);
-    a = fm;
-    b = f0;
-    c = fp;
-}
+struct Chimera {
+    R a0, a1, m0, m1, p0, p1;
+    __device__ __forceinline__ explicit Chimera(R u)
+    {
+        const R uu = u * u;
+        a0 = R(1) - uu;
+        a1 = R(-2) * u;
+        m0 = R(0.5) * (uu - u);
+        m1 = u - R(0.5);
+        p0 = R(0.5) * (uu + u);
+        p1 = u + R(0.5);
+    }
+    __device__ __forceinline__ void apply(R &a, R &b, R &c) const
+    {
+        const R k0 = a, k1 = b, k2 = c, h = R(0.5) * k2;
+        a = m0 * k0 + (m1 * k1 + h);
+        b = a0 * k0 + (a1 * k1 - k2);
+        c = p0 * k0 + (p1 * k1 + h);
+    }
+};
 
 // Cumulant collision (Geier et al. 2015, as chosen in Section 2.1: shear
 // rate omega, bulk and all higher-order rates 1) on PDF deviations
@@ -157,52 +170,46 @@ template <class R, class E, bool GC = false>
 __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz, E out[27], double &rho_out)
 {
     // Raw moments of the deviations, passes x, y, z of (sum, odd, even), in
-    // FP64 in every form: the non-equilibrium second moments are small
-    // differences of O(1e-3) sums, which FP32 would resolve only to a few
-    // times the storage rounding.  FP64 adds issue at the FP32 rate here.
-    double m[27];
+    // M = FP64 with FP64 and FP32 storage: the non-equilibrium second
+    // moments are small differences of O(1e-3) sums, which FP32 would
+    // resolve only to a few times the FP32 storage rounding (FP64 adds issue
+    // at the unpacked FP32 rate).  With FP16 storage its own rounding is far
+    // coarser and the moments are taken in FP32.
+    using M = E;
+    M m[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) m[i] = (double)d[i];
+    for (int i = 0; i < 27; ++i) m[i] = (M)d[i];
+    auto pass = [&](int i0, int i1, int i2) {
+        const M vm = m[i0], v0 = m[i1], vp = m[i2], s = vp + vm;
+        m[i0] = s + v0;
+        m[i1] = vp - vm;
+        m[i2] = s;
+    };
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            double vm = m[MI(0, b, c)], v0 = m[MI(1, b, c)], vp = m[MI(2, b, c)];
-            m[MI(0, b, c)] = vm + v0 + vp;
-            m[MI(1, b, c)] = vp - vm;
-            m[MI(2, b, c)] = vp + vm;
-        }
+        for (int b = 0; b < 3; ++b) pass(MI(0, b, c), MI(1, b, c), MI(2, b, c));
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double vm = m[MI(a, 0, c)], v0 = m[MI(a, 1, c)], vp = m[MI(a, 2, c)];
-            m[MI(a, 0, c)] = vm + v0 + vp;
-            m[MI(a, 1, c)] = vp - vm;
-            m[MI(a, 2, c)] = vp + vm;
-        }
+        for (int a = 0; a < 3; ++a) pass(MI(a, 0, c), MI(a, 1, c), MI(a, 2, c));
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double vm = m[MI(a, b, 0)], v0 = m[MI(a, b, 1)], vp = m[MI(a, b, 2)];
-            m[MI(a, b, 0)] = vm + v0 + vp;
-            m[MI(a, b, 1)] = vp - vm;
-            m[MI(a, b, 2)] = vp + vm;
-        }
-    const double drho_d = m[MI(0, 0, 0)];
-    const double rho_d = 1.0 + drho_d;
-    rho_out = rho_d;
-    const double irho_d = 1.0 / rho_d;
-    const double jxd = m[MI(1, 0, 0)], jyd = m[MI(0, 1, 0)], jzd = m[MI(0, 0, 1)];
-    const double uxd = (jxd + 0.5 * rho_d * (double)gx) * irho_d;
-    const double uyd = (jyd + 0.5 * rho_d * (double)gy) * irho_d;
-    const double uzd = (jzd + 0.5 * rho_d * (double)gz) * irho_d;
-    const double dtr = drho_d * irho_d * (1.0 / 3.0);
+        for (int a = 0; a < 3; ++a) pass(MI(a, b, 0), MI(a, b, 1), MI(a, b, 2));
+    const M drho_d = m[MI(0, 0, 0)];
+    const M rho_d = M(1) + drho_d;
+    rho_out = (double)rho_d;
+    const M irho_d = M(1) / rho_d;
+    const M jxd = m[MI(1, 0, 0)], jyd = m[MI(0, 1, 0)], jzd = m[MI(0, 0, 1)];
+    const M uxd = (jxd + M(0.5) * rho_d * (M)gx) * irho_d;
+    const M uyd = (jyd + M(0.5) * rho_d * (M)gy) * irho_d;
+    const M uzd = (jzd + M(0.5) * rho_d * (M)gz) * irho_d;
+    const M dtr = drho_d * irho_d * M(1.0 / 3.0);
     // second-order central moments minus I/3
-    const R Kxx = R((m[MI(2, 0, 0)] - 2.0 * uxd * jxd) * irho_d + uxd * uxd - dtr);
-    const R Kyy = R((m[MI(0, 2, 0)] - 2.0 * uyd * jyd) * irho_d + uyd * uyd - dtr);
-    const R Kzz = R((m[MI(0, 0, 2)] - 2.0 * uzd * jzd) * irho_d + uzd * uzd - dtr);
+    const R Kxx = R((m[MI(2, 0, 0)] - M(2) * uxd * jxd) * irho_d + uxd * uxd - dtr);
+    const R Kyy = R((m[MI(0, 2, 0)] - M(2) * uyd * jyd) * irho_d + uyd * uyd - dtr);
+    const R Kzz = R((m[MI(0, 0, 2)] - M(2) * uzd * jzd) * irho_d + uzd * uzd - dtr);
     const R Kxy = R((m[MI(1, 1, 0)] - uxd * jyd - uyd * jxd) * irho_d + uxd * uyd);
     const R Kxz = R((m[MI(1, 0, 1)] - uxd * jzd - uzd * jxd) * irho_d + uxd * uzd);
     const R Kyz = R((m[MI(0, 1, 1)] - uyd * jzd - uzd * jyd) * irho_d + uyd * uzd);
@@ -252,18 +259,19 @@ __device__ __forceinline__ void collide(const R d[27], R omega, R gx, R gy, R gz
                      + R(2) * (sx * byz * byz + sy * bxz * bxz + sz * bxy * bxy)
                      + R(8) * bxy * bxz * byz;
     // back to velocity space about u (linear, so applied to the deviations)
+    const Chimera<R> chx(ux), chy(uy), chz(uz);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) inv_chimera(k[MI(0, b, c)], k[MI(1, b, c)], k[MI(2, b, c)], ux);
+        for (int b = 0; b < 3; ++b) chx.apply(k[MI(0, b, c)], k[MI(1, b, c)], k[MI(2, b, c)]);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) inv_chimera(k[MI(a, 0, c)], k[MI(a, 1, c)], k[MI(a, 2, c)], uy);
+        for (int a = 0; a < 3; ++a) chy.apply(k[MI(a, 0, c)], k[MI(a, 1, c)], k[MI(a, 2, c)]);
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) inv_chimera(k[MI(a, b, 0)], k[MI(a, b, 1)], k[MI(a, b, 2)], uz);
+        for (int a = 0; a < 3; ++a) chz.apply(k[MI(a, b, 0)], k[MI(a, b, 1)], k[MI(a, b, 2)]);
     // rest state about u is the product equilibrium: f* = rho (w + D + G)
     E D[27];
     product_dev(E(uxd), E(uyd), E(uzd), D);
