@@ -153,6 +153,46 @@ __device__ __forceinline__ void st_at(S *base, uint32_t e, S v)
     // pass, so they should not displace lines the pulls still use
     __builtin_nontemporal_store(v, (S *)((char *)base + e * (uint32_t)sizeof(S)));
 }
+// Row streams of the dense kernel through buffer descriptors: one
+// descriptor per row block (its 27 direction sub-rows, 27 nx values; the
+// hardware returns 0 for loads and drops stores beyond it), the direction's
+// sub-row offset i nx in the scalar offset register and the lane's x in the
+// vector one, so that a load or store costs no vector address arithmetic.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int BUF_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+constexpr int BUF_NT = 2;              // cache policy: non-temporal (the new PDFs stream out)
+template <class S>
+__device__ __forceinline__ Rsrc row_rsrc(const S *pdf, int nx, int row)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(pdf + pdf_index(nx, 0, row, 0)), 0,
+                                             27 * nx * (int)sizeof(S), BUF_WORD3);
+}
+__device__ __forceinline__ float bload(const float *, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double bload(const double *, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, (u32x2)__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float bload(const _Float16 *, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, BUF_NT);
+}
+__device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, BUF_NT);
+}
+__device__ __forceinline__ void bstore(_Float16 v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, BUF_NT);
+}
+
 // Ties a loaded value to this point (an empty asm statement that reads and
 // writes the register; no instruction is emitted).  Placed after all loads
 // of a stage, it keeps the compiler from sinking a load into the branch of
@@ -177,9 +217,28 @@ __device__ __forceinline__ T at(const T *base, uint32_t e)
 // NEAR: the wavefront holds a cell next to a solid or a wall (the other
 // lanes run the same code with an empty solid mask); without it the code
 // has no bounce-back part at all.
-template <class S, bool NEAR, bool GC>
-__device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
-                                          int x, int row, uint8_t fl, Watch &wd)
+// What one liquid cell of the dense step reads: the pulled PDFs, the stored
+// mass, and next to solids the bounce-back values, the solid-link mask and
+// the moving-wall record.
+template <class S, bool NEAR>
+struct BulkIn {
+    using R = typename Real<S>::type;
+    R f[27];
+    double mq0;
+    R fb[NEAR ? 27 : 1];
+    uint4 rv[NEAR ? 28 * sizeof(R) / 16 : 1];
+    uint32_t solid;
+    int slot;
+};
+
+// The loads of one liquid cell of the dense step, all issued before any
+// arithmetic so that a wavefront keeps its streams in flight; fl is the
+// cell's flag byte (liquid).  NEAR: the wavefront holds a cell next to a
+// solid or a wall (the other lanes run the same code with an empty solid
+// mask); without it the code has no bounce-back part at all.
+template <class S, bool NEAR>
+__device__ __forceinline__ void bulk_loads(const Dev &d, const S *__restrict__ src, int x, int row, uint8_t fl,
+                                           BulkIn<S, NEAR> &in)
 {
     using R = typename Real<S>::type;
     const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -190,58 +249,99 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     const bool near = NEAR && (fl & F_NEAR_SOLID) != 0;
 
     // bookkeeping loads first: the record slot gates a second round of loads
-    const double mq0 = d.mq[c];
-    uint32_t solid = 0;
-    int slot = -1;
+    in.mq0 = d.mq[c];
+    in.solid = 0;
+    in.slot = -1;
     if (near) {
-        solid = d.smask[c];
-        slot = d.bbslot[c];
+        in.solid = d.smask[c];
+        in.slot = d.bbslot[c];
     }
 
-    // source x - c_i: its row (scalar; periodic in y, z clamped -- the wall
-    // layers are near-solid cells whose wall links are replaced below) and
-    // its x (per lane; periodic)
-    const int RY[3] = {y == ny - 1 ? 1 - ny : 1, 0, y == 0 ? ny - 1 : -1};
-    const int RZ[3] = {z == nz - 1 ? 0 : ny, 0, z == 0 ? 0 : -ny};
-    const int XS[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
-    R f[27];
+    // Source x - c_i: its row (scalar; periodic in y, z clamped -- the wall
+    // layers are near-solid cells whose wall links are replaced) and its x
+    // (per lane; periodic).  One descriptor per source row (index b + 3 c
+    // for the row y + 1 - b, z + 1 - c) and the byte offset of each source x
+    // per lane; the direction selects the sub-row through the scalar offset.
+    const int ryp = y == ny - 1 ? 1 - ny : 1, rym = y == 0 ? ny - 1 : -1;
+    const int rzp = z == nz - 1 ? 0 : ny, rzm = z == 0 ? 0 : -ny;
+    const int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    Rsrc rs[9];
 #pragma unroll
-    for (int i = 0; i < 27; ++i)
-        f[i] = ld_at(src + pdf_index(nx, 0, row + RY[(i / 3) % 3] + RZ[i / 9], 0), (uint32_t)(i * nx + XS[i % 3]));
-
-    // links whose source is solid or beyond a wall bounce back: the cell's
-    // own post-collision value of the opposite direction, plus the
-    // precomputed moving-wall term of sphere links (zero for wall links).
-    // In FP32 only the lanes whose link is solid load it (fewer bytes; the
-    // FP16 and FP64 forms run slower with the per-link masks).
-    R fb[27];
-#pragma unroll
-    for (int j = 0; j < 27; ++j) fb[j] = R(0);
-    uint4 rv[28 * sizeof(R) / 16];
-    if (near) {
-#pragma unroll
-        for (int j = 0; j < 27; ++j)
-            if (j != REST && (sizeof(S) != 4 || ((solid >> j) & 1u)))
-                fb[j] = ld_at(src + pdf_index(nx, 0, row, 0), (uint32_t)(opp(j) * nx + x));
+    for (int k = 0; k < 9; ++k) {
+        if constexpr (sizeof(S) == 8) break;
+        const int b = k % 3, cc = k / 3;
+        rs[k] = row_rsrc(src, nx, row + (b == 0 ? ryp : (b == 2 ? rym : 0)) + (cc == 0 ? rzp : (cc == 2 ? rzm : 0)));
     }
-    load_record<R>(d, slot, rv);
-    __builtin_amdgcn_sched_barrier(0);
-    R rec[28];
-    __builtin_memcpy(rec, rv, sizeof(rv));
+    const uint32_t vx[3] = {(uint32_t)(xp * (int)sizeof(S)), (uint32_t)(x * (int)sizeof(S)),
+                            (uint32_t)(xm * (int)sizeof(S))};
+    const uint32_t sub = (uint32_t)(nx * (int)sizeof(S));  // bytes of one direction sub-row
+    // (FP64 keeps plain loads from scalar row bases: with its 64-bit values
+    // the descriptors' registers would cost it one of its two wavefronts
+    // per SIMD)
+    constexpr bool BUF = sizeof(S) < 8;
+    auto pull = [&](int i) -> R {
+        if constexpr (BUF) return bload(src, rs[i / 3], vx[i % 3], (uint32_t)i * sub);
+        const int b = (i / 3) % 3, cc = i / 9;
+        const int sr = row + (b == 0 ? ryp : (b == 2 ? rym : 0)) + (cc == 0 ? rzp : (cc == 2 ? rzm : 0));
+        return ld_at(src + pdf_index(nx, 0, sr, 0), (uint32_t)(i * nx) + vx[i % 3] / (uint32_t)sizeof(S));
+    };
+#pragma unroll
+    for (int i = 0; i < 27; ++i) in.f[i] = pull(i);
 
+    if constexpr (NEAR) {
+        // links whose source is solid or beyond a wall bounce back: the
+        // cell's own post-collision value of the opposite direction, plus the
+        // precomputed moving-wall term of sphere links (zero for wall links).
+        // In FP32 only the lanes whose link is solid load it (fewer bytes;
+        // the FP16 and FP64 forms run slower with the per-link masks).
+#pragma unroll
+        for (int j = 0; j < 27; ++j) in.fb[j] = R(0);
+        if (near) {
+#pragma unroll
+            for (int j = 0; j < 27; ++j)
+                if (j != REST && (sizeof(S) != 4 || ((in.solid >> j) & 1u)))
+                    in.fb[j] = BUF ? bload(src, rs[4], vx[1], (uint32_t)opp(j) * sub)
+                                   : ld_at(src + pdf_index(nx, 0, row, 0), (uint32_t)(opp(j) * nx + x));
+        }
+        load_record<R>(d, in.slot, in.rv);
+    }
+}
+
+// The update of one liquid cell from its loads: bounce-back, mass
+// bookkeeping, collision and the stores.
+template <class S, bool NEAR, bool GC>
+__device__ __forceinline__ void bulk_update(const Dev &d, S *__restrict__ dst, int x, int row,
+                                            BulkIn<S, NEAR> &in, Watch &wd)
+{
+    using R = typename Real<S>::type;
+    const int nx = d.nx, nz = d.nz;
+    row = __builtin_amdgcn_readfirstlane(row);
+    const int z = row / d.ny;
+    const int c = x + nx * row;
+    R *f = in.f;
+    const uint32_t solid = NEAR ? in.solid : 0u;
     // incoming mass over the non-solid links; links beyond a z wall (the
     // bottom and top rows, uniform over the wavefront) carry no wall term
     double in_sum = 0.0;
+    if constexpr (NEAR) {
+        R rec[28];
+        __builtin_memcpy(rec, in.rv, sizeof(in.rv));
+        const int slot = in.slot;
 #pragma unroll
-    for (int j = 0; j < 27; ++j) {
-        if (j == REST) continue;
-        const bool sj = (solid >> j) & 1u;
-        in_sum += sj ? 0.0 : (double)f[j];
-        const bool wall = (z == 0 && j / 9 == 2) || (z == nz - 1 && j / 9 == 0);
-        // FP16 storage keeps full records: its dense pass is bound by ALU work
-        // rather than by the record bytes
-        const R tm = sizeof(S) > 2 ? (wall ? R(0) : record_term<R>(rec, slot, j)) : rec[j];
-        f[j] = sj ? fb[j] + tm : f[j];
+        for (int j = 0; j < 27; ++j) {
+            if (j == REST) continue;
+            const bool sj = (solid >> j) & 1u;
+            in_sum += sj ? 0.0 : (double)f[j];
+            const bool wall = (z == 0 && j / 9 == 2) || (z == nz - 1 && j / 9 == 0);
+            // FP16 storage keeps full records: its dense pass is bound by ALU
+            // work rather than by the record bytes
+            const R tm = sizeof(S) > 2 ? (wall ? R(0) : record_term<R>(rec, slot, j)) : rec[j];
+            f[j] = sj ? in.fb[j] + tm : f[j];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 27; ++j)
+            if (j != REST) in_sum += (double)f[j];
     }
 
     using E = typename Eq<S>::type;
@@ -249,17 +349,33 @@ __device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ sr
     double rho;
     collide<R, E, GC>(f, R(d.omega), R(d.gx), R(d.gy), R(d.gz), fo, rho);
 
+    constexpr bool BUF = sizeof(S) < 8;
+    const uint32_t sub = (uint32_t)(nx * (int)sizeof(S)), vx = (uint32_t)(x * (int)sizeof(S));
     double out_sum = 0.0;
+    Rsrc rd;
+    if constexpr (BUF) rd = row_rsrc(dst, nx, row);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const S v = to_store<S, E>(fo[i]);
-        st_at(dst + pdf_index(nx, 0, row, 0), (uint32_t)(i * nx + x), v);
+        if constexpr (BUF) bstore(v, rd, vx, (uint32_t)i * sub);
+        else st_at(dst + pdf_index(nx, 0, row, 0), (uint32_t)(i * nx + x), v);
         if (i != REST) out_sum += ((solid >> opp(i)) & 1u) ? 0.0 : (double)ld(&v);
     }
     // liquid cells keep m - own outgoing: m' = (m - out) + in over non-solid links
-    const double m = mq0 + in_sum;
+    const double m = in.mq0 + in_sum;
     d.mq[c] = m - out_sum;
     wd.add(m, rho);
+}
+
+// one liquid cell of the dense step: its loads, then its update
+template <class S, bool NEAR, bool GC>
+__device__ __forceinline__ void bulk_cell(const Dev &d, const S *__restrict__ src, S *__restrict__ dst,
+                                          int x, int row, uint8_t fl, Watch &wd)
+{
+    BulkIn<S, NEAR> in;
+    bulk_loads<S, NEAR>(d, src, x, row, fl, in);
+    __builtin_amdgcn_sched_barrier(0);
+    bulk_update<S, NEAR, GC>(d, dst, x, row, in, wd);
 }
 
 // Dense part over the rows (y, z) up to the highest fluid row; each block
@@ -309,6 +425,8 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
             if (la) bulk_cell<S, true, GC>(d, src, dst, xa, rowa, fla, wd);
             if (lb) bulk_cell<S, true, GC>(d, src, dst, xb, rowb, flb, wd);
         } else if (__ballot(la || lb) != 0) {
+            // (issuing both cells' loads before either update gains nothing
+            // measurable here and costs the FP16 form a wavefront per SIMD)
             if (la) bulk_cell<S, false, GC>(d, src, dst, xa, rowa, fla, wd);
             if (lb) bulk_cell<S, false, GC>(d, src, dst, xb, rowb, flb, wd);
         }

@@ -150,6 +150,47 @@ template <class T> inline T __shfl_up(T v, unsigned delta, int = 64)
 // divergent code, where a lane exchange cannot run: the lane's own value is
 // the wavefront's.
 inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
+// Buffer descriptors: base and size in bytes.  Every access of the library
+// lies inside its descriptor (the hardware would return 0 for a load beyond
+// it and drop a store), so an access outside one stops the run here.
+namespace hipemu {
+struct BufRsrc {
+    char *base;
+    uint32_t bytes;
+};
+inline char *buf_at(BufRsrc r, uint32_t voff, uint32_t soff, uint32_t n)
+{
+    const uint64_t o = (uint64_t)voff + soff;
+    if (o + n > r.bytes) {
+        fprintf(stderr, "hostemu: buffer access at byte %llu (+%u) beyond a descriptor of %u bytes\n",
+                (unsigned long long)o, n, r.bytes);
+        abort();
+    }
+    return r.base + o;
+}
+}  // namespace hipemu
+#define __amdgpu_buffer_rsrc_t hipemu::BufRsrc
+inline hipemu::BufRsrc __builtin_amdgcn_make_buffer_rsrc(void *p, short, int bytes, int)
+{
+    return hipemu::BufRsrc{(char *)p, (uint32_t)bytes};
+}
+#define HIPEMU_BUF_IO(bits, T)                                                                        \
+    inline T __builtin_amdgcn_raw_buffer_load_b##bits(hipemu::BufRsrc r, uint32_t vo, uint32_t so, int) \
+    {                                                                                                 \
+        T v;                                                                                          \
+        memcpy(&v, hipemu::buf_at(r, vo, so, sizeof(T)), sizeof(T));                                  \
+        return v;                                                                                     \
+    }                                                                                                 \
+    inline void __builtin_amdgcn_raw_buffer_store_b##bits(T v, hipemu::BufRsrc r, uint32_t vo, uint32_t so, int) \
+    {                                                                                                 \
+        memcpy(hipemu::buf_at(r, vo, so, sizeof(T)), &v, sizeof(T));                                  \
+    }
+typedef unsigned int hipemu_u32x2 __attribute__((ext_vector_type(2)));
+HIPEMU_BUF_IO(16, unsigned short)
+HIPEMU_BUF_IO(32, uint32_t)
+HIPEMU_BUF_IO(64, hipemu_u32x2)
+#undef HIPEMU_BUF_IO
+
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 inline int __ffsll(unsigned long long v) { return __builtin_ffsll((long long)v); }
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }

@@ -79,3 +79,23 @@ def test_surface_at_the_top_wall_on_the_cpu():
         compare(g, o, "lid after %d steps" % (2 * (k + 1)))
     assert o.counters()[2] > 0                 # cells filled next to the wall
     g.destroy()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp16", 2e-3)])
+def test_storage_forms_on_the_cpu(prec, tol):
+    """The FP32 and FP16 forms (whose dense pass reads and writes its rows
+    through buffer descriptors, bounds-checked here) against the oracle
+    storing the same precision: to a few units of the storage rounding."""
+    w = lid()
+    g = emu.EmuLattice(w, prec)
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, sigma=w.sigma, fill=w.fill, rho=w.rho, vel=w.vel,
+                        store=prec)
+    o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    g.step(4)
+    o.step(4)
+    t = o.read(O.F_TYPE)
+    assert np.array_equal(g.read(F.FIELD_TYPE), t)
+    fl = (t == O.LIQUID) | (t == O.INTERFACE)
+    d = np.abs(g.read(F.FIELD_PDF)[:, fl] - o.read(O.F_PDF)[:, fl]).max()
+    assert d <= tol, d
+    g.destroy()
