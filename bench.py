@@ -171,24 +171,56 @@ def interface_error(lat, fsl):
     return {"rms_angle_deg": ang, "rms_kappa": kap, "cells": int(len(cells))}
 
 
-def learned_weights(lat, fsl, n_analytic=100000, steps=200, every=50, epochs=30, seed=0):
-    """Train the estimator for a lattice: analytic stencils plus height-
-    function labelled stencils of the lattice's own fill fields (taken while
-    it runs the plain estimator), on the GPU; returns weights and report."""
+def learned_weights(lat, fsl, n_analytic=1000000, ss=16, n_flume=200000, steps=200, every=50, epochs=30,
+                    seed=0):
+    """Train the estimator: n_analytic analytic stencils (fill levels
+    supersampled on ss^3 points per cell on the GPU) plus height-function
+    labelled stencils of the lattice's own fill fields (taken while it runs
+    the plain estimator); returns weights and report."""
     from paper_2301_10674_amd import train as T
 
     t0 = time.perf_counter()
-    Xa, Ya = T.analytic_dataset(n_analytic, seed=seed)
-    Xf, Yf = T.flume_dataset(lat, fsl, steps, every, n_analytic, seed=seed)
+    Xa, Ya = T.analytic_dataset_gpu(fsl, n_analytic, seed=seed, ss=ss)
+    Xf, Yf = T.flume_dataset(lat, fsl, steps, every, n_flume, seed=seed)
     X, Y = np.concatenate([Xa, Xf]), np.concatenate([Ya, Yf])
     Xt, Yt, Xv, Yv = T.split(X, Y, 0.1, seed=seed)
     rep = T.train(fsl, Xt, Yt, Xv, Yv, epochs=epochs, seed=seed)
     rep["data_seconds"] = time.perf_counter() - t0 - rep["train_seconds"]
     rep.update(analytic_samples=int(len(Xa)), flume_samples=int(len(Xf)), epochs=epochs,
-               supersampling="6^3")
+               supersampling="%d^3 points per cell (GPU)" % ss)
     w = rep.pop("weights")
     rep.pop("losses")
     return w, rep
+
+
+def droplet_check(fsl, weights, steps=2000, R=10.0, n=40, sigma=1e-3):
+    """A static droplet (radius R in an n^3 box, sigma, no gravity, FP32) with
+    finite differences and with the network: the Laplace jump of the core
+    density against 6 sigma / R (Section 2.1's 2 sigma kappa) and the
+    largest speed left (spurious currents)."""
+    from paper_2301_10674_amd import inputs
+
+    w = inputs.droplet(n=n, radius=R, sigma=sigma)
+    x = np.arange(n) + 0.5 - 0.5 * n
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    out = {"steps": steps, "radius": R, "sigma": sigma}
+    for name, wts in (("finite_differences", None), ("network", weights)):
+        lat = fsl.lattice_from_workload(w, "fp32", normals=1 if wts is not None else 0, check_every=50)
+        if wts is not None:
+            lat.set_estimator(wts)
+        try:
+            lat.step(steps)
+            f = lat.read_fields([fsl.FIELD_TYPE, fsl.FIELD_RHO, fsl.FIELD_VEL])
+            t = f[fsl.FIELD_TYPE]
+            core = (t == fsl.LIQUID) & (r < R - 3)
+            fluid = (t == fsl.LIQUID) | (t == fsl.INTERFACE)
+            drho = float(f[fsl.FIELD_RHO][core].mean() - 1.0)
+            out[name] = {"laplace_rel_err": drho / (6.0 * sigma / R) - 1.0,
+                         "max_speed": float(np.sqrt((f[fsl.FIELD_VEL][:, fluid] ** 2).sum(0)).max())}
+        except fsl.FslError as e:
+            out[name] = {"unstable": str(e)}
+        lat.destroy()
+    return out
 
 
 def flow_check(w, fsl, weights, steps=1000, check_every=10):
@@ -304,6 +336,7 @@ def trained_estimator(fsl):
         lat.destroy()
         rep["held_out_gate"] = rep.pop("gate")
         rep["flow_check"] = flow_check(w, fsl, weights)
+        rep["droplet"] = droplet_check(fsl, weights)
         rep["gate"] = bool(rep["held_out_gate"] and rep["flow_check"]["pass"])
         _WEIGHTS["w"], _WEIGHTS["report"] = weights, rep
     return _WEIGHTS["w"], dict(_WEIGHTS["report"])

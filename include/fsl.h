@@ -294,6 +294,22 @@ FslStatus fsl_estimator_grad_device(const float *weights, const float *x, const 
 FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n,
                               float *y, void *hip_stream);
 
+/* Training stencils of the learned estimator (Section 2.1's normal and
+ * curvature; analytic shapes): fill levels x float [n][27] (entry
+ * a + 3b + 9c = the cell at offset (a-1, b-1, c-1) from the centre cell)
+ * of n analytic shapes by supersampling each cell on ss^3 points
+ * (i + 1/2)/ss - 1/2 per axis around its centre.  params double [n][16]
+ * per shape: [0] kind (0 sphere, 1 sinusoidal sheet), [1] nonzero to take
+ * the outside (1 - fraction: a bubble); sphere: [2..4] centre, [5] radius,
+ * a point is inside if |p - centre|^2 <= radius^2; sheet: [2..4] e1,
+ * [5..7] e3, [8] A, [9] k, [10] psi, [11] s, inside if
+ * p.e3 < A sin(k p.e1 + psi) + s; the other entries are ignored.  The
+ * tests are evaluated in FP64, each product and sum rounded on its own in
+ * the order written.  Host arrays, owned by the caller; FSL_ERR_ARG for
+ * NULL, n outside [1, 2^26] or ss outside [1, 64], FSL_ERR_DEVICE for a
+ * failed allocation or launch; synchronises hip_stream. */
+FslStatus fsl_estimator_stencils(const double *params, int64_t n, int32_t ss, float *x, void *hip_stream);
+
 /* Finite-difference geometry (Section 2.1 curvature; Parker-Youngs normal
  * and Hessian mean curvature, evaluated in FP64) of n stencils x float
  * [n][27] of fill levels (entry a + 3b + 9c = offset (a-1, b-1, c-1);

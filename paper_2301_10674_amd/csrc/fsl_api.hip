@@ -1767,6 +1767,24 @@ FslStatus fsl_estimator_infer(const float *weights, const float *x, int64_t n, f
     return FSL_OK;
 }
 
+FslStatus fsl_estimator_stencils(const double *params, int64_t n, int32_t ss, float *x, void *hip_stream)
+{
+    if (!params || !x || n <= 0 || n > (1 << 26) || ss < 1 || ss > 64)
+        return fail(FSL_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBufs B;
+    double *P;
+    float *X;
+    HIP_TRY(B.get(&P, (size_t)n * 16));
+    HIP_TRY(B.get(&X, (size_t)n * 27));
+    HIP_TRY(hipMemcpyAsync(P, params, (size_t)n * 16 * 8, hipMemcpyHostToDevice, st));
+    stencil_fill(P, (int)n, ss, X, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(x, X, (size_t)n * 27 * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return FSL_OK;
+}
+
 FslStatus fsl_fd_geometry(const float *x, int64_t n, float *y, void *hip_stream)
 {
     if (!x || !y || n <= 0 || n > (1 << 30)) return fail(FSL_ERR_ARG, "bad argument");

@@ -36,6 +36,7 @@ void mlp_train_step(const float *X, const float *T, const int32_t *idx, int nbat
                     hipStream_t st);
 void mlp_infer(const float *X, int n, const float *P, const uint16_t *pk, float *Y, hipStream_t st);
 void fd_stencils(const float *X, int n, float *Y, hipStream_t st);
+void stencil_fill(const double *P, int n, int ss, float *X, hipStream_t st);
 template <class R>
 void launch_geom_mlp(const Dev &d, int which, int blocks, const float *P, const uint16_t *pk, hipStream_t st);
 

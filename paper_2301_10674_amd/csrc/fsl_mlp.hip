@@ -580,7 +580,59 @@ __global__ __launch_bounds__(256) void k_fd_stencils(const float *X, int n, floa
     }
 }
 
+// Fill levels of analytic stencils by supersampling: one wavefront per
+// (stencil, cell); each cell is sampled on ss^3 points (i + 1/2)/ss - 1/2
+// per axis around its offset (a-1, b-1, c-1), entry a + 3b + 9c.  Shape
+// parameters per stencil, 16 doubles: [0] kind (0 sphere, 1 sinusoidal
+// sheet), [1] 1 to count the outside (a bubble), sphere: [2..4] centre X,
+// [5] radius R -- inside if |p - X|^2 <= R^2; sheet: [2..4] e1, [5..7] e3,
+// [8] A, [9] k, [10] psi, [11] s -- inside if p.e3 < A sin(k p.e1 + psi) + s.
+// The inside tests round each product and sum on its own (no fused
+// multiply-add), in the order written.
+__global__ __launch_bounds__(256) void k_stencil_fill(const double *P, int n, int ss, float *X)
+{
+    const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = __lane_id();
+    if (g >= n * 27) return;
+    const int s = g / 27, k = g % 27;
+    const double *q = P + (size_t)16 * s;
+    const double ox = (double)(k % 3 - 1), oy = (double)((k / 3) % 3 - 1), oz = (double)(k / 9 - 1);
+    const int np = ss * ss * ss;
+    const double inv = 1.0 / (double)ss;
+    int count = 0;
+    for (int t = lane; t < np; t += 64) {
+        const int i = t / (ss * ss), j = (t / ss) % ss, l = t % ss;
+        const double px = __dadd_rn(ox, __dsub_rn(__dmul_rn((double)i + 0.5, inv), 0.5));
+        const double py = __dadd_rn(oy, __dsub_rn(__dmul_rn((double)j + 0.5, inv), 0.5));
+        const double pz = __dadd_rn(oz, __dsub_rn(__dmul_rn((double)l + 0.5, inv), 0.5));
+        bool in;
+        if (q[0] == 0.0) {
+            const double dx = __dsub_rn(px, q[2]), dy = __dsub_rn(py, q[3]), dz = __dsub_rn(pz, q[4]);
+            const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            in = r2 <= __dmul_rn(q[5], q[5]);
+        } else {
+            const double u = __dadd_rn(__dadd_rn(__dmul_rn(px, q[2]), __dmul_rn(py, q[3])), __dmul_rn(pz, q[4]));
+            const double w = __dadd_rn(__dadd_rn(__dmul_rn(px, q[5]), __dmul_rn(py, q[6])), __dmul_rn(pz, q[7]));
+            const double h = __dadd_rn(__dmul_rn(q[8], sin(__dadd_rn(__dmul_rn(q[9], u), q[10]))), q[11]);
+            in = w < h;
+        }
+        count += in ? 1 : 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) count += __shfl_xor(count, o);
+    if (lane == 0) {
+        const float phi = (float)((double)count / (double)np);
+        X[(size_t)s * 27 + k] = q[1] != 0.0 ? 1.0f - phi : phi;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+void stencil_fill(const double *P, int n, int ss, float *X, hipStream_t st)
+{
+    const int64_t waves = (int64_t)n * 27;
+    k_stencil_fill<<<(int)((waves + 3) / 4), 256, 0, st>>>(P, n, ss, X);
+}
+
 void fd_stencils(const float *X, int n, float *Y, hipStream_t st)
 {
     int blocks = (n + 255) / 256;

@@ -31,7 +31,7 @@ GAS, LIQUID, INTERFACE, SOLID = 0, 1, 2, 3
 EXPORTS = ("fsl_workspace_bytes", "fsl_create_lattice", "fsl_set_particles", "fsl_step",
            "fsl_read_fields", "fsl_total_mass", "fsl_counters", "fsl_info", "fsl_timing",
            "fsl_timing_read", "fsl_estimator_train", "fsl_estimator_grad", "fsl_estimator_infer",
-           "fsl_fd_geometry", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
+           "fsl_fd_geometry", "fsl_estimator_stencils", "fsl_particle_forces", "fsl_set_accel", "fsl_bulk_velocity",
            "fsl_bed_profile", "fsl_move_particles", "fsl_move_particles_device",
            "fsl_set_estimator", "fsl_estimator_stats", "fsl_dem_create", "fsl_dem_step",
            "fsl_dem_read", "fsl_dem_bedload", "fsl_dem_destroy", "fsl_last_error", "fsl_destroy",
@@ -146,6 +146,8 @@ def lib():
         L.fsl_estimator_infer.argtypes = [fp, fp, ctypes.c_int64, fp, vp]
         L.fsl_fd_geometry.restype = ctypes.c_int
         L.fsl_fd_geometry.argtypes = [fp, ctypes.c_int64, fp, vp]
+        L.fsl_estimator_stencils.restype = ctypes.c_int
+        L.fsl_estimator_stencils.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, fp, vp]
         L.fsl_set_estimator.restype = ctypes.c_int
         L.fsl_particle_forces.argtypes = [vp, dp, i32]
         L.fsl_set_accel.argtypes = [vp, dp]
@@ -431,6 +433,16 @@ def estimator_infer(weights, x):
     y = np.zeros(4 * n, dtype=np.float32)
     _check(lib().fsl_estimator_infer(_fp(w), _fp(x), n, _fp(y), _stream()))
     return y.reshape(n, 4)
+
+
+def estimator_stencils(params, ss):
+    """Fill levels (n, 27) of analytic shapes params (n, 16) supersampled
+    on ss^3 points per cell (fsl_estimator_stencils)."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    n = params.shape[0]
+    x = np.zeros(27 * n, dtype=np.float32)
+    _check(lib().fsl_estimator_stencils(_dp(params), n, int(ss), _fp(x), _stream()))
+    return x.reshape(n, 27)
 
 
 def fd_geometry(x):

@@ -9,8 +9,9 @@ of Section 2.1).
 * ``analytic_stencils``: seeded droplets / bubbles (radius log-uniform in
   [4, 64]) and sinusoidal sheets (minimum radius of curvature log-uniform in
   [4, 64], random orientation and phase); fill levels by supersampling each
-  cell on an ss^3 grid; labels exact at the surface point nearest to the
-  centre of the stencil.
+  cell on an ss^3 grid (``fill_cpu``, or the library's
+  ``fsl_estimator_stencils`` on the GPU for large sets at 16^3); labels
+  exact at the surface point nearest to the centre of the stencil.
 * ``height_function_samples``: interface cells of a simulated fill field,
   labelled by the height-function method (heights are column sums of the
   fill level over 7 cells along the dominant normal axis, normal and
@@ -40,23 +41,29 @@ def _random_rotations(rng, m):
     return q
 
 
-def _spheres(rng, m, P, ss):
+NPARAM = 16  # shape parameters per stencil, the layout of fsl_estimator_stencils
+
+
+def _sphere_params(rng, m):
+    """m droplets / bubbles: (params (m, 16), labels (m, 4))."""
     R = np.exp(rng.uniform(np.log(4.0), np.log(64.0), m))
     p0 = rng.uniform(-0.5, 0.5, (m, 3))
     d = rng.standard_normal((m, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     X = p0 - R[:, None] * d
-    inside = ((P[None, :, :] - X[:, None, :]) ** 2).sum(-1) <= (R ** 2)[:, None]
-    phi = inside.reshape(m, 27, ss ** 3).mean(-1)
     bubble = rng.random(m) < 0.5
-    phi[bubble] = 1.0 - phi[bubble]
     out = -X / np.linalg.norm(X, axis=1, keepdims=True)   # from the centre towards the origin
     n = np.where(bubble[:, None], -out, out)
     kap = np.where(bubble, -1.0 / R, 1.0 / R)
-    return phi, np.concatenate([n, kap[:, None]], axis=1)
+    prm = np.zeros((m, NPARAM))
+    prm[:, 1] = bubble
+    prm[:, 2:5] = X
+    prm[:, 5] = R
+    return prm, np.concatenate([n, kap[:, None]], axis=1)
 
 
-def _sinusoids(rng, m, P, ss):
+def _sinusoid_params(rng, m):
+    """m sinusoidal sheets: (params (m, 16), labels (m, 4))."""
     lam = np.exp(rng.uniform(np.log(8.0), np.log(128.0), m))
     k = 2 * np.pi / lam
     rmin = np.exp(rng.uniform(np.log(4.0), np.log(64.0), m))
@@ -65,10 +72,6 @@ def _sinusoids(rng, m, P, ss):
     Q = _random_rotations(rng, m)                            # columns e1, e2, e3
     p0 = rng.uniform(-0.5, 0.5, (m, 3))
     s = np.einsum("mi,mi->m", p0, Q[:, :, 2]) - A * np.sin(k * np.einsum("mi,mi->m", p0, Q[:, :, 0]) + psi)
-    u = np.einsum("pi,mi->mp", P, Q[:, :, 0])
-    w = np.einsum("pi,mi->mp", P, Q[:, :, 2])
-    liquid = w < A[:, None] * np.sin(k[:, None] * u + psi[:, None]) + s[:, None]
-    phi = liquid.reshape(m, 27, ss ** 3).mean(-1)
     # nearest point of the curve w = h(u) to the origin (Newton on u + h h' = 0)
     uu = np.zeros(m)
     for _ in range(50):
@@ -83,24 +86,72 @@ def _sinusoids(rng, m, P, ss):
     h2 = -A * k * k * np.sin(k * uu + psi)
     nrm = (-h1[:, None] * Q[:, :, 0] + Q[:, :, 2]) / np.sqrt(1 + h1 * h1)[:, None]
     kap = -h2 / (2.0 * (1 + h1 * h1) ** 1.5)                # mean curvature of a cylinder
-    return phi, np.concatenate([nrm, kap[:, None]], axis=1)
+    prm = np.zeros((m, NPARAM))
+    prm[:, 0] = 1.0
+    prm[:, 2:5] = Q[:, :, 0]
+    prm[:, 5:8] = Q[:, :, 2]
+    prm[:, 8], prm[:, 9], prm[:, 10], prm[:, 11] = A, k, psi, s
+    return prm, np.concatenate([nrm, kap[:, None]], axis=1)
 
 
-def analytic_stencils(n: int, seed: int = 0, ss: int = 8, chunk: int = 256):
-    """n stencils (fill levels, shape (n, 27)) and labels (n, 4)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+def fill_cpu(prm, ss):
+    """Fill levels (m, 27) of shapes prm (m, 16) supersampled on ss^3 points
+    per cell (the definition fsl_estimator_stencils evaluates on the GPU)."""
     P = _subpoints(ss)
-    xs, ys = [], []
-    have = 0
+    m = len(prm)
+    out = np.empty((m, 27))
+    sph = prm[:, 0] == 0.0
+    if sph.any():
+        q = prm[sph]
+        d = P[None, :, :] - q[:, None, 2:5]
+        r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+        out[sph] = (r2 <= (q[:, 5] * q[:, 5])[:, None]).reshape(-1, 27, ss ** 3).mean(-1)
+    if (~sph).any():
+        q = prm[~sph]
+        u = (P[None, :, 0] * q[:, None, 2] + P[None, :, 1] * q[:, None, 3]) + P[None, :, 2] * q[:, None, 4]
+        w = (P[None, :, 0] * q[:, None, 5] + P[None, :, 1] * q[:, None, 6]) + P[None, :, 2] * q[:, None, 7]
+        h = q[:, None, 8] * np.sin(q[:, None, 9] * u + q[:, None, 10]) + q[:, None, 11]
+        out[~sph] = (w < h).reshape(-1, 27, ss ** 3).mean(-1)
+    out = np.where(prm[:, 1:2] != 0.0, 1.0 - out, out)
+    return out
+
+
+def analytic_params(n, seed=0):
+    """Shape parameters and labels of n candidate stencils, half droplets /
+    bubbles and half sinusoidal sheets, in interleaved chunks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    prms, labs = [], []
+    have, chunk = 0, 4096
     while have < n:
-        m = min(chunk, 2 * (n - have) + 8)
+        m = min(chunk, n - have + 1)
         half = m // 2
-        for fn, mm in ((_spheres, half), (_sinusoids, m - half)):
-            phi, lab = fn(rng, mm, P, ss)
-            ok = (phi[:, 13] > 0.0) & (phi[:, 13] < 1.0)
-            xs.append(phi[ok])
-            ys.append(lab[ok])
-            have += int(ok.sum())
+        for fn, mm in ((_sphere_params, half), (_sinusoid_params, m - half)):
+            if mm:
+                a, b = fn(rng, mm)
+                prms.append(a)
+                labs.append(b)
+                have += mm
+    return np.concatenate(prms)[:n], np.concatenate(labs)[:n]
+
+
+def analytic_stencils(n: int, seed: int = 0, ss: int = 8, chunk: int = 256, fill=None):
+    """n stencils (fill levels, shape (n, 27)) and labels (n, 4): shapes drawn
+    until n of them have a partly filled centre cell.  fill(prm, ss) makes
+    the fill levels (fill_cpu by default; the GPU's fsl_estimator_stencils
+    gives the same values)."""
+    fill = fill or fill_cpu
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs, ys = [], []
+    have, rnd = 0, 0
+    while have < n:
+        want = int(1.3 * (n - have)) + 64
+        prm, lab = analytic_params(want, seed=int(np.random.SeedSequence([seed, rnd]).generate_state(1)[0]))
+        rnd += 1
+        phi = np.asarray(fill(prm, ss), dtype=np.float64)
+        ok = (phi[:, 13] > 0.0) & (phi[:, 13] < 1.0)
+        xs.append(phi[ok])
+        ys.append(lab[ok])
+        have += int(ok.sum())
     X = np.concatenate(xs)[:n]
     Y = np.concatenate(ys)[:n]
     perm = rng.permutation(n)

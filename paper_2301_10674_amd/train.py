@@ -52,6 +52,12 @@ def analytic_dataset(n, seed=0, ss=6, chunk=20000, workers=None):
     return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
 
+def analytic_dataset_gpu(fsl, n, seed=0, ss=16):
+    """n analytic stencils with their fill levels supersampled on ss^3 points
+    per cell on the GPU (fsl_estimator_stencils)."""
+    return ST.analytic_stencils(n, seed=seed, ss=ss, fill=fsl.estimator_stencils)
+
+
 def lattice_samples(lat, fsl):
     """Height-function labelled stencils of a lattice's current fill field."""
     f = lat.read_fields([fsl.FIELD_TYPE, fsl.FIELD_FILL])
