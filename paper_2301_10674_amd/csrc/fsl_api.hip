@@ -31,7 +31,7 @@ template <class S>
 void launch_mem(const Dev &d, int p, int nsph, const int32_t *offs, const int2 *ent, double *out,
                 hipStream_t st);
 template <class R>
-void launch_bb_terms(const Dev &d, hipStream_t st);
+void launch_bb_terms(const Dev &d, int nrec, hipStream_t st);
 }  // namespace fsl
 
 using namespace fsl;
@@ -84,6 +84,7 @@ struct FslLattice {
     bool timing = false;
     double mass_ref = 0.0;    // watchdog: total mass after set-up (fsl_total_mass)
     bool mass_fast = false;   // the last call was fsl_step: its mass partials are current
+    int nrec = 0;             // bounce-back records (compact + full) of the current geometry
     double watch_last[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t ev_used = 0;
@@ -127,7 +128,7 @@ static bool params_ok(const FslParams *p, std::string &why)
 
 struct Layout {
     size_t pdf[2], mq, phi, rho, share, poolc, geom, mark, est, owner, flags, smask, bbslot, list0, list1,
-        lnew, cnt, stats, partial, total;
+        lnew, rcell, cnt, stats, partial, total;
 };
 
 static Layout layout(const FslParams *p)
@@ -158,6 +159,7 @@ static Layout layout(const FslParams *p)
     L.list0 = take(4 * N);
     L.list1 = take(4 * N);
     L.lnew = take(4 * N);
+    L.rcell = take(4 * N);
     L.cnt = take(64);
     L.stats = take(8 * 16);
     L.partial = take(8 * (5 * RED_BLOCKS + 8 + WD_SIZE));
@@ -222,10 +224,12 @@ __global__ void k_closure(Dev d)
 
 // liquid cells: switch between the mass m and the stored form m - own outgoing
 template <class S>
-__global__ void k_liquid_form(Dev d, int p, int to_q, const uint8_t *mark)
+__global__ void k_liquid_form(Dev d, int p, int to_q, const int32_t *list, const int *count)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N || (d.flags[c] & T_MASK) != T_LIQ || (mark && !mark[c])) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (list ? t >= *count : t >= d.N) return;
+    const int c = list ? list[t] : t;
+    if ((d.flags[c] & T_MASK) != T_LIQ) return;
     const S *pdf = (const S *)d.pdf[p];
     double fluid = 0.0;
     for (int i = 0; i < 27; ++i) {
@@ -302,14 +306,29 @@ __global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own
     if (ch) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = c;
 }
 
-// mark (v = 1) or clear (v = 0) the listed cells and their 26 neighbours
-__global__ void k_mark_around(Dev d, const int32_t *list, int n, uint8_t *mark, uint8_t v)
+// The listed cells and their 26 neighbours, each once: the first visitor
+// of a cell turns its mark from 0 to 1 and appends it to out (count).
+__global__ __launch_bounds__(256) void k_mark_list(Dev d, const int32_t *list, int n, uint32_t *mark,
+                                                   int32_t *out, int *count)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n * 27) return;
-    const int c = list[t / 27];
-    const int y = nbr(d, c, (int)(t % 27));
-    if (y >= 0) mark[y] = v;
+    int y = -1;
+    if (t < (int64_t)n * 27) y = nbr(d, list[t / 27], (int)(t % 27));
+    const bool first = y >= 0 && atomicCAS(&mark[y], 0u, 1u) == 0u;
+    const uint64_t m = __ballot(first);
+    if (m == 0) return;
+    const int lane = __lane_id();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, (int)__popcll(m));
+    base = __shfl(base, 0);
+    if (first) out[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = y;
+}
+
+// clear the marks of the cells in list[0 .. *count)
+__global__ void k_unmark_list(const int32_t *list, const int *count, uint32_t *mark)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < *count) mark[list[t]] = 0u;
 }
 
 // covered fluid cells turn solid, their mass (m form) into the pool;
@@ -447,11 +466,12 @@ __global__ void k_owner_commit(Dev d, const int32_t *own, const int32_t *list, i
     d.owner[c] = own[c] == INT_MAX ? -1 : own[c];
 }
 
-// solid-link mask and near-solid bit of the marked cells only
-__global__ void k_near_solid_marked(Dev d, const uint8_t *mark)
+// solid-link mask and near-solid bit of the cells in list[0 .. *count)
+__global__ void k_near_solid_list(Dev d, const int32_t *list, const int *count)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N || !mark[c]) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *count) return;
+    const int c = list[t];
     uint32_t m = 0;
     for (int j = 0; j < 27; ++j) {
         if (j == REST) continue;
@@ -749,9 +769,13 @@ static void run_setup(FslLattice *L, const double *fill, const double *rho, cons
     k_closure<<<blocks_for(d.N), 256, 0, L->st>>>(d);
 }
 
-template <class S> static void run_liquid_form(FslLattice *L, int to_q, const uint8_t *mark = nullptr)
+// all liquid cells, or those in list[0 .. *count) (at most `bound` of them)
+template <class S>
+static void run_liquid_form(FslLattice *L, int to_q, const int32_t *list = nullptr, const int *count = nullptr,
+                            int64_t bound = 0)
 {
-    k_liquid_form<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, to_q, mark);
+    const int blocks = list ? (int)((bound + 255) / 256) : blocks_for(L->d.N);
+    if (blocks > 0) k_liquid_form<S><<<blocks, 256, 0, L->st>>>(L->d, L->parity, to_q, list, count);
 }
 
 template <class S> static void run_refresh(FslLattice *L)
@@ -789,11 +813,11 @@ template <class S> static void run_read(FslLattice *L, int field, void *out)
 
 static void run_bb_terms(FslLattice *L)
 {
-    if (!L->d.bbterm) return;
+    if (!L->d.bbterm || L->nrec == 0) return;
     if (L->P.precision == FSL_FP64)
-        launch_bb_terms<double>(L->d, L->st);
+        launch_bb_terms<double>(L->d, L->nrec, L->st);
     else
-        launch_bb_terms<float>(L->d, L->st);
+        launch_bb_terms<float>(L->d, L->nrec, L->st);
 }
 
 template <class S>
@@ -881,6 +905,7 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     HIP_TRY(hipStreamSynchronize(L->st));
     d.bbterm = nullptr;
     d.bbfull = nullptr;
+    L->nrec = nrec[0] + nrec[1];
     if (nrec[0] > 0 || nrec[1] > 0) {
         // compact records, then the full ones, in one allocation (kept and
         // reused while large enough: moving spheres rebuild it often)
@@ -1068,6 +1093,7 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.list[0] = (int32_t *)(base + lay.list0);
     d.list[1] = (int32_t *)(base + lay.list1);
     d.lnew = (int32_t *)(base + lay.lnew);
+    d.rcell = (int32_t *)(base + lay.rcell);
     d.cnt = (int32_t *)(base + lay.cnt);
     d.stats = (unsigned long long *)(base + lay.stats);
     d.partial = (double *)(base + lay.partial);
@@ -1220,22 +1246,25 @@ static FslStatus remap(FslLattice *L)
     const int n = L->nsph;
     Dev &d = L->d;
     const size_t N = (size_t)d.N;
-    // scratch: densities (8 B), new owners (4 B), changed cells (4 B), round
-    // types (1 B) and marks (1 B) per cell, a counter; marks start zero and
-    // are cleared again after use
+    // scratch: densities (8 B), new owners (4 B), changed cells (4 B), marks
+    // (4 B), the marked cells (4 B) and round types (1 B) per cell, two
+    // counters; marks start zero and are cleared again after use
     const size_t nm = (N + 15) & ~(size_t)15;
-    const size_t tn_off = N * 16;
+    const size_t tn_off = N * 24;
     if (!L->move_dev) {
-        HIP_TRY(hipMalloc(&L->move_dev, tn_off + nm + nm + 64));
-        k_zero_bytes<<<(int)((nm / 16 + 255) / 256), 256, 0, L->st>>>(
-            (uint4 *)((char *)L->move_dev + tn_off + nm), nm / 16);
+        HIP_TRY(hipMalloc(&L->move_dev, tn_off + nm + 64));
+        // the marks, rounded up to 16 bytes (the excess lies in the list after them)
+        const size_t z16 = (N * 4 + 15) / 16;
+        k_zero_bytes<<<(int)((z16 + 255) / 256), 256, 0, L->st>>>((uint4 *)((char *)L->move_dev + N * 16), z16);
     }
     double *rn = (double *)L->move_dev;
     int32_t *own = (int32_t *)((char *)L->move_dev + N * 8);
     int32_t *chg = (int32_t *)((char *)L->move_dev + N * 12);
+    uint32_t *mark = (uint32_t *)((char *)L->move_dev + N * 16);
+    int32_t *mlist = (int32_t *)((char *)L->move_dev + N * 20);
     uint8_t *tn = (uint8_t *)((char *)L->move_dev + tn_off);
-    uint8_t *mark = tn + nm;
-    int *counter = (int *)(mark + nm);
+    int *counter = (int *)(tn + nm);
+    int *mcount = counter + 4;
     k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
     k_map<<<n, 256, 0, L->st>>>(d, n, own);
     k_zero_int<<<1, 64, 0, L->st>>>(counter);
@@ -1252,9 +1281,12 @@ static FslStatus remap(FslLattice *L)
         return FSL_OK;
     }
     const int gch = (nch + 255) / 256, gmk = (int)(((int64_t)nch * 27 + 255) / 256);
-    // only the changed cells and their neighbours change type or solid neighbours
-    k_mark_around<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, 1);
-    DISPATCH(L, run_liquid_form, L, 0, mark);
+    const int64_t nmax = std::min<int64_t>((int64_t)nch * 27, (int64_t)N);
+    // only the changed cells and their neighbours change type or solid
+    // neighbours: listed once each
+    k_zero_int<<<1, 64, 0, L->st>>>(mcount);
+    k_mark_list<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, mlist, mcount);
+    DISPATCH(L, run_liquid_form, L, 0, mlist, mcount, nmax);
     k_cover<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
     for (int round = 0;; ++round) {
         if (round > nch) return fail(FSL_ERR_DEVICE, "uncovered cells: rounds do not end");
@@ -1269,9 +1301,10 @@ static FslStatus remap(FslLattice *L)
     }
     DISPATCH(L, run_uncover_finish, L, chg, nch, rn);
     k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
-    k_near_solid_marked<<<blocks_for(d.N), 256, 0, L->st>>>(d, mark);
-    DISPATCH(L, run_liquid_form, L, 1, mark);
-    k_mark_around<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, 0);
+    const int gml = (int)((nmax + 255) / 256);
+    k_near_solid_list<<<gml, 256, 0, L->st>>>(d, mlist, mcount);
+    DISPATCH(L, run_liquid_form, L, 1, mlist, mcount, nmax);
+    k_unmark_list<<<gml, 256, 0, L->st>>>(mlist, mcount, mark);
     HIP_TRY(hipGetLastError());
     FslStatus r = finalize(L, false, true);
     if (r != FSL_OK) return r;

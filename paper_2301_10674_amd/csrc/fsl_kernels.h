@@ -33,6 +33,8 @@ struct Dev {
     void *bbfull;             // full records of cells next to three or more spheres (every
                               // cell in the FP16-storage form): the moving-wall term of each
                               // direction, 32 Real values each
+    int32_t *rcell;           // cell of each record: compact record k at rcell[k], full record
+                              // f at rcell[N - 1 - f]
     int rec_compact;          // 1: compact records where they suffice (FP64, FP32 storage)
     int img_check;            // 1: some sphere nearly spans the periodic box, so a link
                               // midpoint and its cell centre may see different images

@@ -439,14 +439,16 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
     }
 }
 
-// moving-wall records of every cell that has sphere links
+// moving-wall records of every cell that has sphere links (one thread per
+// record, through the record-cell list)
 template <class R>
-__global__ void k_bb_terms(Dev d)
+__global__ void k_bb_terms(Dev d, int nrec)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrec) return;
+    const int nc = d.cnt[4];
+    const int c = t < nc ? d.rcell[t] : d.rcell[d.N - 1 - (t - nc)];
     const int slot = d.bbslot[c];
-    if (slot == -1) return;
     const Cell pc = cell_xyz(d, c);
     const uint32_t sm = d.smask[c];
     if (slot <= -2) {
@@ -753,6 +755,8 @@ __global__ __launch_bounds__(SLOT_THREADS) void k_slot_write(Dev d, const uint8_
     if (k == 1) slot = oc + (int)__popcll(mc & below);
     else if (k == 2) slot = -2 - (of + (int)__popcll(mf & below));
     if (c < d.N) d.bbslot[c] = slot;
+    if (slot >= 0) d.rcell[slot] = c;
+    else if (slot <= -2) d.rcell[d.N - 1 - (-slot - 2)] = c;
 }
 
 // highest z that holds a liquid or interface cell
@@ -1531,11 +1535,11 @@ void launch_setup_links(const Dev &d, hipStream_t st)
 }
 
 template <class R>
-void launch_bb_terms(const Dev &d, hipStream_t st)
+void launch_bb_terms(const Dev &d, int nrec, hipStream_t st)
 {
-    k_bb_terms<R><<<(d.N + 255) / 256, 256, 0, st>>>(d);
+    k_bb_terms<R><<<(nrec + 255) / 256, 256, 0, st>>>(d, nrec);
 }
-template void launch_bb_terms<double>(const Dev &, hipStream_t);
-template void launch_bb_terms<float>(const Dev &, hipStream_t);
+template void launch_bb_terms<double>(const Dev &, int, hipStream_t);
+template void launch_bb_terms<float>(const Dev &, int, hipStream_t);
 
 }  // namespace fsl
