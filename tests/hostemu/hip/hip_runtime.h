@@ -235,8 +235,17 @@ template <class T> inline T atomicOr(T *p, typename hipemu::same<T>::type v)
     return o;
 }
 
+template <class T>
+inline T atomicCAS(T *p, typename hipemu::same<T>::type cmp, typename hipemu::same<T>::type v)
+{
+    T o = *p;
+    if (o == cmp) *p = v;
+    return o;
+}
+
 inline double __dadd_rn(double a, double b) { return a + b; }
 inline double __dmul_rn(double a, double b) { return a * b; }
+inline double __dsub_rn(double a, double b) { return a - b; }
 
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
