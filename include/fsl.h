@@ -82,6 +82,12 @@ typedef struct {
     int32_t check_every;    /* watchdog interval in steps (0: never; see fsl_step) */
     int32_t variants;       /* FSL_VAR_* bits; 0 is the model of Section 2.1
                                as the cited FSLBM and collision define it */
+    int32_t grid_blocks;    /* 0: launch geometry chosen from the lattice size;
+                               otherwise 8..2048 workgroups for the dense pass and
+                               the interface-list kernels.  Results do not depend
+                               on it (every cell is updated on its own, every
+                               reduction has a fixed order per geometry); it
+                               exists to test that. */
 } FslParams;
 
 /* Optional variants of the free surface (Thuerey 2007) and of the collision

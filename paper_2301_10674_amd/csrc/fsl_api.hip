@@ -103,8 +103,12 @@ static bool params_ok(const FslParams *p, std::string &why)
 {
     if (!p) { why = "params is NULL"; return false; }
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) { why = "each lattice extent must be >= 3"; return false; }
-    // PDF element offsets are 32-bit byte offsets within one direction array
+    // per-cell arrays of 8-byte values are addressed with 32-bit byte offsets
     if ((double)p->nx * p->ny * p->nz * 8.0 >= 4294967296.0) { why = "lattice too large"; return false; }
+    if (p->grid_blocks != 0 && (p->grid_blocks < 8 || p->grid_blocks > 2048)) {
+        why = "grid_blocks must be 0 or lie in [8, 2048]";
+        return false;
+    }
     if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return false; }
     if (!(p->omega > 0.0 && p->omega < 2.0)) { why = "omega must lie in (0, 2)"; return false; }
     for (int a = 0; a < 3; ++a)
@@ -1072,6 +1076,7 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.nbx = (d.nx + BULK_THREADS - 1) / BULK_THREADS;
     d.rows = d.ny * d.nz;
     d.xcd_map = (d.rows % 8) == 0;
+    d.bulk_blocks = params->grid_blocks;
     d.pdf[0] = base + lay.pdf[0];
     d.pdf[1] = base + lay.pdf[1];
     d.mq = (double *)(base + lay.mq);
@@ -1109,7 +1114,8 @@ FslStatus fsl_create_lattice(const FslParams *params, void *ws, size_t bytes, vo
     d.tie = params->normal_tie;
     d.rule_iso = params->rule_isolated;
     d.variants = params->variants;
-    L->list_blocks = (int)std::min<size_t>(2048, std::max<size_t>(64, N / 4096));
+    L->list_blocks = params->grid_blocks ? params->grid_blocks
+                                         : (int)std::min<size_t>(2048, std::max<size_t>(64, N / 4096));
 
     // stage the host inputs
     double *tmp = nullptr;

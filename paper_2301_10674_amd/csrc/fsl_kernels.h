@@ -13,6 +13,7 @@ struct Dev {
     int nx, ny, nz, N;
     int nbx, rows;            // dense grid: x-blocks of 256 cells per (y, z) row
     int xcd_map;              // 1: rows are interleaved over the 8 XCDs
+    int bulk_blocks;          // workgroups of the dense pass (0: one per row segment, at most 2048)
     void *pdf[2];             // storage type depends on the precision form
     double *mq;               // interface: mass m; liquid: m minus own outgoing PDFs
     double *phi;              // interface fill level m / rho*

@@ -1462,7 +1462,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_geom(Dev d, int which)
 // workgroups of the persistent dense kernel
 static int bulk_grid(const Dev &d)
 {
-    int gb = d.nbx * d.rows;
+    int gb = d.bulk_blocks > 0 ? d.bulk_blocks : d.nbx * d.rows;
     if (gb > BULK_MAX_BLOCKS) gb = BULK_MAX_BLOCKS;
     if (d.xcd_map) gb &= ~7;
     return gb;

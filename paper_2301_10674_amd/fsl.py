@@ -53,7 +53,7 @@ class FslParams(ctypes.Structure):
         ("rho_gas", ctypes.c_double), ("conv_eps", ctypes.c_double),
         ("normal_tie", ctypes.c_double), ("rule_isolated", ctypes.c_int32),
         ("normals", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("variants", ctypes.c_int32),
+        ("variants", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
     ]
 
 
@@ -78,7 +78,7 @@ class FslTrainParams(ctypes.Structure):
 def make_params(shape, precision="fp64", omega=1.0, accel=(0.0, 0.0, 0.0), sigma=0.0,
                 rho_gas=1.0, conv_eps=1e-2, normal_tie=1e-6, rule_isolated=True,
                 normals=0, check_every=0, flux_modifiers=False, normal_excess=False, csf_curvature=False,
-                galilean=False):
+                galilean=False, grid_blocks=0):
     p = FslParams()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -92,6 +92,7 @@ def make_params(shape, precision="fp64", omega=1.0, accel=(0.0, 0.0, 0.0), sigma
     p.variants = (FSL_VAR_FLUX_MODIFIERS if flux_modifiers else 0) | \
         (FSL_VAR_NORMAL_EXCESS if normal_excess else 0) | (FSL_VAR_CSF_CURVATURE if csf_curvature else 0) | \
         (FSL_VAR_GALILEAN if galilean else 0)
+    p.grid_blocks = int(grid_blocks)
     return p
 
 

@@ -46,12 +46,18 @@ def test_workspace_bytes(lib):
 
 
 @pytest.mark.parametrize("kw", [dict(omega=0.0), dict(omega=2.0), dict(conv_eps=-1.0),
-                                dict(rho_gas=0.0), dict(normals=2), dict(check_every=-1)])
+                                dict(rho_gas=0.0), dict(normals=2), dict(check_every=-1),
+                                dict(grid_blocks=4), dict(grid_blocks=4096)])
 def test_bad_params_rejected(lib, kw):
     base = dict(shape=(16, 8, 8), precision="fp32", omega=1.5)
     base.update(kw)
     assert F.workspace_bytes(F.make_params(**base)) == 0
     assert len(lib.fsl_last_error()) > 0
+
+
+def test_grid_blocks_accepted(lib):
+    for gb in (0, 8, 24, 2048):
+        assert F.workspace_bytes(F.make_params((16, 8, 8), "fp32", omega=1.5, grid_blocks=gb)) > 0
 
 
 def test_variant_bits(lib):

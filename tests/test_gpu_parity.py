@@ -196,6 +196,27 @@ def test_determinism_fp32():
         assert np.array_equal(res[0][k], res[1][k]), k
 
 
+@pytest.mark.parametrize("case,prec", [("film", "fp64"), ("splash", "fp32")])
+def test_launch_geometry_does_not_change_results(case, prec):
+    """The same lattice stepped with the automatic launch geometry and with 8
+    and 24 workgroups for the dense pass and the interface-list kernels
+    (each workgroup then walks many more row segments and list entries):
+    every cell's state is bit-identical; the total mass, a sum of
+    per-workgroup partials, agrees to rounding."""
+    w = I.film_with_surface_spheres(sigma=1e-3) if case == "film" else I.splash(shape=(24, 16, 20))
+    res, mass = [], []
+    for gb in (0, 8, 24):
+        g = F().lattice_from_workload(w, prec, grid_blocks=gb)
+        g.step(40)
+        res.append(gpu_fields(g))
+        mass.append(g.total_mass())
+        g.destroy()
+    for r in res[1:]:
+        for k in res[0]:
+            assert np.array_equal(res[0][k], r[k]), k
+    assert max(abs(m - mass[0]) for m in mass) <= 1e-14 * mass[0], mass
+
+
 # ------------------------------------------------------------------ error paths
 def test_argument_and_state_errors():
     f = F()
