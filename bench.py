@@ -391,6 +391,7 @@ def run_form(w, form, steps, warmup, main_form=None, particles=True):
     s = STORE_BYTES[precision]
     bulk_avg_s = bulk_ms / 1e3 / max(launches, 1)
     bytes_per_launch = liq * (54 * s + 16) + w.ncells * 1
+    pdf_bytes_per_launch = liq * 54 * s
     # whole step: the dense pass plus the interface cells (own and pulled
     # PDFs read, PDFs written, fill level, mass, density, mark)
     itf = 0.5 * (itf0 + itf1)
@@ -400,6 +401,7 @@ def run_form(w, form, steps, warmup, main_form=None, particles=True):
         mlups_fluid=fluid * steps / secs / 1e6, mlups_all=w.ncells * steps / secs / 1e6,
         bulk_us=1e6 * bulk_avg_s, bulk_launches=launches,
         bulk_gbs=bytes_per_launch / bulk_avg_s / 1e9, bytes_per_launch=bytes_per_launch,
+        bulk_pdf_gbs=pdf_bytes_per_launch / bulk_avg_s / 1e9,
         step_gbs=bytes_per_step / (secs / steps) / 1e9, bytes_per_step=bytes_per_step,
         liquid_cells=liq, fluid_cells=fluid, interface_cells=0.5 * (itf0 + itf1),
         mass_drift=abs(M1 - M0) / M0, total_mass_us=total_mass_us, interface_error=interface_error(lat, fsl))
@@ -472,12 +474,26 @@ def cpu_baseline(ny, nz, seconds_target=12.0):
 
     v1, c1, fluid, n1, s1 = timed(1)
     va, ca, _, na, sa = timed(0)
+    # the channel film (64 x 8 x 32, 200 steps) on one thread and on all
+    wf = inputs.channel_film()
+    film = {}
+    for threads in (1, 0):
+        used = O.set_threads(threads)
+        o = O.OracleLattice(wf.shape, wf.omega, accel=wf.accel, sigma=wf.sigma, rho_gas=wf.rho_gas,
+                            conv_eps=wf.conv_eps, fill=wf.fill, rho=wf.rho, vel=wf.vel)
+        o.set_particles(wf.centre, wf.radius, wf.sphere_vel, wf.sphere_angvel)
+        t = o.read(O.F_TYPE)
+        nf = int(((t == O.LIQUID) | (t == O.INTERFACE)).sum())
+        t0 = time.perf_counter()
+        o.step(200)
+        film["threads_%d" % used] = nf * 200 / (time.perf_counter() - t0) / 1e6
     O.set_threads(0)
     return {"value": v1, "unit": "MLUPS (fluid cells)", "cores": c1, "kind": "oracle",
             "sample": "FP64 oracle, the flume recipe on a 64x%dx%d periodic box (%d fluid cells), "
                       "%d steps after 1 warm-up step, %.1f s on 1 thread" % (ny, nz, fluid, n1, s1),
             "all_cores": {"value": va, "cores": ca,
-                          "sample": "%d steps after 1 warm-up step, %.1f s on %d threads" % (na, sa, ca)}}
+                          "sample": "%d steps after 1 warm-up step, %.1f s on %d threads" % (na, sa, ca)},
+            "channel_film_64x8x32": dict(film, unit="MLUPS (fluid cells)", sample="200 steps")}
 
 
 def gpu_weights(w):
@@ -491,11 +507,12 @@ def gpu_weights(w):
     return p
 
 
-def accuracy_vs_oracle(weights=None, crop_steps=500, film_steps=200):
+def accuracy_vs_oracle(weights=None, crop_steps=500, film_steps=200, crop5_steps=200):
     """Velocity and fill-level error of each storage form against the FP64
     oracle on the same seeded inputs: the flume recipe on its own periodic
     128 x 40 x 192 box after crop_steps steps (also the oracle's own error
-    when it stores FP16 deviations: the floor of any FP16-storage form), and
+    when it stores FP16 deviations: the floor of any FP16-storage form), the
+    large flume's recipe on a 64 x 80 x 256 box after crop5_steps steps, and
     the channel film 64 x 8 x 32 after film_steps steps, where the learned
     form is compared with the oracle running the same (BF16-rounded) network
     with the same fallback rules."""
@@ -559,6 +576,16 @@ def accuracy_vs_oracle(weights=None, crop_steps=500, film_steps=200):
                        "mass_drift_1e-12": max(crop[p]["mass_drift"] for p in ("fp64", "fp32", "fp16")) <= 1e-12}
     out[w.name] = crop
     log("accuracy crop:", json.dumps(crop))
+
+    # the large flume's recipe (80 x 256 cross-section) on a 64-cell-long box
+    w = inputs.flume(nx=64, ny=80, nz=256, seed=3)
+    ref = oracle_run(w, crop5_steps)
+    c5 = {"steps": crop5_steps}
+    for prec in ("fp64", "fp32", "fp16"):
+        tg, vg, fg, drift = gpu_run(w, crop5_steps, prec)
+        c5[prec] = dict(compare(tg, vg, fg, ref), mass_drift=drift)
+    out[w.name] = c5
+    log("accuracy large-flume crop:", json.dumps(c5))
 
     w = inputs.channel_film()
     ref = oracle_run(w, film_steps)
@@ -728,6 +755,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r["bulk_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["bulk_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_bulk", "bytes_per_launch": r["bytes_per_launch"],
+                     "pdf_only_achieved": r["bulk_pdf_gbs"],
                      "avg_launch_us": r["bulk_us"], "copy_gbs": copy_gbs,
                      "frac_of_copy": r["bulk_gbs"] / copy_gbs},
         "step_roofline": {"achieved": r["step_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
