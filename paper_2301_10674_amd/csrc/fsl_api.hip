@@ -26,10 +26,9 @@ void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
 void launch_watch_final(const Dev &d, int list_blocks, hipStream_t st);
 void launch_setup_links(const Dev &d, hipStream_t st);
 void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st);
-void launch_mem_fill(const Dev &d, int nsph, const int32_t *offs, int2 *ent, hipStream_t st);
+void launch_mem_fill(const Dev &d, int nsph, const MemLists &ml, int only_changed, hipStream_t st);
 template <class S>
-void launch_mem(const Dev &d, int p, int nsph, const int32_t *offs, const int2 *ent, double *out,
-                hipStream_t st);
+void launch_mem(const Dev &d, int p, int nsph, const MemLists &ml, double *out, hipStream_t st);
 template <class R>
 void launch_bb_terms(const Dev &d, int nrec, hipStream_t st);
 }  // namespace fsl
@@ -72,11 +71,12 @@ struct FslLattice {
     bool sph_host_stale = false;   // the table was last written from device arrays
     void *bb_dev = nullptr;   // moving-wall bounce-back records
     size_t bb_cap = 0;
-    void *mem_dev = nullptr;  // momentum exchange: per-sphere entry offsets, then the entries
+    void *mem_dev = nullptr;  // momentum exchange: the link lists (ml points into it)
     void *move_dev = nullptr; // moving spheres: new owner map, round types and densities, counter
     size_t mem_cap = 0;
+    MemLists ml{};
     bool mem_stale = true;    // link lists must be rebuilt before the next force evaluation
-    size_t mem_ent_off = 0;
+    bool mem_moved = false;   // spheres moved since the lists were last brought up to date
     float *mlpP = nullptr;    // learned estimator: FP32 weights
     uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
     void *read_buf = nullptr; // device staging of fields read to the host
@@ -296,18 +296,27 @@ __global__ void k_apply_solid(Dev d)
 constexpr uint8_t F_OPEN = 8, F_NEWC = 16;
 
 // cells whose owner changes with the new map (INT_MAX: no sphere), appended
-// to a list (one atomic per wavefront); count = list length
+// to a list in cell order (one atomic per wavefront); count = list length.
+// Four cells per thread (both maps are 256-byte aligned).
 __global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own, int *count, int32_t *list)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ch = c < d.N && (own[c] == INT_MAX ? -1 : own[c]) != d.owner[c];
-    const uint64_t m = __ballot(ch);
-    if (m == 0) return;
-    const int lane = __lane_id();
-    int base = 0;
-    if (lane == 0) base = atomicAdd(count, (int)__popcll(m));
-    base = __shfl(base, 0);
-    if (ch) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = c;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    int a[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX}, b[4] = {-1, -1, -1, -1};
+    if (4 * w + 3 < d.N) {
+        const int4 va = ((const int4 *)own)[w], vb = ((const int4 *)d.owner)[w];
+        a[0] = va.x, a[1] = va.y, a[2] = va.z, a[3] = va.w;
+        b[0] = vb.x, b[1] = vb.y, b[2] = vb.z, b[3] = vb.w;
+    } else {
+        for (int k = 0; k < 4 && 4 * w + k < d.N; ++k) {
+            a[k] = own[4 * w + k];
+            b[k] = d.owner[4 * w + k];
+        }
+    }
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if ((a[k] == INT_MAX ? -1 : a[k]) != b[k]) bits |= 1u << k;
+    list_append_bits(list, count, bits, 4 * w);
 }
 
 // The listed cells and their 26 neighbours, each once: the first visitor
@@ -486,6 +495,25 @@ __global__ void k_near_solid_list(Dev d, const int32_t *list, const int *count)
     d.flags[c] = (uint8_t)((d.flags[c] & ~F_NEAR_SOLID) | (m ? F_NEAR_SOLID : 0));
 }
 
+// Momentum-exchange lists a remap may change: a cell's links into spheres
+// change only when the cell or a neighbour changes owner, so only the cells
+// of list[0 .. *count) (the changed cells and their neighbours) change
+// entries, and only in the lists of the old and the new owners of their
+// neighbours (before the new owners are committed).
+__global__ void k_mem_dirty(Dev d, const int32_t *own, const int32_t *list, const int *count, int32_t *dirty)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *count) return;
+    const int c = list[t];
+    for (int j = 0; j < 27; ++j) {
+        const int y = nbr(d, c, j);
+        if (y < 0) continue;
+        const int qo = d.owner[y], qn = own[y];
+        if (qo >= 0) dirty[qo] = 1;
+        if (qn != INT_MAX) dirty[qn] = 1;
+    }
+}
+
 // zero n bytes (16 per thread; n a multiple of 16)
 __global__ void k_zero_bytes(uint4 *p, size_t n16)
 {
@@ -527,11 +555,25 @@ __global__ void k_refresh_if(Dev d, int p)
     d.phi[c] = d.mq[c] / d.rho[c];
 }
 
+// the interface cells in cell order, sixteen flag bytes per thread (the flag
+// array is 256-byte aligned; bytes past N are never appended)
 __global__ void k_build_list(Dev d, int which)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool pred = c < d.N && (d.flags[c] & T_MASK) == T_IF;
-    list_append(d.list[which], &d.cnt[which], pred, c);
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (16 * w + 15 < d.N) {
+        v = ((const uint4 *)d.flags)[w];
+    } else if (16 * w < d.N) {
+        uint32_t b[4] = {0u, 0u, 0u, 0u};
+        for (int k = 0; 16 * w + k < d.N; ++k) b[k >> 2] |= (uint32_t)d.flags[16 * w + k] << (8 * (k & 3));
+        v = make_uint4(b[0], b[1], b[2], b[3]);
+    }
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (((u[k >> 2] >> (8 * (k & 3))) & T_MASK) == T_IF) bits |= 1u << k;
+    list_append_bits(d.list[which], &d.cnt[which], bits, 16 * w);
 }
 
 __global__ void k_zero_counts(Dev d, int stats)
@@ -827,13 +869,13 @@ static void run_bb_terms(FslLattice *L)
 template <class S>
 static void run_mem(FslLattice *L, double *out)
 {
-    const int32_t *offs = (const int32_t *)L->mem_dev;
-    const int2 *ent = (const int2 *)((const char *)L->mem_dev + L->mem_ent_off);
-    launch_mem<S>(L->d, L->parity, L->nsph, offs, ent, out, L->st);
+    launch_mem<S>(L->d, L->parity, L->nsph, L->ml, out, L->st);
 }
 
 // Per-sphere lists of the cells that can link into each sphere (for the
-// momentum exchange): count on the device, offsets on the host, fill.
+// momentum exchange), built from scratch: count on the device, slots on the
+// host (a quarter and 16 entries more than the count, room for the lists to
+// grow as the spheres move), fill.
 static FslStatus build_mem_lists(FslLattice *L)
 {
     Dev &d = L->d;
@@ -847,21 +889,34 @@ static FslStatus build_mem_lists(FslLattice *L)
     HIP_TRY(hipStreamSynchronize(L->st));
     int64_t total = 0;
     for (int q = 0; q < n; ++q) {
-        total += offs[q + 1];
+        const int64_t c = offs[q + 1];
+        total += c + c / 4 + 16;
         if (total > INT32_MAX) return fail(FSL_ERR_NOMEM, "too many momentum-exchange entries");
         offs[q + 1] = (int32_t)total;
     }
-    L->mem_ent_off = (((size_t)n + 1) * 4 + 255) & ~(size_t)255;
-    const size_t need = L->mem_ent_off + (size_t)std::max<int64_t>(total, 1) * 8;
+    // slot offsets, counts, marks, boxes (6 per sphere), flag, entries
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_cnt = al(((size_t)n + 1) * 4), o_dirty = o_cnt + al((size_t)n * 4),
+                 o_box = o_dirty + al((size_t)n * 4), o_flag = o_box + al((size_t)n * 24), o_ent = o_flag + 256;
+    const size_t need = o_ent + (size_t)total * 8;
     if (need > L->mem_cap) {
         if (L->mem_dev) HIP_TRY(hipFree(L->mem_dev));
         L->mem_dev = nullptr;
         L->mem_cap = 0;
+        L->ml = MemLists{};
         HIP_TRY(hipMalloc(&L->mem_dev, need + need / 8));
         L->mem_cap = need + need / 8;
     }
-    HIP_TRY(hipMemcpyAsync(L->mem_dev, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, L->st));
-    launch_mem_fill(d, n, (const int32_t *)L->mem_dev, (int2 *)((char *)L->mem_dev + L->mem_ent_off), L->st);
+    char *base = (char *)L->mem_dev;
+    L->ml.offs = (int32_t *)base;
+    L->ml.cnt = (int32_t *)(base + o_cnt);
+    L->ml.dirty = (int32_t *)(base + o_dirty);
+    L->ml.box = (int32_t *)(base + o_box);
+    L->ml.flag = (int *)(base + o_flag);
+    L->ml.ent = (int2 *)(base + o_ent);
+    HIP_TRY(hipMemcpyAsync(L->ml.offs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, L->st));
+    k_zero_int<<<1, 64, 0, L->st>>>(L->ml.flag);
+    launch_mem_fill(d, n, L->ml, 0, L->st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
@@ -889,7 +944,7 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     if (!near_done) k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     DISPATCH(L, run_refresh, L);
     k_zero_counts<<<1, 64, 0, L->st>>>(d, reset_stats ? 1 : 0);
-    k_build_list<<<blocks_for(d.N), 256, 0, L->st>>>(d, L->parity);
+    k_build_list<<<blocks_for((d.N + 15) / 16), 256, 0, L->st>>>(d, L->parity);
     // running pool total of the watchdog, exact after every rebuild
     k_pool_partial<<<RED_BLOCKS, 256, 0, L->st>>>(d);
     k_sum_partials<<<1, 256, 0, L->st>>>(d, RED_BLOCKS, (int)(d.wd - d.partial) + WD_POOL);
@@ -1230,18 +1285,35 @@ FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
     if (!L) return fail(FSL_ERR_STATE, "lattice is NULL");
     if (L->nsph == 0) return FSL_OK;
     if (!out) return fail(FSL_ERR_ARG, "out is NULL");
+    // the lists: rebuilt after set-up, else refilled for the spheres that
+    // moved their box or were marked by a remap; a list that outgrew its
+    // slot is only found after the sums, which are then redone
+    bool refill = false;
     if (L->mem_stale) {
         FslStatus r = build_mem_lists(L);
         if (r != FSL_OK) return r;
         L->mem_stale = false;
+    } else if (L->mem_moved) {
+        k_zero_int<<<1, 64, 0, L->st>>>(L->ml.flag);
+        launch_mem_fill(L->d, L->nsph, L->ml, 1, L->st);
+        refill = true;
     }
+    L->mem_moved = false;
     if (!L->mem_dev) return fail(FSL_ERR_STATE, "sphere link lists missing");
     double *buf = out_on_device ? out : L->sph_dev + (size_t)L->nsph * 10;
-    DISPATCH(L, run_mem, L, buf);
-    HIP_TRY(hipGetLastError());
-    if (!out_on_device)
-        HIP_TRY(hipMemcpyAsync(out, buf, (size_t)L->nsph * 6 * 8, hipMemcpyDeviceToHost, L->st));
-    HIP_TRY(hipStreamSynchronize(L->st));
+    for (int pass = 0; pass < 2; ++pass) {
+        DISPATCH(L, run_mem, L, buf);
+        HIP_TRY(hipGetLastError());
+        if (!out_on_device)
+            HIP_TRY(hipMemcpyAsync(out, buf, (size_t)L->nsph * 6 * 8, hipMemcpyDeviceToHost, L->st));
+        int outgrown = 0;
+        if (refill) HIP_TRY(hipMemcpyAsync(&outgrown, L->ml.flag, 4, hipMemcpyDeviceToHost, L->st));
+        HIP_TRY(hipStreamSynchronize(L->st));
+        if (!outgrown) break;
+        FslStatus r = build_mem_lists(L);
+        if (r != FSL_OK) return r;
+        refill = false;
+    }
     return FSL_OK;
 }
 
@@ -1252,33 +1324,38 @@ static FslStatus remap(FslLattice *L)
     const int n = L->nsph;
     Dev &d = L->d;
     const size_t N = (size_t)d.N;
-    // scratch: densities (8 B), new owners (4 B), changed cells (4 B), marks
-    // (4 B), the marked cells (4 B) and round types (1 B) per cell, two
-    // counters; marks start zero and are cleared again after use
-    const size_t nm = (N + 15) & ~(size_t)15;
-    const size_t tn_off = N * 24;
+    // scratch, each part 256-byte aligned: densities (8 B), new owners
+    // (4 B), changed cells (4 B), marks (4 B), the marked cells (4 B) and
+    // round types (1 B) per cell, two counters; marks start zero and are
+    // cleared again after use
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_own = al(N * 8), o_chg = o_own + al(N * 4), o_mark = o_chg + al(N * 4),
+                 o_mlist = o_mark + al(N * 4), o_tn = o_mlist + al(N * 4), o_cnt = o_tn + al(N);
     if (!L->move_dev) {
-        HIP_TRY(hipMalloc(&L->move_dev, tn_off + nm + 64));
-        // the marks, rounded up to 16 bytes (the excess lies in the list after them)
-        const size_t z16 = (N * 4 + 15) / 16;
-        k_zero_bytes<<<(int)((z16 + 255) / 256), 256, 0, L->st>>>((uint4 *)((char *)L->move_dev + N * 16), z16);
+        HIP_TRY(hipMalloc(&L->move_dev, o_cnt + 64));
+        const size_t z16 = al(N * 4) / 16;
+        k_zero_bytes<<<(int)((z16 + 255) / 256), 256, 0, L->st>>>((uint4 *)((char *)L->move_dev + o_mark), z16);
     }
-    double *rn = (double *)L->move_dev;
-    int32_t *own = (int32_t *)((char *)L->move_dev + N * 8);
-    int32_t *chg = (int32_t *)((char *)L->move_dev + N * 12);
-    uint32_t *mark = (uint32_t *)((char *)L->move_dev + N * 16);
-    int32_t *mlist = (int32_t *)((char *)L->move_dev + N * 20);
-    uint8_t *tn = (uint8_t *)((char *)L->move_dev + tn_off);
-    int *counter = (int *)(tn + nm);
+    char *mv = (char *)L->move_dev;
+    double *rn = (double *)mv;
+    int32_t *own = (int32_t *)(mv + o_own);
+    int32_t *chg = (int32_t *)(mv + o_chg);
+    uint32_t *mark = (uint32_t *)(mv + o_mark);
+    int32_t *mlist = (int32_t *)(mv + o_mlist);
+    uint8_t *tn = (uint8_t *)(mv + o_tn);
+    int *counter = (int *)(mv + o_cnt);
     int *mcount = counter + 4;
     k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
     k_map<<<n, 256, 0, L->st>>>(d, n, own);
     k_zero_int<<<1, 64, 0, L->st>>>(counter);
-    k_owner_changes<<<blocks_for(d.N), 256, 0, L->st>>>(d, own, counter, chg);
+    k_owner_changes<<<blocks_for((d.N + 3) / 4), 256, 0, L->st>>>(d, own, counter, chg);
     HIP_TRY(hipGetLastError());
     int nch = 0;
     HIP_TRY(hipMemcpyAsync(&nch, counter, 4, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
+    // live momentum-exchange lists are refilled where they may have changed
+    const bool lists_live = L->mem_dev && !L->mem_stale;
+    L->mem_moved = true;
     if (nch == 0) {
         // no cell changes owner: only the moving-wall records follow the spheres
         run_bb_terms(L);
@@ -1292,6 +1369,8 @@ static FslStatus remap(FslLattice *L)
     // neighbours: listed once each
     k_zero_int<<<1, 64, 0, L->st>>>(mcount);
     k_mark_list<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, mlist, mcount);
+    const int gml = (int)((nmax + 255) / 256);
+    if (lists_live) k_mem_dirty<<<gml, 256, 0, L->st>>>(d, own, mlist, mcount, L->ml.dirty);
     DISPATCH(L, run_liquid_form, L, 0, mlist, mcount, nmax);
     k_cover<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
     for (int round = 0;; ++round) {
@@ -1307,13 +1386,13 @@ static FslStatus remap(FslLattice *L)
     }
     DISPATCH(L, run_uncover_finish, L, chg, nch, rn);
     k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
-    const int gml = (int)((nmax + 255) / 256);
     k_near_solid_list<<<gml, 256, 0, L->st>>>(d, mlist, mcount);
     DISPATCH(L, run_liquid_form, L, 1, mlist, mcount, nmax);
     k_unmark_list<<<gml, 256, 0, L->st>>>(mlist, mcount, mark);
     HIP_TRY(hipGetLastError());
     FslStatus r = finalize(L, false, true);
     if (r != FSL_OK) return r;
+    L->mem_stale = !lists_live;
     HIP_TRY(hipStreamSynchronize(L->st));
     return FSL_OK;
 }

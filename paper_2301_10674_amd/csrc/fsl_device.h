@@ -444,4 +444,30 @@ __device__ __forceinline__ void list_append(int32_t *list, int32_t *counter, boo
     if (pred) list[base + (int)__popcll(mask & ((1ull << lane) - 1ull))] = value;
 }
 
+// Appends c0 + k for every set bit k of bits (ascending) to list: lanes hold
+// consecutive cell groups, so the list gets the wavefront's cells in cell
+// order (the list kernels' loads stay coalesced); one atomic per wavefront.
+__device__ __forceinline__ void list_append_bits(int32_t *list, int32_t *counter, uint32_t bits, int32_t c0)
+{
+    const int n = __popcll((unsigned long long)bits);
+    const int lane = __lane_id();
+    int inc = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+    }
+    const int total = __shfl(inc, 63);
+    if (total == 0) return;
+    int base = 0;
+    if (lane == 63) base = atomicAdd(counter, total);
+    base = __shfl(base, 63);
+    int pos = base + inc - n;
+    while (bits) {
+        const int k = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1u;
+        list[pos++] = c0 + k;
+    }
+}
+
 }  // namespace fsl

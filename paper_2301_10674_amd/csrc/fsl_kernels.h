@@ -53,6 +53,17 @@ struct Dev {
     int variants;             // VAR_* bits
 };
 
+// Momentum-exchange link lists.  Sphere q owns the entry slot
+// [offs[q], offs[q+1]) of ent, cnt[q] entries of it in use (cell index,
+// mask of the cell's links into the sphere).  dirty[q] is set where a remap
+// may have changed the list, box[6q .. 6q+5] is the bounding box the list
+// was last filled from, flag[0] is set when a list outgrows its slot.
+struct MemLists {
+    int32_t *offs, *cnt, *dirty, *box;
+    int *flag;
+    int2 *ent;
+};
+
 // variants: flux modifiers between interface cells and normal-weighted
 // excess mass (Thuerey 2007), curvature from corner normals (Brackbill et al.
 // 1992), Galilean correction of the cumulant collision (Geier et al. 2015)

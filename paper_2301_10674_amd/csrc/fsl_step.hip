@@ -544,50 +544,167 @@ __device__ __forceinline__ uint32_t box_links(const Dev &d, const SphereBox &b, 
     return m;
 }
 
+// The walk over the cells of box b that can link into sphere q, in box
+// order (z, then y, then x ascending from the box origin), one cell per
+// thread and call of visit(m, c) (the mask of the cell's links into q and
+// the cell; m = 0 for idle threads).  Every thread makes the same calls, so
+// visit may synchronise the block.  A link into q starts within sqrt(3) of
+// a cell centre at most r from the sphere's centre, so only cells centred
+// within r + 1.75 can hold one, and cells centred within r - 0.5 are solid:
+// per box row the walk takes the one or two x-runs of that shell.  Where
+// the sphere nearly spans a periodic axis (the box's offsets may then not
+// be the nearest image) it walks the whole box.
+template <class Visit>
+__device__ __forceinline__ void sphere_walk(const Dev &d, const SphereBox &b, int q, Visit &&visit)
+{
+    __shared__ int s_end[256], s_lo0[256], s_n0[256], s_lo1[256];
+    const double *sp = d.sph + 10 * q;
+    const double X = sp[0], Y = sp[1], Z = sp[2], rad = sp[3];
+    const int t = (int)threadIdx.x;
+    if (!(2.0 * (rad + 4.0) < (double)d.nx && 2.0 * (rad + 4.0) < (double)d.ny)) {
+        const int ncell = b.ex * b.ey * b.ez;
+        for (int k0 = 0; k0 < ncell; k0 += 256) {
+            const int k = k0 + t;
+            int c = 0;
+            const uint32_t m = k < ncell ? box_links(d, b, q, k, c) : 0u;
+            visit(m, c);
+        }
+        return;
+    }
+    const double ro = rad + 1.75, ri = rad - 0.5;
+    const int nrow = b.ey * b.ez;
+    for (int r0 = 0; r0 < nrow; r0 += 256) {
+        // this thread's row of the chunk: its runs [lo0, lo0 + n0) and
+        // [lo1, lo1 + n) - n0 (x offsets in the box)
+        const int row = r0 + t;
+        int lo0 = 0, n0 = 0, lo1 = 0, n = 0;
+        if (row < nrow) {
+            const double dy = (double)(b.y0 + row % b.ey) + 0.5 - Y, dz = (double)(b.z0 + row / b.ey) + 0.5 - Z;
+            const double ho = ro * ro - dy * dy - dz * dz;
+            if (ho >= 0.0) {
+                const double wo = sqrt(ho);
+                const int a = max((int)ceil(X - wo - 0.5) - b.x0, 0);
+                const int e = min((int)floor(X + wo - 0.5) - b.x0, b.ex - 1);
+                const double hi = ri * ri - dy * dy - dz * dz;
+                int ia = e + 1, ie = e;
+                if (ri > 0.0 && hi > 0.0) {
+                    const double wi = sqrt(hi);
+                    ia = max((int)ceil(X - wi - 0.5) - b.x0, a);
+                    ie = min((int)floor(X + wi - 0.5) - b.x0, e);
+                }
+                if (a <= e) {
+                    if (ia <= ie) {
+                        lo0 = a;
+                        n0 = ia - a;
+                        lo1 = ie + 1;
+                        n = n0 + (e - ie);
+                    } else {
+                        lo0 = a;
+                        n0 = e - a + 1;
+                        n = n0;
+                    }
+                }
+            }
+        }
+        // inclusive prefix of the run lengths over the chunk's rows
+        int inc = n;
+        const int lane = __lane_id();
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o);
+            if (lane >= o) inc += v;
+        }
+        s_end[t] = inc;
+        __syncthreads();
+        int wbase = 0;
+        for (int w = 0; w < (t >> 6); ++w) wbase += s_end[64 * w + 63];
+        const int total = s_end[63] + s_end[127] + s_end[191] + s_end[255];
+        __syncthreads();
+        s_end[t] = wbase + inc;
+        s_lo0[t] = lo0;
+        s_n0[t] = n0;
+        s_lo1[t] = lo1;
+        __syncthreads();
+        for (int k0 = 0; k0 < total; k0 += 256) {
+            const int k = k0 + t;
+            uint32_t m = 0u;
+            int c = 0;
+            if (k < total) {
+                // the row holding shell cell k: the first with s_end > k
+                int lo = 0, hi = 255;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_end[mid] > k) hi = mid;
+                    else lo = mid + 1;
+                }
+                const int j = k - (lo ? s_end[lo - 1] : 0);
+                const int xi = j < s_n0[lo] ? s_lo0[lo] + j : s_lo1[lo] + (j - s_n0[lo]);
+                m = box_links(d, b, q, xi + b.ex * (r0 + lo), c);
+            }
+            visit(m, c);
+        }
+        __syncthreads();
+    }
+}
+
 // entries per sphere (one block per sphere)
 __global__ __launch_bounds__(256) void k_mem_count(Dev d, int32_t *counts)
 {
     __shared__ int s_cnt[4];
     const int q = blockIdx.x;
     const SphereBox b = sphere_box(d, q);
-    const int ncell = b.ex * b.ey * b.ez;
     int n = 0;
-    for (int k = (int)threadIdx.x; k < ncell; k += 256) {
-        int c;
-        n += box_links(d, b, q, k, c) != 0u;
-    }
+    sphere_walk(d, b, q, [&](uint32_t m, int) { n += m != 0u; });
     for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
     if (__lane_id() == 0) s_cnt[threadIdx.x >> 6] = n;
     __syncthreads();
     if (threadIdx.x == 0) counts[q] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
-// the entries, in walk order, from offs[q] on (one block per sphere)
-__global__ __launch_bounds__(256) void k_mem_fill(Dev d, const int32_t *offs, int2 *ent)
+// The entries of sphere q in walk order into its slot, their number and the
+// box they were taken from (one block per sphere).  With only_changed a
+// sphere keeps its list when no remap marked it and its box is the same: a
+// list depends only on the solid cells, solid-link masks and owners inside
+// the box, which a remap changes only at the cells it marks.
+__global__ __launch_bounds__(256) void k_mem_fill(Dev d, MemLists ml, int only_changed)
 {
     __shared__ int s_cnt[4];
     const int q = blockIdx.x;
     const SphereBox b = sphere_box(d, q);
-    const int ncell = b.ex * b.ey * b.ez;
-    int base = offs[q];
+    int32_t *bx = ml.box + 6 * q;
+    if (only_changed && ml.dirty[q] == 0 && bx[0] == b.x0 && bx[1] == b.y0 && bx[2] == b.z0 && bx[3] == b.ex &&
+        bx[4] == b.ey && bx[5] == b.ez)
+        return;
+    const int start = ml.offs[q], cap = ml.offs[q + 1] - start;
+    int base = 0;
     const int w = (int)threadIdx.x >> 6, lane = __lane_id();
-    for (int k0 = 0; k0 < ncell; k0 += 256) {
-        const int k = k0 + (int)threadIdx.x;
-        int c = 0;
-        const uint32_t m = k < ncell ? box_links(d, b, q, k, c) : 0u;
+    sphere_walk(d, b, q, [&](uint32_t m, int c) {
         const uint64_t bal = __ballot(m != 0u);
         if (lane == 0) s_cnt[w] = (int)__popcll(bal);
         __syncthreads();
         int pos = base;
         for (int i = 0; i < w; ++i) pos += s_cnt[i];
-        if (m != 0u) ent[pos + (int)__popcll(bal & ((1ull << lane) - 1ull))] = make_int2(c, (int)m);
+        pos += (int)__popcll(bal & ((1ull << lane) - 1ull));
+        if (m != 0u && pos < cap) ml.ent[start + pos] = make_int2(c, (int)m);
         base += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
         __syncthreads();
+    });
+    // every thread has read dirty[q] and the box above
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ml.cnt[q] = base;
+        if (base > cap) ml.flag[0] = 1;
+        bx[0] = b.x0;
+        bx[1] = b.y0;
+        bx[2] = b.z0;
+        bx[3] = b.ex;
+        bx[4] = b.ey;
+        bx[5] = b.ez;
+        ml.dirty[q] = 0;
     }
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_mem(Dev d, int p, const int32_t *offs, const int2 *ent, double *out)
+__global__ __launch_bounds__(256) void k_mem(Dev d, int p, MemLists ml, double *out)
 {
     __shared__ double sh[6][256];
     const int q = blockIdx.x;
@@ -597,9 +714,9 @@ __global__ __launch_bounds__(256) void k_mem(Dev d, int p, const int32_t *offs, 
     const S *pdf = (const S *)d.pdf[p];
     const size_t N = (size_t)d.N;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int e1 = offs[q + 1];
-    for (int e = offs[q] + (int)threadIdx.x; e < e1; e += 256) {
-        const int2 en = ent[e];
+    const int e0 = ml.offs[q], e1 = e0 + min(ml.cnt[q], ml.offs[q + 1] - e0);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+        const int2 en = ml.ent[e];
         const int c = en.x;
         const uint8_t ty = d.flags[c] & T_MASK;
         if (ty != T_LIQ && ty != T_IF) continue;
@@ -641,63 +758,111 @@ void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st)
     if (nsph > 0) k_mem_count<<<nsph, 256, 0, st>>>(d, counts);
 }
 
-void launch_mem_fill(const Dev &d, int nsph, const int32_t *offs, int2 *ent, hipStream_t st)
+void launch_mem_fill(const Dev &d, int nsph, const MemLists &ml, int only_changed, hipStream_t st)
 {
-    if (nsph > 0) k_mem_fill<<<nsph, 256, 0, st>>>(d, offs, ent);
+    if (nsph > 0) k_mem_fill<<<nsph, 256, 0, st>>>(d, ml, only_changed);
 }
 
 template <class S>
-void launch_mem(const Dev &d, int p, int nsph, const int32_t *offs, const int2 *ent, double *out,
-                hipStream_t st)
+void launch_mem(const Dev &d, int p, int nsph, const MemLists &ml, double *out, hipStream_t st)
 {
-    if (nsph > 0) k_mem<S><<<nsph, 256, 0, st>>>(d, p, offs, ent, out);
+    if (nsph > 0) k_mem<S><<<nsph, 256, 0, st>>>(d, p, ml, out);
 }
-template void launch_mem<double>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
-template void launch_mem<float>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
-template void launch_mem<_Float16>(const Dev &, int, int, const int32_t *, const int2 *, double *, hipStream_t);
+template void launch_mem<double>(const Dev &, int, int, const MemLists &, double *, hipStream_t);
+template void launch_mem<float>(const Dev &, int, int, const MemLists &, double *, hipStream_t);
+template void launch_mem<_Float16>(const Dev &, int, int, const MemLists &, double *, hipStream_t);
+
+constexpr int SLOT_THREADS = 1024, SLOT_CELLS = 4 * SLOT_THREADS;  // four cells per thread
+
+// record kind of cell c with solid-link mask sm: 0 none, 1 compact, 2 full
+__device__ __forceinline__ uint32_t slot_kind(const Dev &d, int c, uint32_t sm)
+{
+    if (sm == 0 || (d.flags[c] & T_MASK) == T_SOLID) return 0u;
+    const Cell pc = cell_xyz(d, c);
+    int q1 = -1, q2 = -1;
+    bool more = false;
+    for (int j = 0; j < 27; ++j) {
+        if (j == REST || !((sm >> j) & 1u)) continue;
+        const int s = nb_of(d, pc, opp(j));
+        if (s < 0) continue;
+        const int q = d.owner[s];
+        if (q1 < 0 || q == q1) q1 = q;
+        else if (q2 < 0 || q == q2) q2 = q;
+        else more = true;
+        if (d.img_check && !same_image(d, q, pc, j)) more = true;
+    }
+    if (q1 < 0) return 0u;
+    return (more || !d.rec_compact) ? 2u : 1u;
+}
+
+// exclusive prefix over the block's threads (in thread order) of a and b,
+// and the block totals
+__device__ __forceinline__ void slot_scan(int a, int b, int &ea, int &eb, int &ta, int &tb)
+{
+    __shared__ int s_a[SLOT_THREADS / 64], s_b[SLOT_THREADS / 64];
+    const int lane = __lane_id(), w = (int)threadIdx.x >> 6;
+    int ia = a, ib = b;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int ya = __shfl_up(ia, o), yb = __shfl_up(ib, o);
+        if (lane >= o) {
+            ia += ya;
+            ib += yb;
+        }
+    }
+    if (lane == 63) {
+        s_a[w] = ia;
+        s_b[w] = ib;
+    }
+    __syncthreads();
+    int oa = 0, ob = 0;
+    ta = 0;
+    tb = 0;
+    for (int k = 0; k < SLOT_THREADS / 64; ++k) {
+        if (k == w) {
+            oa = ta;
+            ob = tb;
+        }
+        ta += s_a[k];
+        tb += s_b[k];
+    }
+    ea = oa + ia - a;
+    eb = ob + ib - b;
+    __syncthreads();
+}
 
 // Cells with links into spheres get a record: compact when the links reach
 // at most two spheres, full otherwise.  Three passes without contended
-// atomics: each cell's kind (0 none, 1 compact, 2 full) and per-block
-// counts; exclusive prefix sums of the counts; slots from the kinds (compact
-// records count up from 0 in cell order, full ones from -2 down).
-constexpr int SLOT_THREADS = 1024;
-
+// atomics, numbering the records in cell order: each cell's kind and the
+// per-block counts; exclusive prefix sums of the counts; slots from the
+// kinds (compact records count up from 0, full ones from -2 down).
 __global__ __launch_bounds__(SLOT_THREADS) void k_slot_kinds(Dev d, uint8_t *kind, int32_t *bc, int32_t *bf)
 {
-    __shared__ int s_c[SLOT_THREADS / 64], s_f[SLOT_THREADS / 64];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    uint8_t k = 0;
-    const uint32_t sm = c < d.N ? d.smask[c] : 0u;
-    if (sm != 0 && (d.flags[c] & T_MASK) != T_SOLID) {
-        const Cell pc = cell_xyz(d, c);
-        int q1 = -1, q2 = -1;
-        bool more = false;
-        for (int j = 0; j < 27; ++j) {
-            if (j == REST || !((sm >> j) & 1u)) continue;
-            const int s = nb_of(d, pc, opp(j));
-            if (s < 0) continue;
-            const int q = d.owner[s];
-            if (q1 < 0 || q == q1) q1 = q;
-            else if (q2 < 0 || q == q2) q2 = q;
-            else more = true;
-            if (d.img_check && !same_image(d, q, pc, j)) more = true;
-        }
-        if (q1 >= 0) k = (more || !d.rec_compact) ? 2 : 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, c0 = 4 * t;
+    uint32_t sm[4] = {0u, 0u, 0u, 0u};
+    if (c0 + 3 < d.N) {
+        const uint4 v = ((const uint4 *)d.smask)[t];
+        sm[0] = v.x, sm[1] = v.y, sm[2] = v.z, sm[3] = v.w;
+    } else {
+        for (int k = 0; k < 4 && c0 + k < d.N; ++k) sm[k] = d.smask[c0 + k];
     }
-    if (c < d.N) kind[c] = k;
-    const uint64_t mc = __ballot(k == 1), mf = __ballot(k == 2);
-    if (__lane_id() == 0) {
-        s_c[threadIdx.x >> 6] = (int)__popcll(mc);
-        s_f[threadIdx.x >> 6] = (int)__popcll(mf);
+    uint32_t packed = 0u;
+    int nc = 0, nf = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t kd = sm[k] ? slot_kind(d, c0 + k, sm[k]) : 0u;
+        packed |= kd << (8 * k);
+        nc += kd == 1u;
+        nf += kd == 2u;
     }
-    __syncthreads();
+    if (c0 + 3 < d.N) {
+        ((uint32_t *)kind)[t] = packed;
+    } else {
+        for (int k = 0; k < 4 && c0 + k < d.N; ++k) kind[c0 + k] = (uint8_t)(packed >> (8 * k));
+    }
+    int ec, ef, tc, tf;
+    slot_scan(nc, nf, ec, ef, tc, tf);
     if (threadIdx.x == 0) {
-        int tc = 0, tf = 0;
-        for (int i = 0; i < SLOT_THREADS / 64; ++i) {
-            tc += s_c[i];
-            tf += s_f[i];
-        }
         bc[blockIdx.x] = tc;
         bf[blockIdx.x] = tf;
     }
@@ -735,28 +900,42 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int32_t *v, int n, int32_t
 __global__ __launch_bounds__(SLOT_THREADS) void k_slot_write(Dev d, const uint8_t *kind, const int32_t *bc,
                                                              const int32_t *bf)
 {
-    __shared__ int s_c[SLOT_THREADS / 64], s_f[SLOT_THREADS / 64];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint8_t k = c < d.N ? kind[c] : 0;
-    const uint64_t mc = __ballot(k == 1), mf = __ballot(k == 2);
-    const int lane = __lane_id(), w = (int)threadIdx.x >> 6;
-    if (lane == 0) {
-        s_c[w] = (int)__popcll(mc);
-        s_f[w] = (int)__popcll(mf);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, c0 = 4 * t;
+    uint32_t packed = 0u;
+    if (c0 + 3 < d.N) {
+        packed = ((const uint32_t *)kind)[t];
+    } else {
+        for (int k = 0; k < 4 && c0 + k < d.N; ++k) packed |= (uint32_t)kind[c0 + k] << (8 * k);
     }
-    __syncthreads();
-    int oc = bc[blockIdx.x], of = bf[blockIdx.x];
-    for (int i = 0; i < w; ++i) {
-        oc += s_c[i];
-        of += s_f[i];
+    int nc = 0, nf = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        nc += ((packed >> (8 * k)) & 255u) == 1u;
+        nf += ((packed >> (8 * k)) & 255u) == 2u;
     }
-    const uint64_t below = (1ull << lane) - 1ull;
-    int slot = -1;
-    if (k == 1) slot = oc + (int)__popcll(mc & below);
-    else if (k == 2) slot = -2 - (of + (int)__popcll(mf & below));
-    if (c < d.N) d.bbslot[c] = slot;
-    if (slot >= 0) d.rcell[slot] = c;
-    else if (slot <= -2) d.rcell[d.N - 1 - (-slot - 2)] = c;
+    int oc, of, tc, tf;
+    slot_scan(nc, nf, oc, of, tc, tf);
+    oc += bc[blockIdx.x];
+    of += bf[blockIdx.x];
+    int slot[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t kd = (packed >> (8 * k)) & 255u;
+        slot[k] = -1;
+        if (kd == 1u) {
+            slot[k] = oc++;
+            d.rcell[slot[k]] = c0 + k;
+        } else if (kd == 2u) {
+            slot[k] = -2 - of;
+            d.rcell[d.N - 1 - of] = c0 + k;
+            ++of;
+        }
+    }
+    if (c0 + 3 < d.N) {
+        ((int4 *)d.bbslot)[t] = make_int4(slot[0], slot[1], slot[2], slot[3]);
+    } else {
+        for (int k = 0; k < 4 && c0 + k < d.N; ++k) d.bbslot[c0 + k] = slot[k];
+    }
 }
 
 // highest z that holds a liquid or interface cell
@@ -764,11 +943,26 @@ __global__ __launch_bounds__(SLOT_THREADS) void k_slot_write(Dev d, const uint8_
 __global__ __launch_bounds__(256) void k_zmax(Dev d)
 {
     __shared__ int s_max[4];
-    int zm = -1;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) {
-        const uint8_t ty = d.flags[c] & T_MASK;
-        if (ty == T_LIQ || ty == T_IF) zm = max(zm, c / (d.nx * d.ny));
+    // sixteen flag bytes per load (the flag array is 256-byte aligned); a
+    // byte is liquid or interface when its two type bits differ
+    const int nw = d.N >> 4;
+    const uint4 *f4 = (const uint4 *)d.flags;
+    int last = -1;   // highest fluid cell seen by this thread
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+        const uint4 v = f4[w];
+        const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t t = (u[k] ^ (u[k] >> 1)) & 0x01010101u;
+            if (t) last = 16 * w + 4 * k + (31 - __clz(t)) / 8;
+        }
     }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (d.N & 15)) {
+        const int c = 16 * nw + (int)threadIdx.x;
+        const uint8_t ty = d.flags[c] & T_MASK;
+        if (ty == T_LIQ || ty == T_IF) last = max(last, c);
+    }
+    int zm = last >= 0 ? last / (d.nx * d.ny) : -1;
     for (int o = 32; o > 0; o >>= 1) zm = max(zm, __shfl_xor(zm, o));
     if (__lane_id() == 0) s_max[threadIdx.x >> 6] = zm;
     __syncthreads();
@@ -1524,7 +1718,7 @@ template void launch_geom<float>(const Dev &, int, int, hipStream_t);
 void launch_setup_links(const Dev &d, hipStream_t st)
 {
     const int b = (d.N + 255) / 256;
-    const int bs = (d.N + SLOT_THREADS - 1) / SLOT_THREADS;
+    const int bs = (d.N + SLOT_CELLS - 1) / SLOT_CELLS;
     uint8_t *kind = (uint8_t *)d.share;
     int32_t *bc = d.lnew, *bf = d.lnew + bs;
     k_slot_kinds<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf);

@@ -54,6 +54,8 @@ def lib(path=None):
         L.fsl_read_fields.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(vp), i32]
         L.fsl_total_mass.argtypes = [vp, dp]
         L.fsl_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.fsl_move_particles.argtypes = [vp, dp, dp, dp]
+        L.fsl_particle_forces.argtypes = [vp, dp, i32]
         L.fsl_last_error.restype = ctypes.c_char_p
         L.fsl_destroy.argtypes = [vp]
         _lib = L
@@ -119,6 +121,17 @@ class EmuLattice:
         if f == F.FIELD_PDF:
             return a.reshape(27, nz, ny, nx)
         return a.reshape(nz, ny, nx)
+
+    def move_particles(self, centre, vel=None, angvel=None):
+        c = np.ascontiguousarray(centre, dtype=np.float64)
+        v = None if vel is None else np.ascontiguousarray(vel, dtype=np.float64)
+        a = None if angvel is None else np.ascontiguousarray(angvel, dtype=np.float64)
+        _check(lib().fsl_move_particles(self.h, _dp(c), _dp(v), _dp(a)))
+
+    def particle_forces(self, nsph):
+        out = np.zeros((nsph, 6))
+        _check(lib().fsl_particle_forces(self.h, _dp(out), 0))
+        return out
 
     def total_mass(self):
         m = ctypes.c_double()

@@ -47,6 +47,9 @@ struct int2 {
 struct uint4 {
     unsigned x, y, z, w;
 };
+struct int4 {
+    int x, y, z, w;
+};
 struct float4 {
     float x, y, z, w;
 };
@@ -55,6 +58,7 @@ struct double4 {
 };
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
 inline uint4 make_uint4(unsigned a, unsigned b, unsigned c, unsigned d) { return uint4{a, b, c, d}; }
+inline int4 make_int4(int a, int b, int c, int d) { return int4{a, b, c, d}; }
 inline double4 make_double4(double a, double b, double c, double d) { return double4{a, b, c, d}; }
 inline float4 make_float4(float a, float b, float c, float d) { return float4{a, b, c, d}; }
 
@@ -192,6 +196,7 @@ HIPEMU_BUF_IO(64, hipemu_u32x2)
 #undef HIPEMU_BUF_IO
 
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+inline int __clz(int v) { return v == 0 ? 32 : __builtin_clz((unsigned)v); }
 inline int __ffsll(unsigned long long v) { return __builtin_ffsll((long long)v); }
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 

@@ -11,6 +11,10 @@ against the oracle's, through the C-ABI.
   a sphere's links.
 * Repeated evaluation and a repeated run give bit-identical results (fixed
   summation order); no spheres: nothing to compute; argument errors.
+* Spheres that move between evaluations: the link lists refilled only for
+  the spheres a remap touched give forces bit-identical to lists built
+  from scratch after the same moves, also for a sphere whose box wraps
+  across the periodic boundary and one whose list outgrows its slot.
 """
 import numpy as np
 import pytest
@@ -123,3 +127,59 @@ def test_no_spheres_and_errors():
     g = f.lattice_from_workload(spinning_box(), "fp64")
     assert f.lib().fsl_particle_forces(g.h, None, 0) == f.FSL_ERR_ARG
     g.destroy()
+
+
+def _moving_setup():
+    f = F()
+    nx, ny, nz = 30, 16, 22
+    z = np.arange(nz)[:, None, None] + np.zeros((nz, ny, nx))
+    fill = np.clip(14.4 - z, 0.0, 1.0)
+    p = f.make_params(shape=(nx, ny, nz), precision="fp64", omega=1.6, accel=(2e-5, 0.0, -1e-5), sigma=0.0,
+                      rho_gas=1.0, conv_eps=1e-3, check_every=0)
+    g = f.Lattice(p, fill, np.ones((nz, ny, nx)))
+    # sphere 1 lies inside sphere 2 (it owns its cells, but no fluid cell
+    # links into it) until it leaves; sphere 0 crosses x = 0
+    c = np.array([[1.2, 8.0, 6.0], [18.0, 8.0, 7.0], [18.0, 8.0, 7.0]])
+    g.set_particles(c, [2.6, 2.0, 3.4], np.tile([[1e-3, -5e-4, 2e-4]], (3, 1)), np.tile([[0.0, 1e-3, 0.0]], (3, 1)))
+    return g, c
+
+
+def _moves():
+    rng = np.random.default_rng(21)
+    out = []
+    for k in range(8):
+        d = rng.uniform(-0.6, 0.6, size=(3, 3)) if k % 3 else rng.uniform(-0.03, 0.03, size=(3, 3))
+        d[:, 2] *= 0.3
+        d[0, 0] = -0.45          # sphere 0 drifts across the periodic boundary
+        d[1] = [0.0, 0.0, 0.0]
+        if k == 4:
+            d[1] = [-7.0, 0.0, 2.5]   # sphere 1 leaves sphere 2: its list outgrows its slot
+        out.append(d)
+    return out
+
+
+def test_refilled_lists_match_lists_built_from_scratch():
+    moves = _moves()
+    a, c = _moving_setup()
+    a.step(3)
+    a.particle_forces()
+    checks = {1: None, 4: None, 5: None, 7: None}
+    ca = c.copy()
+    for k, d in enumerate(moves):
+        ca = ca + d
+        a.move_particles(ca, np.full((3, 3), 1e-3))
+        a.step(2)
+        if k in checks:
+            checks[k] = a.particle_forces()
+    a.destroy()
+    for k, fa in checks.items():
+        b, cb = _moving_setup()
+        b.step(3)
+        for d in moves[:k + 1]:
+            cb = cb + d
+            b.move_particles(cb, np.full((3, 3), 1e-3))
+            b.step(2)
+        fb = b.particle_forces()
+        b.destroy()
+        assert np.abs(fb).max() > 0.0
+        assert np.array_equal(fa, fb), (k, np.abs(fa - fb).max())

@@ -81,6 +81,51 @@ def test_surface_at_the_top_wall_on_the_cpu():
     g.destroy()
 
 
+def test_refilled_link_lists_on_the_cpu():
+    """Momentum-exchange lists refilled only for the spheres a remap
+    touched (a sphere crossing x = 0, one leaving the sphere it sat inside,
+    so that its list outgrows its slot) against lists built from scratch
+    after the same moves (bit-identical) and against the oracle's forces."""
+    nx, ny, nz = 20, 16, 16
+    z = np.arange(nz)[:, None, None] + np.zeros((nz, ny, nx))
+    c0 = np.array([[1.2, 6.0, 5.0], [12.0, 6.0, 6.0], [12.0, 6.0, 6.0]])
+    w = I.Workload(name="moving", shape=(nx, ny, nz), omega=1.6, accel=(2e-5, 0.0, -1e-5), sigma=0.0,
+                   fill=np.clip(11.4 - z, 0.0, 1.0), rho=np.ones((nz, ny, nx)), vel=np.zeros((3, nz, ny, nx)),
+                   centre=c0, radius=np.array([2.3, 1.6, 3.0]), sphere_vel=np.full((3, 3), 1e-3),
+                   sphere_angvel=np.zeros((3, 3)))
+    moves = [np.array([[-0.45, 0.1, 0.0], [0.0, 0.0, 0.0], [0.2, -0.3, 0.1]]),
+             np.array([[-0.45, -0.2, 0.05], [-5.5, 0.0, 2.0], [0.01, 0.02, -0.01]]),
+             np.array([[-0.45, 0.3, 0.0], [0.3, 0.2, 0.0], [-0.4, 0.1, 0.0]])]
+    vel = np.full((3, 3), 1e-3)
+    a = emu.EmuLattice(w, "fp64")
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, fill=w.fill, rho=w.rho, vel=w.vel, conv_eps=w.conv_eps)
+    o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    a.step(2)
+    o.step(2)
+    a.particle_forces(3)
+    c = c0.copy()
+    got = []
+    for d in moves:
+        c = c + d
+        a.move_particles(c, vel)
+        o.move_particles(c, vel)
+        a.step(1)
+        o.step(1)
+        fa, fo = a.particle_forces(3), o.particle_forces()
+        assert np.abs(fa - fo).max() <= 1e-11 * max(np.abs(fo).max(), 1.0)
+        got.append(fa)
+    a.destroy()
+    b = emu.EmuLattice(w, "fp64")
+    b.step(2)
+    c = c0.copy()
+    for d in moves:
+        c = c + d
+        b.move_particles(c, vel)
+        b.step(1)
+    assert np.array_equal(b.particle_forces(3), got[-1])
+    b.destroy()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp16", 2e-3)])
 def test_storage_forms_on_the_cpu(prec, tol):
     """The FP32 and FP16 forms (whose dense pass reads and writes its rows
