@@ -24,7 +24,8 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
 void launch_watch_final(const Dev &d, int list_blocks, hipStream_t st);
-void launch_setup_links(const Dev &d, hipStream_t st);
+void launch_setup_links(const Dev &d, int from_slots, hipStream_t st);
+void launch_kinds_list(const Dev &d, const int32_t *list, const int *count, int bound, hipStream_t st);
 void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st);
 void launch_mem_fill(const Dev &d, int nsph, const MemLists &ml, int only_changed, hipStream_t st);
 template <class S>
@@ -235,11 +236,15 @@ __global__ void k_liquid_form(Dev d, int p, int to_q, const int32_t *list, const
     const int c = list ? list[t] : t;
     if ((d.flags[c] & T_MASK) != T_LIQ) return;
     const S *pdf = (const S *)d.pdf[p];
+    // the neighbour x + c_i is solid or beyond a wall where the solid-link
+    // mask has bit opp(i); the 26 loads are issued together
+    const uint32_t sm = d.smask[c];
     double fluid = 0.0;
+#pragma unroll
     for (int i = 0; i < 27; ++i) {
         if (i == REST) continue;
-        const int y = nbr(d, c, i);
-        if (y >= 0 && (d.flags[y] & T_MASK) != T_SOLID) fluid += (double)ld(pdf + pdf_index(d.nx, i, c));
+        const double v = (double)ld(pdf + pdf_index(d.nx, i, c));
+        if (!((sm >> opp(i)) & 1u)) fluid += v;
     }
     d.mq[c] = to_q ? d.mq[c] - fluid : d.mq[c] + fluid;
 }
@@ -505,12 +510,19 @@ __global__ void k_mem_dirty(Dev d, const int32_t *own, const int32_t *list, cons
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *count) return;
     const int c = list[t];
+    // a cell solid before and after has no links
+    if (d.owner[c] >= 0 && own[c] != INT_MAX) return;
+    int qo[27], qn[27];
+#pragma unroll
     for (int j = 0; j < 27; ++j) {
         const int y = nbr(d, c, j);
-        if (y < 0) continue;
-        const int qo = d.owner[y], qn = own[y];
-        if (qo >= 0) dirty[qo] = 1;
-        if (qn != INT_MAX) dirty[qn] = 1;
+        qo[j] = y >= 0 ? d.owner[y] : -1;
+        qn[j] = y >= 0 ? own[y] : INT_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+        if (qo[j] >= 0) dirty[qo[j]] = 1;
+        if (qn[j] != INT_MAX) dirty[qn[j]] = 1;
     }
 }
 
@@ -937,7 +949,9 @@ static void run_uncover_finish(FslLattice *L, const int32_t *list, int n, const 
 // rebuild everything derived from the cell types: solid-link masks,
 // bounce-back records, the highest fluid row, the interface list and the
 // interface geometry
-static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done = false)
+// near_done: the solid-link masks are current; kinds_done: the slot array
+// holds every cell's record kind (a remap re-encoded the cells it changed)
+static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done = false, bool kinds_done = false)
 {
     Dev &d = L->d;
     L->mass_fast = false;
@@ -948,7 +962,7 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     // running pool total of the watchdog, exact after every rebuild
     k_pool_partial<<<RED_BLOCKS, 256, 0, L->st>>>(d);
     k_sum_partials<<<1, 256, 0, L->st>>>(d, RED_BLOCKS, (int)(d.wd - d.partial) + WD_POOL);
-    launch_setup_links(d, L->st);
+    launch_setup_links(d, kinds_done ? 1 : 0, L->st);
     // the geometry of the rebuilt list, with the estimator the steps use
     const bool learned = L->P.normals == 1 && L->mlpP;
     if (L->P.precision == FSL_FP64) {
@@ -1388,9 +1402,13 @@ static FslStatus remap(FslLattice *L)
     k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
     k_near_solid_list<<<gml, 256, 0, L->st>>>(d, mlist, mcount);
     DISPATCH(L, run_liquid_form, L, 1, mlist, mcount, nmax);
+    // record kinds: only the listed cells can change theirs, unless a sphere
+    // nearly spans the periodic box (kinds then depend on sphere positions)
+    const bool kinds_done = !d.img_check;
+    if (kinds_done) launch_kinds_list(d, mlist, mcount, (int)nmax, L->st);
     k_unmark_list<<<gml, 256, 0, L->st>>>(mlist, mcount, mark);
     HIP_TRY(hipGetLastError());
-    FslStatus r = finalize(L, false, true);
+    FslStatus r = finalize(L, false, true, kinds_done);
     if (r != FSL_OK) return r;
     L->mem_stale = !lists_live;
     HIP_TRY(hipStreamSynchronize(L->st));

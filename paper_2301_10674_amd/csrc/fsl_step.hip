@@ -58,6 +58,23 @@ __device__ __forceinline__ double min_image(double v, int n)
     return v;
 }
 
+// Owners of the sources x - c_j of the solid links j of cell p (mask sm):
+// qo[j] for the links of the returned mask, whose sources lie inside the
+// lattice.  The loads do not depend on each other and are all issued before
+// any is used (masked-off links load the cell's own entry).
+__device__ __forceinline__ uint32_t link_owners(const Dev &d, const Cell &p, int c, uint32_t sm, int (&qo)[27])
+{
+    uint32_t vm = 0u;
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+        const int s = j != REST ? nb_of(d, p, opp(j)) : -1;
+        const bool on = ((sm >> j) & 1u) && s >= 0;
+        qo[j] = d.owner[on ? s : c];
+        vm |= on ? 1u << j : 0u;
+    }
+    return vm;
+}
+
 // Moving-wall bounce-back term 6 w_j (c_j . u_w) for the link from fluid
 // cell p along -c_j into the solid cell s (Ladd; wall density 1).
 template <class R>
@@ -536,11 +553,11 @@ __device__ __forceinline__ uint32_t box_links(const Dev &d, const SphereBox &b, 
     uint32_t m = 0u;
     if (sm == 0u) return 0u;
     const Cell pc{x, y, z};
-    for (int j = 0; j < 27; ++j) {
-        if (j == REST || !((sm >> j) & 1u)) continue;
-        const int s = nb_of(d, pc, opp(j));
-        if (s >= 0 && d.owner[s] == q) m |= 1u << j;
-    }
+    int qo[27];
+    const uint32_t vm = link_owners(d, pc, c, sm, qo);
+#pragma unroll
+    for (int j = 0; j < 27; ++j)
+        if (((vm >> j) & 1u) && qo[j] == q) m |= 1u << j;
     return m;
 }
 
@@ -836,21 +853,32 @@ __device__ __forceinline__ void slot_scan(int a, int b, int &ea, int &eb, int &t
 // atomics, numbering the records in cell order: each cell's kind and the
 // per-block counts; exclusive prefix sums of the counts; slots from the
 // kinds (compact records count up from 0, full ones from -2 down).
-__global__ __launch_bounds__(SLOT_THREADS) void k_slot_kinds(Dev d, uint8_t *kind, int32_t *bc, int32_t *bf)
+// With from_slots the kinds are read from the slot array instead, where a
+// remap has re-encoded the cells whose kind may have changed (k_kinds_list).
+__global__ __launch_bounds__(SLOT_THREADS) void k_slot_kinds(Dev d, uint8_t *kind, int32_t *bc, int32_t *bf,
+                                                             int from_slots)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x, c0 = 4 * t;
+    // smask, or with from_slots the slot of each of the four cells
     uint32_t sm[4] = {0u, 0u, 0u, 0u};
+    const uint32_t *src = from_slots ? (const uint32_t *)d.bbslot : d.smask;
     if (c0 + 3 < d.N) {
-        const uint4 v = ((const uint4 *)d.smask)[t];
+        const uint4 v = ((const uint4 *)src)[t];
         sm[0] = v.x, sm[1] = v.y, sm[2] = v.z, sm[3] = v.w;
     } else {
-        for (int k = 0; k < 4 && c0 + k < d.N; ++k) sm[k] = d.smask[c0 + k];
+        for (int k = 0; k < 4 && c0 + k < d.N; ++k) sm[k] = src[c0 + k];
     }
     uint32_t packed = 0u;
     int nc = 0, nf = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t kd = sm[k] ? slot_kind(d, c0 + k, sm[k]) : 0u;
+        uint32_t kd;
+        if (from_slots) {
+            const int sl = (int)sm[k];
+            kd = c0 + k >= d.N ? 0u : (sl >= 0 ? 1u : (sl <= -2 ? 2u : 0u));
+        } else {
+            kd = sm[k] ? slot_kind(d, c0 + k, sm[k]) : 0u;
+        }
         packed |= kd << (8 * k);
         nc += kd == 1u;
         nf += kd == 2u;
@@ -895,6 +923,20 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int32_t *v, int n, int32_t
         __syncthreads();
     }
     if (threadIdx.x == 0) *total = s_carry;
+}
+
+// The kinds of the cells in list[0 .. *count) into their slot entries
+// (0, -2 or -1 for compact, full or none): after a remap the only cells
+// whose kind can change are the changed cells and their neighbours, and
+// every other cell's slot entry still encodes its kind.
+__global__ void k_kinds_list(Dev d, const int32_t *list, const int *count)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *count) return;
+    const int c = list[t];
+    const uint32_t sm = d.smask[c];
+    const uint32_t kd = sm ? slot_kind(d, c, sm) : 0u;
+    d.bbslot[c] = kd == 1u ? 0 : (kd == 2u ? -2 : -1);
 }
 
 __global__ __launch_bounds__(SLOT_THREADS) void k_slot_write(Dev d, const uint8_t *kind, const int32_t *bc,
@@ -1715,17 +1757,22 @@ template void launch_geom<float>(const Dev &, int, int, hipStream_t);
 // record slots and the highest fluid row.  Scratch: the per-cell kinds in
 // the excess-share array and the per-block counts in the new-cell list
 // (both free between steps; 2 * blocks <= N)
-void launch_setup_links(const Dev &d, hipStream_t st)
+void launch_setup_links(const Dev &d, int from_slots, hipStream_t st)
 {
     const int b = (d.N + 255) / 256;
     const int bs = (d.N + SLOT_CELLS - 1) / SLOT_CELLS;
     uint8_t *kind = (uint8_t *)d.share;
     int32_t *bc = d.lnew, *bf = d.lnew + bs;
-    k_slot_kinds<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf);
+    k_slot_kinds<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf, from_slots);
     k_scan_counts<<<1, 1024, 0, st>>>(bc, bs, d.cnt + 4);
     k_scan_counts<<<1, 1024, 0, st>>>(bf, bs, d.cnt + 5);
     k_slot_write<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf);
     k_zmax<<<b < 1024 ? b : 1024, 256, 0, st>>>(d);
+}
+
+void launch_kinds_list(const Dev &d, const int32_t *list, const int *count, int bound, hipStream_t st)
+{
+    if (bound > 0) k_kinds_list<<<(bound + 255) / 256, 256, 0, st>>>(d, list, count);
 }
 
 template <class R>
