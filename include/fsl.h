@@ -407,10 +407,12 @@ FslStatus fsl_bed_profile(FslLattice *lat, double *phi_b, double *h_b, int32_t o
  * Fx, Fy, Fz, Tx, Ty, Tz (lattice units); host memory, or device memory when
  * out_on_device != 0.  Sums run in FP64 in a fixed order (deterministic).
  * Nothing is written when no spheres are mapped; FSL_ERR_ARG for a NULL out
- * otherwise.  The first call after set-up or after a remap that changed
- * cells rebuilds per-sphere lists of the cells with links into each sphere
- * (in a library buffer that grows with hipMalloc when needed and is kept
- * until fsl_destroy); synchronises the lattice's stream. */
+ * otherwise.  The first call after set-up builds per-sphere lists of the
+ * cells with links into each sphere (in a library buffer that grows with
+ * hipMalloc when needed and is kept until fsl_destroy); the first call after
+ * moves refills the lists of the spheres whose cells or box changed, and
+ * rebuilds them all when one has outgrown its slot.  The result does not
+ * depend on which of these happened.  Synchronises the lattice's stream. */
 FslStatus fsl_particle_forces(FslLattice *lat, double *out, int32_t out_on_device);
 
 /* Interface-cell updates since creation that used the network / fell back. */
