@@ -78,6 +78,8 @@ struct FslLattice {
     MemLists ml{};
     bool mem_stale = true;    // link lists must be rebuilt before the next force evaluation
     bool mem_moved = false;   // spheres moved since the lists were last brought up to date
+    bool own_stale = true;    // the remap's owner map is not the current one
+    int own_zlo = 0, own_zhi = -1;  // rows the spheres reached at the last remap (widened by two)
     float *mlpP = nullptr;    // learned estimator: FP32 weights
     uint16_t *mlpPk = nullptr;  //   and their packed BF16 copies
     void *read_buf = nullptr; // device staging of fields read to the host
@@ -276,10 +278,11 @@ __global__ void k_map(Dev d, int nsph, int32_t *own)
     }
 }
 
-__global__ void k_owner_reset(Dev d, int32_t *own)
+// no owner for cells c0 .. c1 - 1
+__global__ void k_owner_reset(int32_t *own, int c0, int c1)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < d.N) own[c] = INT_MAX;
+    const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < c1) own[c] = INT_MAX;
 }
 
 // cells inside spheres become solid (their mass leaves the system)
@@ -302,12 +305,16 @@ constexpr uint8_t F_OPEN = 8, F_NEWC = 16;
 
 // cells whose owner changes with the new map (INT_MAX: no sphere), appended
 // to a list in cell order (one atomic per wavefront); count = list length.
-// Four cells per thread (both maps are 256-byte aligned).
-__global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own, int *count, int32_t *list)
+// Four cells per thread (both maps are 256-byte aligned), the groups w0 ..
+// w1 - 1 of four.
+__global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own, int *count, int32_t *list,
+                                                       int w0, int w1)
 {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = w0 + blockIdx.x * blockDim.x + threadIdx.x;
     int a[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX}, b[4] = {-1, -1, -1, -1};
-    if (4 * w + 3 < d.N) {
+    if (w >= w1) {
+        // past the range: no cells (the wavefront still appends together)
+    } else if (4 * w + 3 < d.N) {
         const int4 va = ((const int4 *)own)[w], vb = ((const int4 *)d.owner)[w];
         a[0] = va.x, a[1] = va.y, a[2] = va.z, a[3] = va.w;
         b[0] = vb.x, b[1] = vb.y, b[2] = vb.z, b[3] = vb.w;
@@ -649,8 +656,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(Dev d, int n, int out_slot
 
 __global__ __launch_bounds__(256) void k_pool_partial(Dev d)
 {
+    // two cells per load (the array is 256-byte aligned); an odd last cell
+    // goes to the first thread
     double acc = 0.0;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) acc += d.poolc[c];
+    const int n2 = d.N >> 1;
+    const double2 *p2 = (const double2 *)d.poolc;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += gridDim.x * blockDim.x) {
+        const double2 v = p2[c];
+        acc += v.x + v.y;
+    }
+    if ((d.N & 1) && blockIdx.x == 0 && threadIdx.x == 0) acc += d.poolc[d.N - 1];
     acc = block_sum256(acc);
     if (threadIdx.x == 0) d.partial[blockIdx.x] = acc;
 }
@@ -1037,6 +1052,18 @@ __global__ void k_sph_stage(const double *table, double *stage, int n, const dou
     t[1] -= ny * floor(t[1] / ny);
     t[3] = table[10 * q + 3];
     for (int k = 0; k < 10; ++k) stage[10 * q + k] = t[k];
+    // the rows the spheres reach, widened by two (flag[1], flag[2])
+    atomicMin(flag + 1, (int)fmax(floor(t[2] - t[3]) - 2.0, -2147483648.0));
+    atomicMax(flag + 2, (int)fmin(floor(t[2] + t[3]) + 2.0, 2147483647.0));
+}
+
+__global__ void k_stage_init(int *flag)
+{
+    if (threadIdx.x == 0) {
+        flag[0] = 0;
+        flag[1] = INT_MAX;
+        flag[2] = INT_MIN;
+    }
 }
 
 static bool finite_all(const float *v, size_t n)
@@ -1283,7 +1310,8 @@ FslStatus fsl_set_particles(FslLattice *L, int32_t n, const double *centre, cons
         if (2.0 * (t[10 * (size_t)q + 3] + 2.0) >= (double)std::min(nx, ny)) d.img_check = 1;
     // liquid cells back to m, re-map, then the stored form with the new solids
     DISPATCH(L, run_liquid_form, L, 0);
-    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, d.owner);
+    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d.owner, 0, d.N);
+    L->own_stale = true;
     if (n > 0) k_map<<<n, 256, 0, L->st>>>(d, n, d.owner);
     k_apply_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
     k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
@@ -1333,11 +1361,28 @@ FslStatus fsl_particle_forces(FslLattice *L, double *out, int32_t out_on_device)
 
 // The spheres of the lattice move to the state in the device table: remap
 // owners, cover and uncover cells, rebuild what follows from the cell types.
-static FslStatus remap(FslLattice *L)
+// zlo .. zhi: the rows the spheres reach at their new positions, widened by
+// two.  Between remaps the remap's own owner map (own) holds the current
+// owners, none outside the rows the spheres reached, so only the rows the
+// spheres reach before or after the move are cleared and compared.
+static FslStatus remap(FslLattice *L, int zlo, int zhi)
 {
     const int n = L->nsph;
     Dev &d = L->d;
     const size_t N = (size_t)d.N;
+    const int nz = L->P.nz, plane = L->P.nx * L->P.ny;
+    zlo = std::max(zlo, 0);
+    zhi = std::min(zhi, nz - 1);
+    int slo = zlo, shi = zhi;
+    if (L->own_stale) {
+        slo = 0;
+        shi = nz - 1;
+    } else {
+        slo = std::min(slo, L->own_zlo);
+        shi = std::max(shi, L->own_zhi);
+    }
+    L->own_stale = true;
+    const int c0 = slo * plane, c1 = shi >= slo ? (shi + 1) * plane : c0;
     // scratch, each part 256-byte aligned: densities (8 B), new owners
     // (4 B), changed cells (4 B), marks (4 B), the marked cells (4 B) and
     // round types (1 B) per cell, two counters; marks start zero and are
@@ -1359,10 +1404,11 @@ static FslStatus remap(FslLattice *L)
     uint8_t *tn = (uint8_t *)(mv + o_tn);
     int *counter = (int *)(mv + o_cnt);
     int *mcount = counter + 4;
-    k_owner_reset<<<blocks_for(d.N), 256, 0, L->st>>>(d, own);
+    if (c1 > c0) k_owner_reset<<<blocks_for(c1 - c0), 256, 0, L->st>>>(own, c0, c1);
     k_map<<<n, 256, 0, L->st>>>(d, n, own);
     k_zero_int<<<1, 64, 0, L->st>>>(counter);
-    k_owner_changes<<<blocks_for((d.N + 3) / 4), 256, 0, L->st>>>(d, own, counter, chg);
+    const int w0 = c0 / 4, w1 = (c1 + 3) / 4;
+    if (w1 > w0) k_owner_changes<<<blocks_for(w1 - w0), 256, 0, L->st>>>(d, own, counter, chg, w0, w1);
     HIP_TRY(hipGetLastError());
     int nch = 0;
     HIP_TRY(hipMemcpyAsync(&nch, counter, 4, hipMemcpyDeviceToHost, L->st));
@@ -1375,6 +1421,9 @@ static FslStatus remap(FslLattice *L)
         run_bb_terms(L);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(L->st));
+        L->own_stale = false;
+        L->own_zlo = zlo;
+        L->own_zhi = zhi;
         return FSL_OK;
     }
     const int gch = (nch + 255) / 256, gmk = (int)(((int64_t)nch * 27 + 255) / 256);
@@ -1412,6 +1461,9 @@ static FslStatus remap(FslLattice *L)
     if (r != FSL_OK) return r;
     L->mem_stale = !lists_live;
     HIP_TRY(hipStreamSynchronize(L->st));
+    L->own_stale = false;
+    L->own_zlo = zlo;
+    L->own_zhi = zhi;
     return FSL_OK;
 }
 
@@ -1439,7 +1491,13 @@ FslStatus fsl_move_particles(FslLattice *L, const double *centre, const double *
     }
     HIP_TRY(hipMemcpyAsync(L->sph_dev, t.data(), (size_t)n * 10 * 8, hipMemcpyHostToDevice, L->st));
     L->sph_host = t;
-    return remap(L);
+    int zlo = INT_MAX, zhi = INT_MIN;
+    for (int q = 0; q < n; ++q) {
+        const double z = t[10 * (size_t)q + 2], r = t[10 * (size_t)q + 3];
+        zlo = std::min(zlo, (int)std::max(std::floor(z - r) - 2.0, -2147483648.0));
+        zhi = std::max(zhi, (int)std::min(std::floor(z + r) + 2.0, 2147483647.0));
+    }
+    return remap(L, zlo, zhi);
 }
 
 FslStatus fsl_move_particles_device(FslLattice *L, const double *centre, const double *vel, const double *angvel)
@@ -1451,17 +1509,17 @@ FslStatus fsl_move_particles_device(FslLattice *L, const double *centre, const d
     const size_t tsz = L->sph_host.size();
     double *stage = L->sph_dev + tsz + (size_t)std::max(n, 1) * 6;
     int *flag = (int *)(stage + tsz);
-    k_zero_int<<<1, 64, 0, L->st>>>(flag);
+    k_stage_init<<<1, 64, 0, L->st>>>(flag);
     k_sph_stage<<<(n + 255) / 256, 256, 0, L->st>>>(L->sph_dev, stage, n, centre, vel, angvel, (double)L->P.nx,
                                                      (double)L->P.ny, flag);
     HIP_TRY(hipGetLastError());
-    int bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, L->st));
+    int fl[3] = {0, 0, 0};   // non-finite input, lowest and highest row reached
+    HIP_TRY(hipMemcpyAsync(fl, flag, 12, hipMemcpyDeviceToHost, L->st));
     HIP_TRY(hipStreamSynchronize(L->st));
-    if (bad) return fail(FSL_ERR_ARG, "non-finite sphere centre or velocity");
+    if (fl[0]) return fail(FSL_ERR_ARG, "non-finite sphere centre or velocity");
     HIP_TRY(hipMemcpyAsync(L->sph_dev, stage, (size_t)n * 10 * 8, hipMemcpyDeviceToDevice, L->st));
     L->sph_host_stale = true;
-    return remap(L);
+    return remap(L, fl[1], fl[2]);
 }
 
 // reference mass of the watchdog: the exact total after set-up

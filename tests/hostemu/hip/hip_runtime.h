@@ -53,6 +53,9 @@ struct int4 {
 struct float4 {
     float x, y, z, w;
 };
+struct double2 {
+    double x, y;
+};
 struct double4 {
     double x, y, z, w;
 };
