@@ -565,13 +565,17 @@ __global__ void k_near_solid(Dev d)
 template <class S>
 __global__ void k_refresh_if(Dev d, int p)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.N || (d.flags[c] & T_MASK) != T_IF) return;
+    // the interface list of the current state (rebuilt just before)
+    const int n = d.cnt[p];
+    const int32_t *list = d.list[p];
     const S *pdf = (const S *)d.pdf[p];
-    double s = 0.0;
-    for (int i = 0; i < 27; ++i) s += (double)ld(pdf + pdf_index(d.nx, i, c));
-    d.rho[c] = 1.0 + s;
-    d.phi[c] = d.mq[c] / d.rho[c];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int c = list[t];
+        double s = 0.0;
+        for (int i = 0; i < 27; ++i) s += (double)ld(pdf + pdf_index(d.nx, i, c));
+        d.rho[c] = 1.0 + s;
+        d.phi[c] = d.mq[c] / d.rho[c];
+    }
 }
 
 // the interface cells in cell order, sixteen flag bytes per thread (the flag
@@ -853,7 +857,7 @@ static void run_liquid_form(FslLattice *L, int to_q, const int32_t *list = nullp
 
 template <class S> static void run_refresh(FslLattice *L)
 {
-    k_refresh_if<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity);
+    k_refresh_if<S><<<std::max(1, std::min(blocks_for(L->d.N), 1024)), 256, 0, L->st>>>(L->d, L->parity);
 }
 
 template <class S> static void run_mass(FslLattice *L)
@@ -971,9 +975,10 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     Dev &d = L->d;
     L->mass_fast = false;
     if (!near_done) k_near_solid<<<blocks_for(d.N), 256, 0, L->st>>>(d);
-    DISPATCH(L, run_refresh, L);
     k_zero_counts<<<1, 64, 0, L->st>>>(d, reset_stats ? 1 : 0);
     k_build_list<<<blocks_for((d.N + 15) / 16), 256, 0, L->st>>>(d, L->parity);
+    // density and fill level of the listed interface cells
+    DISPATCH(L, run_refresh, L);
     // running pool total of the watchdog, exact after every rebuild
     k_pool_partial<<<RED_BLOCKS, 256, 0, L->st>>>(d);
     k_sum_partials<<<1, 256, 0, L->st>>>(d, RED_BLOCKS, (int)(d.wd - d.partial) + WD_POOL);
