@@ -356,7 +356,7 @@ FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
  *     total of fsl_total_mass() is unchanged; everything derived from the
  *     cell types is rebuilt.
  * FSL_ERR_STATE when no spheres are mapped, FSL_ERR_ARG for a NULL centre or
- * non-finite values.  The first call allocates a scratch buffer of 14
+ * non-finite values.  The first call allocates a scratch buffer of 25
  * bytes per cell, kept until fsl_destroy().  Synchronises the stream. */
 FslStatus fsl_move_particles(FslLattice *lat, const double *centre, const double *vel,
                              const double *angvel);

@@ -1441,16 +1441,22 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
     if (lists_live) k_mem_dirty<<<gml, 256, 0, L->st>>>(d, own, mlist, mcount, L->ml.dirty);
     DISPATCH(L, run_liquid_form, L, 0, mlist, mcount, nmax);
     k_cover<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
-    for (int round = 0;; ++round) {
-        if (round > nch) return fail(FSL_ERR_DEVICE, "uncovered cells: rounds do not end");
+    // rounds in pairs between checks by the host: a round that types no
+    // cell changes nothing (its apply finds no typed cell), so the second
+    // of a pair may run idle
+    for (int round = 0;; round += 2) {
+        if (round > nch + 1) return fail(FSL_ERR_DEVICE, "uncovered cells: rounds do not end");
         k_zero_int<<<1, 64, 0, L->st>>>(counter);
-        DISPATCH(L, run_uncover_round, L, chg, nch, tn, rn, counter);
+        k_zero_int<<<1, 64, 0, L->st>>>(counter + 1);
+        for (int k = 0; k < 2; ++k) {
+            DISPATCH(L, run_uncover_round, L, chg, nch, tn, rn, counter + k);
+            k_uncover_apply<<<gch, 256, 0, L->st>>>(d, chg, nch, tn);
+        }
         HIP_TRY(hipGetLastError());
-        int typed = 0;
-        HIP_TRY(hipMemcpyAsync(&typed, counter, 4, hipMemcpyDeviceToHost, L->st));
+        int typed[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(typed, counter, 8, hipMemcpyDeviceToHost, L->st));
         HIP_TRY(hipStreamSynchronize(L->st));
-        if (typed == 0) break;
-        k_uncover_apply<<<gch, 256, 0, L->st>>>(d, chg, nch, tn);
+        if (typed[0] == 0 || typed[1] == 0) break;
     }
     DISPATCH(L, run_uncover_finish, L, chg, nch, rn);
     k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
