@@ -303,10 +303,42 @@ __global__ void k_apply_solid(Dev d)
 // typed yet, and one typed in an earlier round.
 constexpr uint8_t F_OPEN = 8, F_NEWC = 16;
 
+// Appends c0 + k for every set bit k of bits (ascending) to list, in thread
+// order over a block of 256: one atomic per block, so that long lists built
+// by many blocks do not queue on the counter.  Every thread of the block
+// calls it.
+__device__ void block_append_bits(int32_t *list, int32_t *counter, uint32_t bits, int32_t c0)
+{
+    __shared__ int s_w[4], s_base;
+    const int n = __popcll((unsigned long long)bits);
+    const int lane = __lane_id(), w = (int)threadIdx.x >> 6;
+    int inc = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (k == w) off = total;
+        total += s_w[k];
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(counter, total) : 0;
+    __syncthreads();
+    int pos = s_base + off + inc - n;
+    while (bits) {
+        const int k = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1u;
+        list[pos++] = c0 + k;
+    }
+}
+
 // cells whose owner changes with the new map (INT_MAX: no sphere), appended
-// to a list in cell order (one atomic per wavefront); count = list length.
-// Four cells per thread (both maps are 256-byte aligned), the groups w0 ..
-// w1 - 1 of four.
+// to a list in cell order within a block (one atomic per block); count =
+// list length.  Four cells per thread (both maps are 256-byte aligned), the
+// groups w0 .. w1 - 1 of four.
 __global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own, int *count, int32_t *list,
                                                        int w0, int w1)
 {
@@ -328,11 +360,12 @@ __global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if ((a[k] == INT_MAX ? -1 : a[k]) != b[k]) bits |= 1u << k;
-    list_append_bits(list, count, bits, 4 * w);
+    block_append_bits(list, count, bits, 4 * w);
 }
 
 // The listed cells and their 26 neighbours, each once: the first visitor
-// of a cell turns its mark from 0 to 1 and appends it to out (count).
+// of a cell turns its mark from 0 to 1 and appends it to out (count; one
+// atomic per block).
 __global__ __launch_bounds__(256) void k_mark_list(Dev d, const int32_t *list, int n, uint32_t *mark,
                                                    int32_t *out, int *count)
 {
@@ -340,13 +373,7 @@ __global__ __launch_bounds__(256) void k_mark_list(Dev d, const int32_t *list, i
     int y = -1;
     if (t < (int64_t)n * 27) y = nbr(d, list[t / 27], (int)(t % 27));
     const bool first = y >= 0 && atomicCAS(&mark[y], 0u, 1u) == 0u;
-    const uint64_t m = __ballot(first);
-    if (m == 0) return;
-    const int lane = __lane_id();
-    int base = 0;
-    if (lane == 0) base = atomicAdd(count, (int)__popcll(m));
-    base = __shfl(base, 0);
-    if (first) out[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = y;
+    block_append_bits(out, count, first ? 1u : 0u, first ? y : 0);
 }
 
 // clear the marks of the cells in list[0 .. *count)
@@ -682,7 +709,6 @@ __global__ __launch_bounds__(256) void k_bulkvel_partial(Dev d, int p)
 {
     __shared__ double sh[4][256];
     const S *pdf = (const S *)d.pdf[p];
-    const size_t N = (size_t)d.N;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.N; c += gridDim.x * blockDim.x) {
         const uint8_t ty = d.flags[c] & T_MASK;

@@ -729,7 +729,6 @@ __global__ __launch_bounds__(256) void k_mem(Dev d, int p, MemLists ml, double *
     const double X = sp[0], Y = sp[1], Z = sp[2];
     const int nx = d.nx, ny = d.ny;
     const S *pdf = (const S *)d.pdf[p];
-    const size_t N = (size_t)d.N;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int e0 = ml.offs[q], e1 = e0 + min(ml.cnt[q], ml.offs[q + 1] - e0);
     for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
@@ -1037,7 +1036,6 @@ __device__ __forceinline__ void iface_cell(const Dev &d, const S *__restrict__ s
     using R4 = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
     using Et = typename Eq<S>::type;
     const int nx = d.nx, ny = d.ny, nz = d.nz, nxy = nx * ny;
-    const size_t N = (size_t)d.N;
     const int x = c % nx, row = c / nx, y = row % ny, z = row / ny;
     // neighbour x + c_i = c + OX[cx+1] + OY[cy+1] + OZ[cz+1] (periodic in x
     // and y); -1 beyond the z walls
@@ -1403,7 +1401,6 @@ template <class S>
 __device__ __forceinline__ void stored_sums(const Dev &d, const S *pdf, int c, const Cell &pc,
                                             double &all, double &fluid)
 {
-    const size_t N = (size_t)d.N;
     all = 0.0;
     fluid = 0.0;
     for (int i = 0; i < 27; ++i) {
@@ -1420,7 +1417,6 @@ template <class S>
 __device__ __forceinline__ void conv2_cell(const Dev &d, int p, uint32_t epoch, int c)
 {
     S *pdf = (S *)d.pdf[p ^ 1];
-    const size_t N = (size_t)d.N;
     {
         const Cell pc = cell_xyz(d, c);
         if ((d.flags[c] & T_MASK) == T_GAS) {
