@@ -336,44 +336,70 @@ __device__ void block_append_bits(int32_t *list, int32_t *counter, uint32_t bits
 }
 
 // cells whose owner changes with the new map (INT_MAX: no sphere), appended
-// to a list in cell order within a block (one atomic per block); count =
-// list length.  Four cells per thread (both maps are 256-byte aligned), the
-// groups w0 .. w1 - 1 of four.
+// to a list in cell order within a block (one atomic per block of 4096
+// cells: the counter is the bottleneck when many blocks append); count =
+// list length.  Sixteen cells per thread (both maps are 256-byte aligned),
+// the groups w0 .. w1 - 1 of four cells.
 __global__ __launch_bounds__(256) void k_owner_changes(Dev d, const int32_t *own, int *count, int32_t *list,
                                                        int w0, int w1)
 {
-    const int w = w0 + blockIdx.x * blockDim.x + threadIdx.x;
-    int a[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX}, b[4] = {-1, -1, -1, -1};
-    if (w >= w1) {
-        // past the range: no cells (the wavefront still appends together)
-    } else if (4 * w + 3 < d.N) {
-        const int4 va = ((const int4 *)own)[w], vb = ((const int4 *)d.owner)[w];
-        a[0] = va.x, a[1] = va.y, a[2] = va.z, a[3] = va.w;
-        b[0] = vb.x, b[1] = vb.y, b[2] = vb.z, b[3] = vb.w;
-    } else {
-        for (int k = 0; k < 4 && 4 * w + k < d.N; ++k) {
-            a[k] = own[4 * w + k];
-            b[k] = d.owner[4 * w + k];
-        }
-    }
+    const int g = w0 + 4 * (blockIdx.x * blockDim.x + threadIdx.x);
     uint32_t bits = 0u;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if ((a[k] == INT_MAX ? -1 : a[k]) != b[k]) bits |= 1u << k;
-    block_append_bits(list, count, bits, 4 * w);
+    for (int h = 0; h < 4; ++h) {
+        const int w = g + h;
+        int a[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX}, b[4] = {-1, -1, -1, -1};
+        if (w >= w1) {
+            // past the range: no cells (the block still appends together)
+        } else if (4 * w + 3 < d.N) {
+            const int4 va = ((const int4 *)own)[w], vb = ((const int4 *)d.owner)[w];
+            a[0] = va.x, a[1] = va.y, a[2] = va.z, a[3] = va.w;
+            b[0] = vb.x, b[1] = vb.y, b[2] = vb.z, b[3] = vb.w;
+        } else {
+            for (int k = 0; k < 4 && 4 * w + k < d.N; ++k) {
+                a[k] = own[4 * w + k];
+                b[k] = d.owner[4 * w + k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if ((a[k] == INT_MAX ? -1 : a[k]) != b[k]) bits |= 1u << (4 * h + k);
+    }
+    block_append_bits(list, count, bits, 4 * g);
 }
 
-// The listed cells and their 26 neighbours, each once: the first visitor
-// of a cell turns its mark from 0 to 1 and appends it to out (count; one
-// atomic per block).
-__global__ __launch_bounds__(256) void k_mark_list(Dev d, const int32_t *list, int n, uint32_t *mark,
-                                                   int32_t *out, int *count)
+// The listed cells and their 26 neighbours get mark 1 (repeats store the
+// same value).
+__global__ __launch_bounds__(256) void k_mark_list(Dev d, const int32_t *list, int n, uint32_t *mark)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int y = -1;
-    if (t < (int64_t)n * 27) y = nbr(d, list[t / 27], (int)(t % 27));
-    const bool first = y >= 0 && atomicCAS(&mark[y], 0u, 1u) == 0u;
-    block_append_bits(out, count, first ? 1u : 0u, first ? y : 0);
+    if (t >= (int64_t)n * 27) return;
+    const int y = nbr(d, list[t / 27], (int)(t % 27));
+    if (y >= 0) mark[y] = 1u;
+}
+
+// The marked cells of the groups w0 .. w1 - 1 of four cells, appended to out
+// in cell order within a block (count): the lists the remap's per-cell
+// passes walk then read neighbouring cells from neighbouring lanes.
+__global__ __launch_bounds__(256) void k_marked_cells(const uint32_t *mark, int N, int32_t *out, int *count, int w0,
+                                                      int w1)
+{
+    // sixteen cells per thread, as k_owner_changes
+    const int g = w0 + 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const int w = g + h;
+        if (w >= w1) continue;
+        if (4 * w + 3 < N) {
+            const uint4 v = ((const uint4 *)mark)[w];
+            bits |= ((v.x ? 1u : 0u) | (v.y ? 2u : 0u) | (v.z ? 4u : 0u) | (v.w ? 8u : 0u)) << (4 * h);
+        } else {
+            for (int k = 0; k < 4 && 4 * w + k < N; ++k)
+                if (mark[4 * w + k]) bits |= 1u << (4 * h + k);
+        }
+    }
+    block_append_bits(out, count, bits, 4 * g);
 }
 
 // clear the marks of the cells in list[0 .. *count)
@@ -1439,7 +1465,7 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
     k_map<<<n, 256, 0, L->st>>>(d, n, own);
     k_zero_int<<<1, 64, 0, L->st>>>(counter);
     const int w0 = c0 / 4, w1 = (c1 + 3) / 4;
-    if (w1 > w0) k_owner_changes<<<blocks_for(w1 - w0), 256, 0, L->st>>>(d, own, counter, chg, w0, w1);
+    if (w1 > w0) k_owner_changes<<<blocks_for((w1 - w0 + 3) / 4), 256, 0, L->st>>>(d, own, counter, chg, w0, w1);
     HIP_TRY(hipGetLastError());
     int nch = 0;
     HIP_TRY(hipMemcpyAsync(&nch, counter, 4, hipMemcpyDeviceToHost, L->st));
@@ -1462,7 +1488,10 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
     // only the changed cells and their neighbours change type or solid
     // neighbours: listed once each
     k_zero_int<<<1, 64, 0, L->st>>>(mcount);
-    k_mark_list<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark, mlist, mcount);
+    // (the changed cells lie in the rows of the spheres before or after the
+    // move, their neighbours in the rows scanned for changes, widened by two)
+    k_mark_list<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark);
+    k_marked_cells<<<blocks_for((w1 - w0 + 3) / 4), 256, 0, L->st>>>(mark, d.N, mlist, mcount, w0, w1);
     const int gml = (int)((nmax + 255) / 256);
     if (lists_live) k_mem_dirty<<<gml, 256, 0, L->st>>>(d, own, mlist, mcount, L->ml.dirty);
     DISPATCH(L, run_liquid_form, L, 0, mlist, mcount, nmax);
