@@ -231,11 +231,8 @@ __global__ void k_closure(Dev d)
 
 // liquid cells: switch between the mass m and the stored form m - own outgoing
 template <class S>
-__global__ void k_liquid_form(Dev d, int p, int to_q, const int32_t *list, const int *count)
+__device__ void liquid_form_cell(const Dev &d, int p, int to_q, int c)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (list ? t >= *count : t >= d.N) return;
-    const int c = list ? list[t] : t;
     if ((d.flags[c] & T_MASK) != T_LIQ) return;
     const S *pdf = (const S *)d.pdf[p];
     // the neighbour x + c_i is solid or beyond a wall where the solid-link
@@ -249,6 +246,13 @@ __global__ void k_liquid_form(Dev d, int p, int to_q, const int32_t *list, const
         if (!((sm >> opp(i)) & 1u)) fluid += v;
     }
     d.mq[c] = to_q ? d.mq[c] - fluid : d.mq[c] + fluid;
+}
+
+template <class S>
+__global__ void k_liquid_form(Dev d, int p, int to_q)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < d.N) liquid_form_cell<S>(d, p, to_q, c);
 }
 
 // sphere -> solid cells; owner = lowest covering sphere index
@@ -544,12 +548,9 @@ __global__ void k_owner_commit(Dev d, const int32_t *own, const int32_t *list, i
     d.owner[c] = own[c] == INT_MAX ? -1 : own[c];
 }
 
-// solid-link mask and near-solid bit of the cells in list[0 .. *count)
-__global__ void k_near_solid_list(Dev d, const int32_t *list, const int *count)
+// solid-link mask and near-solid bit of cell c
+__device__ void near_solid_cell(const Dev &d, int c)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *count) return;
-    const int c = list[t];
     uint32_t m = 0;
     for (int j = 0; j < 27; ++j) {
         if (j == REST) continue;
@@ -561,15 +562,12 @@ __global__ void k_near_solid_list(Dev d, const int32_t *list, const int *count)
 }
 
 // Momentum-exchange lists a remap may change: a cell's links into spheres
-// change only when the cell or a neighbour changes owner, so only the cells
-// of list[0 .. *count) (the changed cells and their neighbours) change
-// entries, and only in the lists of the old and the new owners of their
-// neighbours (before the new owners are committed).
-__global__ void k_mem_dirty(Dev d, const int32_t *own, const int32_t *list, const int *count, int32_t *dirty)
+// change only when the cell or a neighbour changes owner, so only the
+// changed cells and their neighbours change entries, and only in the lists
+// of the old and the new owners of their neighbours (marked before the new
+// owners are committed).
+__device__ void mem_dirty_cell(const Dev &d, const int32_t *own, int c, int32_t *dirty)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *count) return;
-    const int c = list[t];
     // a cell solid before and after has no links
     if (d.owner[c] >= 0 && own[c] != INT_MAX) return;
     int qo[27], qn[27];
@@ -584,6 +582,31 @@ __global__ void k_mem_dirty(Dev d, const int32_t *own, const int32_t *list, cons
         if (qo[j] >= 0) dirty[qo[j]] = 1;
         if (qn[j] != INT_MAX) dirty[qn[j]] = 1;
     }
+}
+
+// The remap's passes over the changed cells and their neighbours
+// (list[0 .. *count)): before the cover, their link lists marked (dirty,
+// when the lists are live) and their liquid mass back to m; after the new
+// owners are committed, their solid-link masks and the stored liquid form.
+template <class S>
+__global__ void k_before_cover(Dev d, int p, const int32_t *list, const int *count, const int32_t *own,
+                               int32_t *dirty)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *count) return;
+    const int c = list[t];
+    if (dirty) mem_dirty_cell(d, own, c, dirty);
+    liquid_form_cell<S>(d, p, 0, c);
+}
+
+template <class S>
+__global__ void k_after_commit(Dev d, int p, const int32_t *list, const int *count)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *count) return;
+    const int c = list[t];
+    near_solid_cell(d, c);
+    liquid_form_cell<S>(d, p, 1, c);
 }
 
 // zero n bytes (16 per thread; n a multiple of 16)
@@ -900,11 +923,23 @@ static void run_setup(FslLattice *L, const double *fill, const double *rho, cons
 
 // all liquid cells, or those in list[0 .. *count) (at most `bound` of them)
 template <class S>
-static void run_liquid_form(FslLattice *L, int to_q, const int32_t *list = nullptr, const int *count = nullptr,
-                            int64_t bound = 0)
+static void run_liquid_form(FslLattice *L, int to_q)
 {
-    const int blocks = list ? (int)((bound + 255) / 256) : blocks_for(L->d.N);
-    if (blocks > 0) k_liquid_form<S><<<blocks, 256, 0, L->st>>>(L->d, L->parity, to_q, list, count);
+    k_liquid_form<S><<<blocks_for(L->d.N), 256, 0, L->st>>>(L->d, L->parity, to_q);
+}
+
+template <class S>
+static void run_before_cover(FslLattice *L, const int32_t *list, const int *count, int64_t bound, const int32_t *own,
+                             int32_t *dirty)
+{
+    if (bound > 0)
+        k_before_cover<S><<<(int)((bound + 255) / 256), 256, 0, L->st>>>(L->d, L->parity, list, count, own, dirty);
+}
+
+template <class S>
+static void run_after_commit(FslLattice *L, const int32_t *list, const int *count, int64_t bound)
+{
+    if (bound > 0) k_after_commit<S><<<(int)((bound + 255) / 256), 256, 0, L->st>>>(L->d, L->parity, list, count);
 }
 
 template <class S> static void run_refresh(FslLattice *L)
@@ -1493,8 +1528,7 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
     k_mark_list<<<gmk, 256, 0, L->st>>>(d, chg, nch, mark);
     k_marked_cells<<<blocks_for((w1 - w0 + 3) / 4), 256, 0, L->st>>>(mark, d.N, mlist, mcount, w0, w1);
     const int gml = (int)((nmax + 255) / 256);
-    if (lists_live) k_mem_dirty<<<gml, 256, 0, L->st>>>(d, own, mlist, mcount, L->ml.dirty);
-    DISPATCH(L, run_liquid_form, L, 0, mlist, mcount, nmax);
+    DISPATCH(L, run_before_cover, L, mlist, mcount, nmax, own, lists_live ? L->ml.dirty : nullptr);
     k_cover<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
     // rounds in pairs between checks by the host: a round that types no
     // cell changes nothing (its apply finds no typed cell), so the second
@@ -1515,8 +1549,7 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
     }
     DISPATCH(L, run_uncover_finish, L, chg, nch, rn);
     k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
-    k_near_solid_list<<<gml, 256, 0, L->st>>>(d, mlist, mcount);
-    DISPATCH(L, run_liquid_form, L, 1, mlist, mcount, nmax);
+    DISPATCH(L, run_after_commit, L, mlist, mcount, nmax);
     // record kinds: only the listed cells can change theirs, unless a sphere
     // nearly spans the periodic box (kinds then depend on sphere positions)
     const bool kinds_done = !d.img_check;
