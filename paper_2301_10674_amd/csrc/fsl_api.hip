@@ -24,7 +24,7 @@ void launch_step(const Dev &d, int p, uint32_t epoch, int list_blocks, int watch
 template <class R>
 void launch_geom(const Dev &d, int which, int list_blocks, hipStream_t st);
 void launch_watch_final(const Dev &d, int list_blocks, hipStream_t st);
-void launch_setup_links(const Dev &d, int from_slots, hipStream_t st);
+void launch_setup_links(const Dev &d, int from_slots, int c0, int c1, hipStream_t st);
 void launch_kinds_list(const Dev &d, const int32_t *list, const int *count, int bound, hipStream_t st);
 void launch_mem_count(const Dev &d, int nsph, int32_t *counts, hipStream_t st);
 void launch_mem_fill(const Dev &d, int nsph, const MemLists &ml, int only_changed, hipStream_t st);
@@ -1056,8 +1056,11 @@ static void run_uncover_finish(FslLattice *L, const int32_t *list, int n, const 
 // bounce-back records, the highest fluid row, the interface list and the
 // interface geometry
 // near_done: the solid-link masks are current; kinds_done: the slot array
-// holds every cell's record kind (a remap re-encoded the cells it changed)
-static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done = false, bool kinds_done = false)
+// holds every cell's record kind (a remap re-encoded the cells it changed);
+// rec_c0 .. rec_c1 - 1: the only cells that can hold records (rec_c1 < 0:
+// any cell)
+static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done = false, bool kinds_done = false,
+                          int rec_c0 = 0, int rec_c1 = -1)
 {
     Dev &d = L->d;
     L->mass_fast = false;
@@ -1069,7 +1072,7 @@ static FslStatus finalize(FslLattice *L, bool reset_stats = true, bool near_done
     // running pool total of the watchdog, exact after every rebuild
     k_pool_partial<<<RED_BLOCKS, 256, 0, L->st>>>(d);
     k_sum_partials<<<1, 256, 0, L->st>>>(d, RED_BLOCKS, (int)(d.wd - d.partial) + WD_POOL);
-    launch_setup_links(d, kinds_done ? 1 : 0, L->st);
+    launch_setup_links(d, kinds_done ? 1 : 0, rec_c0, rec_c1, L->st);
     // the geometry of the rebuilt list, with the estimator the steps use
     const bool learned = L->P.normals == 1 && L->mlpP;
     if (L->P.precision == FSL_FP64) {
@@ -1556,7 +1559,8 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
     if (kinds_done) launch_kinds_list(d, mlist, mcount, (int)nmax, L->st);
     k_unmark_list<<<gml, 256, 0, L->st>>>(mlist, mcount, mark);
     HIP_TRY(hipGetLastError());
-    FslStatus r = finalize(L, false, true, kinds_done);
+    // records lie next to spheres: in the rows scanned for owner changes
+    FslStatus r = finalize(L, false, true, kinds_done, c0, c1);
     if (r != FSL_OK) return r;
     L->mem_stale = !lists_live;
     HIP_TRY(hipStreamSynchronize(L->st));

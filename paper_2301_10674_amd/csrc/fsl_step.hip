@@ -855,9 +855,9 @@ __device__ __forceinline__ void slot_scan(int a, int b, int &ea, int &eb, int &t
 // With from_slots the kinds are read from the slot array instead, where a
 // remap has re-encoded the cells whose kind may have changed (k_kinds_list).
 __global__ __launch_bounds__(SLOT_THREADS) void k_slot_kinds(Dev d, uint8_t *kind, int32_t *bc, int32_t *bf,
-                                                             int from_slots)
+                                                             int from_slots, int b0)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x, c0 = 4 * t;
+    const int t = (b0 + (int)blockIdx.x) * blockDim.x + threadIdx.x, c0 = 4 * t;
     // smask, or with from_slots the slot of each of the four cells
     uint32_t sm[4] = {0u, 0u, 0u, 0u};
     const uint32_t *src = from_slots ? (const uint32_t *)d.bbslot : d.smask;
@@ -939,9 +939,9 @@ __global__ void k_kinds_list(Dev d, const int32_t *list, const int *count)
 }
 
 __global__ __launch_bounds__(SLOT_THREADS) void k_slot_write(Dev d, const uint8_t *kind, const int32_t *bc,
-                                                             const int32_t *bf)
+                                                             const int32_t *bf, int b0)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x, c0 = 4 * t;
+    const int t = (b0 + (int)blockIdx.x) * blockDim.x + threadIdx.x, c0 = 4 * t;
     uint32_t packed = 0u;
     if (c0 + 3 < d.N) {
         packed = ((const uint32_t *)kind)[t];
@@ -1752,17 +1752,21 @@ template void launch_geom<float>(const Dev &, int, int, hipStream_t);
 
 // record slots and the highest fluid row.  Scratch: the per-cell kinds in
 // the excess-share array and the per-block counts in the new-cell list
-// (both free between steps; 2 * blocks <= N)
-void launch_setup_links(const Dev &d, int from_slots, hipStream_t st)
+// (both free between steps; 2 * blocks <= N).  Only the cells c0 .. c1 - 1
+// can hold records (c1 < 0: all): outside them every cell keeps slot -1.
+void launch_setup_links(const Dev &d, int from_slots, int c0, int c1, hipStream_t st)
 {
     const int b = (d.N + 255) / 256;
     const int bs = (d.N + SLOT_CELLS - 1) / SLOT_CELLS;
+    const int b0 = c1 < 0 ? 0 : c0 / SLOT_CELLS, b1 = c1 < 0 ? bs : std::min((c1 + SLOT_CELLS - 1) / SLOT_CELLS, bs);
     uint8_t *kind = (uint8_t *)d.share;
     int32_t *bc = d.lnew, *bf = d.lnew + bs;
-    k_slot_kinds<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf, from_slots);
-    k_scan_counts<<<1, 1024, 0, st>>>(bc, bs, d.cnt + 4);
-    k_scan_counts<<<1, 1024, 0, st>>>(bf, bs, d.cnt + 5);
-    k_slot_write<<<bs, SLOT_THREADS, 0, st>>>(d, kind, bc, bf);
+    if (b1 > b0) {
+        k_slot_kinds<<<b1 - b0, SLOT_THREADS, 0, st>>>(d, kind, bc + b0, bf + b0, from_slots, b0);
+        k_scan_counts<<<1, 1024, 0, st>>>(bc + b0, b1 - b0, d.cnt + 4);
+        k_scan_counts<<<1, 1024, 0, st>>>(bf + b0, b1 - b0, d.cnt + 5);
+        k_slot_write<<<b1 - b0, SLOT_THREADS, 0, st>>>(d, kind, bc + b0, bf + b0, b0);
+    }
     k_zmax<<<b < 1024 ? b : 1024, 256, 0, st>>>(d);
 }
 
