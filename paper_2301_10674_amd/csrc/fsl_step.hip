@@ -456,6 +456,18 @@ __device__ __forceinline__ void dense_rows(const Dev &d, const S *__restrict__ s
     }
 }
 
+// four values of a record in one 16-byte store (FP32) or two (FP64): the
+// records are 256-byte aligned, 8 or 32 values apart
+__device__ __forceinline__ void store4(float *dst, float a, float b, float c, float e)
+{
+    *(float4 *)dst = make_float4(a, b, c, e);
+}
+__device__ __forceinline__ void store4(double *dst, double a, double b, double c, double e)
+{
+    ((double2 *)dst)[0] = make_double2(a, b);
+    ((double2 *)dst)[1] = make_double2(c, e);
+}
+
 // moving-wall records of every cell that has sphere links (one thread per
 // record, through the record-cell list)
 template <class R>
@@ -470,13 +482,16 @@ __global__ void k_bb_terms(Dev d, int nrec)
     const uint32_t sm = d.smask[c];
     if (slot <= -2) {
         R *rec = (R *)d.bbfull + (size_t)(-slot - 2) * 32;
-        for (int j = 0; j < 32; ++j) {
-            R t = R(0);
-            if (j < 27 && j != REST && ((sm >> j) & 1u)) {
-                const int s = nb_of(d, pc, opp(j));
-                if (s >= 0) t = bb_term<R>(d, s, j, pc);
+        for (int j0 = 0; j0 < 32; j0 += 4) {
+            R t[4] = {R(0), R(0), R(0), R(0)};
+            for (int k = 0; k < 4; ++k) {
+                const int j = j0 + k;
+                if (j < 27 && j != REST && ((sm >> j) & 1u)) {
+                    const int s = nb_of(d, pc, opp(j));
+                    if (s >= 0) t[k] = bb_term<R>(d, s, j, pc);
+                }
             }
-            rec[j] = t;
+            store4(rec + j0, t[0], t[1], t[2], t[3]);
         }
         return;
     }
@@ -499,14 +514,10 @@ __global__ void k_bb_terms(Dev d, int nrec)
     if (q1 >= 0) rigid_velocity(d, q1, pc, V1);
     if (q2 >= 0) rigid_velocity(d, q2, pc, V2);
     R *h = (R *)d.bbterm + (size_t)slot * 8;
-    for (int a = 0; a < 3; ++a) {
-        h[a] = R(V1[a]);
-        h[3 + a] = R(V2[a]);
-    }
     R mbits = R(0);
     __builtin_memcpy(&mbits, &m2, 4);
-    h[6] = mbits;
-    h[7] = R(0);
+    store4(h, R(V1[0]), R(V1[1]), R(V1[2]), R(V2[0]));
+    store4(h + 4, R(V2[1]), R(V2[2]), mbits, R(0));
 }
 
 // ---------------------------------------------------------------- momentum exchange

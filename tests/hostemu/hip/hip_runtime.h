@@ -62,6 +62,7 @@ struct double4 {
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
 inline uint4 make_uint4(unsigned a, unsigned b, unsigned c, unsigned d) { return uint4{a, b, c, d}; }
 inline int4 make_int4(int a, int b, int c, int d) { return int4{a, b, c, d}; }
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
 inline double4 make_double4(double a, double b, double c, double d) { return double4{a, b, c, d}; }
 inline float4 make_float4(float a, float b, float c, float d) { return float4{a, b, c, d}; }
 
