@@ -29,6 +29,7 @@
 // every sum and product rounds as written.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -65,6 +66,12 @@ struct DemDev {
     double *wxi;                  // bottom and top wall displacement (6 per sphere)
     const double *hydro;          // 6 per sphere or null
     int32_t *err;                 // bit 0: list overflow, bit 1: moved beyond the skin
+    // bins for the partner search (nbx = 0: every sphere tests every other):
+    // nbx x nby x nbz boxes of at least the largest reach, periodic in x
+    // and y; per bin its first entry and count in bin_idx (sphere indices)
+    int nbx, nby, nbz;
+    double wbx, wby, wbz;
+    int32_t *bin_cnt, *bin_start, *bin_cur, *bin_idx;
 };
 
 __device__ __forceinline__ double min_image(double d, double L)
@@ -120,6 +127,152 @@ __global__ __launch_bounds__(DEM_THREADS) void k_dem_list(DemDev D, int s, int c
             }
         }
         c += (int)__popcll(m);
+    }
+    if (lane == 0) {
+        if (c > DEM_MAXN) atomicOr(D.err, 1);
+        D.cnt[nxt][i] = min(c, DEM_MAXN);
+        D.x0[3 * i] = xi0;
+        D.x0[3 * i + 1] = xi1;
+        D.x0[3 * i + 2] = xi2;
+    }
+}
+
+// bin of sphere i (x and y wrapped into the box, z clamped to the bins)
+__device__ __forceinline__ int dem_bin(const DemDev &D, int s, int i)
+{
+    const double x = D.x[s][3 * i], y = D.x[s][3 * i + 1], z = D.x[s][3 * i + 2];
+    const int bx = min(max((int)floor((x - D.Lx * floor(x / D.Lx)) / D.wbx), 0), D.nbx - 1);
+    const int by = min(max((int)floor((y - D.Ly * floor(y / D.Ly)) / D.wby), 0), D.nby - 1);
+    const int bz = min(max((int)floor(z / D.wbz), 0), D.nbz - 1);
+    return bx + D.nbx * (by + D.nby * bz);
+}
+
+__global__ void k_bin_zero(DemDev D)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < D.nbx * D.nby * D.nbz) D.bin_cnt[b] = 0;
+}
+
+__global__ void k_bin_count(DemDev D, int s)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < D.n) atomicAdd(&D.bin_cnt[dem_bin(D, s, i)], 1);
+}
+
+// exclusive prefix of the bin counts (one block of 1024), also as cursors
+__global__ __launch_bounds__(1024) void k_bin_scan(DemDev D)
+{
+    __shared__ int s_w[16];
+    __shared__ int s_carry;
+    const int nbins = D.nbx * D.nby * D.nbz;
+    const int lane = __lane_id(), w = (int)threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nbins; base += 1024) {
+        const int b = base + (int)threadIdx.x;
+        const int x = b < nbins ? D.bin_cnt[b] : 0;
+        int sc = x;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(sc, o);
+            if (lane >= o) sc += y;
+        }
+        if (lane == 63) s_w[w] = sc;
+        __syncthreads();
+        int off = s_carry;
+        for (int k = 0; k < w; ++k) off += s_w[k];
+        if (b < nbins) {
+            D.bin_start[b] = off + sc - x;
+            D.bin_cur[b] = off + sc - x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = off + sc;
+        __syncthreads();
+    }
+}
+
+__global__ void k_bin_fill(DemDev D, int s)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < D.n) D.bin_idx[atomicAdd(&D.bin_cur[dem_bin(D, s, i)], 1)] = i;
+}
+
+// The partner lists as k_dem_list builds them, candidates taken from the
+// 27 bins around the sphere's (bins are at least as wide as any reach, at
+// least three per periodic axis, so the 27 are distinct).  A bin's spheres
+// come in no particular order: the hits are gathered in LDS and each takes
+// the position of its rank by index, so the lists are identical.
+constexpr int DEM_HITS = 64;   // hits kept per sphere (more than DEM_MAXN: overflow is reported)
+
+__global__ __launch_bounds__(DEM_THREADS) void k_dem_list_bins(DemDev D, int s, int cur)
+{
+    __shared__ int s_hit[DEM_THREADS / 64][DEM_HITS];
+    const int wv = (int)threadIdx.x >> 6;
+    const int i = (int)((blockIdx.x * DEM_THREADS + threadIdx.x) >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const bool active = i < D.n;   // the whole wavefront shares i; every one reaches the barrier
+    const int nxt = cur ^ 1;
+    int c = 0, co = 0;
+    double xi0 = 0.0, xi1 = 0.0, xi2 = 0.0;
+    if (active) {
+        xi0 = D.x[s][3 * i];
+        xi1 = D.x[s][3 * i + 1];
+        xi2 = D.x[s][3 * i + 2];
+        const double ri = D.r[i];
+        const double reach = D.lub_cut + D.skin;
+        co = D.cnt[cur][i];
+        const int b = dem_bin(D, s, i);
+        const int bx = b % D.nbx, by = (b / D.nbx) % D.nby, bz = b / (D.nbx * D.nby);
+        for (int k = 0; k < 27; ++k) {
+            const int zz = bz + k / 9 - 1;
+            if (zz < 0 || zz >= D.nbz) continue;
+            const int xx = (bx + k % 3 - 1 + D.nbx) % D.nbx, yy = (by + (k / 3) % 3 - 1 + D.nby) % D.nby;
+            const int bb = xx + D.nbx * (yy + D.nby * zz);
+            const int b0 = D.bin_start[bb], nbn = D.bin_cnt[bb];
+            for (int base = 0; base < nbn; base += 64) {
+                int j = -1;
+                bool hit = false;
+                if (base + lane < nbn) {
+                    j = D.bin_idx[b0 + base + lane];
+                    if (j != i) {
+                        const double dx = min_image(D.x[s][3 * j] - xi0, D.Lx);
+                        const double dy = min_image(D.x[s][3 * j + 1] - xi1, D.Ly);
+                        const double dz = D.x[s][3 * j + 2] - xi2;
+                        const double lim = ri + D.r[j] + reach;
+                        hit = dx * dx + dy * dy + dz * dz < lim * lim;
+                    }
+                }
+                const uint64_t m = __ballot(hit);
+                if (hit) {
+                    const int pos = c + (int)__popcll(m & ((1ull << lane) - 1ull));
+                    if (pos < DEM_HITS) s_hit[wv][pos] = j;
+                }
+                c += (int)__popcll(m);
+            }
+        }
+    }
+    __syncthreads();   // the hits are in LDS
+    if (!active) return;
+    const int nh = min(c, DEM_HITS);
+    if (lane < nh) {
+        const int j = s_hit[wv][lane];
+        int pos = 0;
+        for (int q = 0; q < nh; ++q) pos += s_hit[wv][q] < j;
+        if (pos < DEM_MAXN) {
+            const size_t slot = (size_t)i * DEM_MAXN + pos;
+            D.nb[nxt][slot] = j;
+            double a = 0.0, bq = 0.0, e = 0.0;
+            for (int q = 0; q < co; ++q)
+                if (D.nb[cur][(size_t)i * DEM_MAXN + q] == j) {
+                    const size_t o = 3 * ((size_t)i * DEM_MAXN + q);
+                    a = D.xi[cur][o];
+                    bq = D.xi[cur][o + 1];
+                    e = D.xi[cur][o + 2];
+                    break;
+                }
+            D.xi[nxt][3 * slot] = a;
+            D.xi[nxt][3 * slot + 1] = bq;
+            D.xi[nxt][3 * slot + 2] = e;
+        }
     }
     if (lane == 0) {
         if (c > DEM_MAXN) atomicOr(D.err, 1);
@@ -361,6 +514,7 @@ struct FslDem {
     int s = 0;          // state parity
     int l = 0;          // list parity
     double *hbuf = nullptr;   // device copy of a host hydrodynamic load
+    void *bins = nullptr;     // bin counts, starts, cursors and sphere indices
 };
 
 #define DEM_TRY(expr)                                                                          \
@@ -486,6 +640,42 @@ FslStatus fsl_dem_create(const FslDemParams *p, void *hip_stream, int32_t n, con
         delete D;
         return set_error(FSL_ERR_DEVICE, std::string("particle state upload: ") + hipGetErrorString(e));
     }
+    // bins for the partner search on large sets: at least as wide as the
+    // largest reach 2 r_max + lub_cut + skin, at least three per periodic
+    // axis, and not many more bins than spheres
+    d.nbx = 0;
+    double rmax = 0.0;
+    for (size_t i = 0; i < N; ++i) rmax = std::max(rmax, radius[i]);
+    double hb = 2.0 * rmax + p->lub_cut + p->skin;
+    if (n >= 512) {
+        for (;;) {
+            const int bx = (int)std::floor(d.Lx / hb), by = (int)std::floor(d.Ly / hb);
+            const int bz = std::max(1, (int)std::floor(d.Lz / hb));
+            if (bx < 3 || by < 3) break;
+            if ((double)bx * by * bz <= 4.0 * n + 64.0) {
+                d.nbx = bx;
+                d.nby = by;
+                d.nbz = bz;
+                break;
+            }
+            hb *= 1.25;
+        }
+    }
+    if (d.nbx > 0) {
+        d.wbx = d.Lx / d.nbx;
+        d.wby = d.Ly / d.nby;
+        d.wbz = d.Lz / d.nbz;
+        const size_t nbins = (size_t)d.nbx * d.nby * d.nbz;
+        if (hipMalloc(&D->bins, (3 * nbins + N) * 4) != hipSuccess) {
+            (void)hipFree(D->mem);
+            delete D;
+            return set_error(FSL_ERR_NOMEM, "particle bins");
+        }
+        d.bin_cnt = (int32_t *)D->bins;
+        d.bin_start = d.bin_cnt + nbins;
+        d.bin_cur = d.bin_start + nbins;
+        d.bin_idx = d.bin_cur + nbins;
+    }
     *out = D;
     return FSL_OK;
 }
@@ -500,8 +690,18 @@ FslStatus fsl_dem_step(FslDem *D, const double *hydro, int32_t hydro_on_device, 
     DemDev d = D->d;
     d.hydro = hydro ? (hydro_on_device ? hydro : D->hbuf) : nullptr;
     const int nb = dem_blocks(n);
+    const int lb = (n + DEM_THREADS / 64 - 1) / (DEM_THREADS / 64);
     for (int t = 0; t < nsteps; ++t) {
-        k_dem_list<<<(n + DEM_THREADS / 64 - 1) / (DEM_THREADS / 64), DEM_THREADS, 0, D->st>>>(d, D->s, D->l);
+        if (d.nbx > 0) {
+            const int nbins = d.nbx * d.nby * d.nbz;
+            k_bin_zero<<<(nbins + 255) / 256, 256, 0, D->st>>>(d);
+            k_bin_count<<<nb, DEM_THREADS, 0, D->st>>>(d, D->s);
+            k_bin_scan<<<1, 1024, 0, D->st>>>(d);
+            k_bin_fill<<<nb, DEM_THREADS, 0, D->st>>>(d, D->s);
+            k_dem_list_bins<<<lb, DEM_THREADS, 0, D->st>>>(d, D->s, D->l);
+        } else {
+            k_dem_list<<<lb, DEM_THREADS, 0, D->st>>>(d, D->s, D->l);
+        }
         D->l ^= 1;
         for (int k = 0; k < D->P.substeps; ++k) {
             k_dem_sub<<<(n + DEM_PER_BLOCK - 1) / DEM_PER_BLOCK, DEM_THREADS, 0, D->st>>>(d, D->s, D->l);
@@ -550,6 +750,7 @@ void fsl_dem_destroy(FslDem *D)
         (void)hipStreamSynchronize(D->st);
         (void)hipFree(D->mem);
     }
+    if (D->bins) (void)hipFree(D->bins);
     delete D;
 }
 
