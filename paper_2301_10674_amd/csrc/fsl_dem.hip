@@ -642,12 +642,13 @@ FslStatus fsl_dem_create(const FslDemParams *p, void *hip_stream, int32_t n, con
     }
     // bins for the partner search on large sets: at least as wide as the
     // largest reach 2 r_max + lub_cut + skin, at least three per periodic
-    // axis, and not many more bins than spheres
+    // axis, and not many more bins than spheres (below a few thousand
+    // spheres testing every pair is as fast as the five binning launches)
     d.nbx = 0;
     double rmax = 0.0;
     for (size_t i = 0; i < N; ++i) rmax = std::max(rmax, radius[i]);
     double hb = 2.0 * rmax + p->lub_cut + p->skin;
-    if (n >= 512) {
+    if (n >= 4096) {
         for (;;) {
             const int bx = (int)std::floor(d.Lx / hb), by = (int)std::floor(d.Ly / hb);
             const int bz = std::max(1, (int)std::floor(d.Lz / hb));
