@@ -256,8 +256,14 @@ __global__ void k_liquid_form(Dev d, int p, int to_q)
 }
 
 // sphere -> solid cells; owner = lowest covering sphere index
-__global__ void k_map(Dev d, int nsph, int32_t *own)
+__global__ __launch_bounds__(256) void k_map(Dev d, int nsph, int32_t *own)
 {
+    // Cells whose centre lies inside sphere q (the rule in inside()).  The
+    // box rows (y, z) are walked over the x-run where the centre can be
+    // inside (widened by a cell against rounding), 256 rows at a time: each
+    // thread takes a row, a prefix over the rows numbers the cells of the
+    // runs, and the threads then test those cells.
+    __shared__ int s_end[256], s_x0[256];
     const int q = blockIdx.x;
     if (q >= nsph) return;
     const double *s = d.sph + 10 * q;
@@ -267,9 +273,8 @@ __global__ void k_map(Dev d, int nsph, int32_t *own)
     const int z0 = max((int)floor(s[2] - r) - 1, 0), z1 = min((int)floor(s[2] + r) + 1, d.nz - 1);
     const int wx = x1 - x0 + 1, wy = y1 - y0 + 1, wz = z1 - z0 + 1;
     if (wz <= 0) return;
-    const int total = wx * wy * wz;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int xx = x0 + t % wx, yy = y0 + (t / wx) % wy, z = z0 + t / (wx * wy);
+    const int t = (int)threadIdx.x, lane = __lane_id();
+    auto inside = [&](int xx, int yy, int z) {
         const int x = ((xx % d.nx) + d.nx) % d.nx, y = ((yy % d.ny) + d.ny) % d.ny;
         // same rounding as written: no contraction into fused multiply-adds
         double dx = (x + 0.5) - s[0];
@@ -279,6 +284,54 @@ __global__ void k_map(Dev d, int nsph, int32_t *own)
         const double dz = (z + 0.5) - s[2];
         const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
         if (r2 <= __dmul_rn(r, r)) atomicMin(&own[x + d.nx * (y + d.ny * z)], q);
+    };
+    if (2 * wx >= d.nx || 2 * wy >= d.ny) {
+        // the box reaches half a period: a cell's nearest image need not be
+        // its box position, so every box cell is tested
+        const int total = wx * wy * wz;
+        for (int k = t; k < total; k += blockDim.x)
+            inside(x0 + k % wx, y0 + (k / wx) % wy, z0 + k / (wx * wy));
+        return;
+    }
+    const int nrow = wy * wz;
+    for (int r0 = 0; r0 < nrow; r0 += 256) {
+        const int row = r0 + t;
+        int a = 0, n = 0;
+        if (row < nrow) {
+            const double ey = (y0 + row % wy + 0.5) - s[1], ez = (z0 + row / wy + 0.5) - s[2];
+            const double h = r * r - ey * ey - ez * ez;
+            if (h >= -1e-9 * (r * r + 1.0)) {
+                const double w = sqrt(fmax(h, 0.0)) + 1.0;
+                a = max((int)floor(s[0] - w - 0.5) - x0, 0);
+                const int e = min((int)ceil(s[0] + w - 0.5) - x0, wx - 1);
+                n = max(e - a + 1, 0);
+            }
+        }
+        int inc = n;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o);
+            if (lane >= o) inc += v;
+        }
+        s_end[t] = inc;
+        __syncthreads();
+        int wbase = 0;
+        for (int w = 0; w < (t >> 6); ++w) wbase += s_end[64 * w + 63];
+        const int total = s_end[63] + s_end[127] + s_end[191] + s_end[255];
+        __syncthreads();
+        s_end[t] = wbase + inc;
+        s_x0[t] = a;
+        __syncthreads();
+        for (int k = t; k < total; k += 256) {
+            int lo = 0, hi = 255;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_end[mid] > k) hi = mid;
+                else lo = mid + 1;
+            }
+            const int rr = r0 + lo;
+            inside(x0 + s_x0[lo] + (k - (lo ? s_end[lo - 1] : 0)), y0 + rr % wy, z0 + rr / wy);
+        }
+        __syncthreads();
     }
 }
 
