@@ -350,7 +350,9 @@ FslStatus fsl_set_estimator(FslLattice *lat, const float *weights);
  *     the excess-mass pool; uncovered cells are typed in rounds from
  *     neighbours typed before each round: liquid (liquid or interface
  *     neighbours, no gas), interface of fill 0 (both), gas (gas only, or
- *     never reached); liquid and interface cells get the equilibrium at the
+ *     never reached); a cell typed liquid beside one typed gas in the same
+ *     round is an interface cell of fill 0 instead (no liquid cell borders
+ *     gas); liquid and interface cells get the equilibrium at the
  *     mean density of those neighbours and the sphere's rigid velocity at
  *     the cell centre, liquid cells taking that mass from the pool, so the
  *     total of fsl_total_mass() is unchanged; everything derived from the

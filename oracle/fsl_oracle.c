@@ -1248,6 +1248,22 @@ int ol_move_particles(OlLattice *L, const double *centre, const double *vel, con
     }
     for (int64_t c = 0; c < L->N; ++c)
         if (tn[c] == 255) tn[c] = OL_GAS; /* enclosed by solid cells */
+    /* closure of the surface: a cell typed liquid in the same round as a
+     * neighbour typed gas would border gas; it is an interface cell of
+     * fill 0 instead */
+    for (int64_t c = 0; c < L->N; ++c) {
+        if (own[c] >= 0 || t0[c] != OL_SOLID || tn[c] != OL_LIQUID) continue;
+        for (int i = 0; i < Q; ++i) {
+            if (i == REST) continue;
+            const int64_t y = nbr(L, c, i, 1);
+            if (y < 0) continue;
+            const int ty = (own[y] < 0 && t0[y] == OL_SOLID) ? tn[y] : L->type[y];
+            if (ty == OL_GAS) {
+                tn[c] = OL_INTERFACE;
+                break;
+            }
+        }
+    }
     free(dens);
     free(tv);
     for (int64_t c = 0; c < L->N; ++c) {

@@ -164,7 +164,9 @@ int64_t ol_steps_done(const OlLattice *L);
  * the owner map is rebuilt; covered fluid cells turn solid and give their
  * mass to the pool; uncovered cells, typed in rounds from neighbours typed
  * in earlier rounds, become liquid (fluid and no gas neighbours), empty
- * interface (both) or gas (gas only, or never reached), fluid ones at the
+ * interface (both) or gas (gas only, or never reached) -- a cell typed
+ * liquid beside one typed gas in the same round is an empty interface
+ * cell instead, so that no liquid cell borders gas --, fluid ones at the
  * equilibrium of their neighbours' mean density and the sphere's rigid
  * velocity, liquid ones taking that mass from the pool.  -1 when no spheres
  * are mapped. */

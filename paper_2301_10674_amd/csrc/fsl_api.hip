@@ -593,6 +593,28 @@ __global__ void k_uncover_finish(Dev d, int p, const int32_t *list, int n, const
     }
 }
 
+// Closure of the surface after the uncovering rounds: a cell typed liquid in
+// the same round as a neighbour typed gas (or never reached, which becomes
+// gas) would border gas; it is an interface cell of fill 0 instead.
+__global__ void k_uncover_closure(Dev d, const int32_t *list, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c = list[t];
+    const uint8_t f = d.flags[c];
+    if (!(f & F_NEWC) || (f & T_MASK) != T_LIQ) return;
+    for (int i = 0; i < 27; ++i) {
+        if (i == REST) continue;
+        const int y = nbr(d, c, i);
+        if (y < 0) continue;
+        const uint8_t fy = d.flags[y];
+        if ((fy & F_OPEN) || (fy & T_MASK) == T_GAS) {
+            d.flags[c] = (uint8_t)(T_IF | F_NEWC);
+            return;
+        }
+    }
+}
+
 __global__ void k_owner_commit(Dev d, const int32_t *own, const int32_t *list, int n)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1603,6 +1625,7 @@ static FslStatus remap(FslLattice *L, int zlo, int zhi)
         HIP_TRY(hipStreamSynchronize(L->st));
         if (typed[0] == 0 || typed[1] == 0) break;
     }
+    k_uncover_closure<<<gch, 256, 0, L->st>>>(d, chg, nch);
     DISPATCH(L, run_uncover_finish, L, chg, nch, rn);
     k_owner_commit<<<gch, 256, 0, L->st>>>(d, own, chg, nch);
     DISPATCH(L, run_after_commit, L, mlist, mcount, nmax);

@@ -93,6 +93,34 @@ def test_two_cell_shift_fp64():
     g.destroy()
 
 
+def test_far_moves_in_height_fp64():
+    """Spheres jumping several cells up and down between moves, through
+    liquid and into the gas above it: a remap clears and scans only the
+    rows the spheres reach before or after the move, and those rows change
+    from move to move.  Also the device move path, which reports the new
+    rows from the device."""
+    import torch
+    shape = (22, 16, 28)
+    c = np.array([[6.0, 8.0, 5.5], [15.0, 6.0, 6.0]])
+    g, o = pair(shape, film(shape, 17.2), c, [2.4, 2.1])
+    jumps = [np.array([[0.3, 0.0, 6.5], [0.0, -0.4, 0.0]]), np.array([[0.0, 0.2, 8.0], [0.5, 0.0, 9.0]]),
+             np.array([[0.0, 0.0, -13.0], [0.0, 0.3, -7.5]]), np.array([[-0.4, 0.0, 3.0], [0.0, 0.0, 12.0]])]
+    for k, dj in enumerate(jumps):
+        c = c + dj
+        v = np.full(c.shape, 1e-3)
+        if k % 2:
+            dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+            g.move_particles_device(dev(c), dev(v), None)
+        else:
+            g.move_particles(c, v)
+        o.move_particles(c, v)
+        compare(g, o, "jump %d" % k)
+        g.step(3)
+        o.step(3)
+        compare(g, o, "jump %d + 3 steps" % k)
+    g.destroy()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
 def test_mass_exact_reduced_storage(prec):
     shape = (24, 12, 20)

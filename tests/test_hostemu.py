@@ -126,6 +126,38 @@ def test_refilled_link_lists_on_the_cpu():
     b.destroy()
 
 
+def test_spheres_jumping_through_the_surface_on_the_cpu():
+    """Spheres moved several cells up into the gas and back down into the
+    liquid (the uncovering rounds type cells liquid next to cells typed
+    gas in the same round, which the closure makes interface cells),
+    against the oracle after each move and after steps: types, masses, fill
+    levels and PDFs to 1e-12, the total mass exact."""
+    nx, ny, nz = 22, 16, 28
+    z = np.arange(nz)[:, None, None] + np.zeros((nz, ny, nx))
+    c = np.array([[6.0, 8.0, 5.5], [15.0, 6.0, 6.0]])
+    w = I.Workload(name="jumps", shape=(nx, ny, nz), omega=1.5, accel=(1e-5, 0.0, -1e-5), sigma=0.0,
+                   fill=np.clip(17.2 - z, 0.0, 1.0), rho=np.ones((nz, ny, nx)), vel=np.zeros((3, nz, ny, nx)),
+                   centre=c, radius=np.array([2.4, 2.1]), sphere_vel=np.zeros((2, 3)),
+                   sphere_angvel=np.zeros((2, 3)))
+    g = emu.EmuLattice(w, "fp64")
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, fill=w.fill, rho=w.rho, vel=w.vel, conv_eps=w.conv_eps)
+    o.set_particles(w.centre, w.radius, w.sphere_vel, w.sphere_angvel)
+    M0 = o.total_mass()
+    jumps = [[[0.3, 0.0, 6.5], [0.0, -0.4, 0.0]], [[0.0, 0.2, 8.0], [0.5, 0.0, 9.0]],
+             [[0.0, 0.0, -13.0], [0.0, 0.3, -7.5]]]
+    for k, dj in enumerate(jumps):
+        c = c + np.array(dj)
+        v = np.full(c.shape, 1e-3)
+        g.move_particles(c, v)
+        o.move_particles(c, v)
+        compare(g, o, "jump %d" % k)
+        g.step(3)
+        o.step(3)
+        compare(g, o, "jump %d + 3 steps" % k)
+        assert abs(g.total_mass() - M0) <= 1e-12 * M0
+    g.destroy()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp16", 2e-3)])
 def test_storage_forms_on_the_cpu(prec, tol):
     """The FP32 and FP16 forms (whose dense pass reads and writes its rows

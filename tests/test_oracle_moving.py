@@ -9,6 +9,9 @@ rules are readings).
   sphere's rigid-body velocity at its centre;
 * a sphere lifted out of a film: cells uncovered above the surface are gas,
   no liquid cell ever touches a gas cell, the film keeps its mass;
+* a sphere dropped from the gas into a film: the cells uncovered in one
+  round next to cells typed gas in the same round are interface cells, no
+  liquid cell touches a gas cell, and the mass stays exact;
 * moving back to the start gives back the original solid cells.
 """
 import numpy as np
@@ -100,6 +103,29 @@ def test_sphere_lifted_out_of_a_film():
     assert np.any(t[uncovered] == O.LIQUID)
     assert no_liquid_next_to_gas(t)
     assert abs(o.total_mass() - M0) <= 1e-12 * M0
+
+
+def test_sphere_dropped_from_the_gas_into_a_film():
+    """A sphere above the surface dropped into the liquid: the cells it
+    uncovers just above the surface are typed in one round, some liquid
+    (liquid neighbours below) next to others gas (gas neighbours above);
+    the liquid ones become interface cells, so that no liquid cell
+    borders gas, and the total mass stays exact over the following
+    steps."""
+    shape = (22, 16, 28)
+    nx, ny, nz = shape
+    z = np.arange(nz)[:, None, None] + np.zeros((nz, ny, nx))
+    fill = np.clip(17.2 - z, 0.0, 1.0)
+    o = O.OracleLattice(shape, 1.5, accel=(1e-5, 0.0, -1e-5), fill=fill, conv_eps=1e-3)
+    c = np.array([[6.3, 8.2, 20.0], [15.5, 6.0, 15.0]])
+    o.set_particles(c, [2.4, 2.1])
+    M0 = o.total_mass()
+    o.move_particles(c + np.array([[0.0, 0.0, -13.0], [0.0, 0.3, -7.5]]), vel=np.full((2, 3), 1e-3))
+    assert no_liquid_next_to_gas(o.read(O.F_TYPE))
+    for _ in range(4):
+        o.step(2)
+        assert abs(o.total_mass() - M0) <= 1e-12 * M0
+        assert no_liquid_next_to_gas(o.read(O.F_TYPE))
 
 
 def test_round_trip_restores_the_solid_cells():
