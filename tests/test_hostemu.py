@@ -9,7 +9,10 @@ five cells high (every cell neighbours every cell of the next row, filled
 cells share their excess with a whole row) with and without the Galilean
 correction, and a film whose crests touch the top wall -- so that a
 difference between the GPU and the oracle there can be placed: in the
-source if this test fails too, in the compiled code if it does not.
+source if this test fails too, in the compiled code if it does not.  The
+moving spheres are checked here too (remaps, refilled link lists, spheres
+jumping through the surface, random moves), since their kernels are long
+chains of list passes that are easiest to check bounds-checked.
 """
 import dataclasses
 import os
@@ -154,6 +157,39 @@ def test_spheres_jumping_through_the_surface_on_the_cpu():
         g.step(3)
         o.step(3)
         compare(g, o, "jump %d + 3 steps" % k)
+        assert abs(g.total_mass() - M0) <= 1e-12 * M0
+    g.destroy()
+
+
+def test_random_moves_through_the_surface_on_the_cpu():
+    """Three spheres in a film, moved at random by a fraction of a cell or
+    by several cells (through the surface, into the gas and the liquid),
+    with steps between: against the oracle after every move and step,
+    the total mass exact."""
+    rng = np.random.default_rng(101)
+    nx, ny, nz = 18, 14, 22
+    z = np.arange(nz)[:, None, None] + np.zeros((nz, ny, nx))
+    n = 3
+    c = np.stack([(2.0 + np.arange(n) * nx / n) % nx, rng.uniform(0, ny, n), rng.uniform(4, nz - 5, n)], 1)
+    r = rng.uniform(1.6, 2.6, n)
+    w = I.Workload(name="random", shape=(nx, ny, nz), omega=1.5, accel=(1e-5, 0.0, -1e-5), sigma=0.0,
+                   fill=np.clip(11.6 - z, 0.0, 1.0), rho=np.ones((nz, ny, nx)), vel=np.zeros((3, nz, ny, nx)),
+                   centre=c, radius=r, sphere_vel=np.zeros((n, 3)), sphere_angvel=np.zeros((n, 3)))
+    g = emu.EmuLattice(w, "fp64")
+    o = O.OracleLattice(w.shape, w.omega, accel=w.accel, fill=w.fill, rho=w.rho, vel=w.vel, conv_eps=w.conv_eps)
+    o.set_particles(c, r, w.sphere_vel, w.sphere_angvel)
+    M0 = o.total_mass()
+    for k in range(5):
+        far = k % 2 == 0
+        c = c + (rng.uniform(-6, 6, size=(n, 3)) if far else rng.uniform(-0.6, 0.6, size=(n, 3)))
+        c[:, 2] = np.clip(c[:, 2], 3.0, nz - 4.0)
+        v = rng.normal(0, 1e-3, size=(n, 3))
+        g.move_particles(c, v)
+        o.move_particles(c, v)
+        compare(g, o, "move %d" % k)
+        g.step(2)
+        o.step(2)
+        compare(g, o, "move %d + 2 steps" % k)
         assert abs(g.total_mass() - M0) <= 1e-12 * M0
     g.destroy()
 
